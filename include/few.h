@@ -1,0 +1,233 @@
+/*
+ * few.h -- C ABI of libfew, an MI355X (gfx950) implementation of the
+ * interpolated harmonic-mode summation of Katz, Chua, Speri, Warburton and
+ * Hughes, "Fast extreme-mass-ratio-inspiral waveforms" (arXiv:2104.04582).
+ *
+ * The library computes, on a dense grid t_j = t_start + j dt (j < n_samples,
+ * evaluated in binary64 exactly as written),
+ *
+ *   h(t_j) = scale * sum_{listed (l,m,n)} [ A_lmn(t_j) -2Y_lm(theta, phi) e^{-i psi}
+ *            + [m > 0] (-1)^l conj(A_lmn(t_j)) -2Y_{l,-m}(theta, phi) e^{+i psi} ],
+ *   psi = m Phi_phi(t_j) + n Phi_r(t_j)
+ *
+ * i.e. the Schwarzschild-eccentric sum of Eq. (10) (Sec. IV) with the
+ * negative-m modes supplied by the amplitude symmetry of Eq. (9) (k = 0):
+ * A_{l,-m,-n} = (-1)^l conj(A_lmn).  The output is h = h_plus - i h_cross
+ * (Sec. II), so Re h = h_plus and Im h = -h_cross.  `scale` is the mu/d_L
+ * prefactor of Eq. (10).
+ *
+ * A_lmn(t), Phi_phi(t) and Phi_r(t) are not-a-knot cubic splines through their
+ * values on one shared sparse knot grid (Sec. III C, "Interpolated
+ * Summation"); the real and imaginary parts of each amplitude are splined
+ * separately (equivalent to a complex spline by linearity).
+ *
+ * Conventions
+ *  - List only modes with 0 <= m <= l, l >= 2; the m < 0 partners are implied
+ *    (Sec. III C).  m = 0 modes are summed once and never mirrored.
+ *  - Initial phases are part of Phi_phi[0] and Phi_r[0].
+ *  - Interval rule: sample t_j uses the cubic of the largest knot interval i
+ *    (0 <= i <= K-2) with t_i <= t_j; the last interval is closed at t_{K-1}.
+ *  - -2Y_lm follows the standard spin-weighted convention fixed by
+ *    -2Y_22 = sqrt(5/(64 pi)) (1 + cos theta)^2 e^{2 i phi}.
+ *
+ * Memory and ownership
+ *  - "host" pointers are read before the call returns.
+ *  - "device" pointers are HIP device memory of the plan's device (for example
+ *    torch tensors).  Inputs must stay alive and unmodified, and outputs must
+ *    not be read, until the work has completed: for the synchronous calls,
+ *    until the plan's stream passes the enqueued work; for few_submit, until
+ *    few_poll returns something other than FEW_PENDING.
+ *  - The library owns plan scratch, few_spline objects and request state,
+ *    all carved from one device arena of hbm_budget_bytes per plan.
+ *
+ * Errors
+ *  - Every function returns a few_status.  Argument, knot and mode errors are
+ *    detected on the host before anything is enqueued.  No C++ exception
+ *    crosses this interface.  few_last_error() returns the calling thread's
+ *    last message.
+ *
+ * Threading
+ *  - few_submit / few_poll / few_wait are thread-safe.  The synchronous calls
+ *    (few_spline_fit, few_mode_sum) take one plan per thread.
+ */
+#ifndef FEW_H
+#define FEW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FEW_OK = 0,
+    FEW_PENDING = 1,
+    FEW_E_ARG = -1,        /* null pointer, dt <= 0, n_samples <= 0, NaN/Inf */
+    FEW_E_KNOTS = -2,      /* K < 4, K > max_knots, knots not strictly increasing */
+    FEW_E_MODES = -3,      /* M < 1, M > max_modes, l < 2, l > 30, m < 0, m > l, |n| > 1000 */
+    FEW_E_RANGE = -4,      /* samples outside [t_0, t_{K-1}] */
+    FEW_E_TOO_LARGE = -5,  /* request footprint exceeds the whole plan budget */
+    FEW_E_NOMEM = -6,      /* arena or host allocation failed */
+    FEW_E_HIP = -7,        /* a HIP runtime call failed */
+    FEW_E_STATE = -8       /* bad handle, unknown ticket, plan being destroyed */
+} few_status;
+
+typedef enum {
+    FEW_FP64 = 0,   /* every step in binary64 (phases in double-double) */
+    FEW_MIXED = 1   /* binary64 spline solve, phases and mod-2pi reduction;
+                       binary32 amplitude evaluation, harmonics and products,
+                       compensated binary32 accumulation; complex64 output */
+} few_precision;
+
+enum { FEW_FLAG_TIMING = 1 };   /* record HIP events around every kernel launch */
+
+typedef struct few_plan_s *few_plan;
+typedef struct few_spline_s *few_spline;
+
+typedef struct {
+    int32_t device;            /* HIP device ordinal */
+    void *stream;              /* hipStream_t for the synchronous calls (borrowed; NULL = null stream) */
+    int32_t precision;         /* few_precision */
+    int32_t max_knots;         /* <= 2048; 0 -> 2048 */
+    int32_t max_modes;         /* 0 -> 65536 */
+    int32_t max_inflight;      /* served path: concurrent batch streams, 1..8; 0 -> 2 */
+    uint64_t hbm_budget_bytes; /* device arena per plan; 0 -> 2 GiB */
+    int32_t flags;             /* FEW_FLAG_* */
+} few_plan_desc;
+
+/* One served waveform request: the few_spline_fit arguments followed by the
+ * few_mode_sum arguments (same meaning, layout and ownership). */
+typedef struct {
+    int32_t n_knots;
+    const double *t_knots;     /* host [K] */
+    const double *phi_phi;     /* device [K] */
+    const double *phi_r;       /* device [K] */
+    int32_t n_modes;
+    const int32_t *lmn;        /* host [M][3] */
+    const double *amp;         /* device [K][M][2], knot-major (re, im) */
+    double theta, phi, scale, t_start, dt;
+    int64_t n_samples;
+    void *out;                 /* device complex128 (FEW_FP64) / complex64 (FEW_MIXED) [n_samples] */
+} few_request;
+
+/* Per-plan kernel timing (FEW_FLAG_TIMING), milliseconds summed over launches. */
+typedef struct {
+    double spline_ms;  int64_t spline_launches;
+    double prepare_ms; int64_t prepare_launches;
+    double sum_ms;     int64_t sum_launches;
+} few_timing;
+
+/* Create a plan on `desc->device`: validates the descriptor and reserves the
+ * device arena.  *out is set only on FEW_OK. */
+int32_t few_plan_create(const few_plan_desc *desc, few_plan *out);
+
+/* Drain in-flight work on every plan stream and release the plan, its arena
+ * and every few_spline made from it.  Outstanding tickets become invalid. */
+int32_t few_plan_destroy(few_plan plan);
+
+/*
+ * Spline stage (Sec. III C): fit not-a-knot cubic splines to Phi_phi, Phi_r
+ * and the real and imaginary part of every listed amplitude, all on the knot
+ * grid t_knots, and keep the coefficients resident in the plan arena.
+ *   K        number of knots, 4 <= K <= max_knots
+ *   t_knots  host [K], strictly increasing
+ *   phi_phi  device [K]  azimuthal phase at the knots (radians)
+ *   phi_r    device [K]  radial phase at the knots (radians)
+ *   M        number of listed modes, 1 <= M <= max_modes
+ *   lmn      host [M][3] int32 (l, m, n), 2 <= l <= 30, 0 <= m <= l, |n| <= 1000
+ *   amp      device [K][M][2] float64, knot-major: amp[(i*M + k)*2 + 0/1] is
+ *            Re/Im A of mode k at knot i (the amplitude module's 2-D layout, Sec. III B)
+ * Enqueued on the plan stream; *out is a library-owned handle.
+ */
+int32_t few_spline_fit(few_plan plan, int32_t K, const double *t_knots,
+                       const double *phi_phi, const double *phi_r,
+                       int32_t M, const int32_t *lmn, const double *amp,
+                       few_spline *out);
+
+/* Release a spline's arena memory (stream-ordered: safe while work using it is queued). */
+int32_t few_spline_free(few_spline spline);
+
+/*
+ * Copy a fitted spline's coefficients into device memory `dst` (plan stream):
+ *   which = 0: amplitudes, float64 [K-1][M][4][2]: coefficient of x^p (x = t - t_i)
+ *              of Re/Im A_k on interval i at dst[((i*M + k)*4 + p)*2 + re/im].
+ *   which = 1: phases, float64 [K-1][2][4][2]: coefficient p of Phi_phi (0) /
+ *              Phi_r (1) as a double-double (hi, lo); p = 0 holds the knot value
+ *              reduced to [-pi, pi) (adding 2 pi k leaves e^{-i psi} unchanged).
+ */
+int32_t few_spline_coefs(few_spline spline, int32_t which, void *dst);
+
+/*
+ * Summation stage (Sec. III C and Eqs. (9)-(10)): evaluate the splines on
+ * t_j = t_start + j dt, j < n_samples, combine each listed mode and its
+ * mirror with -2Y_lm(theta, phi), sum over modes and write
+ *   out[j] = h(t_j) = h_plus - i h_cross
+ * as interleaved complex128 (FEW_FP64) or complex64 (FEW_MIXED) device memory.
+ * Requires t_0 <= t_start and t_start + (n_samples-1) dt <= t_{K-1}.
+ * Enqueued on the plan stream; returns before the kernels finish.
+ */
+int32_t few_mode_sum(few_plan plan, few_spline spline, double theta, double phi,
+                     double scale, double t_start, double dt, int64_t n_samples,
+                     void *out);
+
+/*
+ * Served path: queue one request (spline fit + summation) for continuous
+ * batching.  A host scheduler thread admits queued requests in arrival order
+ * while their arena footprint fits the plan budget, packs the admitted ones
+ * into one batched launch on one of max_inflight streams, and retires them
+ * when that launch completes.  Each result is bitwise identical to the same
+ * request run alone.  Returns FEW_E_TOO_LARGE if the request can never fit.
+ */
+int32_t few_submit(few_plan plan, const few_request *req, uint64_t *ticket);
+
+/* FEW_PENDING while queued or running; FEW_OK once `out` holds the result
+ * (the ticket is then retired); or the request's asynchronous error. */
+int32_t few_poll(few_plan plan, uint64_t ticket);
+
+/* Block until the ticket is no longer pending; returns what few_poll would. */
+int32_t few_wait(few_plan plan, uint64_t ticket);
+
+/* Kernel times recorded so far (FEW_FLAG_TIMING), after synchronising the
+ * plan stream; reset != 0 clears the counters. */
+int32_t few_plan_timing(few_plan plan, few_timing *out, int32_t reset);
+
+/* The calling thread's last error message ("" if none). */
+const char *few_last_error(void);
+
+/* ---- Host-side helpers (no device work; usable without a GPU) ---------- */
+
+/*
+ * Term layout used by the summation kernel.  For fixed theta and phi the l-sum
+ * of Eq. (10) folds into one complex cubic per signed (m, n):
+ *   C_{m,n}  = sum_l -2Y_lm A_lmn                  (listed modes, m >= 0)
+ *   C_{-m,-n} = sum_l (-1)^l -2Y_{l,-m} conj(A_lmn)  (mirrors, m > 0)
+ * so h = sum_{m,n} C_{m,n}(t) e^{-i(m Phi_phi + n Phi_r)}.  Terms are grouped
+ * into segments of one signed m and a contiguous n range (gaps of at most
+ * `max_gap` zero terms are filled).  Writes up to cap_* entries:
+ *   segs[4*s + 0..3] = (m, n_lo, length, first term index)
+ *   term_ptr[n_terms + 1], term_src[2*e + 0/1] = (mode index, l | m << 8 | mirror << 16)
+ * and the counts.  Returns FEW_E_ARG if a capacity is too small.
+ */
+int32_t few_host_terms(int32_t M, const int32_t *lmn, int32_t max_gap,
+                       int32_t cap_segs, int32_t *segs, int32_t *n_segs,
+                       int32_t cap_terms, int32_t *term_ptr, int32_t *n_terms,
+                       int32_t cap_src, int32_t *term_src, int32_t *n_src);
+
+/*
+ * First sample of each knot interval: starts[i] = min{ j in [0, n] :
+ * t_start + j dt >= t_knots[i] } for 1 <= i <= K-2 (binary64 sample times),
+ * starts[0] = 0 and starts[K-1] = n.  The device computes the same starts.
+ */
+int32_t few_host_interval_starts(int32_t K, const double *t_knots, double t_start,
+                                 double dt, int64_t n, int64_t *starts);
+
+/* Arena bytes a served request of this shape reserves (precision of the plan
+ * descriptor `precision`), or 0 for invalid shapes. */
+uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t M,
+                                int32_t n_terms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEW_H */

@@ -1,0 +1,858 @@
+// libfew host runtime: the C ABI of include/few.h.
+//
+// Synchronous path: few_spline_fit (upload small host arrays, fit kernel) and
+// few_mode_sum (prepare kernel, sum kernel) enqueue on the caller's stream.
+// Served path: few_submit queues requests; one scheduler thread per plan
+// admits them in arrival order while their footprint fits the device arena,
+// packs the admitted ones into one batched launch (fit, prepare, persistent
+// sum) on one of max_inflight streams, and retires a batch when its completion
+// event fires.  Work of different requests never shares a wave, so every
+// result is bitwise the same alone or in a batch.
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/few.h"
+#include "few_internal.h"
+
+using namespace few;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(FEW_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));            \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device arena: one hipMalloc per plan, first-fit sub-allocation on the host.
+// ---------------------------------------------------------------------------
+class Arena {
+  public:
+    void init(char *base, size_t size) {
+        base_ = base;
+        size_ = size;
+        free_.clear();
+        free_[0] = size;
+        used_ = 0;
+    }
+    // returns offset or SIZE_MAX
+    size_t alloc(size_t bytes) {
+        std::lock_guard<std::mutex> g(mu_);
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (bytes == 0) bytes = 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                size_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > bytes) free_[off + bytes] = sz - bytes;
+                live_[off] = bytes;
+                used_ += bytes;
+                return off;
+            }
+        }
+        return SIZE_MAX;
+    }
+    void release(size_t off) {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = live_.find(off);
+        if (it == live_.end()) return;
+        size_t sz = it->second;
+        live_.erase(it);
+        used_ -= sz;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + sz == nx->first) {
+            sz += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += sz;
+                return;
+            }
+        }
+        free_[off] = sz;
+    }
+    char *ptr(size_t off) const { return base_ + off; }
+    size_t size() const { return size_; }
+
+  private:
+    std::mutex mu_;
+    char *base_ = nullptr;
+    size_t size_ = 0, used_ = 0;
+    std::map<size_t, size_t> free_, live_;
+};
+
+// Reusable pinned host buffers (hipHostMalloc is slow; keep them).
+class PinnedPool {
+  public:
+    void *get(size_t bytes) {
+        std::lock_guard<std::mutex> g(mu_);
+        for (auto &b : bufs_)
+            if (!b.busy && b.size >= bytes) {
+                b.busy = true;
+                return b.ptr;
+            }
+        void *p = nullptr;
+        size_t sz = std::max<size_t>(bytes, 1 << 16);
+        if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) return nullptr;
+        bufs_.push_back({p, sz, true});
+        return p;
+    }
+    void put(void *p) {
+        std::lock_guard<std::mutex> g(mu_);
+        for (auto &b : bufs_)
+            if (b.ptr == p) b.busy = false;
+    }
+    void clear() {
+        std::lock_guard<std::mutex> g(mu_);
+        for (auto &b : bufs_) hipHostFree(b.ptr);
+        bufs_.clear();
+    }
+
+  private:
+    struct Buf {
+        void *ptr;
+        size_t size;
+        bool busy;
+    };
+    std::mutex mu_;
+    std::vector<Buf> bufs_;
+};
+
+enum Stage { ST_FIT = 0, ST_PREP = 1, ST_SUM = 2 };
+
+// One request's host-side description and arena placement.
+struct HostReq {
+    int K = 0, M = 0;
+    std::vector<double> t;
+    TermLayout terms;
+    ReqLayout L{};
+    size_t upload_bytes = 0;   // [0, upload_bytes) of the layout comes from the host
+    ~HostReq() { free_term_layout(&terms); }
+};
+
+int validate_fit_args(int K, const double *t, int M, const int32_t *lmn, const void *pp,
+                      const void *pr, const void *amp, int max_knots, int max_modes) {
+    if (!t || !lmn || !pp || !pr || !amp) return fail(FEW_E_ARG, "null pointer argument");
+    if (K < 4 || K > max_knots)
+        return fail(FEW_E_KNOTS, "K = %d outside [4, %d]", K, max_knots);
+    for (int i = 0; i < K; ++i)
+        if (!std::isfinite(t[i])) return fail(FEW_E_KNOTS, "knot %d is not finite", i);
+    for (int i = 0; i + 1 < K; ++i)
+        if (!(t[i + 1] > t[i]))
+            return fail(FEW_E_KNOTS, "knots not strictly increasing at %d", i);
+    if (M < 1 || M > max_modes) return fail(FEW_E_MODES, "M = %d outside [1, %d]", M, max_modes);
+    for (int k = 0; k < M; ++k) {
+        int l = lmn[3 * k], m = lmn[3 * k + 1], n = lmn[3 * k + 2];
+        if (l < 2 || l > kMaxL || m < 0 || m > l || n < -kMaxAbsN || n > kMaxAbsN)
+            return fail(FEW_E_MODES, "mode %d = (%d,%d,%d) invalid (2<=l<=%d, 0<=m<=l, |n|<=%d)",
+                        k, l, m, n, kMaxL, kMaxAbsN);
+    }
+    return FEW_OK;
+}
+
+int validate_sum_args(const double *t, int K, double theta, double phi, double scale,
+                      double t_start, double dt, int64_t n, const void *out) {
+    if (!out) return fail(FEW_E_ARG, "null output pointer");
+    if (!std::isfinite(theta) || !std::isfinite(phi) || !std::isfinite(scale) ||
+        !std::isfinite(t_start) || !std::isfinite(dt))
+        return fail(FEW_E_ARG, "non-finite scalar argument");
+    if (!(dt > 0.0)) return fail(FEW_E_ARG, "dt must be > 0");
+    if (n < 1) return fail(FEW_E_ARG, "n_samples must be >= 1");
+    if ((n + 255) / 64 + K > (int64_t)0x3fffffff) return fail(FEW_E_ARG, "n_samples too large");
+    if (!(t_start >= t[0])) return fail(FEW_E_RANGE, "t_start before the first knot");
+    if (!(sample_time(t_start, dt, n - 1) <= t[K - 1]))
+        return fail(FEW_E_RANGE, "last sample after the last knot");
+    return FEW_OK;
+}
+
+// Fill the upload region [0, upload_bytes) of a request layout in host memory.
+void stage_upload(const HostReq &r, char *dst) {
+    std::memcpy(dst + r.L.off_t, r.t.data(), sizeof(double) * r.K);
+    std::memcpy(dst + r.L.off_segs, r.terms.segs, sizeof(int) * 4 * r.terms.n_segs);
+    std::memcpy(dst + r.L.off_term_ptr, r.terms.term_ptr, sizeof(int) * (r.terms.n_terms + 1));
+    std::memcpy(dst + r.L.off_term_src, r.terms.term_src, sizeof(int) * 2 * r.terms.n_src);
+    std::memcpy(dst + r.L.off_chunk_ptr, r.terms.chunk_ptr, sizeof(int) * (r.terms.n_chunks + 1));
+}
+
+int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, HostReq *r) {
+    r->K = K;
+    r->M = M;
+    r->t.assign(t, t + K);
+    int rc = build_term_layout(M, lmn, kMaxGap, &r->terms);
+    if (rc) return fail(rc, "mode list rejected while building the term layout");
+    r->L = request_layout(fp32, K, M, r->terms.n_segs, r->terms.n_terms, r->terms.n_src,
+                          r->terms.n_chunks);
+    r->upload_bytes = r->L.off_chunk_ptr + sizeof(int) * (r->terms.n_chunks + 1);
+    return FEW_OK;
+}
+
+FitJob fit_job(const HostReq &r, char *base, const double *pp, const double *pr,
+               const double *amp) {
+    FitJob j{};
+    j.t = (const double *)(base + r.L.off_t);
+    j.phi_phi = pp;
+    j.phi_r = pr;
+    j.amp = amp;
+    j.pcoef = (double *)(base + r.L.off_pcoef);
+    j.acoef = (double *)(base + r.L.off_acoef);
+    j.K = r.K;
+    j.M = r.M;
+    j.amp_blocks = (2 * r.M + 255) / 256;
+    return j;
+}
+
+PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double scale,
+                 double t_start, double dt, int64_t n, bool fp32) {
+    PrepJob j{};
+    j.t = (const double *)(base + r.L.off_t);
+    j.acoef = (const double *)(base + r.L.off_acoef);
+    j.term_ptr = (const int *)(base + r.L.off_term_ptr);
+    j.term_src = (const int2 *)(base + r.L.off_term_src);
+    j.chunk_ptr = (const int *)(base + r.L.off_chunk_ptr);
+    j.table = base + r.L.off_table;
+    j.starts = (long long *)(base + r.L.off_starts);
+    j.tile_pref = (int *)(base + r.L.off_tile_pref);
+    j.theta = theta;
+    j.phi = phi;
+    j.scale = scale;
+    j.t_start = t_start;
+    j.dt = dt;
+    j.n = n;
+    j.K = r.K;
+    j.M = r.M;
+    j.n_terms = r.terms.n_terms;
+    j.n_chunks = r.terms.n_chunks;
+    j.tile = tile_samples(fp32);
+    return j;
+}
+
+SumJob sum_job(const HostReq &r, char *base, double t_start, double dt, int64_t n, void *out) {
+    SumJob j{};
+    j.t = (const double *)(base + r.L.off_t);
+    j.pcoef = (const double *)(base + r.L.off_pcoef);
+    j.table = base + r.L.off_table;
+    j.segs = (const int4 *)(base + r.L.off_segs);
+    j.starts = (const long long *)(base + r.L.off_starts);
+    j.tile_pref = (const int *)(base + r.L.off_tile_pref);
+    j.out = out;
+    j.t_start = t_start;
+    j.dt = dt;
+    j.n = n;
+    j.K = r.K;
+    j.n_terms = r.terms.n_terms;
+    j.n_segs = r.terms.n_segs;
+    j.wave_base = 0;
+    return j;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan and spline objects.
+// ---------------------------------------------------------------------------
+struct ServedReq {
+    uint64_t ticket;
+    few_request r;
+    HostReq h;
+    int status = FEW_PENDING;
+    size_t footprint = 0;
+};
+
+struct Batch {
+    int slot;                  // stream index
+    size_t arena_off = SIZE_MAX;
+    void *pinned = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<ServedReq *> reqs;
+};
+
+struct few_plan_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool fp32 = false;
+    int max_knots = kMaxKnots, max_modes = 65536, max_inflight = 2;
+    uint64_t budget = 0;
+    int flags = 0;
+    char *arena_base = nullptr;
+    Arena arena;
+    PinnedPool pinned;
+    // synchronous-path staging: two alternating pinned slots
+    void *stage[2] = {nullptr, nullptr};
+    size_t stage_size[2] = {0, 0};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    bool stage_pending[2] = {false, false};
+    int stage_next = 0;
+    std::mutex sync_mu;
+    std::set<few_spline> splines;
+    // timing
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timed;
+    std::vector<hipEvent_t> ev_pool;
+    double acc_ms[3] = {0, 0, 0};
+    int64_t acc_n[3] = {0, 0, 0};
+    // served path
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<ServedReq *> pending;
+    std::unordered_map<uint64_t, ServedReq *> tickets;
+    std::vector<Batch *> inflight;
+    std::vector<hipStream_t> bstreams;
+    std::vector<bool> slot_busy;
+    std::thread worker;
+    bool stop = false, worker_started = false;
+    uint64_t next_ticket = 1;
+    unsigned *counters = nullptr;   // one persistent-kernel counter per stream slot
+};
+
+struct few_spline_s {
+    few_plan plan = nullptr;
+    HostReq h;
+    size_t arena_off = SIZE_MAX;
+};
+
+namespace {
+
+hipEvent_t pool_event(few_plan p) {
+    if (!p->ev_pool.empty()) {
+        hipEvent_t e = p->ev_pool.back();
+        p->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Run launch() between two timing events when FEW_FLAG_TIMING is set.
+template <typename F>
+int timed_launch(few_plan p, int stage, hipStream_t s, F launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (p->flags & FEW_FLAG_TIMING) {
+        a = pool_event(p);
+        b = pool_event(p);
+        if (a && b) hipEventRecord(a, s);
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return fail(FEW_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    if (a && b) {
+        hipEventRecord(b, s);
+        p->timed.push_back({stage, {a, b}});
+    }
+    return FEW_OK;
+}
+
+// Copy n bytes from host to device on the plan stream through a pinned slot.
+int sync_upload(few_plan p, const HostReq &r, char *dst) {
+    int s = p->stage_next;
+    p->stage_next ^= 1;
+    if (p->stage_pending[s]) {
+        HIP_TRY(hipEventSynchronize(p->stage_ev[s]));
+        p->stage_pending[s] = false;
+    }
+    if (p->stage_size[s] < r.upload_bytes) {
+        if (p->stage[s]) hipHostFree(p->stage[s]);
+        p->stage[s] = nullptr;
+        size_t sz = std::max<size_t>(r.upload_bytes, 1 << 20);
+        HIP_TRY(hipHostMalloc(&p->stage[s], sz, hipHostMallocDefault));
+        p->stage_size[s] = sz;
+    }
+    stage_upload(r, (char *)p->stage[s]);
+    HIP_TRY(hipMemcpyAsync(dst, p->stage[s], r.upload_bytes, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipEventRecord(p->stage_ev[s], p->stream));
+    p->stage_pending[s] = true;
+    return FEW_OK;
+}
+
+void scheduler_main(few_plan p);
+
+}  // namespace
+
+extern "C" {
+
+const char *few_last_error(void) { return g_err.c_str(); }
+
+int32_t few_plan_create(const few_plan_desc *desc, few_plan *out) {
+    try {
+        if (!desc || !out) return fail(FEW_E_ARG, "null argument");
+        if (desc->precision != FEW_FP64 && desc->precision != FEW_MIXED)
+            return fail(FEW_E_ARG, "unknown precision %d", desc->precision);
+        if (desc->max_knots < 0 || desc->max_knots > kMaxKnots)
+            return fail(FEW_E_ARG, "max_knots must be in [0, %d]", kMaxKnots);
+        if (desc->max_modes < 0) return fail(FEW_E_ARG, "max_modes < 0");
+        if (desc->max_inflight < 0 || desc->max_inflight > 8)
+            return fail(FEW_E_ARG, "max_inflight must be in [0, 8]");
+        int ndev = 0;
+        HIP_TRY(hipGetDeviceCount(&ndev));
+        if (desc->device < 0 || desc->device >= ndev)
+            return fail(FEW_E_ARG, "device %d not present (%d devices)", desc->device, ndev);
+        HIP_TRY(hipSetDevice(desc->device));
+        few_plan p = new (std::nothrow) few_plan_s;
+        if (!p) return fail(FEW_E_NOMEM, "host allocation failed");
+        p->device = desc->device;
+        p->stream = (hipStream_t)desc->stream;
+        p->fp32 = desc->precision == FEW_MIXED;
+        p->max_knots = desc->max_knots ? desc->max_knots : kMaxKnots;
+        p->max_modes = desc->max_modes ? desc->max_modes : 65536;
+        p->max_inflight = desc->max_inflight ? desc->max_inflight : 2;
+        p->budget = desc->hbm_budget_bytes ? desc->hbm_budget_bytes : (2ull << 30);
+        p->flags = desc->flags;
+        void *base = nullptr;
+        hipError_t e = hipMalloc(&base, p->budget);
+        if (e != hipSuccess) {
+            delete p;
+            return fail(FEW_E_NOMEM, "arena hipMalloc(%llu) failed: %s",
+                        (unsigned long long)desc->hbm_budget_bytes, hipGetErrorString(e));
+        }
+        p->arena_base = (char *)base;
+        p->arena.init(p->arena_base, p->budget);
+        for (int s = 0; s < 2; ++s) {
+            if (hipEventCreateWithFlags(&p->stage_ev[s], hipEventDisableTiming) != hipSuccess) {
+                hipFree(base);
+                delete p;
+                return fail(FEW_E_HIP, "hipEventCreate failed");
+            }
+        }
+        *out = p;
+        return FEW_OK;
+    } catch (...) {
+        return fail(FEW_E_NOMEM, "exception in few_plan_create");
+    }
+}
+
+int32_t few_plan_destroy(few_plan p) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    try {
+        hipSetDevice(p->device);
+        {
+            std::unique_lock<std::mutex> g(p->mu);
+            p->stop = true;
+        }
+        p->cv_work.notify_all();
+        if (p->worker_started) p->worker.join();
+        for (hipStream_t s : p->bstreams) {
+            hipStreamSynchronize(s);
+            hipStreamDestroy(s);
+        }
+        for (auto &kv : p->tickets) delete kv.second;
+        for (ServedReq *r : p->pending)
+            if (!p->tickets.count(r->ticket)) delete r;
+        hipStreamSynchronize(p->stream);
+        for (few_spline s : p->splines) delete s;
+        for (auto &t : p->timed) {
+            hipEventDestroy(t.second.first);
+            hipEventDestroy(t.second.second);
+        }
+        for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
+        for (int s = 0; s < 2; ++s) {
+            if (p->stage[s]) hipHostFree(p->stage[s]);
+            hipEventDestroy(p->stage_ev[s]);
+        }
+        p->pinned.clear();
+        hipFree(p->arena_base);
+        delete p;
+        return FEW_OK;
+    } catch (...) {
+        return fail(FEW_E_STATE, "exception in few_plan_destroy");
+    }
+}
+
+int32_t few_spline_fit(few_plan p, int32_t K, const double *t_knots, const double *phi_phi,
+                       const double *phi_r, int32_t M, const int32_t *lmn, const double *amp,
+                       few_spline *out) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    if (!out) return fail(FEW_E_ARG, "null output handle");
+    try {
+        int rc = validate_fit_args(K, t_knots, M, lmn, phi_phi, phi_r, amp, p->max_knots,
+                                   p->max_modes);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> g(p->sync_mu);
+        HIP_TRY(hipSetDevice(p->device));
+        few_spline s = new (std::nothrow) few_spline_s;
+        if (!s) return fail(FEW_E_NOMEM, "host allocation failed");
+        rc = make_host_req(K, t_knots, M, lmn, p->fp32, &s->h);
+        if (rc) {
+            delete s;
+            return rc;
+        }
+        if (s->h.L.total > p->budget) {
+            delete s;
+            return fail(FEW_E_TOO_LARGE, "spline needs %zu bytes, plan budget %llu",
+                        s->h.L.total, (unsigned long long)p->budget);
+        }
+        s->arena_off = p->arena.alloc(s->h.L.total);
+        if (s->arena_off == SIZE_MAX) {
+            delete s;
+            return fail(FEW_E_NOMEM, "plan arena exhausted");
+        }
+        s->plan = p;
+        char *base = p->arena.ptr(s->arena_off);
+        rc = sync_upload(p, s->h, base);
+        if (!rc) {
+            FitJob job = fit_job(s->h, base, phi_phi, phi_r, amp);
+            rc = timed_launch(p, ST_FIT, p->stream, [&] { return launch_fit(job, p->stream); });
+        }
+        if (rc) {
+            p->arena.release(s->arena_off);
+            delete s;
+            return rc;
+        }
+        p->splines.insert(s);
+        *out = s;
+        return FEW_OK;
+    } catch (...) {
+        return fail(FEW_E_NOMEM, "exception in few_spline_fit");
+    }
+}
+
+int32_t few_spline_free(few_spline s) {
+    if (!s || !s->plan) return fail(FEW_E_STATE, "bad spline handle");
+    few_plan p = s->plan;
+    std::lock_guard<std::mutex> g(p->sync_mu);
+    if (!p->splines.count(s)) return fail(FEW_E_STATE, "spline not owned by its plan");
+    // stream-ordered reuse: later work on the plan stream runs after queued work
+    p->arena.release(s->arena_off);
+    p->splines.erase(s);
+    delete s;
+    return FEW_OK;
+}
+
+int32_t few_spline_coefs(few_spline s, int32_t which, void *dst) {
+    if (!s || !s->plan) return fail(FEW_E_STATE, "bad spline handle");
+    if (!dst) return fail(FEW_E_ARG, "null destination");
+    few_plan p = s->plan;
+    HIP_TRY(hipSetDevice(p->device));
+    char *base = p->arena.ptr(s->arena_off);
+    if (which == 0) {
+        HIP_TRY(hipMemcpyAsync(dst, base + s->h.L.off_acoef,
+                               sizeof(double) * 8 * (size_t)(s->h.K - 1) * s->h.M,
+                               hipMemcpyDeviceToDevice, p->stream));
+    } else if (which == 1) {
+        HIP_TRY(hipMemcpyAsync(dst, base + s->h.L.off_pcoef,
+                               sizeof(double) * 16 * (size_t)(s->h.K - 1),
+                               hipMemcpyDeviceToDevice, p->stream));
+    } else {
+        return fail(FEW_E_ARG, "which must be 0 (amplitudes) or 1 (phases)");
+    }
+    return FEW_OK;
+}
+
+int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double scale,
+                     double t_start, double dt, int64_t n, void *out) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    if (!s || s->plan != p) return fail(FEW_E_STATE, "spline does not belong to this plan");
+    try {
+        int rc = validate_sum_args(s->h.t.data(), s->h.K, theta, phi, scale, t_start, dt, n, out);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> g(p->sync_mu);
+        HIP_TRY(hipSetDevice(p->device));
+        char *base = p->arena.ptr(s->arena_off);
+        PrepJob pj = prep_job(s->h, base, theta, phi, scale, t_start, dt, n, p->fp32);
+        rc = timed_launch(p, ST_PREP, p->stream,
+                          [&] { return launch_prepare(pj, p->fp32, p->stream); });
+        if (rc) return rc;
+        SumJob sj = sum_job(s->h, base, t_start, dt, n, out);
+        long long slots = tile_upper_bound(n, s->h.K, tile_samples(p->fp32));
+        return timed_launch(p, ST_SUM, p->stream, [&] {
+            return launch_sum(sj, (int)slots, p->fp32, p->stream);
+        });
+    } catch (...) {
+        return fail(FEW_E_NOMEM, "exception in few_mode_sum");
+    }
+}
+
+int32_t few_plan_timing(few_plan p, few_timing *out, int32_t reset) {
+    if (!p || !out) return fail(FEW_E_ARG, "null argument");
+    std::lock_guard<std::mutex> g(p->sync_mu);
+    HIP_TRY(hipSetDevice(p->device));
+    for (auto &t : p->timed) {
+        HIP_TRY(hipEventSynchronize(t.second.second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, t.second.first, t.second.second));
+        p->acc_ms[t.first] += ms;
+        p->acc_n[t.first] += 1;
+        p->ev_pool.push_back(t.second.first);
+        p->ev_pool.push_back(t.second.second);
+    }
+    p->timed.clear();
+    out->spline_ms = p->acc_ms[ST_FIT];
+    out->spline_launches = p->acc_n[ST_FIT];
+    out->prepare_ms = p->acc_ms[ST_PREP];
+    out->prepare_launches = p->acc_n[ST_PREP];
+    out->sum_ms = p->acc_ms[ST_SUM];
+    out->sum_launches = p->acc_n[ST_SUM];
+    if (reset) {
+        for (int i = 0; i < 3; ++i) {
+            p->acc_ms[i] = 0;
+            p->acc_n[i] = 0;
+        }
+    }
+    return FEW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Served path.
+// ---------------------------------------------------------------------------
+int32_t few_submit(few_plan p, const few_request *req, uint64_t *ticket) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    if (!req || !ticket) return fail(FEW_E_ARG, "null argument");
+    try {
+        int rc = validate_fit_args(req->n_knots, req->t_knots, req->n_modes, req->lmn,
+                                   req->phi_phi, req->phi_r, req->amp, p->max_knots,
+                                   p->max_modes);
+        if (rc) return rc;
+        rc = validate_sum_args(req->t_knots, req->n_knots, req->theta, req->phi, req->scale,
+                               req->t_start, req->dt, req->n_samples, req->out);
+        if (rc) return rc;
+        ServedReq *r = new (std::nothrow) ServedReq;
+        if (!r) return fail(FEW_E_NOMEM, "host allocation failed");
+        r->r = *req;
+        rc = make_host_req(req->n_knots, req->t_knots, req->n_modes, req->lmn, p->fp32, &r->h);
+        if (rc) {
+            delete r;
+            return rc;
+        }
+        r->r.t_knots = r->h.t.data();
+        r->r.lmn = nullptr;   // consumed into the term layout
+        r->footprint = r->h.L.total + 3 * 256 + sizeof(FitJob) + sizeof(PrepJob) + sizeof(SumJob);
+        if (r->footprint > p->budget) {
+            size_t need = r->footprint;
+            delete r;
+            return fail(FEW_E_TOO_LARGE, "request needs %zu bytes, plan budget %llu", need,
+                        (unsigned long long)p->budget);
+        }
+        std::unique_lock<std::mutex> g(p->mu);
+        if (p->stop) {
+            delete r;
+            return fail(FEW_E_STATE, "plan is being destroyed");
+        }
+        if (!p->worker_started) {
+            HIP_TRY(hipSetDevice(p->device));
+            p->bstreams.resize(p->max_inflight);
+            p->slot_busy.assign(p->max_inflight, false);
+            for (int s = 0; s < p->max_inflight; ++s)
+                HIP_TRY(hipStreamCreateWithFlags(&p->bstreams[s], hipStreamNonBlocking));
+            size_t off = p->arena.alloc(256 * (size_t)p->max_inflight);
+            if (off == SIZE_MAX) return fail(FEW_E_NOMEM, "arena exhausted (counters)");
+            p->counters = (unsigned *)p->arena.ptr(off);
+            p->worker = std::thread(scheduler_main, p);
+            p->worker_started = true;
+        }
+        r->ticket = p->next_ticket++;
+        p->tickets[r->ticket] = r;
+        p->pending.push_back(r);
+        *ticket = r->ticket;
+        g.unlock();
+        p->cv_work.notify_one();
+        return FEW_OK;
+    } catch (...) {
+        return fail(FEW_E_NOMEM, "exception in few_submit");
+    }
+}
+
+int32_t few_poll(few_plan p, uint64_t ticket) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    std::lock_guard<std::mutex> g(p->mu);
+    auto it = p->tickets.find(ticket);
+    if (it == p->tickets.end()) return fail(FEW_E_STATE, "unknown or retired ticket");
+    int st = it->second->status;
+    if (st == FEW_PENDING) return FEW_PENDING;
+    delete it->second;
+    p->tickets.erase(it);
+    if (st != FEW_OK) return fail(st, "request failed on the device path");
+    return FEW_OK;
+}
+
+int32_t few_wait(few_plan p, uint64_t ticket) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    {
+        std::unique_lock<std::mutex> g(p->mu);
+        auto it = p->tickets.find(ticket);
+        if (it == p->tickets.end()) return fail(FEW_E_STATE, "unknown or retired ticket");
+        ServedReq *r = it->second;
+        p->cv_done.wait(g, [&] { return r->status != FEW_PENDING; });
+    }
+    return few_poll(p, ticket);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Build and launch one batch on stream slot `slot`.  Called without p->mu held.
+int launch_batch(few_plan p, Batch *b) {
+    const int n = (int)b->reqs.size();
+    // arena block: [FitJob[n] | PrepJob[n] | SumJob[n] | per-request uploads | rest]
+    size_t off_fit = 0;
+    size_t off_prep = (off_fit + sizeof(FitJob) * n + 255) & ~(size_t)255;
+    size_t off_sum = (off_prep + sizeof(PrepJob) * n + 255) & ~(size_t)255;
+    size_t cur = (off_sum + sizeof(SumJob) * n + 255) & ~(size_t)255;
+    std::vector<size_t> req_off(n);
+    for (int i = 0; i < n; ++i) {
+        req_off[i] = cur;
+        cur += (b->reqs[i]->h.L.total + 255) & ~(size_t)255;
+    }
+    // only the job arrays and each request's upload region are copied; the
+    // whole staged image is sent in one copy up to the last upload region
+    size_t upload_end = n ? req_off[n - 1] + b->reqs[n - 1]->h.upload_bytes : off_sum;
+    char *dev = p->arena.ptr(b->arena_off);
+    b->pinned = p->pinned.get(upload_end);
+    if (!b->pinned) return fail(FEW_E_NOMEM, "pinned staging allocation failed");
+    char *host = (char *)b->pinned;
+    FitJob *fj = (FitJob *)(host + off_fit);
+    PrepJob *pj = (PrepJob *)(host + off_prep);
+    SumJob *sj = (SumJob *)(host + off_sum);
+    const bool fp32 = p->fp32;
+    const int tile = tile_samples(fp32);
+    int max_amp_blocks = 0, max_K = 4, max_chunks = 0;
+    long long waves = 0;
+    for (int i = 0; i < n; ++i) {
+        ServedReq *r = b->reqs[i];
+        char *rb = dev + req_off[i];
+        stage_upload(r->h, host + req_off[i]);
+        fj[i] = fit_job(r->h, rb, r->r.phi_phi, r->r.phi_r, r->r.amp);
+        pj[i] = prep_job(r->h, rb, r->r.theta, r->r.phi, r->r.scale, r->r.t_start, r->r.dt,
+                         r->r.n_samples, fp32);
+        sj[i] = sum_job(r->h, rb, r->r.t_start, r->r.dt, r->r.n_samples, r->r.out);
+        sj[i].wave_base = (int)waves;
+        waves += tile_upper_bound(r->r.n_samples, r->h.K, tile);
+        max_amp_blocks = std::max(max_amp_blocks, fj[i].amp_blocks);
+        max_K = std::max(max_K, r->h.K);
+        max_chunks = std::max(max_chunks, pj[i].n_chunks);
+    }
+    if (waves > 0x3fffffff) return fail(FEW_E_ARG, "batch too large");
+    hipStream_t s = p->bstreams[b->slot];
+    HIP_TRY(hipMemcpyAsync(dev, host, upload_end, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fit_batch((const FitJob *)(dev + off_fit), n, max_amp_blocks, max_K, s));
+    HIP_TRY(launch_prepare_batch((const PrepJob *)(dev + off_prep), n, max_chunks, fp32, s));
+    HIP_TRY(launch_sum_batch((const SumJob *)(dev + off_sum), n, (int)waves, fp32, true,
+                             p->counters + 64 * b->slot, s));
+    HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(b->done, s));
+    return FEW_OK;
+}
+
+size_t batch_bytes(const std::vector<ServedReq *> &reqs) {
+    size_t n = reqs.size();
+    size_t cur = 0;
+    cur = (cur + sizeof(FitJob) * n + 255) & ~(size_t)255;
+    cur = (cur + sizeof(PrepJob) * n + 255) & ~(size_t)255;
+    cur = (cur + sizeof(SumJob) * n + 255) & ~(size_t)255;
+    for (ServedReq *r : reqs) cur += (r->h.L.total + 255) & ~(size_t)255;
+    return cur;
+}
+
+void scheduler_main(few_plan p) {
+    hipSetDevice(p->device);
+    std::unique_lock<std::mutex> g(p->mu);
+    for (;;) {
+        // retire finished batches
+        bool retired = false;
+        for (size_t i = 0; i < p->inflight.size();) {
+            Batch *b = p->inflight[i];
+            hipError_t q = hipEventQuery(b->done);
+            if (q == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
+            int st = (q == hipSuccess) ? FEW_OK : FEW_E_HIP;
+            for (ServedReq *r : b->reqs) r->status = st;
+            p->arena.release(b->arena_off);
+            p->pinned.put(b->pinned);
+            hipEventDestroy(b->done);
+            p->slot_busy[b->slot] = false;
+            delete b;
+            p->inflight.erase(p->inflight.begin() + i);
+            retired = true;
+        }
+        if (retired) p->cv_done.notify_all();
+        // admit: arrival order, as many as fit the arena, one free stream slot
+        int slot = -1;
+        for (int s = 0; s < p->max_inflight; ++s)
+            if (!p->slot_busy[s]) {
+                slot = s;
+                break;
+            }
+        if (slot >= 0 && !p->pending.empty()) {
+            std::vector<ServedReq *> take;
+            size_t off = SIZE_MAX;
+            for (ServedReq *r : p->pending) {
+                take.push_back(r);
+                if (take.size() > 256) {
+                    take.pop_back();
+                    break;
+                }
+            }
+            while (!take.empty()) {
+                off = p->arena.alloc(batch_bytes(take));
+                if (off != SIZE_MAX) break;
+                take.pop_back();
+            }
+            if (off != SIZE_MAX && !take.empty()) {
+                for (size_t i = 0; i < take.size(); ++i) p->pending.pop_front();
+                Batch *b = new Batch;
+                b->slot = slot;
+                b->arena_off = off;
+                b->reqs = take;
+                p->slot_busy[slot] = true;
+                g.unlock();
+                int rc = launch_batch(p, b);
+                g.lock();
+                if (rc != FEW_OK) {
+                    if (b->done) {
+                        hipEventSynchronize(b->done);
+                        hipEventDestroy(b->done);
+                    } else {
+                        hipStreamSynchronize(p->bstreams[slot]);
+                    }
+                    for (ServedReq *r : b->reqs) r->status = rc;
+                    p->arena.release(b->arena_off);
+                    if (b->pinned) p->pinned.put(b->pinned);
+                    p->slot_busy[slot] = false;
+                    delete b;
+                    p->cv_done.notify_all();
+                } else {
+                    p->inflight.push_back(b);
+                }
+                continue;
+            }
+        }
+        if (p->stop && p->pending.empty() && p->inflight.empty()) break;
+        if (p->inflight.empty() && p->pending.empty())
+            p->cv_work.wait(g, [&] { return p->stop || !p->pending.empty(); });
+        else
+            p->cv_work.wait_for(g, std::chrono::microseconds(50));
+    }
+}
+
+}  // namespace

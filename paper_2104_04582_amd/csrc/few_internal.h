@@ -1,0 +1,123 @@
+// Internal declarations shared by the host runtime (few_api.cpp,
+// host_core.cpp) and the gfx950 kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace few {
+
+constexpr int kMaxKnots = 2048;       // LDS holds three binary64 arrays of this length (48 KiB)
+constexpr int kMaxL = 30;             // Wigner-d sum stays well conditioned in binary64
+constexpr int kMaxAbsN = 1000;
+constexpr int kWave = 64;
+constexpr int kFoldSrcCap = 1024;     // contributor entries staged in LDS per fold block
+constexpr int kFoldMaxTerms = 64;     // terms per fold block
+constexpr int kMaxGap = 4;            // zero terms filled inside one segment
+
+// Samples per lane in one wave tile of the summation kernel.
+constexpr int kSamplesPerLaneF32 = 4;
+constexpr int kSamplesPerLaneF64 = 2;
+
+inline int tile_samples(bool fp32) {
+    return kWave * (fp32 ? kSamplesPerLaneF32 : kSamplesPerLaneF64);
+}
+
+// ---------------------------------------------------------------------------
+// Device-side job descriptors.  Pointers are device addresses in the plan
+// arena (or caller memory for inputs/outputs).
+// ---------------------------------------------------------------------------
+
+// Spline stage for one request.
+struct FitJob {
+    const double *t;        // [K] knot times
+    const double *phi_phi;  // [K]
+    const double *phi_r;    // [K]
+    const double *amp;      // [K][M][2]
+    double *pcoef;          // [K-1][2][4][2] double-double phase cubics
+    double *acoef;          // [K-1][M][4][2] amplitude cubics
+    int K, M;
+    int amp_blocks;         // blocks covering the 2M amplitude series
+};
+
+// Fold + interval bookkeeping for one request.
+struct PrepJob {
+    const double *t;
+    const double *acoef;
+    const int *term_ptr;    // [n_terms + 1]
+    const int2 *term_src;   // [n_src]: (mode, l | m << 8 | mirror << 16)
+    const int *chunk_ptr;   // [n_chunks + 1] first term of each fold block
+    void *table;            // [K-1][n_terms][8] binary32 or binary64
+    long long *starts;      // [K]
+    int *tile_pref;         // [K]
+    double theta, phi, scale, t_start, dt;
+    long long n;
+    int K, M, n_terms, n_chunks;
+    int tile;               // samples per wave tile
+};
+
+// Summation stage for one request.
+struct SumJob {
+    const double *t;
+    const double *pcoef;
+    const void *table;
+    const int4 *segs;       // [n_segs]: (m, n_lo, length, first term)
+    const long long *starts;
+    const int *tile_pref;
+    void *out;
+    double t_start, dt;
+    long long n;
+    int K, n_terms, n_segs;
+    int wave_base;          // first global wave slot of this job (batched launch)
+};
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
+hipError_t launch_fit(const FitJob &job, hipStream_t stream);
+hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
+                            hipStream_t stream);
+hipError_t launch_prepare(const PrepJob &job, bool fp32, hipStream_t stream);
+hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_chunks,
+                                bool fp32, hipStream_t stream);
+hipError_t launch_sum(const SumJob &job, int wave_slots, bool fp32, hipStream_t stream);
+hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_slots,
+                            bool fp32, bool persistent, unsigned *counter_dev,
+                            hipStream_t stream);
+hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Host core (host_core.cpp): no device work.
+// ---------------------------------------------------------------------------
+struct TermLayout {
+    int n_segs = 0, n_terms = 0, n_src = 0, n_chunks = 0;
+    int *segs = nullptr;       // 4 * n_segs
+    int *term_ptr = nullptr;   // n_terms + 1
+    int *term_src = nullptr;   // 2 * n_src
+    int *chunk_ptr = nullptr;  // n_chunks + 1
+};
+
+// Build the folded term layout; returns 0 or a few_status error code.
+int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out);
+void free_term_layout(TermLayout *t);
+
+// starts[i] for i in [0, K): see few_host_interval_starts.
+void interval_starts(int K, const double *t, double t_start, double dt, long long n,
+                     long long *starts);
+
+// Upper bound of the wave tiles a request needs.
+inline long long tile_upper_bound(long long n, int K, int tile) {
+    return (n + tile - 1) / tile + (K - 1);
+}
+
+// Arena layout of one request's resident state.
+struct ReqLayout {
+    size_t off_t, off_pcoef, off_acoef, off_segs, off_term_ptr, off_term_src, off_chunk_ptr,
+        off_table, off_starts, off_tile_pref, total;
+};
+ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
+                         int n_chunks);
+
+// Binary64 sample time exactly as written: t_start + j * dt, no contraction.
+double sample_time(double t_start, double dt, long long j);
+
+}  // namespace few

@@ -1,0 +1,212 @@
+// Host-side bookkeeping of libfew: the folded term layout, the first sample of
+// each knot interval, and the arena layout of one request.  No device work;
+// the exported few_host_* helpers are usable on machines without a GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/few.h"
+#include "few_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace few {
+
+double sample_time(double t_start, double dt, long long j) {
+    volatile double prod = (double)j * dt;
+    return t_start + prod;
+}
+
+void interval_starts(int K, const double *t, double t_start, double dt, long long n,
+                     long long *starts) {
+    starts[0] = 0;
+    for (int i = 1; i < K - 1; ++i) {
+        double est = std::ceil((t[i] - t_start) / dt);
+        long long j;
+        if (!(est > 0.0)) j = 0;
+        else if (est >= (double)n) j = n;
+        else j = (long long)est;
+        while (j > 0 && sample_time(t_start, dt, j - 1) >= t[i]) --j;
+        while (j < n && sample_time(t_start, dt, j) < t[i]) ++j;
+        starts[i] = j;
+    }
+    starts[K - 1] = n;
+}
+
+namespace {
+struct Entry {
+    int m, n, k, l, mode_m, mirror;
+};
+}  // namespace
+
+void free_term_layout(TermLayout *t) {
+    std::free(t->segs);
+    std::free(t->term_ptr);
+    std::free(t->term_src);
+    std::free(t->chunk_ptr);
+    *t = TermLayout{};
+}
+
+// Eq. (9) with k = 0: every listed mode (l, m >= 0, n) contributes A_lmn Y_lm to
+// the signed term (m, n); for m > 0 its mirror contributes
+// (-1)^l conj(A_lmn) Y_{l,-m} to the term (-m, -n).  For fixed viewing angles
+// the l-sum of Eq. (10) then folds into one complex cubic per signed (m, n).
+int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
+    *out = TermLayout{};
+    if (M < 1 || !lmn) return FEW_E_ARG;
+    std::vector<Entry> e;
+    e.reserve(2 * (size_t)M);
+    for (int k = 0; k < M; ++k) {
+        int l = lmn[3 * k], m = lmn[3 * k + 1], n = lmn[3 * k + 2];
+        if (l < 2 || l > kMaxL || m < 0 || m > l || n < -kMaxAbsN || n > kMaxAbsN)
+            return FEW_E_MODES;
+        e.push_back({m, n, k, l, m, 0});
+        if (m > 0) e.push_back({-m, -n, k, l, m, 1});
+    }
+    std::sort(e.begin(), e.end(), [](const Entry &a, const Entry &b) {
+        if (a.m != b.m) return a.m < b.m;
+        if (a.n != b.n) return a.n < b.n;
+        if (a.k != b.k) return a.k < b.k;
+        return a.mirror < b.mirror;
+    });
+    // segments over distinct (m, n)
+    std::vector<int> segs;              // m, n_lo, len, first
+    std::vector<int> term_ptr;          // per term: first entry
+    std::vector<int> src;
+    size_t p = 0;
+    int term = 0;
+    while (p < e.size()) {
+        int m = e[p].m;
+        int n_lo = e[p].n, n_prev = e[p].n;
+        int first = term;
+        // extend while the next distinct n in this m is within the allowed gap
+        size_t q = p;
+        while (q < e.size() && e[q].m == m) {
+            int n = e[q].n;
+            if (n > n_prev + 1 + max_gap && q != p) break;
+            // fill zero terms between n_prev and n
+            for (int z = n_prev + 1; z < n; ++z) {
+                term_ptr.push_back((int)src.size() / 2);
+                ++term;
+            }
+            term_ptr.push_back((int)src.size() / 2);
+            ++term;
+            while (q < e.size() && e[q].m == m && e[q].n == n) {
+                src.push_back(e[q].k);
+                src.push_back(e[q].l | (e[q].mode_m << 8) | (e[q].mirror << 16));
+                ++q;
+            }
+            n_prev = n;
+        }
+        segs.push_back(m);
+        segs.push_back(n_lo);
+        segs.push_back(term - first);
+        segs.push_back(first);
+        p = q;
+    }
+    term_ptr.push_back((int)src.size() / 2);
+    // fold chunks: consecutive terms with at most kFoldMaxTerms terms and
+    // kFoldSrcCap contributor entries each
+    std::vector<int> chunks;
+    chunks.push_back(0);
+    int t0 = 0;
+    while (t0 < term) {
+        int t1 = t0;
+        while (t1 < term && t1 - t0 < kFoldMaxTerms &&
+               term_ptr[t1 + 1] - term_ptr[t0] <= kFoldSrcCap)
+            ++t1;
+        if (t1 == t0) return FEW_E_MODES;   // one term repeats a mode > kFoldSrcCap times
+        chunks.push_back(t1);
+        t0 = t1;
+    }
+    out->n_segs = (int)segs.size() / 4;
+    out->n_terms = term;
+    out->n_src = (int)src.size() / 2;
+    out->n_chunks = (int)chunks.size() - 1;
+    out->segs = (int *)std::malloc(sizeof(int) * segs.size());
+    out->term_ptr = (int *)std::malloc(sizeof(int) * term_ptr.size());
+    out->term_src = (int *)std::malloc(sizeof(int) * std::max<size_t>(src.size(), 2));
+    out->chunk_ptr = (int *)std::malloc(sizeof(int) * chunks.size());
+    if (!out->segs || !out->term_ptr || !out->term_src || !out->chunk_ptr) {
+        free_term_layout(out);
+        return FEW_E_NOMEM;
+    }
+    std::memcpy(out->segs, segs.data(), sizeof(int) * segs.size());
+    std::memcpy(out->term_ptr, term_ptr.data(), sizeof(int) * term_ptr.size());
+    std::memcpy(out->term_src, src.data(), sizeof(int) * src.size());
+    std::memcpy(out->chunk_ptr, chunks.data(), sizeof(int) * chunks.size());
+    return FEW_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
+                         int n_chunks) {
+    ReqLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    // host-uploaded arrays first, contiguous, so one copy stages them
+    L.off_t = take(sizeof(double) * K);
+    L.off_segs = take(sizeof(int) * 4 * (size_t)n_segs);
+    L.off_term_ptr = take(sizeof(int) * (size_t)(n_terms + 1));
+    L.off_term_src = take(sizeof(int) * 2 * (size_t)std::max(n_src, 1));
+    L.off_chunk_ptr = take(sizeof(int) * (size_t)(n_chunks + 1));
+    // device-produced arrays
+    L.off_pcoef = take(sizeof(double) * 16 * (size_t)(K - 1));
+    L.off_acoef = take(sizeof(double) * 8 * (size_t)(K - 1) * M);
+    L.off_table = take((fp32 ? 4 : 8) * 8 * (size_t)(K - 1) * n_terms);
+    L.off_starts = take(sizeof(long long) * K);
+    L.off_tile_pref = take(sizeof(int) * K);
+    L.total = o;
+    return L;
+}
+
+}  // namespace few
+
+using namespace few;
+
+extern "C" int32_t few_host_terms(int32_t M, const int32_t *lmn, int32_t max_gap,
+                                  int32_t cap_segs, int32_t *segs, int32_t *n_segs,
+                                  int32_t cap_terms, int32_t *term_ptr, int32_t *n_terms,
+                                  int32_t cap_src, int32_t *term_src, int32_t *n_src) {
+    if (!lmn || !segs || !n_segs || !term_ptr || !n_terms || !term_src || !n_src ||
+        max_gap < 0)
+        return FEW_E_ARG;
+    TermLayout L;
+    int rc = build_term_layout(M, lmn, max_gap, &L);
+    if (rc) return rc;
+    *n_segs = L.n_segs;
+    *n_terms = L.n_terms;
+    *n_src = L.n_src;
+    if (L.n_segs > cap_segs || L.n_terms + 1 > cap_terms || L.n_src > cap_src) {
+        free_term_layout(&L);
+        return FEW_E_ARG;
+    }
+    std::memcpy(segs, L.segs, sizeof(int) * 4 * L.n_segs);
+    std::memcpy(term_ptr, L.term_ptr, sizeof(int) * (L.n_terms + 1));
+    std::memcpy(term_src, L.term_src, sizeof(int) * 2 * L.n_src);
+    free_term_layout(&L);
+    return FEW_OK;
+}
+
+extern "C" int32_t few_host_interval_starts(int32_t K, const double *t_knots, double t_start,
+                                            double dt, int64_t n, int64_t *starts) {
+    if (!t_knots || !starts || K < 4 || n < 1 || !(dt > 0.0)) return FEW_E_ARG;
+    interval_starts(K, t_knots, t_start, dt, (long long)n, (long long *)starts);
+    return FEW_OK;
+}
+
+extern "C" uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t M,
+                                           int32_t n_terms) {
+    if (K < 4 || M < 1 || n_terms < 1) return 0;
+    // n_src <= 2M, n_segs <= n_terms, chunks <= n_terms
+    ReqLayout L = request_layout(precision == FEW_MIXED, K, M, n_terms, n_terms, 2 * M,
+                                 n_terms);
+    return (uint64_t)L.total;
+}

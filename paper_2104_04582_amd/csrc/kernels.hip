@@ -1,0 +1,693 @@
+// gfx950 kernels of libfew: the interpolated harmonic-mode summation of
+// arXiv:2104.04582, Sec. III C (spline stage, then summation stage) for the
+// Schwarzschild sum of Eq. (10) with the mirror modes of Eq. (9).
+//
+//  fit_kernel      not-a-knot cubic splines of every series on the shared knot
+//                  grid.  Amplitude series: binary64, one lane per real series,
+//                  the grid's tridiagonal factor computed once per workgroup
+//                  in LDS.  Phase series: double-double, one lane each.
+//  prepare_kernel  per-request constants: first sample of every knot interval
+//                  and the wave-tile prefix; -2Y_lm and the fold of the l-sum
+//                  into one complex cubic per signed (m, n) term.
+//  sum_kernel      one wave = one tile of consecutive samples inside one knot
+//                  interval.  Per sample: phases in binary64 (double-double on
+//                  the FP64 path) reduced mod 2 pi, one sincos each; then for
+//                  every segment of terms a Horner recurrence in
+//                  e^{-i Phi_r} over n, seeded by e^{-i(m Phi_phi + n_lo Phi_r)}
+//                  (chained by e^{-i Phi_phi} across consecutive m).  Term
+//                  coefficients are wave-uniform and are read through the
+//                  scalar cache straight into SGPR operands of the FMAs.
+#include "dd.h"
+#include "few_internal.h"
+#include "swsh.h"
+
+#include <climits>
+
+namespace few {
+
+#define FEW_AS4 __attribute__((address_space(4)))
+
+// Wave-uniform read-only data: the constant address space makes the compiler
+// use scalar loads (SGPR destinations) for uniform addresses.
+template <typename T>
+__device__ __forceinline__ const FEW_AS4 T *cptr(const T *p) {
+    return (const FEW_AS4 T *)(p);
+}
+
+// Copy a trivially copyable object from a wave-uniform address as 32-bit
+// scalar loads.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "4-byte granularity");
+    T v;
+    const FEW_AS4 uint32_t *s = (const FEW_AS4 uint32_t *)(p);
+    uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = s[i];
+    return v;
+}
+
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Binary64 sample time exactly as written: t_start + j * dt.
+__device__ __forceinline__ double dev_sample_time(double t_start, double dt, long long j) {
+    return __dadd_rn(t_start, __dmul_rn((double)j, dt));
+}
+
+// ===========================================================================
+// Spline stage (Sec. III C: not-a-knot spline, all series on one knot grid).
+//
+// Slope form: on [t_i, t_{i+1}], x = t - t_i, h_i = t_{i+1} - t_i,
+// delta_i = (y_{i+1} - y_i) / h_i and end slopes s_i, s_{i+1}:
+//   y = y_i + s_i x + c_i x^2 + d_i x^3,
+//   c_i = (3 delta_i - 2 s_i - s_{i+1}) / h_i,  d_i = (s_i + s_{i+1} - 2 delta_i) / h_i^2.
+// Tridiagonal system for the slopes (rows: sub, diag, super | rhs):
+//   row 0      : -, h_1, h_0 + h_1 | ((h_0 + 2(h_0 + h_1)) h_1 delta_0 + h_0^2 delta_1) / (h_0 + h_1)
+//   row 1..K-2 : h_i, 2 (h_{i-1} + h_i), h_{i-1} | 3 (h_i delta_{i-1} + h_{i-1} delta_i)
+//   row K-1    : h_{K-2} + h_{K-3}, h_{K-3}, - |
+//                (h_{K-2}^2 delta_{K-3} + (2 (h_{K-3} + h_{K-2}) + h_{K-2}) h_{K-3} delta_{K-2})
+//                / (h_{K-3} + h_{K-2})
+// (interior rows: continuous second derivative; end rows: the not-a-knot
+// conditions d_0 = d_1 and d_{K-3} = d_{K-2} with s_2 / s_{K-3} eliminated).
+// Solved by forward elimination and back substitution without pivoting.
+// ===========================================================================
+
+// Double-double solve of one phase series; lane ph of the first workgroup.
+// pcoef[((i * 2 + ph) * 4 + p) * 2 + {0, 1}] = (hi, lo) of coefficient p on
+// interval i; p = 0 holds y_i reduced mod 2 pi.  During the forward sweep the
+// b and c slots of interval r hold the eliminated rhs g_r and multiplier w_r.
+__device__ void fit_phase_dd(const FitJob &jb, int ph) {
+    const double *y = ph ? jb.phi_r : jb.phi_phi;
+    const double *t = jb.t;
+    const int K = jb.K;
+    double *pc = jb.pcoef;
+    auto slot = [&](int i, int p) { return pc + (((size_t)i * 2 + ph) * 4 + p) * 2; };
+    auto H = [&](int i) { return two_sum(t[i + 1], -t[i]); };
+    auto D = [&](int i) { return dd_div(two_sum(y[i + 1], -y[i]), H(i)); };
+    auto put = [&](int i, int p, dd v) {
+        double *s = slot(i, p);
+        s[0] = v.hi;
+        s[1] = v.lo;
+    };
+    auto get = [&](int i, int p) {
+        const double *s = slot(i, p);
+        return dd_make(s[0], s[1]);
+    };
+
+    dd h0 = H(0), h1 = H(1), d0 = D(0), d1 = D(1);
+    dd sup = dd_add(h0, h1);
+    dd rhs = dd_div(dd_add(dd_mul(dd_mul(dd_add(h0, dd_mul_d(sup, 2.0)), h1), d0),
+                           dd_mul(dd_mul(h0, h0), d1)),
+                    sup);
+    dd w = dd_div(sup, h1);
+    dd g = dd_div(rhs, h1);
+    put(0, 1, g);
+    put(0, 2, w);
+    dd dprev = d0;
+    for (int r = 1; r <= K - 2; ++r) {
+        dd hp = H(r - 1), hr = H(r);
+        dd dr = D(r);
+        dd diag = dd_mul_d(dd_add(hp, hr), 2.0);
+        dd rr = dd_mul_d(dd_add(dd_mul(hr, dprev), dd_mul(hp, dr)), 3.0);
+        dd den = dd_sub(diag, dd_mul(hr, w));
+        w = dd_div(hp, den);
+        g = dd_div(dd_sub(rr, dd_mul(hr, g)), den);
+        put(r, 1, g);
+        put(r, 2, w);
+        dprev = dr;
+    }
+    {
+        dd ha = H(K - 3), hb = H(K - 2);
+        dd da = D(K - 3), db = D(K - 2);
+        dd sum = dd_add(ha, hb);
+        dd rr = dd_div(dd_add(dd_mul(dd_mul(hb, hb), da),
+                              dd_mul(dd_mul(dd_add(dd_mul_d(sum, 2.0), hb), ha), db)),
+                       sum);
+        dd den = dd_sub(ha, dd_mul(sum, w));
+        g = dd_div(dd_sub(rr, dd_mul(sum, g)), den);
+    }
+    dd s_next = g;   // s_{K-1}
+    for (int r = K - 2; r >= 0; --r) {
+        dd gr = get(r, 1), wr = get(r, 2);
+        dd s = dd_sub(gr, dd_mul(wr, s_next));
+        dd hr = H(r), dr = D(r);
+        dd c = dd_div(dd_sub(dd_sub(dd_mul_d(dr, 3.0), dd_mul_d(s, 2.0)), s_next), hr);
+        dd d = dd_div(dd_sub(dd_add(s, s_next), dd_mul_d(dr, 2.0)), dd_mul(hr, hr));
+        put(r, 0, dd_reduce_2pi(dd_make(y[r])));
+        put(r, 1, s);
+        put(r, 2, c);
+        put(r, 3, d);
+        s_next = s;
+    }
+}
+
+// Binary64 solve of the amplitude series handled by this workgroup.
+// lds: h[K], inverse pivots invd[K], multipliers w[K].
+__device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
+    const int K = jb.K, M = jb.M;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    double *hs = lds, *invd = lds + K, *wv = lds + 2 * K;
+    for (int i = tid; i < K - 1; i += bs) hs[i] = jb.t[i + 1] - jb.t[i];
+    __syncthreads();
+    if (tid == 0) {
+        double dg = hs[1], sp = hs[0] + hs[1];
+        invd[0] = 1.0 / dg;
+        wv[0] = sp * invd[0];
+        for (int r = 1; r <= K - 2; ++r) {
+            double den = 2.0 * (hs[r - 1] + hs[r]) - hs[r] * wv[r - 1];
+            invd[r] = 1.0 / den;
+            wv[r] = hs[r - 1] * invd[r];
+        }
+        double den = hs[K - 3] - (hs[K - 2] + hs[K - 3]) * wv[K - 2];
+        invd[K - 1] = 1.0 / den;
+        wv[K - 1] = 0.0;
+    }
+    __syncthreads();
+    const int q = blk * bs + tid;
+    if (q >= 2 * M) return;
+    const int k = q >> 1, comp = q & 1;
+    const size_t ys = 2 * (size_t)M;                 // knot stride of amp
+    const double *y = jb.amp + 2 * (size_t)k + comp;
+    const size_t cs = 8 * (size_t)M;                 // interval stride of acoef
+    double *o = jb.acoef + 8 * (size_t)k + comp;     // coefficient p at o[i * cs + 2 p]
+
+    double y0 = y[0], y1 = y[ys], y2 = y[2 * ys];
+    double h0 = hs[0], h1 = hs[1];
+    double dprev = (y1 - y0) / h0;
+    double dcur = (y2 - y1) / h1;
+    double g = ((h0 + 2.0 * (h0 + h1)) * h1 * dprev + h0 * h0 * dcur) / (h0 + h1) * invd[0];
+    o[1 * 2] = g;
+    double ynext = y2;
+    for (int r = 1; r <= K - 2; ++r) {
+        if (r > 1) {
+            double yn = y[(size_t)(r + 1) * ys];
+            dprev = dcur;
+            dcur = (yn - ynext) / hs[r];
+            ynext = yn;
+        }
+        double rhs = 3.0 * (hs[r] * dprev + hs[r - 1] * dcur);
+        g = (rhs - hs[r] * g) * invd[r];
+        o[(size_t)r * cs + 2] = g;
+    }
+    {
+        double ha = hs[K - 3], hb = hs[K - 2];
+        double rhs = (hb * hb * dprev + (2.0 * (ha + hb) + hb) * ha * dcur) / (ha + hb);
+        g = (rhs - (hb + ha) * g) * invd[K - 1];
+    }
+    double s_next = g;
+    double yr1 = y[(size_t)(K - 1) * ys];
+    for (int r = K - 2; r >= 0; --r) {
+        double yr = y[(size_t)r * ys];
+        double hr = hs[r];
+        double dr = (yr1 - yr) / hr;
+        double s = o[(size_t)r * cs + 2] - wv[r] * s_next;
+        double *orow = o + (size_t)r * cs;
+        orow[0] = yr;
+        orow[2] = s;
+        orow[4] = (3.0 * dr - 2.0 * s - s_next) / hr;
+        orow[6] = (s + s_next - 2.0 * dr) / (hr * hr);
+        s_next = s;
+        yr1 = yr;
+    }
+}
+
+__device__ __forceinline__ void fit_body(const FitJob &jb, double *lds) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 2) fit_phase_dd(jb, threadIdx.x);
+        return;
+    }
+    if ((int)blockIdx.x > jb.amp_blocks) return;
+    fit_amplitudes(jb, blockIdx.x - 1, lds);
+}
+
+__global__ __launch_bounds__(256) void fit_kernel(FitJob jb) {
+    extern __shared__ double lds_fit[];
+    fit_body(jb, lds_fit);
+}
+
+__global__ __launch_bounds__(256) void fit_batch_kernel(const FitJob *jobs) {
+    extern __shared__ double lds_fit[];
+    FitJob jb = jobs[blockIdx.y];
+    fit_body(jb, lds_fit);
+}
+
+// ===========================================================================
+// Prepare stage.
+// ===========================================================================
+
+// starts[i] = min{ j in [0, n] : t_start + j dt >= t_i } (binary64 times).
+__device__ long long dev_interval_start(double ti, double t_start, double dt, long long n) {
+    double est = ceil((ti - t_start) / dt);
+    long long j;
+    if (!(est > 0.0)) j = 0;
+    else if (est >= (double)n) j = n;
+    else j = (long long)est;
+    while (j > 0 && dev_sample_time(t_start, dt, j - 1) >= ti) --j;
+    while (j < n && dev_sample_time(t_start, dt, j) < ti) ++j;
+    return j;
+}
+
+__device__ void prep_intervals(const PrepJob &jb) {
+    __shared__ int part[256];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int K = jb.K;
+    for (int i = tid; i < K; i += bs) {
+        long long s;
+        if (i == 0) s = 0;
+        else if (i == K - 1) s = jb.n;
+        else s = dev_interval_start(jb.t[i], jb.t_start, jb.dt, jb.n);
+        jb.starts[i] = s;
+    }
+    __syncthreads();
+    // tiles per interval, exclusive prefix by chunks of consecutive intervals
+    const int P = K - 1;
+    const int per = (P + bs - 1) / bs;
+    const int a = tid * per, b = min(a + per, P);
+    int local = 0;
+    for (int i = a; i < b; ++i) {
+        long long cnt = jb.starts[i + 1] - jb.starts[i];
+        local += (int)((cnt + jb.tile - 1) / jb.tile);
+    }
+    part[tid] = local;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int q = 0; q < bs; ++q) {
+            int v = part[q];
+            part[q] = run;
+            run += v;
+        }
+        jb.tile_pref[P] = run;
+    }
+    __syncthreads();
+    int run = part[tid];
+    for (int i = a; i < b; ++i) {
+        jb.tile_pref[i] = run;
+        long long cnt = jb.starts[i + 1] - jb.starts[i];
+        run += (int)((cnt + jb.tile - 1) / jb.tile);
+    }
+}
+
+// Fold the l-sum for the terms of one chunk, for every knot interval:
+//   C_term = scale * sum_e Y_e * (A_k or conj(A_k)),
+// Y_e = -2Y_lm for a listed mode and (-1)^l -2Y_{l,-m} for its mirror (Eq. (9)).
+// Coefficients are rescaled to u = x / h_i (coefficient p times h_i^p).
+template <typename Real>
+__device__ void prep_fold(const PrepJob &jb, int chunk) {
+    __shared__ double2 yw[kFoldSrcCap];
+    __shared__ int ysrc[kFoldSrcCap];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int t0 = jb.chunk_ptr[chunk], t1 = jb.chunk_ptr[chunk + 1];
+    const int e0 = jb.term_ptr[t0], e1 = jb.term_ptr[t1];
+    for (int e = e0 + tid; e < e1; e += bs) {
+        int2 s = jb.term_src[e];
+        int l = s.y & 255, m = (s.y >> 8) & 255, mir = (s.y >> 16) & 1;
+        double yr, yi;
+        if (!mir) {
+            few_swsh_m2(l, m, jb.theta, jb.phi, &yr, &yi);
+        } else {
+            few_swsh_m2(l, -m, jb.theta, jb.phi, &yr, &yi);
+            if (l & 1) {
+                yr = -yr;
+                yi = -yi;
+            }
+        }
+        yw[e - e0] = make_double2(yr, yi);
+        ysrc[e - e0] = s.x | (mir << 30);
+    }
+    __syncthreads();
+    const int nt = t1 - t0;
+    const int P = jb.K - 1;
+    const int M = jb.M;
+    Real *tab = (Real *)jb.table;
+    for (int p = tid; p < P * nt; p += bs) {
+        const int i = p / nt, term = t0 + p % nt;
+        double acc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+        const int ea = jb.term_ptr[term], eb = jb.term_ptr[term + 1];
+        for (int e = ea; e < eb; ++e) {
+            const double2 w = yw[e - e0];
+            const int src = ysrc[e - e0];
+            const int k = src & ((1 << 30) - 1);
+            const double sgn = (src >> 30) ? -1.0 : 1.0;
+            const double *a = jb.acoef + ((size_t)i * M + k) * 8;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double ar = a[2 * q], ai = sgn * a[2 * q + 1];
+                acc[2 * q] += w.x * ar - w.y * ai;
+                acc[2 * q + 1] += w.x * ai + w.y * ar;
+            }
+        }
+        const double h = jb.t[i + 1] - jb.t[i];
+        double f = jb.scale;
+        Real *dst = tab + ((size_t)i * jb.n_terms + term) * 8;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            dst[2 * q] = (Real)(acc[2 * q] * f);
+            dst[2 * q + 1] = (Real)(acc[2 * q + 1] * f);
+            f *= h;
+        }
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void prep_body(const PrepJob &jb) {
+    if (blockIdx.x == 0) {
+        prep_intervals(jb);
+        return;
+    }
+    if ((int)blockIdx.x > jb.n_chunks) return;
+    prep_fold<Real>(jb, blockIdx.x - 1);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void prepare_kernel(PrepJob jb) {
+    prep_body<Real>(jb);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void prepare_batch_kernel(const PrepJob *jobs) {
+    PrepJob jb = jobs[blockIdx.y];
+    prep_body<Real>(jb);
+}
+
+// ===========================================================================
+// Summation stage.
+// ===========================================================================
+
+// Reduced phases at one sample (both in [-pi, pi]).  pc: the interval's
+// [2][4][2] double-double phase cubic.
+template <bool DD>
+__device__ __forceinline__ void phase_eval(const FEW_AS4 double *pc, dd x, double *pf,
+                                           double *pr) {
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+        const FEW_AS4 double *c = pc + ph * 8;
+        double out;
+        if (DD) {
+            dd v = dd_make(c[6], c[7]);
+            v = dd_add(dd_mul(v, x), dd_make(c[4], c[5]));
+            v = dd_add(dd_mul(v, x), dd_make(c[2], c[3]));
+            v = dd_mul(v, x);
+            v = dd_add(v, dd_make(c[0], c[1]));
+            out = dd_reduce_2pi(v).hi;
+        } else {
+            const double xx = x.hi;
+            double v = fma(fma(fma(c[6], xx, c[4]), xx, c[2]), xx, c[0]);
+            out = d_reduce_2pi(v);
+        }
+        if (ph == 0) *pf = out; else *pr = out;
+    }
+}
+
+// One wave tile: samples [j0, j1) of knot interval iv, SL samples per lane.
+template <typename Real, int SL, bool COMP, bool DD>
+__device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int K = jb.K;
+    const FEW_AS4 int *tp = cptr(jb.tile_pref);
+    const int total = tp[K - 1];
+    if (local >= total) return;
+    int lo = 0, hi = K - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tp[mid] <= local) lo = mid; else hi = mid - 1;
+    }
+    const int iv = lo;
+    const FEW_AS4 long long *st = cptr(jb.starts);
+    constexpr int TILE = kWave * SL;
+    const long long j0 = st[iv] + (long long)(local - tp[iv]) * TILE;
+    const long long j1 = min(j0 + (long long)TILE, st[iv + 1]);
+    const FEW_AS4 double *tk = cptr(jb.t);
+    const double ti = tk[iv];
+    const double inv_h = 1.0 / (tk[iv + 1] - ti);
+    const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 16;
+
+    Real u[SL], u2[SL], u3[SL], fr[SL], fi[SL], er[SL], ei[SL];
+    double pf[SL], pr[SL];
+    long long jj[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        long long j = j0 + s * kWave + lane;
+        jj[s] = j;
+        if (j >= j1) j = j1 - 1;
+        const double tj = dev_sample_time(jb.t_start, jb.dt, j);
+        const dd x = two_sum(tj, -ti);
+        phase_eval<DD>(pc, x, &pf[s], &pr[s]);
+        const Real uu = (Real)(x.hi * inv_h);
+        u[s] = uu;
+        u2[s] = uu * uu;
+        u3[s] = u2[s] * uu;
+        double sn, cs;
+        sincos(pf[s], &sn, &cs);
+        er[s] = (Real)cs;
+        ei[s] = (Real)(-sn);
+        sincos(pr[s], &sn, &cs);
+        fr[s] = (Real)cs;
+        fi[s] = (Real)(-sn);
+    }
+
+    Real hr[SL], hq[SL], cr[SL], cq[SL], zr[SL], zi[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        hr[s] = hq[s] = cr[s] = cq[s] = (Real)0;
+        zr[s] = zi[s] = (Real)0;
+    }
+
+    const FEW_AS4 Real *tab = cptr((const Real *)jb.table) + (size_t)iv * jb.n_terms * 8;
+    int pm = INT_MIN / 2, pn = INT_MIN / 2;
+    const int n_segs = jb.n_segs;
+    for (int g = 0; g < n_segs; ++g) {
+        const int4 S = load_uniform(jb.segs + g);
+        if (S.x == pm + 1 && S.y == pn) {
+            // e^{-i((m+1) Phi_phi + n_lo Phi_r)} = seed * e^{-i Phi_phi}
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const Real a = zr[s] * er[s] - zi[s] * ei[s];
+                const Real b = zr[s] * ei[s] + zi[s] * er[s];
+                zr[s] = a;
+                zi[s] = b;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const double a = d_reduce_2pi((double)S.x * pf[s] + (double)S.y * pr[s]);
+                double sn, cs;
+                sincos(a, &sn, &cs);
+                zr[s] = (Real)cs;
+                zi[s] = (Real)(-sn);
+            }
+        }
+        pm = S.x;
+        pn = S.y;
+        // Horner over the segment's terms in f = e^{-i Phi_r}, highest n first:
+        //   S <- S f + C_n(u),  C_n(u) = c0 + c1 u + c2 u^2 + c3 u^3.
+        Real sr[SL], si[SL];
+#pragma unroll
+        for (int s = 0; s < SL; ++s) sr[s] = si[s] = (Real)0;
+        const FEW_AS4 Real *cp = tab + (size_t)(S.w + S.z - 1) * 8;
+        const int len = S.z;
+#pragma unroll 2
+        for (int q = 0; q < len; ++q) {
+            const Real c0r = cp[0], c0i = cp[1], c1r = cp[2], c1i = cp[3];
+            const Real c2r = cp[4], c2i = cp[5], c3r = cp[6], c3i = cp[7];
+            cp -= 8;
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                Real nr = fmar(sr[s], fr[s], c0r);
+                nr = fmar(-si[s], fi[s], nr);
+                nr = fmar(u[s], c1r, nr);
+                nr = fmar(u2[s], c2r, nr);
+                nr = fmar(u3[s], c3r, nr);
+                Real ni = fmar(sr[s], fi[s], c0i);
+                ni = fmar(si[s], fr[s], ni);
+                ni = fmar(u[s], c1i, ni);
+                ni = fmar(u2[s], c2i, ni);
+                ni = fmar(u3[s], c3i, ni);
+                sr[s] = nr;
+                si[s] = ni;
+            }
+        }
+        // h += seed * S
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const Real vr = zr[s] * sr[s] - zi[s] * si[s];
+            const Real vi = zr[s] * si[s] + zi[s] * sr[s];
+            if (COMP) {
+                // Kahan-compensated binary32 accumulation across segments
+                const Real yr = vr - cr[s];
+                const Real tr = hr[s] + yr;
+                cr[s] = (tr - hr[s]) - yr;
+                hr[s] = tr;
+                const Real yi = vi - cq[s];
+                const Real ti2 = hq[s] + yi;
+                cq[s] = (ti2 - hq[s]) - yi;
+                hq[s] = ti2;
+            } else {
+                hr[s] += vr;
+                hq[s] += vi;
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        if (jj[s] < j1) {
+            Real *o = (Real *)jb.out + 2 * jj[s];
+            if (COMP) {
+                o[0] = hr[s] - cr[s];
+                o[1] = hq[s] - cq[s];
+            } else {
+                o[0] = hr[s];
+                o[1] = hq[s];
+            }
+        }
+    }
+}
+
+// Waves are numbered so that each of the 8 XCDs (which receive workgroups
+// round-robin) works on one contiguous eighth of the wave range, i.e. on a
+// few knot intervals whose coefficient tables stay in its own L2.
+__device__ __forceinline__ int xcd_wave_id() {
+    const int nb = gridDim.x;                       // multiple of 8
+    const int b = blockIdx.x;
+    const int bb = (b & 7) * (nb >> 3) + (b >> 3);
+    return bb * (blockDim.x / kWave) + (threadIdx.x / kWave);
+}
+
+template <typename Real, int SL, bool COMP, bool DD>
+__global__ __launch_bounds__(256) void sum_kernel(SumJob jb, int slots) {
+    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
+    if (w >= slots) return;
+    sum_tile<Real, SL, COMP, DD>(jb, w);
+}
+
+// Batched launch: job j owns global wave slots [wave_base_j, wave_base_{j+1}).
+__device__ __forceinline__ int find_job(const SumJob *jobs, int n_jobs, int w) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int base = *cptr(&jobs[mid].wave_base);
+        if (base <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename Real, int SL, bool COMP, bool DD>
+__device__ __forceinline__ void sum_slot(const SumJob *jobs, int n_jobs, int w) {
+    const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, w));
+    const SumJob jb = load_uniform(jobs + jx);
+    sum_tile<Real, SL, COMP, DD>(jb, w - jb.wave_base);
+}
+
+template <typename Real, int SL, bool COMP, bool DD>
+__global__ __launch_bounds__(256) void sum_batch_kernel(const SumJob *jobs, int n_jobs,
+                                                        int slots) {
+    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
+    if (w >= slots) return;
+    sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
+}
+
+// Persistent variant: a fixed grid of waves pulls wave slots from one atomic
+// counter until all `slots` are handed out; every wave then exits.
+template <typename Real, int SL, bool COMP, bool DD>
+__global__ __launch_bounds__(256) void sum_persistent_kernel(const SumJob *jobs, int n_jobs,
+                                                             int slots, unsigned *counter) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        unsigned v = 0;
+        if (lane == 0) v = atomicAdd(counter, 1u);
+        const int w = __builtin_amdgcn_readfirstlane((int)v);
+        if (w >= slots) break;
+        sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
+    }
+}
+
+__global__ void zero_u32_kernel(unsigned *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ===========================================================================
+// Launchers.
+// ===========================================================================
+static inline int round_up8(long long x) { return (int)((x + 7) / 8 * 8); }
+
+hipError_t launch_fit(const FitJob &job, hipStream_t stream) {
+    dim3 grid(1 + job.amp_blocks);
+    size_t lds = sizeof(double) * 3 * (size_t)job.K;
+    hipLaunchKernelGGL(fit_kernel, grid, dim3(256), lds, stream, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
+                            hipStream_t stream) {
+    dim3 grid(1 + max_blocks, n_jobs);
+    size_t lds = sizeof(double) * 3 * (size_t)max_K;
+    hipLaunchKernelGGL(fit_batch_kernel, grid, dim3(256), lds, stream, jobs_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const PrepJob &job, bool fp32, hipStream_t stream) {
+    dim3 grid(1 + job.n_chunks);
+    if (fp32) hipLaunchKernelGGL(prepare_kernel<float>, grid, dim3(256), 0, stream, job);
+    else hipLaunchKernelGGL(prepare_kernel<double>, grid, dim3(256), 0, stream, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_chunks, bool fp32,
+                                hipStream_t stream) {
+    dim3 grid(1 + max_chunks, n_jobs);
+    if (fp32) hipLaunchKernelGGL(prepare_batch_kernel<float>, grid, dim3(256), 0, stream, jobs_dev);
+    else hipLaunchKernelGGL(prepare_batch_kernel<double>, grid, dim3(256), 0, stream, jobs_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const SumJob &job, int wave_slots, bool fp32, hipStream_t stream) {
+    const int waves_per_block = 256 / kWave;
+    dim3 grid(round_up8((wave_slots + waves_per_block - 1) / waves_per_block));
+    if (fp32)
+        hipLaunchKernelGGL((sum_kernel<float, kSamplesPerLaneF32, true, false>), grid, dim3(256),
+                           0, stream, job, wave_slots);
+    else
+        hipLaunchKernelGGL((sum_kernel<double, kSamplesPerLaneF64, false, true>), grid, dim3(256),
+                           0, stream, job, wave_slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_slots, bool fp32,
+                            bool persistent, unsigned *counter_dev, hipStream_t stream) {
+    const int waves_per_block = 256 / kWave;
+    if (!persistent) {
+        dim3 grid(round_up8((total_wave_slots + waves_per_block - 1) / waves_per_block));
+        if (fp32)
+            hipLaunchKernelGGL((sum_batch_kernel<float, kSamplesPerLaneF32, true, false>), grid,
+                               dim3(256), 0, stream, jobs_dev, n_jobs, total_wave_slots);
+        else
+            hipLaunchKernelGGL((sum_batch_kernel<double, kSamplesPerLaneF64, false, true>), grid,
+                               dim3(256), 0, stream, jobs_dev, n_jobs, total_wave_slots);
+        return hipGetLastError();
+    }
+    // one resident grid: 256 CUs x 8 workgroups of 4 waves
+    int blocks = 256 * 8;
+    const int needed = (total_wave_slots + waves_per_block - 1) / waves_per_block;
+    if (blocks > needed) blocks = needed > 0 ? needed : 1;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, counter_dev, 1);
+    if (fp32)
+        hipLaunchKernelGGL((sum_persistent_kernel<float, kSamplesPerLaneF32, true, false>),
+                           dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs,
+                           total_wave_slots, counter_dev);
+    else
+        hipLaunchKernelGGL((sum_persistent_kernel<double, kSamplesPerLaneF64, false, true>),
+                           dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs,
+                           total_wave_slots, counter_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace few

@@ -1,0 +1,236 @@
+"""GPU parity: libfew (through its C ABI) against the CPU oracle.
+
+Bars: binary64 path max relative error <= 1e-10; mixed path mismatch <= 1e-6
+(tolerances of the method's precision targets), with max relative error
+<= 1e-4 as a sanity bound on the binary32 arithmetic.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_04582_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_MISMATCH = 1e-6
+MIXED_MAXREL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def native_mod():
+    from paper_2104_04582_amd import native
+    native.load()
+    return native
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def to_dev(w, dev):
+    import torch
+    return (torch.tensor(w.phi_phi, device=dev), torch.tensor(w.phi_r, device=dev),
+            torch.tensor(w.amp, device=dev))
+
+
+def run_gpu(native, w, prec, dev, t_start=None, n=None, dt=None):
+    import torch
+    pp, pr, amp = to_dev(w, dev)
+    with native.Plan(0, prec) as plan:
+        sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+        out = plan.mode_sum(sp, w.theta, w.phi, dt if dt else w.dt,
+                            n if n else w.n_samples,
+                            t_start=w.t_start if t_start is None else t_start, scale=w.scale)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.complex128)
+
+
+def check(got, ref, prec):
+    err = oracle.max_rel_error(got, ref)
+    mm = oracle.mismatch(got, ref)
+    log(f"    {prec}: max_rel_err={err:.3e} mismatch={mm:.3e}")
+    if prec == "fp64":
+        assert err <= FP64_TOL
+    else:
+        assert mm <= MIXED_MISMATCH
+        assert err <= MIXED_MAXREL
+
+
+def test_spline_coefficients_match_oracle(native_mod, torch_dev):
+    import torch
+    for name, w in [("config0", synth.config0()),
+                    ("tiny K=4", synth.tiny_waveform(11, K=4, M=3)),
+                    ("tiny K=23", synth.tiny_waveform(12, K=23, M=9, l_max=5, n_max=4))]:
+        log(f"[spline] {name} K={w.K} M={w.M}")
+        pp, pr, amp = to_dev(w, torch_dev)
+        with native_mod.Plan(0, "fp64") as plan:
+            sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+            ac = sp.coefs(0).cpu().numpy()          # [K-1, M, 4, 2]
+            pc = sp.coefs(1).cpu().numpy()          # [K-1, 2, 4, 2]
+            torch.cuda.synchronize()
+        ref_a = oracle.spline_coefs(w.t_knots, w.amp.reshape(w.K, -1))  # [K-1, 2M, 4]
+        ref_a = ref_a.reshape(w.K - 1, w.M, 2, 4).transpose(0, 1, 3, 2)
+        for p in range(4):
+            scale = np.abs(ref_a[:, :, p, :]).max()
+            assert np.max(np.abs(ac[:, :, p, :] - ref_a[:, :, p, :])) <= 1e-12 * scale, p
+        for ph, y in enumerate([w.phi_phi, w.phi_r]):
+            ref_p = oracle.spline_coefs(w.t_knots, y)                   # [K-1, 4]
+            got = pc[:, ph, :, 0] + pc[:, ph, :, 1]
+            for p in range(1, 4):
+                scale = np.abs(ref_p[:, p]).max()
+                assert np.max(np.abs(got[:, p] - ref_p[:, p])) <= 1e-13 * scale, (ph, p)
+            red = np.mod(got[:, 0] - y[:-1] + math.pi, 2 * math.pi) - math.pi
+            assert np.max(np.abs(red)) <= 1e-12
+            assert np.all(np.abs(got[:, 0]) <= math.pi + 1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_config0_full(native_mod, torch_dev, prec):
+    w = synth.config0()
+    log(f"[config0] {prec} K={w.K} M={w.M} N={w.n_samples}")
+    ref = oracle.mode_sum_waveform(w)
+    got = run_gpu(native_mod, w, prec, torch_dev)
+    check(got, ref, prec)
+
+
+EDGE_CASES = [
+    # (name, kwargs for tiny_waveform, sample-grid override)
+    ("K4 single m=0 mode", dict(seed=21, K=4, M=1, n_samples=1), None),
+    ("K4 three samples", dict(seed=22, K=4, M=2, n_samples=3), None),
+    ("ragged 1000", dict(seed=23, K=9, M=7, n_samples=1000, l_max=4, n_max=3), None),
+    ("ragged 777 many modes", dict(seed=24, K=30, M=60, n_samples=777, l_max=6, n_max=5), None),
+    ("duplicate-heavy", dict(seed=25, K=6, M=40, n_samples=300, l_max=2, n_max=1), None),
+    ("big phases", dict(seed=26, K=12, M=12, n_samples=5000, phase_scale=5e4), None),
+    ("offset start", dict(seed=27, K=10, M=8, n_samples=400), "offset"),
+    ("ends on last knot", dict(seed=28, K=8, M=5, n_samples=200), "closed"),
+    ("samples on knots", dict(seed=29, K=6, M=4, n_samples=100), "onknots"),
+]
+
+
+@pytest.mark.parametrize("case", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_edge_cases(native_mod, torch_dev, case, prec):
+    name, kw, grid = case
+    w = synth.tiny_waveform(**kw)
+    if grid == "offset":
+        w.t_start = 0.37 * (w.t_knots[1] - w.t_knots[0])
+        w.dt = (w.t_knots[-1] - w.t_start) / (w.n_samples + 0.5)
+    elif grid == "closed":
+        w.dt = w.t_knots[-1] / (w.n_samples - 1)
+        if w.t_start + (w.n_samples - 1) * w.dt > w.t_knots[-1]:
+            w.n_samples -= 1
+    elif grid == "onknots":
+        w.t_knots = np.arange(w.K, dtype=np.float64) * 50.0
+        w.dt = 2.5
+        w.n_samples = int((w.K - 1) * 50.0 / 2.5) + 1   # last sample = last knot
+    log(f"[edge] {name} {prec} K={w.K} M={w.M} N={w.n_samples} t0={w.t_start} dt={w.dt}")
+    ref = oracle.mode_sum_waveform(w)
+    got = run_gpu(native_mod, w, prec, torch_dev)
+    check(got, ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_scale_and_sparse_mode_subset(native_mod, torch_dev, prec):
+    w = synth.top_modes(synth.config0(seed=5), 17)
+    w.scale = 3.5e-3
+    log(f"[subset] {prec} M={w.M}")
+    ref = oracle.mode_sum_waveform(w)
+    got = run_gpu(native_mod, w, prec, torch_dev)
+    check(got, ref, prec)
+
+
+def c1_sample_indices(w, n_random=3000):
+    from paper_2104_04582_amd import native
+    rng = np.random.default_rng(1)
+    starts = native.host_interval_starts(w.t_knots, 0.0, w.dt, w.n_samples)
+    idx = set(rng.choice(w.n_samples, n_random, replace=False).tolist())
+    idx.update([0, 1, w.n_samples - 2, w.n_samples - 1])
+    for s in starts[1:-1]:
+        idx.update([int(s) - 1, int(s), int(s) + 1])
+    return np.array(sorted(i for i in idx if 0 <= i < w.n_samples), dtype=np.int64)
+
+
+def test_config1_full_size_sampled(native_mod, torch_dev):
+    """Full one-year, 3843-mode case: both precisions against the oracle at
+    sampled outputs (random, ends, and both sides of every knot)."""
+    import torch
+    w = synth.config1()
+    idx = c1_sample_indices(w)
+    log(f"[config1] oracle at {idx.size} samples")
+    ref = oracle.mode_sum_waveform(w, idx=idx)
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        log(f"[config1] {prec} N={w.n_samples}")
+        pp, pr, amp = to_dev(w, torch_dev)
+        with native_mod.Plan(0, prec) as plan:
+            sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+            out = plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples)
+            torch.cuda.synchronize()
+            outs[prec] = out
+        got = outs[prec][torch.from_numpy(idx).to(torch_dev)].cpu().numpy().astype(np.complex128)
+        check(got, ref, prec)
+    # whole-waveform property: mixed against the binary64 path on every sample
+    a = outs["fp64"].cpu().numpy()
+    b = outs["mixed"].cpu().numpy().astype(np.complex128)
+    mm = oracle.mismatch(b, a)
+    log(f"[config1] mixed vs fp64 full mismatch={mm:.3e}")
+    assert mm <= MIXED_MISMATCH
+    assert np.all(np.isfinite(a)) and np.all(np.isfinite(b))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_repeat_is_bitwise_deterministic(native_mod, torch_dev, prec):
+    w = synth.config0(seed=3)
+    log(f"[determinism] {prec}")
+    a = run_gpu(native_mod, w, prec, torch_dev)
+    b = run_gpu(native_mod, w, prec, torch_dev)
+    assert np.array_equal(a, b)
+
+
+def test_error_codes(native_mod, torch_dev):
+    import torch
+    w = synth.tiny_waveform(31, K=6, M=3, n_samples=50)
+    pp, pr, amp = to_dev(w, torch_dev)
+    log("[errors]")
+    with native_mod.Plan(0, "fp64") as plan:
+        with pytest.raises(native_mod.FewError) as e:
+            plan.spline_fit(w.t_knots[:3], pp[:3], pr[:3], w.lmn, amp[:3])
+        assert e.value.code == native_mod.FEW_E_KNOTS
+        bad_t = w.t_knots.copy()
+        bad_t[2] = bad_t[1]
+        with pytest.raises(native_mod.FewError) as e:
+            plan.spline_fit(bad_t, pp, pr, w.lmn, amp)
+        assert e.value.code == native_mod.FEW_E_KNOTS
+        bad_m = w.lmn.copy()
+        bad_m[0] = [2, 3, 0]
+        with pytest.raises(native_mod.FewError) as e:
+            plan.spline_fit(w.t_knots, pp, pr, bad_m, amp)
+        assert e.value.code == native_mod.FEW_E_MODES
+        sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+        with pytest.raises(native_mod.FewError) as e:
+            plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples + 10)
+        assert e.value.code == native_mod.FEW_E_RANGE
+        with pytest.raises(native_mod.FewError) as e:
+            plan.mode_sum(sp, w.theta, w.phi, -1.0, 10)
+        assert e.value.code == native_mod.FEW_E_ARG
+        with pytest.raises(native_mod.FewError) as e:
+            plan.mode_sum(sp, w.theta, w.phi, w.dt, 10, t_start=-5.0)
+        assert e.value.code == native_mod.FEW_E_RANGE
+        with pytest.raises(native_mod.FewError) as e:
+            plan.mode_sum(sp, float("nan"), w.phi, w.dt, 10)
+        assert e.value.code == native_mod.FEW_E_ARG
+        # the plan still works after rejected calls
+        out = plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples)
+        torch.cuda.synchronize()
+        ref = oracle.mode_sum_waveform(w)
+        assert oracle.max_rel_error(out.cpu().numpy(), ref) <= FP64_TOL
