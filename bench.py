@@ -1,0 +1,265 @@
+"""Benchmark of the interpolated harmonic-mode summation on one MI355X.
+
+A step is one pass of the whole hot path over one resident batch of synthetic
+input: few_spline_fit (not-a-knot splines of 2 phases + 7686 amplitude
+series on 100 knots) followed by few_mode_sum (3843 modes x 3,155,760
+samples, one year at dt = 10 s).  Inputs and the output buffer are resident in
+HBM before timing starts.  The headline value is the mixed-precision path;
+the binary64 path is timed the same way and reported beside it.
+
+Also reported: the dominant kernel's roofline (the summation kernel, timed
+with HIP events recorded by the library on the stream it launches on), the
+served-stream latency (Poisson arrivals of uneven requests through
+few_submit/few_poll) and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve-seconds S]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X peaks used for the roofline (TFLOP/s, TB/s).
+PEAK_FP32_VALU = 157.3
+PEAK_FP64_VALU = 78.6
+PEAK_HBM_TBS = 8.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(n_terms: int, n_segs: int, n: int) -> float:
+    """Flops of the summation kernel's algorithm per launch.
+
+    Per folded (m, n) term and sample: the complex cubic C(u) with real u is
+    3 complex-by-real FMAs (12 flop) and the Horner step S f + C is one complex
+    multiply-add (8 flop): 20 flop.  Per segment and sample: the seed product
+    (6 flop) and the accumulation (2 flop): 8 flop.
+    """
+    return float(n) * (20.0 * n_terms + 8.0 * n_segs)
+
+
+def time_path(native, plan, w, dev, steps: int, warmup: int):
+    import torch
+    pp = torch.from_numpy(np.ascontiguousarray(w.phi_phi)).to(dev)
+    pr = torch.from_numpy(np.ascontiguousarray(w.phi_r)).to(dev)
+    amp = torch.from_numpy(np.ascontiguousarray(w.amp)).to(dev)
+    out = torch.empty(w.n_samples, dtype=plan.out_dtype, device=dev)
+
+    def step():
+        sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+        plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples, out=out)
+        sp.free()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.timing(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = plan.timing(reset=True)
+    return elapsed / steps, tm, out
+
+
+def cpu_baseline(w, target_s: float = 10.0):
+    """The oracle as it stands on the host cores, on a contiguous sample slice."""
+    import oracle
+    threads = os.cpu_count() or 1
+    probe = 1024
+    t0 = time.perf_counter()
+    oracle.mode_sum_waveform(w, idx=np.arange(probe, dtype=np.int64), n_threads=threads)
+    t_probe = time.perf_counter() - t0
+    n_s = int(min(w.n_samples, max(probe, probe * target_s / max(t_probe, 1e-3))))
+    idx = np.arange(n_s, dtype=np.int64)
+    t0 = time.perf_counter()
+    oracle.mode_sum_waveform(w, idx=idx, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": w.M * n_s / dt, "unit": "mode-samples/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n_s} of {w.n_samples} samples of the 3843-mode 1-yr case, "
+                      f"all {w.M} modes, x87 extended precision, {dt:.1f} s wall"}
+
+
+def served(native, precision: str, seconds: float, dev, budget: int):
+    """Replay a Poisson trace (20 req/s, 10% full 4-yr requests) through
+    few_submit/few_poll; latency = arrival -> completion seen by the host."""
+    import torch
+    from paper_2104_04582_amd import synth
+    trace = synth.served_trace(rate=20.0, duration=seconds, p_full=0.1, seed=4)
+    reqs = []
+    for a in trace:
+        w = synth.served_request(a)
+        reqs.append((a, w,
+                     torch.from_numpy(np.ascontiguousarray(w.phi_phi)).to(dev),
+                     torch.from_numpy(np.ascontiguousarray(w.phi_r)).to(dev),
+                     torch.from_numpy(np.ascontiguousarray(w.amp)).to(dev)))
+    out_dtype = torch.complex64 if precision == "mixed" else torch.complex128
+    torch.cuda.synchronize()
+    lat = []
+    kinds = []
+    mode_samples = 0
+    with native.Plan(0, precision, hbm_budget_bytes=budget, max_inflight=4) as plan:
+        pending = {}
+        t_start = time.perf_counter()
+        nxt = 0
+        while nxt < len(reqs) or pending:
+            now = time.perf_counter() - t_start
+            while nxt < len(reqs) and reqs[nxt][0].t_arrival <= now:
+                a, w, pp, pr, amp = reqs[nxt]
+                out = torch.empty(w.n_samples, dtype=out_dtype, device=dev)
+                tk = plan.submit(w.t_knots, pp, pr, w.lmn, amp, w.theta, w.phi, w.dt,
+                                 w.n_samples, out)
+                pending[tk] = (a, w, out)
+                nxt += 1
+            done = [tk for tk in pending if plan.poll(tk)]
+            t_done = time.perf_counter() - t_start
+            for tk in done:
+                a, w, out = pending.pop(tk)
+                lat.append(t_done - a.t_arrival)
+                kinds.append(a.kind)
+                mode_samples += w.mode_samples
+            if not done:
+                time.sleep(0.0002)
+        wall = time.perf_counter() - t_start
+    lat = np.array(lat) * 1e3
+    kinds = np.array(kinds)
+
+    def pct(x, q):
+        return float(np.percentile(x, q)) if x.size else None
+
+    return {"precision": precision, "requests": int(lat.size), "trace_s": seconds,
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "p50_full_ms": pct(lat[kinds == "full"], 50),
+            "p99_full_ms": pct(lat[kinds == "full"], 99),
+            "p50_small_ms": pct(lat[kinds == "small"], 50),
+            "p99_small_ms": pct(lat[kinds == "small"], 99),
+            "mode_samples_per_s": mode_samples / wall, "waveforms_per_s": lat.size / wall}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--serve-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel(), "copies": 5}), flush=True)
+        return 0
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2104_04582_amd import native, synth
+    dev = torch.device("cuda:0")
+    w = synth.config1()
+    segs, tp, _ = native.host_terms(w.lmn)
+    n_terms, n_segs = tp.shape[0] - 1, segs.shape[0]
+    flops = algorithmic_flops(n_terms, n_segs, w.n_samples)
+    canonical = 32.0 * w.M * w.n_samples
+    log(f"[bench] workload K={w.K} M={w.M} N={w.n_samples} terms={n_terms} segs={n_segs}")
+
+    res = {}
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        log(f"[bench] {prec}: warmup {args.warmup}, steps {args.steps}")
+        with native.Plan(0, prec, timing=True) as plan:
+            sec, tm, out = time_path(native, plan, w, dev, args.steps, args.warmup)
+            outs[prec] = out
+        sum_ms = tm["sum_ms"] / max(tm["sum_launches"], 1)
+        res[prec] = {
+            "ms_per_step": sec * 1e3,
+            "value": w.mode_samples / sec,
+            "spline_ms": tm["spline_ms"] / max(tm["spline_launches"], 1),
+            "prepare_ms": tm["prepare_ms"] / max(tm["prepare_launches"], 1),
+            "sum_ms": sum_ms,
+            "sum_tflops": flops / (sum_ms * 1e-3) / 1e12,
+            "canonical_tflops": canonical / (sum_ms * 1e-3) / 1e12,
+        }
+        log(f"[bench] {prec}: {json.dumps(res[prec])}")
+    a = outs["fp64"]
+    b = outs["mixed"].to(torch.complex128)
+    num = torch.real(torch.vdot(a, b)).item()
+    den = math.sqrt(torch.real(torch.vdot(a, a)).item() * torch.real(torch.vdot(b, b)).item())
+    mm = 1.0 - num / den
+    mx = (torch.max(torch.abs(a - b)) / torch.max(torch.abs(a))).item()
+    del outs, a, b
+    torch.cuda.empty_cache()
+
+    serve = {}
+    if args.serve_seconds > 0:
+        for prec in ("mixed", "fp64"):
+            log(f"[bench] served replay {prec}, {args.serve_seconds:.0f} s")
+            serve[prec] = served(native, prec, args.serve_seconds, dev, 8 << 30)
+            log(f"[bench] served {prec}: {json.dumps(serve[prec])}")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] cpu oracle baseline")
+        cpu = cpu_baseline(w)
+        log(f"[bench] cpu: {json.dumps(cpu)}")
+
+    m = res["mixed"]
+    ach = m["sum_tflops"]
+    line = {
+        "metric": "mode-samples/s at 3843 modes x 1 yr (mixed vs FP64); p50/p99 served latency",
+        "value": m["value"],
+        "unit": "mode-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "interpolated mode sum, 3843 modes (l 2..10, m 0..l, n -30..30), "
+                               "100 knots, 1 yr at dt 10 s (3,155,760 samples), mixed precision",
+                   "modes": w.M, "knots": w.K, "samples": w.n_samples,
+                   "folded_terms": n_terms, "segments": n_segs},
+        "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VALU,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None,
+                     "kernel": "sum_kernel<float>",
+                     "flop_per_launch": flops, "launch_ms": m["sum_ms"]},
+        "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
+                 "sum_ms": res["fp64"]["sum_ms"], "sum_tflops": res["fp64"]["sum_tflops"],
+                 "frac_fp64_peak": res["fp64"]["sum_tflops"] / PEAK_FP64_VALU},
+        "stages_ms": {p: {k: res[p][k] for k in ("spline_ms", "prepare_ms", "sum_ms")}
+                      for p in res},
+        "canonical_32flop_tflops": {p: res[p]["canonical_tflops"] for p in res},
+        "mixed_vs_fp64": {"mismatch": mm, "max_rel_error": mx},
+        "served": serve or None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -645,7 +645,8 @@ int32_t few_submit(few_plan p, const few_request *req, uint64_t *ticket) {
         r->r.t_knots = r->h.t.data();
         r->r.lmn = nullptr;   // consumed into the term layout
         r->footprint = r->h.L.total + 3 * 256 + sizeof(FitJob) + sizeof(PrepJob) + sizeof(SumJob);
-        if (r->footprint > p->budget) {
+        // the arena also holds one 256-byte counter block per stream slot
+        if (r->footprint + 256 * (size_t)p->max_inflight + 256 > p->budget) {
             size_t need = r->footprint;
             delete r;
             return fail(FEW_E_TOO_LARGE, "request needs %zu bytes, plan budget %llu", need,

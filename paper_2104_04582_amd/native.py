@@ -77,6 +77,12 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime with the same soname (libamdhip64.so.7).
+    # Loading torch first makes libfew bind to that already-loaded runtime, so
+    # both share one HIP context and torch's device memory and streams are
+    # valid in libfew.  A second runtime instance in the process would not see
+    # the device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER

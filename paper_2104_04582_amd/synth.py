@@ -105,7 +105,7 @@ def _amp_at_knots(poly: np.ndarray, t: np.ndarray, T: float) -> np.ndarray:
     """Evaluate the generator cubics sum_p c_p (t/T)^p at the knots -> [K, M, 2]."""
     s = t / T
     powers = np.stack([np.ones_like(s), s, s * s, s * s * s], axis=0)   # [4, K]
-    return np.einsum("pk,mpc->kmc", powers, poly)
+    return np.ascontiguousarray(np.einsum("pk,mpc->kmc", powers, poly))
 
 
 def draw_waveform(rng: np.random.Generator, lmn: np.ndarray, T: float, K: int,

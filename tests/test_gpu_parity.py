@@ -39,8 +39,8 @@ def log(msg):
 
 def to_dev(w, dev):
     import torch
-    return (torch.tensor(w.phi_phi, device=dev), torch.tensor(w.phi_r, device=dev),
-            torch.tensor(w.amp, device=dev))
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                 for a in (w.phi_phi, w.phi_r, w.amp))
 
 
 def run_gpu(native, w, prec, dev, t_start=None, n=None, dt=None):
@@ -78,17 +78,25 @@ def test_spline_coefficients_match_oracle(native_mod, torch_dev):
             ac = sp.coefs(0).cpu().numpy()          # [K-1, M, 4, 2]
             pc = sp.coefs(1).cpu().numpy()          # [K-1, 2, 4, 2]
             torch.cuda.synchronize()
+        # Each coefficient is compared through its contribution c_p h_i^p over
+        # its interval, relative to the data it interpolates (the high-order
+        # coefficients are formed by cancellation and are tiny for smooth data).
+        h = np.diff(w.t_knots)
         ref_a = oracle.spline_coefs(w.t_knots, w.amp.reshape(w.K, -1))  # [K-1, 2M, 4]
         ref_a = ref_a.reshape(w.K - 1, w.M, 2, 4).transpose(0, 1, 3, 2)
+        ya = np.abs(w.amp).max()
         for p in range(4):
-            scale = np.abs(ref_a[:, :, p, :]).max()
-            assert np.max(np.abs(ac[:, :, p, :] - ref_a[:, :, p, :])) <= 1e-12 * scale, p
+            d = np.abs(ac[:, :, p, :] - ref_a[:, :, p, :]) * (h ** p)[:, None, None]
+            log(f"    amp p={p}: max |dc_p| h^p / max|y| = {d.max() / ya:.2e}")
+            assert d.max() <= 1e-13 * ya, p
         for ph, y in enumerate([w.phi_phi, w.phi_r]):
             ref_p = oracle.spline_coefs(w.t_knots, y)                   # [K-1, 4]
             got = pc[:, ph, :, 0] + pc[:, ph, :, 1]
+            inc = np.abs(np.diff(y)).max()
             for p in range(1, 4):
-                scale = np.abs(ref_p[:, p]).max()
-                assert np.max(np.abs(got[:, p] - ref_p[:, p])) <= 1e-13 * scale, (ph, p)
+                d = np.abs(got[:, p] - ref_p[:, p]) * h ** p
+                log(f"    phase {ph} p={p}: max |dc_p| h^p = {d.max():.2e} rad")
+                assert d.max() <= 1e-13 * inc, (ph, p)
             red = np.mod(got[:, 0] - y[:-1] + math.pi, 2 * math.pi) - math.pi
             assert np.max(np.abs(red)) <= 1e-12
             assert np.all(np.abs(got[:, 0]) <= math.pi + 1e-12)
