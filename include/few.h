@@ -88,7 +88,7 @@ typedef struct {
     int32_t device;            /* HIP device ordinal */
     void *stream;              /* hipStream_t for the synchronous calls (borrowed; NULL = null stream) */
     int32_t precision;         /* few_precision */
-    int32_t max_knots;         /* <= 2048; 0 -> 2048 */
+    int32_t max_knots;         /* <= 1024; 0 -> 1024 */
     int32_t max_modes;         /* 0 -> 65536 */
     int32_t max_inflight;      /* served path: concurrent batch streams, 1..8; 0 -> 2 */
     uint64_t hbm_budget_bytes; /* device arena per plan; 0 -> 2 GiB */

@@ -203,7 +203,6 @@ void stage_upload(const HostReq &r, char *dst) {
     std::memcpy(dst + r.L.off_segs, r.terms.segs, sizeof(int) * 4 * r.terms.n_segs);
     std::memcpy(dst + r.L.off_term_ptr, r.terms.term_ptr, sizeof(int) * (r.terms.n_terms + 1));
     std::memcpy(dst + r.L.off_term_src, r.terms.term_src, sizeof(int) * 2 * r.terms.n_src);
-    std::memcpy(dst + r.L.off_chunk_ptr, r.terms.chunk_ptr, sizeof(int) * (r.terms.n_chunks + 1));
 }
 
 int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, HostReq *r) {
@@ -212,9 +211,8 @@ int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, 
     r->t.assign(t, t + K);
     int rc = build_term_layout(M, lmn, kMaxGap, &r->terms);
     if (rc) return fail(rc, "mode list rejected while building the term layout");
-    r->L = request_layout(fp32, K, M, r->terms.n_segs, r->terms.n_terms, r->terms.n_src,
-                          r->terms.n_chunks);
-    r->upload_bytes = r->L.off_chunk_ptr + sizeof(int) * (r->terms.n_chunks + 1);
+    r->L = request_layout(fp32, K, M, r->terms.n_segs, r->terms.n_terms, r->terms.n_src);
+    r->upload_bytes = r->L.upload_end;
     return FEW_OK;
 }
 
@@ -240,7 +238,7 @@ PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double 
     j.acoef = (const double *)(base + r.L.off_acoef);
     j.term_ptr = (const int *)(base + r.L.off_term_ptr);
     j.term_src = (const int2 *)(base + r.L.off_term_src);
-    j.chunk_ptr = (const int *)(base + r.L.off_chunk_ptr);
+    j.ybuf = (double2 *)(base + r.L.off_ybuf);
     j.table = base + r.L.off_table;
     j.starts = (long long *)(base + r.L.off_starts);
     j.tile_pref = (int *)(base + r.L.off_tile_pref);
@@ -253,8 +251,10 @@ PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double 
     j.K = r.K;
     j.M = r.M;
     j.n_terms = r.terms.n_terms;
-    j.n_chunks = r.terms.n_chunks;
+    j.n_src = r.terms.n_src;
     j.tile = tile_samples(fp32);
+    j.src_blocks = (r.terms.n_src + 255) / 256;
+    j.fold_blocks = (int)(((long long)(r.K - 1) * r.terms.n_terms + 255) / 256);
     return j;
 }
 
@@ -735,7 +735,7 @@ int launch_batch(few_plan p, Batch *b) {
     SumJob *sj = (SumJob *)(host + off_sum);
     const bool fp32 = p->fp32;
     const int tile = tile_samples(fp32);
-    int max_amp_blocks = 0, max_K = 4, max_chunks = 0;
+    int max_amp_blocks = 0, max_K = 4, max_src_blocks = 0, max_fold_blocks = 0;
     long long waves = 0;
     for (int i = 0; i < n; ++i) {
         ServedReq *r = b->reqs[i];
@@ -749,13 +749,15 @@ int launch_batch(few_plan p, Batch *b) {
         waves += tile_upper_bound(r->r.n_samples, r->h.K, tile);
         max_amp_blocks = std::max(max_amp_blocks, fj[i].amp_blocks);
         max_K = std::max(max_K, r->h.K);
-        max_chunks = std::max(max_chunks, pj[i].n_chunks);
+        max_src_blocks = std::max(max_src_blocks, pj[i].src_blocks);
+        max_fold_blocks = std::max(max_fold_blocks, pj[i].fold_blocks);
     }
     if (waves > 0x3fffffff) return fail(FEW_E_ARG, "batch too large");
     hipStream_t s = p->bstreams[b->slot];
     HIP_TRY(hipMemcpyAsync(dev, host, upload_end, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_fit_batch((const FitJob *)(dev + off_fit), n, max_amp_blocks, max_K, s));
-    HIP_TRY(launch_prepare_batch((const PrepJob *)(dev + off_prep), n, max_chunks, fp32, s));
+    HIP_TRY(launch_prepare_batch((const PrepJob *)(dev + off_prep), n, max_src_blocks,
+                                 max_fold_blocks, fp32, s));
     HIP_TRY(launch_sum_batch((const SumJob *)(dev + off_sum), n, (int)waves, fp32, true,
                              p->counters + 64 * b->slot, s));
     HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));

@@ -8,12 +8,10 @@
 
 namespace few {
 
-constexpr int kMaxKnots = 2048;       // LDS holds three binary64 arrays of this length (48 KiB)
+constexpr int kMaxKnots = 1024;       // phase-solve LDS: eight binary64 arrays of this length (64 KiB)
 constexpr int kMaxL = 30;             // Wigner-d sum stays well conditioned in binary64
 constexpr int kMaxAbsN = 1000;
 constexpr int kWave = 64;
-constexpr int kFoldSrcCap = 1024;     // contributor entries staged in LDS per fold block
-constexpr int kFoldMaxTerms = 64;     // terms per fold block
 constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 
 // Samples per lane in one wave tile of the summation kernel.
@@ -38,7 +36,7 @@ struct FitJob {
     double *pcoef;          // [K-1][2][4][2] double-double phase cubics
     double *acoef;          // [K-1][M][4][2] amplitude cubics
     int K, M;
-    int amp_blocks;         // blocks covering the 2M amplitude series
+    int amp_blocks;         // blocks covering the 2M amplitude series (after 2 phase blocks)
 };
 
 // Fold + interval bookkeeping for one request.
@@ -47,14 +45,16 @@ struct PrepJob {
     const double *acoef;
     const int *term_ptr;    // [n_terms + 1]
     const int2 *term_src;   // [n_src]: (mode, l | m << 8 | mirror << 16)
-    const int *chunk_ptr;   // [n_chunks + 1] first term of each fold block
+    double2 *ybuf;          // [n_src] harmonic weight of each contributor
     void *table;            // [K-1][n_terms][8] binary32 or binary64
     long long *starts;      // [K]
     int *tile_pref;         // [K]
     double theta, phi, scale, t_start, dt;
     long long n;
-    int K, M, n_terms, n_chunks;
+    int K, M, n_terms, n_src;
     int tile;               // samples per wave tile
+    int src_blocks;         // workgroups of the harmonic pass
+    int fold_blocks;        // workgroups of the fold pass
 };
 
 // Summation stage for one request.
@@ -77,8 +77,8 @@ hipError_t launch_fit(const FitJob &job, hipStream_t stream);
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream);
 hipError_t launch_prepare(const PrepJob &job, bool fp32, hipStream_t stream);
-hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_chunks,
-                                bool fp32, hipStream_t stream);
+hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_src_blocks,
+                                int max_fold_blocks, bool fp32, hipStream_t stream);
 hipError_t launch_sum(const SumJob &job, int wave_slots, bool fp32, hipStream_t stream);
 hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_slots,
                             bool fp32, bool persistent, unsigned *counter_dev,
@@ -89,11 +89,10 @@ hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t stream);
 // Host core (host_core.cpp): no device work.
 // ---------------------------------------------------------------------------
 struct TermLayout {
-    int n_segs = 0, n_terms = 0, n_src = 0, n_chunks = 0;
+    int n_segs = 0, n_terms = 0, n_src = 0;
     int *segs = nullptr;       // 4 * n_segs
     int *term_ptr = nullptr;   // n_terms + 1
     int *term_src = nullptr;   // 2 * n_src
-    int *chunk_ptr = nullptr;  // n_chunks + 1
 };
 
 // Build the folded term layout; returns 0 or a few_status error code.
@@ -111,11 +110,10 @@ inline long long tile_upper_bound(long long n, int K, int tile) {
 
 // Arena layout of one request's resident state.
 struct ReqLayout {
-    size_t off_t, off_pcoef, off_acoef, off_segs, off_term_ptr, off_term_src, off_chunk_ptr,
-        off_table, off_starts, off_tile_pref, total;
+    size_t off_t, off_segs, off_term_ptr, off_term_src, upload_end;   // host-staged
+    size_t off_pcoef, off_acoef, off_ybuf, off_table, off_starts, off_tile_pref, total;
 };
-ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
-                         int n_chunks);
+ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src);
 
 // Binary64 sample time exactly as written: t_start + j * dt, no contraction.
 double sample_time(double t_start, double dt, long long j);

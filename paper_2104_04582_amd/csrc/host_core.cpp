@@ -45,7 +45,6 @@ void free_term_layout(TermLayout *t) {
     std::free(t->segs);
     std::free(t->term_ptr);
     std::free(t->term_src);
-    std::free(t->chunk_ptr);
     *t = TermLayout{};
 }
 
@@ -107,43 +106,25 @@ int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
         p = q;
     }
     term_ptr.push_back((int)src.size() / 2);
-    // fold chunks: consecutive terms with at most kFoldMaxTerms terms and
-    // kFoldSrcCap contributor entries each
-    std::vector<int> chunks;
-    chunks.push_back(0);
-    int t0 = 0;
-    while (t0 < term) {
-        int t1 = t0;
-        while (t1 < term && t1 - t0 < kFoldMaxTerms &&
-               term_ptr[t1 + 1] - term_ptr[t0] <= kFoldSrcCap)
-            ++t1;
-        if (t1 == t0) return FEW_E_MODES;   // one term repeats a mode > kFoldSrcCap times
-        chunks.push_back(t1);
-        t0 = t1;
-    }
     out->n_segs = (int)segs.size() / 4;
     out->n_terms = term;
     out->n_src = (int)src.size() / 2;
-    out->n_chunks = (int)chunks.size() - 1;
     out->segs = (int *)std::malloc(sizeof(int) * segs.size());
     out->term_ptr = (int *)std::malloc(sizeof(int) * term_ptr.size());
     out->term_src = (int *)std::malloc(sizeof(int) * std::max<size_t>(src.size(), 2));
-    out->chunk_ptr = (int *)std::malloc(sizeof(int) * chunks.size());
-    if (!out->segs || !out->term_ptr || !out->term_src || !out->chunk_ptr) {
+    if (!out->segs || !out->term_ptr || !out->term_src) {
         free_term_layout(out);
         return FEW_E_NOMEM;
     }
     std::memcpy(out->segs, segs.data(), sizeof(int) * segs.size());
     std::memcpy(out->term_ptr, term_ptr.data(), sizeof(int) * term_ptr.size());
     std::memcpy(out->term_src, src.data(), sizeof(int) * src.size());
-    std::memcpy(out->chunk_ptr, chunks.data(), sizeof(int) * chunks.size());
     return FEW_OK;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
-                         int n_chunks) {
+ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src) {
     ReqLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -156,10 +137,11 @@ ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n
     L.off_segs = take(sizeof(int) * 4 * (size_t)n_segs);
     L.off_term_ptr = take(sizeof(int) * (size_t)(n_terms + 1));
     L.off_term_src = take(sizeof(int) * 2 * (size_t)std::max(n_src, 1));
-    L.off_chunk_ptr = take(sizeof(int) * (size_t)(n_chunks + 1));
+    L.upload_end = L.off_term_src + sizeof(int) * 2 * (size_t)n_src;
     // device-produced arrays
     L.off_pcoef = take(sizeof(double) * 16 * (size_t)(K - 1));
     L.off_acoef = take(sizeof(double) * 8 * (size_t)(K - 1) * M);
+    L.off_ybuf = take(sizeof(double) * 2 * (size_t)std::max(n_src, 1));
     L.off_table = take((fp32 ? 4 : 8) * 8 * (size_t)(K - 1) * n_terms);
     L.off_starts = take(sizeof(long long) * K);
     L.off_tile_pref = take(sizeof(int) * K);
@@ -205,8 +187,7 @@ extern "C" int32_t few_host_interval_starts(int32_t K, const double *t_knots, do
 extern "C" uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t M,
                                            int32_t n_terms) {
     if (K < 4 || M < 1 || n_terms < 1) return 0;
-    // n_src <= 2M, n_segs <= n_terms, chunks <= n_terms
-    ReqLayout L = request_layout(precision == FEW_MIXED, K, M, n_terms, n_terms, 2 * M,
-                                 n_terms);
+    // n_src <= 2M, n_segs <= n_terms
+    ReqLayout L = request_layout(precision == FEW_MIXED, K, M, n_terms, n_terms, 2 * M);
     return (uint64_t)L.total;
 }

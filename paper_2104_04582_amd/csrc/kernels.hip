@@ -73,78 +73,93 @@ __device__ __forceinline__ double dev_sample_time(double t_start, double dt, lon
 // Solved by forward elimination and back substitution without pivoting.
 // ===========================================================================
 
-// Double-double solve of one phase series; lane ph of the first workgroup.
-// pcoef[((i * 2 + ph) * 4 + p) * 2 + {0, 1}] = (hi, lo) of coefficient p on
-// interval i; p = 0 holds y_i reduced mod 2 pi.  During the forward sweep the
-// b and c slots of interval r hold the eliminated rhs g_r and multiplier w_r.
-__device__ void fit_phase_dd(const FitJob &jb, int ph) {
+// Double-double solve of phase series ph (workgroup ph).  All lanes compute
+// the interval widths h_i, slopes delta_i, right-hand sides and diagonals in
+// parallel into LDS; lane 0 runs the two serial sweeps; all lanes then form
+// the cubic coefficients.  pcoef[((i * 2 + ph) * 4 + p) * 2 + {0, 1}] =
+// (hi, lo) of coefficient p on interval i; p = 0 holds y_i reduced mod 2 pi.
+// LDS: eight binary64 arrays of length K (hi/lo of h, delta, g, w).
+__device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     const double *y = ph ? jb.phi_r : jb.phi_phi;
     const double *t = jb.t;
     const int K = jb.K;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    double *Hh = lds, *Hl = lds + K, *Dh = lds + 2 * K, *Dl = lds + 3 * K;
+    double *Gh = lds + 4 * K, *Gl = lds + 5 * K, *Wh = lds + 6 * K, *Wl = lds + 7 * K;
+    auto H = [&](int i) { return dd_make(Hh[i], Hl[i]); };
+    auto D = [&](int i) { return dd_make(Dh[i], Dl[i]); };
+    for (int i = tid; i < K - 1; i += bs) {
+        const dd h = two_sum(t[i + 1], -t[i]);
+        const dd d = dd_div(two_sum(y[i + 1], -y[i]), h);
+        Hh[i] = h.hi; Hl[i] = h.lo;
+        Dh[i] = d.hi; Dl[i] = d.lo;
+    }
+    __syncthreads();
+    // right-hand side into G, diagonal into W
+    for (int r = tid; r < K; r += bs) {
+        dd rhs, diag;
+        if (r == 0) {
+            const dd h0 = H(0), h1 = H(1), sup = dd_add(h0, h1);
+            rhs = dd_div(dd_add(dd_mul(dd_mul(dd_add(h0, dd_mul_d(sup, 2.0)), h1), D(0)),
+                                dd_mul(dd_mul(h0, h0), D(1))),
+                         sup);
+            diag = h1;
+        } else if (r < K - 1) {
+            rhs = dd_mul_d(dd_add(dd_mul(H(r), D(r - 1)), dd_mul(H(r - 1), D(r))), 3.0);
+            diag = dd_mul_d(dd_add(H(r - 1), H(r)), 2.0);
+        } else {
+            const dd ha = H(K - 3), hb = H(K - 2), sum = dd_add(ha, hb);
+            rhs = dd_div(dd_add(dd_mul(dd_mul(hb, hb), D(K - 3)),
+                                dd_mul(dd_mul(dd_add(dd_mul_d(sum, 2.0), hb), ha), D(K - 2))),
+                         sum);
+            diag = ha;
+        }
+        Gh[r] = rhs.hi; Gl[r] = rhs.lo;
+        Wh[r] = diag.hi; Wl[r] = diag.lo;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // forward elimination: w_r = sup_r / den_r, g_r = (rhs_r - sub_r g_{r-1}) / den_r
+        dd inv = dd_div(dd_make(1.0), dd_make(Wh[0], Wl[0]));
+        dd w = dd_mul(dd_add(H(0), H(1)), inv);
+        dd g = dd_mul(dd_make(Gh[0], Gl[0]), inv);
+        Wh[0] = w.hi; Wl[0] = w.lo; Gh[0] = g.hi; Gl[0] = g.lo;
+        for (int r = 1; r < K; ++r) {
+            const dd sub = (r < K - 1) ? H(r) : dd_add(H(K - 2), H(K - 3));
+            const dd den = dd_sub(dd_make(Wh[r], Wl[r]), dd_mul(sub, w));
+            inv = dd_div(dd_make(1.0), den);
+            g = dd_mul(dd_sub(dd_make(Gh[r], Gl[r]), dd_mul(sub, g)), inv);
+            w = (r < K - 1) ? dd_mul(H(r - 1), inv) : dd_make(0.0);
+            Wh[r] = w.hi; Wl[r] = w.lo; Gh[r] = g.hi; Gl[r] = g.lo;
+        }
+        // back substitution: s_r = g_r - w_r s_{r+1}; slopes overwrite G
+        dd s = g;
+        for (int r = K - 2; r >= 0; --r) {
+            s = dd_sub(dd_make(Gh[r], Gl[r]), dd_mul(dd_make(Wh[r], Wl[r]), s));
+            Gh[r] = s.hi; Gl[r] = s.lo;
+        }
+    }
+    __syncthreads();
     double *pc = jb.pcoef;
-    auto slot = [&](int i, int p) { return pc + (((size_t)i * 2 + ph) * 4 + p) * 2; };
-    auto H = [&](int i) { return two_sum(t[i + 1], -t[i]); };
-    auto D = [&](int i) { return dd_div(two_sum(y[i + 1], -y[i]), H(i)); };
-    auto put = [&](int i, int p, dd v) {
-        double *s = slot(i, p);
-        s[0] = v.hi;
-        s[1] = v.lo;
-    };
-    auto get = [&](int i, int p) {
-        const double *s = slot(i, p);
-        return dd_make(s[0], s[1]);
-    };
-
-    dd h0 = H(0), h1 = H(1), d0 = D(0), d1 = D(1);
-    dd sup = dd_add(h0, h1);
-    dd rhs = dd_div(dd_add(dd_mul(dd_mul(dd_add(h0, dd_mul_d(sup, 2.0)), h1), d0),
-                           dd_mul(dd_mul(h0, h0), d1)),
-                    sup);
-    dd w = dd_div(sup, h1);
-    dd g = dd_div(rhs, h1);
-    put(0, 1, g);
-    put(0, 2, w);
-    dd dprev = d0;
-    for (int r = 1; r <= K - 2; ++r) {
-        dd hp = H(r - 1), hr = H(r);
-        dd dr = D(r);
-        dd diag = dd_mul_d(dd_add(hp, hr), 2.0);
-        dd rr = dd_mul_d(dd_add(dd_mul(hr, dprev), dd_mul(hp, dr)), 3.0);
-        dd den = dd_sub(diag, dd_mul(hr, w));
-        w = dd_div(hp, den);
-        g = dd_div(dd_sub(rr, dd_mul(hr, g)), den);
-        put(r, 1, g);
-        put(r, 2, w);
-        dprev = dr;
-    }
-    {
-        dd ha = H(K - 3), hb = H(K - 2);
-        dd da = D(K - 3), db = D(K - 2);
-        dd sum = dd_add(ha, hb);
-        dd rr = dd_div(dd_add(dd_mul(dd_mul(hb, hb), da),
-                              dd_mul(dd_mul(dd_add(dd_mul_d(sum, 2.0), hb), ha), db)),
-                       sum);
-        dd den = dd_sub(ha, dd_mul(sum, w));
-        g = dd_div(dd_sub(rr, dd_mul(sum, g)), den);
-    }
-    dd s_next = g;   // s_{K-1}
-    for (int r = K - 2; r >= 0; --r) {
-        dd gr = get(r, 1), wr = get(r, 2);
-        dd s = dd_sub(gr, dd_mul(wr, s_next));
-        dd hr = H(r), dr = D(r);
-        dd c = dd_div(dd_sub(dd_sub(dd_mul_d(dr, 3.0), dd_mul_d(s, 2.0)), s_next), hr);
-        dd d = dd_div(dd_sub(dd_add(s, s_next), dd_mul_d(dr, 2.0)), dd_mul(hr, hr));
-        put(r, 0, dd_reduce_2pi(dd_make(y[r])));
-        put(r, 1, s);
-        put(r, 2, c);
-        put(r, 3, d);
-        s_next = s;
+    for (int r = tid; r < K - 1; r += bs) {
+        const dd s0 = dd_make(Gh[r], Gl[r]), s1 = dd_make(Gh[r + 1], Gl[r + 1]);
+        const dd h = H(r), d = D(r);
+        const dd c = dd_div(dd_sub(dd_sub(dd_mul_d(d, 3.0), dd_mul_d(s0, 2.0)), s1), h);
+        const dd e = dd_div(dd_sub(dd_add(s0, s1), dd_mul_d(d, 2.0)), dd_mul(h, h));
+        const dd a = dd_reduce_2pi(dd_make(y[r]));
+        double *o = pc + ((size_t)r * 2 + ph) * 8;
+        o[0] = a.hi; o[1] = a.lo;
+        o[2] = s0.hi; o[3] = s0.lo;
+        o[4] = c.hi; o[5] = c.lo;
+        o[6] = e.hi; o[7] = e.lo;
     }
 }
 
 // Binary64 solve of the amplitude series handled by this workgroup.
-// lds: h[K], inverse pivots invd[K], multipliers w[K].
+// LDS: h[K], inverse pivots invd[K], multipliers w[K] of the shared grid.
+// Knot values are fetched eight at a time so their latency overlaps.
 __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
+    constexpr int C = 8;
     const int K = jb.K, M = jb.M;
     const int tid = threadIdx.x, bs = blockDim.x;
     double *hs = lds, *invd = lds + K, *wv = lds + 2 * K;
@@ -172,53 +187,77 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     const size_t cs = 8 * (size_t)M;                 // interval stride of acoef
     double *o = jb.acoef + 8 * (size_t)k + comp;     // coefficient p at o[i * cs + 2 p]
 
-    double y0 = y[0], y1 = y[ys], y2 = y[2 * ys];
-    double h0 = hs[0], h1 = hs[1];
-    double dprev = (y1 - y0) / h0;
-    double dcur = (y2 - y1) / h1;
-    double g = ((h0 + 2.0 * (h0 + h1)) * h1 * dprev + h0 * h0 * dcur) / (h0 + h1) * invd[0];
-    o[1 * 2] = g;
-    double ynext = y2;
-    for (int r = 1; r <= K - 2; ++r) {
-        if (r > 1) {
-            double yn = y[(size_t)(r + 1) * ys];
-            dprev = dcur;
-            dcur = (yn - ynext) / hs[r];
-            ynext = yn;
+    // forward: knot idx gives delta_{idx-1}; rows 0 and 1 close at idx = 2,
+    // row idx - 1 at every later knot, row K - 1 after the last knot.
+    double yprev = y[0];
+    double dm1 = 0.0, d0 = 0.0, g = 0.0;
+    for (int i0 = 1; i0 < K; i0 += C) {
+        double yy[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) yy[c] = (i0 + c < K) ? y[(size_t)(i0 + c) * ys] : 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int idx = i0 + c;
+            if (idx < K) {
+                dm1 = d0;
+                d0 = (yy[c] - yprev) / hs[idx - 1];
+                yprev = yy[c];
+                if (idx == 2) {
+                    const double h0 = hs[0], h1 = hs[1];
+                    g = ((h0 + 2.0 * (h0 + h1)) * h1 * dm1 + h0 * h0 * d0) / (h0 + h1) * invd[0];
+                    o[2] = g;
+                }
+                if (idx >= 2) {
+                    const int r = idx - 1;
+                    const double rhs = 3.0 * (hs[r] * dm1 + hs[r - 1] * d0);
+                    g = (rhs - hs[r] * g) * invd[r];
+                    o[(size_t)r * cs + 2] = g;
+                }
+            }
         }
-        double rhs = 3.0 * (hs[r] * dprev + hs[r - 1] * dcur);
-        g = (rhs - hs[r] * g) * invd[r];
-        o[(size_t)r * cs + 2] = g;
     }
     {
-        double ha = hs[K - 3], hb = hs[K - 2];
-        double rhs = (hb * hb * dprev + (2.0 * (ha + hb) + hb) * ha * dcur) / (ha + hb);
+        const double ha = hs[K - 3], hb = hs[K - 2];
+        const double rhs = (hb * hb * dm1 + (2.0 * (ha + hb) + hb) * ha * d0) / (ha + hb);
         g = (rhs - (hb + ha) * g) * invd[K - 1];
     }
+    // back substitution and coefficients, interval K-2 down to 0
     double s_next = g;
-    double yr1 = y[(size_t)(K - 1) * ys];
-    for (int r = K - 2; r >= 0; --r) {
-        double yr = y[(size_t)r * ys];
-        double hr = hs[r];
-        double dr = (yr1 - yr) / hr;
-        double s = o[(size_t)r * cs + 2] - wv[r] * s_next;
-        double *orow = o + (size_t)r * cs;
-        orow[0] = yr;
-        orow[2] = s;
-        orow[4] = (3.0 * dr - 2.0 * s - s_next) / hr;
-        orow[6] = (s + s_next - 2.0 * dr) / (hr * hr);
-        s_next = s;
-        yr1 = yr;
+    double yr1 = yprev;                              // y_{K-1}
+    for (int r0 = K - 2; r0 >= 0; r0 -= C) {
+        double gg[C], yy[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int r = r0 - c;
+            gg[c] = (r >= 0) ? o[(size_t)r * cs + 2] : 0.0;
+            yy[c] = (r >= 0) ? y[(size_t)r * ys] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int r = r0 - c;
+            if (r >= 0) {
+                const double hr = hs[r];
+                const double dr = (yr1 - yy[c]) / hr;
+                const double s = gg[c] - wv[r] * s_next;
+                double *orow = o + (size_t)r * cs;
+                orow[0] = yy[c];
+                orow[2] = s;
+                orow[4] = (3.0 * dr - 2.0 * s - s_next) / hr;
+                orow[6] = (s + s_next - 2.0 * dr) / (hr * hr);
+                s_next = s;
+                yr1 = yy[c];
+            }
+        }
     }
 }
 
 __device__ __forceinline__ void fit_body(const FitJob &jb, double *lds) {
-    if (blockIdx.x == 0) {
-        if (threadIdx.x < 2) fit_phase_dd(jb, threadIdx.x);
+    if (blockIdx.x < 2) {
+        fit_phase_dd(jb, blockIdx.x, lds);
         return;
     }
-    if ((int)blockIdx.x > jb.amp_blocks) return;
-    fit_amplitudes(jb, blockIdx.x - 1, lds);
+    if ((int)blockIdx.x - 2 >= jb.amp_blocks) return;
+    fit_amplitudes(jb, blockIdx.x - 2, lds);
 }
 
 __global__ __launch_bounds__(256) void fit_kernel(FitJob jb) {
@@ -228,7 +267,7 @@ __global__ __launch_bounds__(256) void fit_kernel(FitJob jb) {
 
 __global__ __launch_bounds__(256) void fit_batch_kernel(const FitJob *jobs) {
     extern __shared__ double lds_fit[];
-    FitJob jb = jobs[blockIdx.y];
+    const FitJob jb = jobs[blockIdx.y];
     fit_body(jb, lds_fit);
 }
 
@@ -260,7 +299,7 @@ __device__ void prep_intervals(const PrepJob &jb) {
         jb.starts[i] = s;
     }
     __syncthreads();
-    // tiles per interval, exclusive prefix by chunks of consecutive intervals
+    // tiles per interval, exclusive prefix by runs of consecutive intervals
     const int P = K - 1;
     const int per = (P + bs - 1) / bs;
     const int a = tid * per, b = min(a + per, P);
@@ -289,88 +328,85 @@ __device__ void prep_intervals(const PrepJob &jb) {
     }
 }
 
-// Fold the l-sum for the terms of one chunk, for every knot interval:
-//   C_term = scale * sum_e Y_e * (A_k or conj(A_k)),
-// Y_e = -2Y_lm for a listed mode and (-1)^l -2Y_{l,-m} for its mirror (Eq. (9)).
-// Coefficients are rescaled to u = x / h_i (coefficient p times h_i^p).
-template <typename Real>
-__device__ void prep_fold(const PrepJob &jb, int chunk) {
-    __shared__ double2 yw[kFoldSrcCap];
-    __shared__ int ysrc[kFoldSrcCap];
-    const int tid = threadIdx.x, bs = blockDim.x;
-    const int t0 = jb.chunk_ptr[chunk], t1 = jb.chunk_ptr[chunk + 1];
-    const int e0 = jb.term_ptr[t0], e1 = jb.term_ptr[t1];
-    for (int e = e0 + tid; e < e1; e += bs) {
-        int2 s = jb.term_src[e];
-        int l = s.y & 255, m = (s.y >> 8) & 255, mir = (s.y >> 16) & 1;
-        double yr, yi;
-        if (!mir) {
-            few_swsh_m2(l, m, jb.theta, jb.phi, &yr, &yi);
-        } else {
-            few_swsh_m2(l, -m, jb.theta, jb.phi, &yr, &yi);
-            if (l & 1) {
-                yr = -yr;
-                yi = -yi;
-            }
-        }
-        yw[e - e0] = make_double2(yr, yi);
-        ysrc[e - e0] = s.x | (mir << 30);
-    }
-    __syncthreads();
-    const int nt = t1 - t0;
-    const int P = jb.K - 1;
-    const int M = jb.M;
-    Real *tab = (Real *)jb.table;
-    for (int p = tid; p < P * nt; p += bs) {
-        const int i = p / nt, term = t0 + p % nt;
-        double acc[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-        const int ea = jb.term_ptr[term], eb = jb.term_ptr[term + 1];
-        for (int e = ea; e < eb; ++e) {
-            const double2 w = yw[e - e0];
-            const int src = ysrc[e - e0];
-            const int k = src & ((1 << 30) - 1);
-            const double sgn = (src >> 30) ? -1.0 : 1.0;
-            const double *a = jb.acoef + ((size_t)i * M + k) * 8;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double ar = a[2 * q], ai = sgn * a[2 * q + 1];
-                acc[2 * q] += w.x * ar - w.y * ai;
-                acc[2 * q + 1] += w.x * ai + w.y * ar;
-            }
-        }
-        const double h = jb.t[i + 1] - jb.t[i];
-        double f = jb.scale;
-        Real *dst = tab + ((size_t)i * jb.n_terms + term) * 8;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            dst[2 * q] = (Real)(acc[2 * q] * f);
-            dst[2 * q + 1] = (Real)(acc[2 * q + 1] * f);
-            f *= h;
+// Harmonic weight of one contributor: -2Y_lm for a listed mode and
+// (-1)^l -2Y_{l,-m} for its mirror (Eq. (9) with k = 0).
+__device__ void prep_harmonic(const PrepJob &jb, int e) {
+    if (e >= jb.n_src) return;
+    const int2 s = jb.term_src[e];
+    const int l = s.y & 255, m = (s.y >> 8) & 255, mir = (s.y >> 16) & 1;
+    double yr, yi;
+    if (!mir) {
+        few_swsh_m2(l, m, jb.theta, jb.phi, &yr, &yi);
+    } else {
+        few_swsh_m2(l, -m, jb.theta, jb.phi, &yr, &yi);
+        if (l & 1) {
+            yr = -yr;
+            yi = -yi;
         }
     }
+    jb.ybuf[e] = make_double2(yr, yi);
 }
 
-template <typename Real>
 __device__ __forceinline__ void prep_body(const PrepJob &jb) {
     if (blockIdx.x == 0) {
         prep_intervals(jb);
         return;
     }
-    if ((int)blockIdx.x > jb.n_chunks) return;
-    prep_fold<Real>(jb, blockIdx.x - 1);
+    prep_harmonic(jb, (blockIdx.x - 1) * blockDim.x + threadIdx.x);
 }
 
-template <typename Real>
-__global__ __launch_bounds__(256) void prepare_kernel(PrepJob jb) {
-    prep_body<Real>(jb);
-}
+__global__ __launch_bounds__(256) void prepare_kernel(PrepJob jb) { prep_body(jb); }
 
-template <typename Real>
 __global__ __launch_bounds__(256) void prepare_batch_kernel(const PrepJob *jobs) {
-    PrepJob jb = jobs[blockIdx.y];
-    prep_body<Real>(jb);
+    const PrepJob jb = jobs[blockIdx.y];
+    prep_body(jb);
+}
+
+// Fold the l-sum for one (interval, term) pair:
+//   C_term = scale * sum_e Y_e * (A_k or conj(A_k)),
+// rescaled to u = x / h_i (coefficient p times h_i^p).  Consecutive lanes take
+// consecutive terms of one interval, so table stores are contiguous.
+template <typename Real>
+__device__ void fold_pair(const PrepJob &jb, long long p) {
+    const long long P = (long long)(jb.K - 1) * jb.n_terms;
+    if (p >= P) return;
+    const int i = (int)(p / jb.n_terms), term = (int)(p % jb.n_terms);
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    const int ea = jb.term_ptr[term], eb = jb.term_ptr[term + 1];
+    for (int e = ea; e < eb; ++e) {
+        const double2 w = jb.ybuf[e];
+        const int2 src = jb.term_src[e];
+        const double sgn = ((src.y >> 16) & 1) ? -1.0 : 1.0;
+        const double *a = jb.acoef + ((size_t)i * jb.M + src.x) * 8;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double ar = a[2 * q], ai = sgn * a[2 * q + 1];
+            acc[2 * q] += w.x * ar - w.y * ai;
+            acc[2 * q + 1] += w.x * ai + w.y * ar;
+        }
+    }
+    const double h = jb.t[i + 1] - jb.t[i];
+    double f = jb.scale;
+    Real *dst = (Real *)jb.table + ((size_t)i * jb.n_terms + term) * 8;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        dst[2 * q] = (Real)(acc[2 * q] * f);
+        dst[2 * q + 1] = (Real)(acc[2 * q + 1] * f);
+        f *= h;
+    }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void fold_kernel(PrepJob jb) {
+    fold_pair<Real>(jb, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void fold_batch_kernel(const PrepJob *jobs) {
+    const PrepJob jb = jobs[blockIdx.y];
+    fold_pair<Real>(jb, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ===========================================================================
@@ -614,33 +650,48 @@ __global__ void zero_u32_kernel(unsigned *p, int n) {
 // ===========================================================================
 static inline int round_up8(long long x) { return (int)((x + 7) / 8 * 8); }
 
+static inline size_t fit_lds_bytes(int K) {
+    // phase workgroups: 8 arrays of K; amplitude workgroups: 3 arrays of K
+    return sizeof(double) * 8 * (size_t)K;
+}
+
 hipError_t launch_fit(const FitJob &job, hipStream_t stream) {
-    dim3 grid(1 + job.amp_blocks);
-    size_t lds = sizeof(double) * 3 * (size_t)job.K;
-    hipLaunchKernelGGL(fit_kernel, grid, dim3(256), lds, stream, job);
+    dim3 grid(2 + job.amp_blocks);
+    hipLaunchKernelGGL(fit_kernel, grid, dim3(256), fit_lds_bytes(job.K), stream, job);
     return hipGetLastError();
 }
 
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream) {
-    dim3 grid(1 + max_blocks, n_jobs);
-    size_t lds = sizeof(double) * 3 * (size_t)max_K;
-    hipLaunchKernelGGL(fit_batch_kernel, grid, dim3(256), lds, stream, jobs_dev);
+    dim3 grid(2 + max_blocks, n_jobs);
+    hipLaunchKernelGGL(fit_batch_kernel, grid, dim3(256), fit_lds_bytes(max_K), stream,
+                       jobs_dev);
     return hipGetLastError();
 }
 
 hipError_t launch_prepare(const PrepJob &job, bool fp32, hipStream_t stream) {
-    dim3 grid(1 + job.n_chunks);
-    if (fp32) hipLaunchKernelGGL(prepare_kernel<float>, grid, dim3(256), 0, stream, job);
-    else hipLaunchKernelGGL(prepare_kernel<double>, grid, dim3(256), 0, stream, job);
+    hipLaunchKernelGGL(prepare_kernel, dim3(1 + job.src_blocks), dim3(256), 0, stream, job);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (fp32)
+        hipLaunchKernelGGL(fold_kernel<float>, dim3(job.fold_blocks), dim3(256), 0, stream, job);
+    else
+        hipLaunchKernelGGL(fold_kernel<double>, dim3(job.fold_blocks), dim3(256), 0, stream, job);
     return hipGetLastError();
 }
 
-hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_chunks, bool fp32,
-                                hipStream_t stream) {
-    dim3 grid(1 + max_chunks, n_jobs);
-    if (fp32) hipLaunchKernelGGL(prepare_batch_kernel<float>, grid, dim3(256), 0, stream, jobs_dev);
-    else hipLaunchKernelGGL(prepare_batch_kernel<double>, grid, dim3(256), 0, stream, jobs_dev);
+hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_src_blocks,
+                                int max_fold_blocks, bool fp32, hipStream_t stream) {
+    hipLaunchKernelGGL(prepare_batch_kernel, dim3(1 + max_src_blocks, n_jobs), dim3(256), 0,
+                       stream, jobs_dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (fp32)
+        hipLaunchKernelGGL(fold_batch_kernel<float>, dim3(max_fold_blocks, n_jobs), dim3(256), 0,
+                           stream, jobs_dev);
+    else
+        hipLaunchKernelGGL(fold_batch_kernel<double>, dim3(max_fold_blocks, n_jobs), dim3(256),
+                           0, stream, jobs_dev);
     return hipGetLastError();
 }
 
