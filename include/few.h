@@ -171,6 +171,16 @@ int32_t few_mode_sum(few_plan plan, few_spline spline, double theta, double phi,
                      void *out);
 
 /*
+ * Batched path: fit and sum n independent requests (each as few_spline_fit +
+ * few_mode_sum, Sec. III C) in one batched launch on the plan stream: one fit
+ * kernel, one prepare/fold pair and one persistent summation kernel whose
+ * waves pull tiles of every request from a shared counter.  Results are
+ * bitwise identical to n separate calls.  Returns before the kernels finish;
+ * request inputs and outputs follow the synchronous-call ownership rule.
+ */
+int32_t few_batch(few_plan plan, int32_t n, const few_request *reqs);
+
+/*
  * Served path: queue one request (spline fit + summation) for continuous
  * batching.  A host scheduler thread admits queued requests in arrival order
  * while their arena footprint fits the plan budget, packs the admitted ones

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <set>
@@ -333,6 +334,15 @@ struct few_plan_s {
     bool stop = false, worker_started = false;
     uint64_t next_ticket = 1;
     unsigned *counters = nullptr;   // one persistent-kernel counter per stream slot
+    // few_batch on the plan stream: its own counter, and arena blocks / pinned
+    // buffers released once the recorded event has completed
+    unsigned *sync_counter = nullptr;
+    struct Deferred {
+        size_t arena_off;
+        void *pinned;
+        hipEvent_t ev;
+    };
+    std::vector<Deferred> deferred;
 };
 
 struct few_spline_s {
@@ -395,6 +405,24 @@ int sync_upload(few_plan p, const HostReq &r, char *dst) {
 }
 
 void scheduler_main(few_plan p);
+int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter);
+size_t batch_bytes(const std::vector<ServedReq *> &reqs);
+
+// Release few_batch resources whose work has completed (all of them if wait).
+void reap_deferred(few_plan p, bool wait) {
+    for (size_t i = 0; i < p->deferred.size();) {
+        auto &d = p->deferred[i];
+        if (wait) hipEventSynchronize(d.ev);
+        if (hipEventQuery(d.ev) == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        p->arena.release(d.arena_off);
+        p->pinned.put(d.pinned);
+        hipEventDestroy(d.ev);
+        p->deferred.erase(p->deferred.begin() + i);
+    }
+}
 
 }  // namespace
 
@@ -468,6 +496,7 @@ int32_t few_plan_destroy(few_plan p) {
         for (ServedReq *r : p->pending)
             if (!p->tickets.count(r->ticket)) delete r;
         hipStreamSynchronize(p->stream);
+        reap_deferred(p, true);
         for (few_spline s : p->splines) delete s;
         for (auto &t : p->timed) {
             hipEventDestroy(t.second.first);
@@ -706,12 +735,68 @@ int32_t few_wait(few_plan p, uint64_t ticket) {
     return few_poll(p, ticket);
 }
 
+int32_t few_batch(few_plan p, int32_t n, const few_request *reqs) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    if (n < 1 || !reqs) return fail(FEW_E_ARG, "need n >= 1 requests");
+    try {
+        std::vector<std::unique_ptr<ServedReq>> own;
+        std::vector<ServedReq *> list;
+        for (int i = 0; i < n; ++i) {
+            const few_request *q = &reqs[i];
+            int rc = validate_fit_args(q->n_knots, q->t_knots, q->n_modes, q->lmn, q->phi_phi,
+                                       q->phi_r, q->amp, p->max_knots, p->max_modes);
+            if (!rc)
+                rc = validate_sum_args(q->t_knots, q->n_knots, q->theta, q->phi, q->scale,
+                                       q->t_start, q->dt, q->n_samples, q->out);
+            if (rc) return rc;
+            own.emplace_back(new ServedReq);
+            ServedReq *r = own.back().get();
+            r->r = *q;
+            rc = make_host_req(q->n_knots, q->t_knots, q->n_modes, q->lmn, p->fp32, &r->h);
+            if (rc) return rc;
+            r->r.t_knots = r->h.t.data();
+            list.push_back(r);
+        }
+        std::lock_guard<std::mutex> g(p->sync_mu);
+        HIP_TRY(hipSetDevice(p->device));
+        reap_deferred(p, false);
+        if (!p->sync_counter) {
+            size_t off = p->arena.alloc(256);
+            if (off == SIZE_MAX) return fail(FEW_E_NOMEM, "arena exhausted (counter)");
+            p->sync_counter = (unsigned *)p->arena.ptr(off);
+        }
+        const size_t bytes = batch_bytes(list);
+        if (bytes > p->budget) return fail(FEW_E_TOO_LARGE, "batch needs %zu bytes", bytes);
+        Batch b;
+        b.slot = -1;
+        b.reqs = list;
+        b.arena_off = p->arena.alloc(bytes);
+        if (b.arena_off == SIZE_MAX) {
+            reap_deferred(p, true);
+            b.arena_off = p->arena.alloc(bytes);
+        }
+        if (b.arena_off == SIZE_MAX) return fail(FEW_E_NOMEM, "plan arena exhausted");
+        int rc = launch_batch(p, &b, p->stream, p->sync_counter);
+        if (rc != FEW_OK) {
+            hipStreamSynchronize(p->stream);
+            if (b.done) hipEventDestroy(b.done);
+            p->arena.release(b.arena_off);
+            if (b.pinned) p->pinned.put(b.pinned);
+            return rc;
+        }
+        p->deferred.push_back({b.arena_off, b.pinned, b.done});
+        return FEW_OK;
+    } catch (...) {
+        return fail(FEW_E_NOMEM, "exception in few_batch");
+    }
+}
+
 }  // extern "C"
 
 namespace {
 
 // Build and launch one batch on stream slot `slot`.  Called without p->mu held.
-int launch_batch(few_plan p, Batch *b) {
+int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
     const int n = (int)b->reqs.size();
     // arena block: [FitJob[n] | PrepJob[n] | SumJob[n] | per-request uploads | rest]
     size_t off_fit = 0;
@@ -753,13 +838,12 @@ int launch_batch(few_plan p, Batch *b) {
         max_fold_blocks = std::max(max_fold_blocks, pj[i].fold_blocks);
     }
     if (waves > 0x3fffffff) return fail(FEW_E_ARG, "batch too large");
-    hipStream_t s = p->bstreams[b->slot];
     HIP_TRY(hipMemcpyAsync(dev, host, upload_end, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_fit_batch((const FitJob *)(dev + off_fit), n, max_amp_blocks, max_K, s));
     HIP_TRY(launch_prepare_batch((const PrepJob *)(dev + off_prep), n, max_src_blocks,
                                  max_fold_blocks, fp32, s));
     HIP_TRY(launch_sum_batch((const SumJob *)(dev + off_sum), n, (int)waves, fp32, true,
-                             p->counters + 64 * b->slot, s));
+                             counter, s));
     HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(b->done, s));
     return FEW_OK;
@@ -829,7 +913,7 @@ void scheduler_main(few_plan p) {
                 b->reqs = take;
                 p->slot_busy[slot] = true;
                 g.unlock();
-                int rc = launch_batch(p, b);
+                int rc = launch_batch(p, b, p->bstreams[slot], p->counters + 64 * slot);
                 g.lock();
                 if (rc != FEW_OK) {
                     if (b->done) {

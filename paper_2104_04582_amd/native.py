@@ -32,7 +32,7 @@ FEW_FLAG_TIMING = 1
 
 EXPORTED = [
     "few_plan_create", "few_plan_destroy", "few_spline_fit", "few_spline_free",
-    "few_spline_coefs", "few_mode_sum", "few_submit", "few_poll", "few_wait",
+    "few_spline_coefs", "few_mode_sum", "few_batch", "few_submit", "few_poll", "few_wait",
     "few_plan_timing", "few_last_error", "few_host_terms", "few_host_interval_starts",
     "few_host_request_bytes",
 ]
@@ -92,6 +92,7 @@ def load() -> ctypes.CDLL:
     lib.few_spline_free.argtypes = [vp]
     lib.few_spline_coefs.argtypes = [vp, i32, vp]
     lib.few_mode_sum.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp]
+    lib.few_batch.argtypes = [vp, i32, P(Request)]
     lib.few_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
     lib.few_poll.argtypes = [vp, ctypes.c_uint64]
     lib.few_wait.argtypes = [vp, ctypes.c_uint64]
@@ -224,8 +225,8 @@ class Plan:
                                    float(scale), float(t_start), float(dt), int(n_samples), op))
         return out
 
-    def submit(self, t_knots, phi_phi, phi_r, lmn, amp, theta, phi, dt, n_samples, out,
-               t_start: float = 0.0, scale: float = 1.0) -> int:
+    def _request(self, t_knots, phi_phi, phi_r, lmn, amp, theta, phi, dt, n_samples, out,
+                 t_start: float = 0.0, scale: float = 1.0):
         import torch
         t = _host_f64(t_knots)
         lm = _host_i32(lmn).reshape(-1, 3)
@@ -238,6 +239,18 @@ class Plan:
                     theta=float(theta), phi=float(phi), scale=float(scale),
                     t_start=float(t_start), dt=float(dt), n_samples=int(n_samples),
                     out=_dev_ptr(out, self.out_dtype, (n_samples,), "out"))
+        return r, (t, lm)
+
+    def batch(self, requests) -> None:
+        """few_batch: each item is a dict of submit() keyword arguments."""
+        built = [self._request(**q) for q in requests]
+        arr = (Request * len(built))(*[b[0] for b in built])
+        _check(load().few_batch(self.handle, len(built), arr))
+
+    def submit(self, t_knots, phi_phi, phi_r, lmn, amp, theta, phi, dt, n_samples, out,
+               t_start: float = 0.0, scale: float = 1.0) -> int:
+        r, keep = self._request(t_knots, phi_phi, phi_r, lmn, amp, theta, phi, dt, n_samples,
+                                out, t_start, scale)
         tk = ctypes.c_uint64()
         _check(load().few_submit(self.handle, ctypes.byref(r), ctypes.byref(tk)))
         self._inflight[tk.value] = (phi_phi, phi_r, amp, out)

@@ -33,6 +33,12 @@ def dev_inputs(torch, w, dev):
                  for a in (w.phi_phi, w.phi_r, w.amp))
 
 
+def submit(plan, w, ins, out):
+    pp, pr, amp = ins
+    return plan.submit(w.t_knots, pp, pr, w.lmn, amp, w.theta, w.phi, w.dt, w.n_samples, out,
+                       t_start=w.t_start, scale=w.scale)
+
+
 def solo(native, torch, dev, w, prec):
     pp, pr, amp = dev_inputs(torch, w, dev)
     with native.Plan(0, prec) as plan:
@@ -63,8 +69,7 @@ def test_batch_bitwise_equals_solo(env, prec):
     dtype = torch.complex64 if prec == "mixed" else torch.complex128
     outs = [torch.empty(w.n_samples, dtype=dtype, device=dev) for w in ws]
     with native.Plan(0, prec, max_inflight=2) as plan:
-        tickets = [plan.submit(w.t_knots, *ins[i], w.lmn, w.theta, w.phi, w.dt, w.n_samples,
-                               outs[i]) for i, w in enumerate(ws)]
+        tickets = [submit(plan, w, ins[i], outs[i]) for i, w in enumerate(ws)]
         for tk in tickets:
             plan.wait(tk)
     for i, w in enumerate(ws):
@@ -85,6 +90,28 @@ def test_batch_bitwise_equals_solo(env, prec):
             assert mm <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_one_launch_batch_bitwise_equals_solo(env, prec):
+    """few_batch: uneven instances in one batched launch on the plan stream."""
+    native, torch, dev = env
+    ws = instances(16, max_samples=300_000)
+    log(f"[batch] {len(ws)} {prec}")
+    refs = [solo(native, torch, dev, w, prec) for w in ws]
+    ins = [dev_inputs(torch, w, dev) for w in ws]
+    dtype = torch.complex64 if prec == "mixed" else torch.complex128
+    outs = [torch.empty(w.n_samples, dtype=dtype, device=dev) for w in ws]
+    with native.Plan(0, prec) as plan:
+        for rep in range(2):
+            for o in outs:
+                o.zero_()
+            plan.batch([dict(t_knots=w.t_knots, phi_phi=ins[i][0], phi_r=ins[i][1],
+                             lmn=w.lmn, amp=ins[i][2], theta=w.theta, phi=w.phi, dt=w.dt,
+                             n_samples=w.n_samples, out=outs[i]) for i, w in enumerate(ws)])
+            torch.cuda.synchronize()
+            for i in range(len(ws)):
+                assert np.array_equal(outs[i].cpu().numpy(), refs[i]), (rep, i)
+
+
 @pytest.mark.parametrize("prec", ["mixed"])
 def test_staggered_arrivals_same_as_alone(env, prec):
     """Requests submitted while earlier ones run are admitted into new
@@ -98,8 +125,7 @@ def test_staggered_arrivals_same_as_alone(env, prec):
     with native.Plan(0, prec, max_inflight=3) as plan:
         tickets = []
         for i, w in enumerate(ws):
-            tickets.append(plan.submit(w.t_knots, *ins[i], w.lmn, w.theta, w.phi, w.dt,
-                                       w.n_samples, outs[i]))
+            tickets.append(submit(plan, w, ins[i], outs[i]))
             time.sleep(0.0007 * (i % 3))
         done = set()
         t0 = time.time()
@@ -127,8 +153,7 @@ def test_admission_under_small_budget(env):
     budget = int(need * 1.6)
     log(f"[serve] budget {budget / 1e6:.1f} MB, full request {need / 1e6:.1f} MB")
     with native.Plan(0, "mixed", hbm_budget_bytes=budget, max_inflight=2) as plan:
-        tickets = [plan.submit(w.t_knots, *ins[i], w.lmn, w.theta, w.phi, w.dt, w.n_samples,
-                               outs[i]) for i, w in enumerate(ws)]
+        tickets = [submit(plan, w, ins[i], outs[i]) for i, w in enumerate(ws)]
         for tk in tickets:
             plan.wait(tk)
     for i in range(len(ws)):
@@ -136,8 +161,7 @@ def test_admission_under_small_budget(env):
     with native.Plan(0, "mixed", hbm_budget_bytes=budget // 4) as small:
         big = ws[0]
         with pytest.raises(native.FewError) as e:
-            small.submit(big.t_knots, *ins[0], big.lmn, big.theta, big.phi, big.dt,
-                         big.n_samples, outs[0])
+            submit(small, big, ins[0], outs[0])
         assert e.value.code == native.FEW_E_TOO_LARGE
 
 
