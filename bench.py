@@ -107,10 +107,45 @@ def batch_run(native, precision: str, dev, n: int, budget: int, reps: int = 3):
             "waveforms_per_s": n / best, "mode_samples": ms, "mode_samples_per_s": ms / best}
 
 
+def host_threads() -> int:
+    """Cores this process may use (affinity mask), at most the 16-core share of
+    one GPU on the measurement host."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2104_04582_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sum_kernel_traffic.txt")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the summation kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that summary was
+    taken on a different kernel source than the one built now."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if fields.get("kernels_sha256") != digest:
+        return None
+    try:
+        return float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, target_s: float = 10.0):
     """The oracle as it stands on the host cores, on a contiguous sample slice."""
     import oracle
-    threads = os.cpu_count() or 1
+    threads = host_threads()
     probe = 1024
     t0 = time.perf_counter()
     oracle.mode_sum_waveform(w, idx=np.arange(probe, dtype=np.int64), n_threads=threads)
@@ -284,7 +319,8 @@ def main() -> int:
                    "modes": w.M, "knots": w.K, "samples": w.n_samples,
                    "folded_terms": n_terms, "segments": n_segs},
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VALU,
-                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU,
+                     "traffic": measured_traffic(),
                      "kernel": "sum_kernel<float>",
                      "flop_per_launch": flops, "launch_ms": m["sum_ms"]},
         "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],

@@ -206,11 +206,75 @@ void stage_upload(const HostReq &r, char *dst) {
     std::memcpy(dst + r.L.off_term_src, r.terms.term_src, sizeof(int) * 2 * r.terms.n_src);
 }
 
-int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, HostReq *r) {
+// Recently used term layouts, keyed by the full mode list (an MCMC client
+// resubmits the same mode set many times; sorting it costs ~1 ms per call).
+class LayoutCache {
+  public:
+    ~LayoutCache() {
+        for (auto &e : entries_) free_term_layout(&e.layout);
+    }
+    // Fill *out with an owned copy of the layout of (M, lmn).
+    int get(int M, const int32_t *lmn, TermLayout *out) {
+        std::lock_guard<std::mutex> g(mu_);
+        for (size_t i = 0; i < entries_.size(); ++i) {
+            Entry &e = entries_[i];
+            if ((int)e.lmn.size() == 3 * M &&
+                std::memcmp(e.lmn.data(), lmn, sizeof(int32_t) * 3 * (size_t)M) == 0) {
+                int rc = copy(e.layout, out);
+                if (!rc && i != 0) std::rotate(entries_.begin(), entries_.begin() + i,
+                                               entries_.begin() + i + 1);
+                return rc;
+            }
+        }
+        TermLayout L;
+        int rc = build_term_layout(M, lmn, kMaxGap, &L);
+        if (rc) return rc;
+        rc = copy(L, out);
+        if (rc) {
+            free_term_layout(&L);
+            return rc;
+        }
+        if (entries_.size() == kCap) {
+            free_term_layout(&entries_.back().layout);
+            entries_.pop_back();
+        }
+        entries_.insert(entries_.begin(), Entry{std::vector<int32_t>(lmn, lmn + 3 * (size_t)M), L});
+        return FEW_OK;
+    }
+
+  private:
+    static constexpr size_t kCap = 8;
+    struct Entry {
+        std::vector<int32_t> lmn;
+        TermLayout layout;
+    };
+    static int copy(const TermLayout &a, TermLayout *b) {
+        *b = TermLayout{};
+        b->n_segs = a.n_segs;
+        b->n_terms = a.n_terms;
+        b->n_src = a.n_src;
+        b->segs = (int *)std::malloc(sizeof(int) * 4 * (size_t)a.n_segs);
+        b->term_ptr = (int *)std::malloc(sizeof(int) * (size_t)(a.n_terms + 1));
+        b->term_src = (int *)std::malloc(sizeof(int) * 2 * (size_t)std::max(a.n_src, 1));
+        if (!b->segs || !b->term_ptr || !b->term_src) {
+            free_term_layout(b);
+            return FEW_E_NOMEM;
+        }
+        std::memcpy(b->segs, a.segs, sizeof(int) * 4 * (size_t)a.n_segs);
+        std::memcpy(b->term_ptr, a.term_ptr, sizeof(int) * (size_t)(a.n_terms + 1));
+        std::memcpy(b->term_src, a.term_src, sizeof(int) * 2 * (size_t)a.n_src);
+        return FEW_OK;
+    }
+    std::mutex mu_;
+    std::vector<Entry> entries_;
+};
+
+int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, HostReq *r,
+                  LayoutCache *cache) {
     r->K = K;
     r->M = M;
     r->t.assign(t, t + K);
-    int rc = build_term_layout(M, lmn, kMaxGap, &r->terms);
+    int rc = cache->get(M, lmn, &r->terms);
     if (rc) return fail(rc, "mode list rejected while building the term layout");
     r->L = request_layout(fp32, K, M, r->terms.n_segs, r->terms.n_terms, r->terms.n_src);
     r->upload_bytes = r->L.upload_end;
@@ -317,6 +381,7 @@ struct few_plan_s {
     int stage_next = 0;
     std::mutex sync_mu;
     std::set<few_spline> splines;
+    LayoutCache layouts;
     // timing
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timed;
     std::vector<hipEvent_t> ev_pool;
@@ -529,7 +594,7 @@ int32_t few_spline_fit(few_plan p, int32_t K, const double *t_knots, const doubl
         HIP_TRY(hipSetDevice(p->device));
         few_spline s = new (std::nothrow) few_spline_s;
         if (!s) return fail(FEW_E_NOMEM, "host allocation failed");
-        rc = make_host_req(K, t_knots, M, lmn, p->fp32, &s->h);
+        rc = make_host_req(K, t_knots, M, lmn, p->fp32, &s->h, &p->layouts);
         if (rc) {
             delete s;
             return rc;
@@ -666,7 +731,8 @@ int32_t few_submit(few_plan p, const few_request *req, uint64_t *ticket) {
         ServedReq *r = new (std::nothrow) ServedReq;
         if (!r) return fail(FEW_E_NOMEM, "host allocation failed");
         r->r = *req;
-        rc = make_host_req(req->n_knots, req->t_knots, req->n_modes, req->lmn, p->fp32, &r->h);
+        rc = make_host_req(req->n_knots, req->t_knots, req->n_modes, req->lmn, p->fp32, &r->h,
+                           &p->layouts);
         if (rc) {
             delete r;
             return rc;
@@ -752,7 +818,8 @@ int32_t few_batch(few_plan p, int32_t n, const few_request *reqs) {
             own.emplace_back(new ServedReq);
             ServedReq *r = own.back().get();
             r->r = *q;
-            rc = make_host_req(q->n_knots, q->t_knots, q->n_modes, q->lmn, p->fp32, &r->h);
+            rc = make_host_req(q->n_knots, q->t_knots, q->n_modes, q->lmn, p->fp32, &r->h,
+                               &p->layouts);
             if (rc) return rc;
             r->r.t_knots = r->h.t.data();
             list.push_back(r);

@@ -15,8 +15,14 @@ constexpr int kWave = 64;
 constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 
 // Samples per lane in one wave tile of the summation kernel.
-constexpr int kSamplesPerLaneF32 = 4;
-constexpr int kSamplesPerLaneF64 = 2;
+#ifndef FEW_SL_F32
+#define FEW_SL_F32 4
+#endif
+#ifndef FEW_SL_F64
+#define FEW_SL_F64 2
+#endif
+constexpr int kSamplesPerLaneF32 = FEW_SL_F32;
+constexpr int kSamplesPerLaneF64 = FEW_SL_F64;
 
 inline int tile_samples(bool fp32) {
     return kWave * (fp32 ? kSamplesPerLaneF32 : kSamplesPerLaneF64);
