@@ -16,7 +16,7 @@ constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 
 // Samples per lane in one wave tile of the summation kernel.
 #ifndef FEW_SL_F32
-#define FEW_SL_F32 4
+#define FEW_SL_F32 2
 #endif
 #ifndef FEW_SL_F64
 #define FEW_SL_F64 2

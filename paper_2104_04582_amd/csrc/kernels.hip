@@ -27,6 +27,13 @@ namespace few {
 
 #define FEW_AS4 __attribute__((address_space(4)))
 
+// Optional minimum waves per SIMD for the summation kernels (register cap).
+#ifdef FEW_SUM_WAVES
+#define FEW_SUM_ATTR __attribute__((amdgpu_waves_per_eu(FEW_SUM_WAVES)))
+#else
+#define FEW_SUM_ATTR
+#endif
+
 // Wave-uniform read-only data: the constant address space makes the compiler
 // use scalar loads (SGPR destinations) for uniform addresses.
 template <typename T>
@@ -73,21 +80,68 @@ __device__ __forceinline__ double dev_sample_time(double t_start, double dt, lon
 // Solved by forward elimination and back substitution without pivoting.
 // ===========================================================================
 
-// Double-double solve of phase series ph (workgroup ph).  All lanes compute
-// the interval widths h_i, slopes delta_i, right-hand sides and diagonals in
-// parallel into LDS; lane 0 runs the two serial sweeps; all lanes then form
-// the cubic coefficients.  pcoef[((i * 2 + ph) * 4 + p) * 2 + {0, 1}] =
-// (hi, lo) of coefficient p on interval i; p = 0 holds y_i reduced mod 2 pi.
-// LDS: eight binary64 arrays of length K (hi/lo of h, delta, g, w).
+// Phase series ph (workgroup ph), to double-double accuracy by one step of
+// iterative refinement: solve the slope system in binary64 (Thomas), form
+// the residual with the exact double-double matrix and right-hand side, solve
+// again for the correction and add it.  After one step the error is of order
+// (eps cond)^2, far below double-double rounding, and only the two binary64
+// sweeps are serial.  pcoef[((i * 2 + ph) * 4 + p) * 2 + {0, 1}] = (hi, lo) of
+// coefficient p on interval i; p = 0 holds y_i reduced mod 2 pi.
+// LDS (binary64 arrays of length K): h hi/lo, delta hi/lo, w, inverse pivot,
+// first solution s0, right-hand side / residual / correction.
 __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     const double *y = ph ? jb.phi_r : jb.phi_phi;
     const double *t = jb.t;
     const int K = jb.K;
     const int tid = threadIdx.x, bs = blockDim.x;
     double *Hh = lds, *Hl = lds + K, *Dh = lds + 2 * K, *Dl = lds + 3 * K;
-    double *Gh = lds + 4 * K, *Gl = lds + 5 * K, *Wh = lds + 6 * K, *Wl = lds + 7 * K;
+    double *wv = lds + 4 * K, *invd = lds + 5 * K, *s0 = lds + 6 * K, *rr = lds + 7 * K;
     auto H = [&](int i) { return dd_make(Hh[i], Hl[i]); };
     auto D = [&](int i) { return dd_make(Dh[i], Dl[i]); };
+    // row r of the slope system: sub, diag, super (double-double)
+    auto row = [&](int r, dd *sub, dd *diag, dd *sup) {
+        if (r == 0) {
+            *sub = dd_make(0.0);
+            *diag = H(1);
+            *sup = dd_add(H(0), H(1));
+        } else if (r < K - 1) {
+            *sub = H(r);
+            *diag = dd_mul_d(dd_add(H(r - 1), H(r)), 2.0);
+            *sup = H(r - 1);
+        } else {
+            *sub = dd_add(H(K - 2), H(K - 3));
+            *diag = H(K - 3);
+            *sup = dd_make(0.0);
+        }
+    };
+    auto rhs = [&](int r) {
+        if (r == 0) {
+            const dd h0 = H(0), h1 = H(1), sup = dd_add(h0, h1);
+            return dd_div(dd_add(dd_mul(dd_mul(dd_add(h0, dd_mul_d(sup, 2.0)), h1), D(0)),
+                                 dd_mul(dd_mul(h0, h0), D(1))),
+                          sup);
+        }
+        if (r < K - 1)
+            return dd_mul_d(dd_add(dd_mul(H(r), D(r - 1)), dd_mul(H(r - 1), D(r))), 3.0);
+        const dd ha = H(K - 3), hb = H(K - 2), sum = dd_add(ha, hb);
+        return dd_div(dd_add(dd_mul(dd_mul(hb, hb), D(K - 3)),
+                             dd_mul(dd_mul(dd_add(dd_mul_d(sum, 2.0), hb), ha), D(K - 2))),
+                      sum);
+    };
+    // binary64 sub-diagonal of row r (the factor only needs the rounded matrix;
+    // the refinement step uses the exact rows)
+    auto sub64 = [&](int r) { return (r < K - 1) ? Hh[r] : Hh[K - 2] + Hh[K - 3]; };
+    // binary64 Thomas sweep with the factor in wv / invd: x <- A^-1 x (in place)
+    auto solve = [&](double *x) {
+        double g = x[0] * invd[0];
+        x[0] = g;
+        for (int r = 1; r < K; ++r) {
+            g = (x[r] - sub64(r) * g) * invd[r];
+            x[r] = g;
+        }
+        for (int r = K - 2; r >= 0; --r) x[r] -= wv[r] * x[r + 1];
+    };
+
     for (int i = tid; i < K - 1; i += bs) {
         const dd h = two_sum(t[i + 1], -t[i]);
         const dd d = dd_div(two_sum(y[i + 1], -y[i]), h);
@@ -95,61 +149,44 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
         Dh[i] = d.hi; Dl[i] = d.lo;
     }
     __syncthreads();
-    // right-hand side into G, diagonal into W
-    for (int r = tid; r < K; r += bs) {
-        dd rhs, diag;
-        if (r == 0) {
-            const dd h0 = H(0), h1 = H(1), sup = dd_add(h0, h1);
-            rhs = dd_div(dd_add(dd_mul(dd_mul(dd_add(h0, dd_mul_d(sup, 2.0)), h1), D(0)),
-                                dd_mul(dd_mul(h0, h0), D(1))),
-                         sup);
-            diag = h1;
-        } else if (r < K - 1) {
-            rhs = dd_mul_d(dd_add(dd_mul(H(r), D(r - 1)), dd_mul(H(r - 1), D(r))), 3.0);
-            diag = dd_mul_d(dd_add(H(r - 1), H(r)), 2.0);
-        } else {
-            const dd ha = H(K - 3), hb = H(K - 2), sum = dd_add(ha, hb);
-            rhs = dd_div(dd_add(dd_mul(dd_mul(hb, hb), D(K - 3)),
-                                dd_mul(dd_mul(dd_add(dd_mul_d(sum, 2.0), hb), ha), D(K - 2))),
-                         sum);
-            diag = ha;
-        }
-        Gh[r] = rhs.hi; Gl[r] = rhs.lo;
-        Wh[r] = diag.hi; Wl[r] = diag.lo;
-    }
+    for (int r = tid; r < K; r += bs) s0[r] = rhs(r).hi;
     __syncthreads();
     if (tid == 0) {
-        // forward elimination: w_r = sup_r / den_r, g_r = (rhs_r - sub_r g_{r-1}) / den_r
-        dd inv = dd_div(dd_make(1.0), dd_make(Wh[0], Wl[0]));
-        dd w = dd_mul(dd_add(H(0), H(1)), inv);
-        dd g = dd_mul(dd_make(Gh[0], Gl[0]), inv);
-        Wh[0] = w.hi; Wl[0] = w.lo; Gh[0] = g.hi; Gl[0] = g.lo;
-        for (int r = 1; r < K; ++r) {
-            const dd sub = (r < K - 1) ? H(r) : dd_add(H(K - 2), H(K - 3));
-            const dd den = dd_sub(dd_make(Wh[r], Wl[r]), dd_mul(sub, w));
-            inv = dd_div(dd_make(1.0), den);
-            g = dd_mul(dd_sub(dd_make(Gh[r], Gl[r]), dd_mul(sub, g)), inv);
-            w = (r < K - 1) ? dd_mul(H(r - 1), inv) : dd_make(0.0);
-            Wh[r] = w.hi; Wl[r] = w.lo; Gh[r] = g.hi; Gl[r] = g.lo;
+        // binary64 factor of the rounded matrix, then the first solve
+        invd[0] = 1.0 / Hh[1];
+        wv[0] = (Hh[0] + Hh[1]) * invd[0];
+        for (int r = 1; r < K - 1; ++r) {
+            const double den = 2.0 * (Hh[r - 1] + Hh[r]) - Hh[r] * wv[r - 1];
+            invd[r] = 1.0 / den;
+            wv[r] = Hh[r - 1] * invd[r];
         }
-        // back substitution: s_r = g_r - w_r s_{r+1}; slopes overwrite G
-        dd s = g;
-        for (int r = K - 2; r >= 0; --r) {
-            s = dd_sub(dd_make(Gh[r], Gl[r]), dd_mul(dd_make(Wh[r], Wl[r]), s));
-            Gh[r] = s.hi; Gl[r] = s.lo;
-        }
+        invd[K - 1] = 1.0 / (Hh[K - 3] - sub64(K - 1) * wv[K - 2]);
+        wv[K - 1] = 0.0;
+        solve(s0);
     }
+    __syncthreads();
+    // residual of the exact (double-double) system at s0
+    for (int r = tid; r < K; r += bs) {
+        dd sub, diag, sup;
+        row(r, &sub, &diag, &sup);
+        dd ax = dd_mul_d(diag, s0[r]);
+        if (r > 0) ax = dd_add(ax, dd_mul_d(sub, s0[r - 1]));
+        if (r < K - 1) ax = dd_add(ax, dd_mul_d(sup, s0[r + 1]));
+        rr[r] = dd_sub(rhs(r), ax).hi;
+    }
+    __syncthreads();
+    if (tid == 0) solve(rr);
     __syncthreads();
     double *pc = jb.pcoef;
     for (int r = tid; r < K - 1; r += bs) {
-        const dd s0 = dd_make(Gh[r], Gl[r]), s1 = dd_make(Gh[r + 1], Gl[r + 1]);
+        const dd sa = two_sum(s0[r], rr[r]), sb = two_sum(s0[r + 1], rr[r + 1]);
         const dd h = H(r), d = D(r);
-        const dd c = dd_div(dd_sub(dd_sub(dd_mul_d(d, 3.0), dd_mul_d(s0, 2.0)), s1), h);
-        const dd e = dd_div(dd_sub(dd_add(s0, s1), dd_mul_d(d, 2.0)), dd_mul(h, h));
+        const dd c = dd_div(dd_sub(dd_sub(dd_mul_d(d, 3.0), dd_mul_d(sa, 2.0)), sb), h);
+        const dd e = dd_div(dd_sub(dd_add(sa, sb), dd_mul_d(d, 2.0)), dd_mul(h, h));
         const dd a = dd_reduce_2pi(dd_make(y[r]));
         double *o = pc + ((size_t)r * 2 + ph) * 8;
         o[0] = a.hi; o[1] = a.lo;
-        o[2] = s0.hi; o[3] = s0.lo;
+        o[2] = sa.hi; o[3] = sa.lo;
         o[4] = c.hi; o[5] = c.lo;
         o[6] = e.hi; o[7] = e.lo;
     }
@@ -157,9 +194,9 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
 
 // Binary64 solve of the amplitude series handled by this workgroup.
 // LDS: h[K], inverse pivots invd[K], multipliers w[K] of the shared grid.
-// Knot values are fetched eight at a time so their latency overlaps.
+// Knot values are fetched sixteen at a time so their latency overlaps.
 __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
-    constexpr int C = 8;
+    constexpr int C = 16;
     const int K = jb.K, M = jb.M;
     const int tid = threadIdx.x, bs = blockDim.x;
     double *hs = lds, *invd = lds + K, *wv = lds + 2 * K;
@@ -308,19 +345,17 @@ __device__ void prep_intervals(const PrepJob &jb) {
         long long cnt = jb.starts[i + 1] - jb.starts[i];
         local += (int)((cnt + jb.tile - 1) / jb.tile);
     }
+    // inclusive block scan of the per-lane counts (Hillis-Steele in LDS)
     part[tid] = local;
     __syncthreads();
-    if (tid == 0) {
-        int run = 0;
-        for (int q = 0; q < bs; ++q) {
-            int v = part[q];
-            part[q] = run;
-            run += v;
-        }
-        jb.tile_pref[P] = run;
+    for (int off = 1; off < bs; off <<= 1) {
+        const int v = (tid >= off) ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
     }
-    __syncthreads();
-    int run = part[tid];
+    if (tid == bs - 1) jb.tile_pref[P] = part[tid];
+    int run = part[tid] - local;
     for (int i = a; i < b; ++i) {
         jb.tile_pref[i] = run;
         long long cnt = jb.starts[i + 1] - jb.starts[i];
@@ -593,7 +628,7 @@ __device__ __forceinline__ int xcd_wave_id() {
 }
 
 template <typename Real, int SL, bool COMP, bool DD>
-__global__ __launch_bounds__(256) void sum_kernel(SumJob jb, int slots) {
+__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_kernel(SumJob jb, int slots) {
     const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
     if (w >= slots) return;
     sum_tile<Real, SL, COMP, DD>(jb, w);
@@ -618,7 +653,7 @@ __device__ __forceinline__ void sum_slot(const SumJob *jobs, int n_jobs, int w) 
 }
 
 template <typename Real, int SL, bool COMP, bool DD>
-__global__ __launch_bounds__(256) void sum_batch_kernel(const SumJob *jobs, int n_jobs,
+__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_batch_kernel(const SumJob *jobs, int n_jobs,
                                                         int slots) {
     const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
     if (w >= slots) return;
@@ -628,7 +663,7 @@ __global__ __launch_bounds__(256) void sum_batch_kernel(const SumJob *jobs, int 
 // Persistent variant: a fixed grid of waves pulls wave slots from one atomic
 // counter until all `slots` are handed out; every wave then exits.
 template <typename Real, int SL, bool COMP, bool DD>
-__global__ __launch_bounds__(256) void sum_persistent_kernel(const SumJob *jobs, int n_jobs,
+__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_persistent_kernel(const SumJob *jobs, int n_jobs,
                                                              int slots, unsigned *counter) {
     const int lane = threadIdx.x & (kWave - 1);
     for (;;) {
