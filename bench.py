@@ -75,6 +75,24 @@ def time_path(native, plan, w, dev, steps: int, warmup: int):
     return elapsed / steps, tm, out
 
 
+def select_timing(native, w, dev, eps: float = 1e-5, reps: int = 20):
+    """Mode selector on the benchmark amplitudes: kept modes and mean time."""
+    import torch
+    amp = torch.from_numpy(np.ascontiguousarray(w.amp)).to(dev)
+    with native.Plan(0, "fp64") as plan:
+        keep = plan.mode_select(amp, eps)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            plan.mode_select(amp, eps, keep=keep)
+        b.record()
+        torch.cuda.synchronize()
+        return {"eps": eps, "kept": int(keep.sum().item()), "of": w.M,
+                "ms": a.elapsed_time(b) / reps}
+
+
 def batch_run(native, precision: str, dev, n: int, budget: int, reps: int = 3):
     """n uneven instances in one few_batch launch; best of reps after a warmup."""
     import torch
@@ -142,15 +160,23 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(w, target_s: float = 10.0):
-    """The oracle as it stands on the host cores, on a contiguous sample slice."""
+def cpu_baseline(w, target_s: float = 12.0):
+    """The oracle as it stands on the host cores, on a contiguous sample slice
+    sized (from two short probes, which separate the fixed spline setup from
+    the per-sample cost) to take about target_s seconds."""
     import oracle
     threads = host_threads()
-    probe = 1024
-    t0 = time.perf_counter()
-    oracle.mode_sum_waveform(w, idx=np.arange(probe, dtype=np.int64), n_threads=threads)
-    t_probe = time.perf_counter() - t0
-    n_s = int(min(w.n_samples, max(probe, probe * target_s / max(t_probe, 1e-3))))
+
+    def run(n):
+        t0 = time.perf_counter()
+        oracle.mode_sum_waveform(w, idx=np.arange(n, dtype=np.int64), n_threads=threads)
+        return time.perf_counter() - t0
+
+    a, b = 512, 4096
+    ta, tb = run(a), run(b)
+    per = max((tb - ta) / (b - a), 1e-9)
+    setup = max(ta - a * per, 0.0)
+    n_s = int(min(w.n_samples, max(b, (target_s - setup) / per)))
     idx = np.arange(n_s, dtype=np.int64)
     t0 = time.perf_counter()
     oracle.mode_sum_waveform(w, idx=idx, n_threads=threads)
@@ -279,6 +305,10 @@ def main() -> int:
     del outs, a, b
     torch.cuda.empty_cache()
 
+    # mode selector (the step before the path) on the same amplitudes
+    sel = select_timing(native, w, dev)
+    log(f"[bench] mode select: {json.dumps(sel)}")
+
     batch = {}
     if args.batch > 0:
         for prec in ("mixed", "fp64"):
@@ -330,6 +360,7 @@ def main() -> int:
                       for p in res},
         "canonical_32flop_tflops": {p: res[p]["canonical_tflops"] for p in res},
         "mixed_vs_fp64": {"mismatch": mm, "max_rel_error": mx},
+        "mode_select": sel,
         "batched": batch or None,
         "served": serve or None,
         "cpu_baseline": cpu,

@@ -171,6 +171,23 @@ int32_t few_mode_sum(few_plan plan, few_spline spline, double theta, double phi,
                      void *out);
 
 /*
+ * Mode selector (Sec. III D): choose the modes that carry all but a fraction
+ * eps of the power at some knot.  At every knot k the power of mode j is
+ * |A_j(t_k)|^2 = re*re + im*im (binary64, no fused multiply-add); modes are
+ * ordered by decreasing power (ties by increasing index), their powers summed
+ * sequentially in that order, and the shortest prefix whose sum reaches
+ * (1 - eps) of the knot's total is kept (at least the top mode).
+ *   K, M   knots and listed modes, K >= 1, 1 <= M <= 4096
+ *   amp    device [K][M][2] float64, the same knot-major layout as few_spline_fit
+ *   eps    in [0, 1)
+ *   keep   device [M] int32: 1 if the mode is kept at any knot (the union), else 0
+ * Enqueued on the plan stream.  The result depends only on the inputs (no
+ * order of floating-point reduction is left open).
+ */
+int32_t few_mode_select(few_plan plan, int32_t K, int32_t M, const double *amp, double eps,
+                        int32_t *keep);
+
+/*
  * Batched path: fit and sum n independent requests (each as few_spline_fit +
  * few_mode_sum, Sec. III C) in one batched launch on the plan stream: one fit
  * kernel, one prepare/fold pair and one persistent summation kernel whose

@@ -801,6 +801,20 @@ int32_t few_wait(few_plan p, uint64_t ticket) {
     return few_poll(p, ticket);
 }
 
+int32_t few_mode_select(few_plan p, int32_t K, int32_t M, const double *amp, double eps,
+                        int32_t *keep) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    if (!amp || !keep) return fail(FEW_E_ARG, "null pointer argument");
+    if (K < 1) return fail(FEW_E_KNOTS, "K must be >= 1");
+    if (M < 1 || M > kMaxSelectModes)
+        return fail(FEW_E_MODES, "M = %d outside [1, %d]", M, kMaxSelectModes);
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(FEW_E_ARG, "eps must be in [0, 1)");
+    std::lock_guard<std::mutex> g(p->sync_mu);
+    HIP_TRY(hipSetDevice(p->device));
+    HIP_TRY(launch_select(amp, K, M, eps, keep, p->stream));
+    return FEW_OK;
+}
+
 int32_t few_batch(few_plan p, int32_t n, const few_request *reqs) {
     if (!p) return fail(FEW_E_STATE, "null plan");
     if (n < 1 || !reqs) return fail(FEW_E_ARG, "need n >= 1 requests");

@@ -23,6 +23,15 @@ constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 #endif
 constexpr int kSamplesPerLaneF32 = FEW_SL_F32;
 constexpr int kSamplesPerLaneF64 = FEW_SL_F64;
+// Software-pipelined coefficient loads in the summation loop.
+#ifndef FEW_PIPE_F32
+#define FEW_PIPE_F32 0
+#endif
+#ifndef FEW_PIPE_F64
+#define FEW_PIPE_F64 0
+#endif
+constexpr bool kPipeF32 = FEW_PIPE_F32 != 0;
+constexpr bool kPipeF64 = FEW_PIPE_F64 != 0;
 
 inline int tile_samples(bool fp32) {
     return kWave * (fp32 ? kSamplesPerLaneF32 : kSamplesPerLaneF64);
@@ -90,6 +99,9 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_s
                             bool fp32, bool persistent, unsigned *counter_dev,
                             hipStream_t stream);
 hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t stream);
+hipError_t launch_select(const double *amp, int K, int M, double eps, int *keep,
+                         hipStream_t stream);
+constexpr int kMaxSelectModes = 4096;   // LDS: (binary64 key + int index) per padded mode
 
 // ---------------------------------------------------------------------------
 // Host core (host_core.cpp): no device work.

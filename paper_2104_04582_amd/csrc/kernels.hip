@@ -474,7 +474,7 @@ __device__ __forceinline__ void phase_eval(const FEW_AS4 double *pc, dd x, doubl
 }
 
 // One wave tile: samples [j0, j1) of knot interval iv, SL samples per lane.
-template <typename Real, int SL, bool COMP, bool DD>
+template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
 __device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
     const int lane = threadIdx.x & (kWave - 1);
     const int K = jb.K;
@@ -560,25 +560,63 @@ __device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
         for (int s = 0; s < SL; ++s) sr[s] = si[s] = (Real)0;
         const FEW_AS4 Real *cp = tab + (size_t)(S.w + S.z - 1) * 8;
         const int len = S.z;
-#pragma unroll 2
-        for (int q = 0; q < len; ++q) {
-            const Real c0r = cp[0], c0i = cp[1], c1r = cp[2], c1i = cp[3];
-            const Real c2r = cp[4], c2i = cp[5], c3r = cp[6], c3i = cp[7];
-            cp -= 8;
+        if (PIPE) {
+            // Software pipeline for wide coefficients: the next term's scalar
+            // load is issued right after the first FMA of the current term,
+            // which forces the wait for the current one; the scheduling
+            // barrier keeps the load behind that FMA, so the next wait only
+            // covers a load issued one term earlier.
+            Real c[8];
 #pragma unroll
-            for (int s = 0; s < SL; ++s) {
-                Real nr = fmar(sr[s], fr[s], c0r);
-                nr = fmar(-si[s], fi[s], nr);
-                nr = fmar(u[s], c1r, nr);
-                nr = fmar(u2[s], c2r, nr);
-                nr = fmar(u3[s], c3r, nr);
-                Real ni = fmar(sr[s], fi[s], c0i);
-                ni = fmar(si[s], fr[s], ni);
-                ni = fmar(u[s], c1i, ni);
-                ni = fmar(u2[s], c2i, ni);
-                ni = fmar(u3[s], c3i, ni);
-                sr[s] = nr;
-                si[s] = ni;
+            for (int k = 0; k < 8; ++k) c[k] = cp[k];
+#pragma unroll 2
+            for (int q = 0; q < len; ++q) {
+                Real nr0 = fmar(sr[0], fr[0], c[0]);
+                __builtin_amdgcn_sched_barrier(0);
+                const FEW_AS4 Real *np = (q + 1 < len) ? cp - 8 : cp;
+                Real nx[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) nx[k] = np[k];
+#pragma unroll
+                for (int s = 0; s < SL; ++s) {
+                    Real nr = (s == 0) ? nr0 : fmar(sr[s], fr[s], c[0]);
+                    nr = fmar(-si[s], fi[s], nr);
+                    nr = fmar(u[s], c[2], nr);
+                    nr = fmar(u2[s], c[4], nr);
+                    nr = fmar(u3[s], c[6], nr);
+                    Real ni = fmar(sr[s], fi[s], c[1]);
+                    ni = fmar(si[s], fr[s], ni);
+                    ni = fmar(u[s], c[3], ni);
+                    ni = fmar(u2[s], c[5], ni);
+                    ni = fmar(u3[s], c[7], ni);
+                    sr[s] = nr;
+                    si[s] = ni;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) c[k] = nx[k];
+                cp = np;
+            }
+        } else {
+#pragma unroll 2
+            for (int q = 0; q < len; ++q) {
+                const Real c0r = cp[0], c0i = cp[1], c1r = cp[2], c1i = cp[3];
+                const Real c2r = cp[4], c2i = cp[5], c3r = cp[6], c3i = cp[7];
+                cp -= 8;
+#pragma unroll
+                for (int s = 0; s < SL; ++s) {
+                    Real nr = fmar(sr[s], fr[s], c0r);
+                    nr = fmar(-si[s], fi[s], nr);
+                    nr = fmar(u[s], c1r, nr);
+                    nr = fmar(u2[s], c2r, nr);
+                    nr = fmar(u3[s], c3r, nr);
+                    Real ni = fmar(sr[s], fi[s], c0i);
+                    ni = fmar(si[s], fr[s], ni);
+                    ni = fmar(u[s], c1i, ni);
+                    ni = fmar(u2[s], c2i, ni);
+                    ni = fmar(u3[s], c3i, ni);
+                    sr[s] = nr;
+                    si[s] = ni;
+                }
             }
         }
         // h += seed * S
@@ -627,11 +665,11 @@ __device__ __forceinline__ int xcd_wave_id() {
     return bb * (blockDim.x / kWave) + (threadIdx.x / kWave);
 }
 
-template <typename Real, int SL, bool COMP, bool DD>
+template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_kernel(SumJob jb, int slots) {
     const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
     if (w >= slots) return;
-    sum_tile<Real, SL, COMP, DD>(jb, w);
+    sum_tile<Real, SL, COMP, DD, PIPE>(jb, w);
 }
 
 // Batched launch: job j owns global wave slots [wave_base_j, wave_base_{j+1}).
@@ -645,24 +683,24 @@ __device__ __forceinline__ int find_job(const SumJob *jobs, int n_jobs, int w) {
     return lo;
 }
 
-template <typename Real, int SL, bool COMP, bool DD>
+template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
 __device__ __forceinline__ void sum_slot(const SumJob *jobs, int n_jobs, int w) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, w));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_tile<Real, SL, COMP, DD>(jb, w - jb.wave_base);
+    sum_tile<Real, SL, COMP, DD, PIPE>(jb, w - jb.wave_base);
 }
 
-template <typename Real, int SL, bool COMP, bool DD>
+template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_batch_kernel(const SumJob *jobs, int n_jobs,
                                                         int slots) {
     const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
     if (w >= slots) return;
-    sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
+    sum_slot<Real, SL, COMP, DD, PIPE>(jobs, n_jobs, w);
 }
 
 // Persistent variant: a fixed grid of waves pulls wave slots from one atomic
 // counter until all `slots` are handed out; every wave then exits.
-template <typename Real, int SL, bool COMP, bool DD>
+template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_persistent_kernel(const SumJob *jobs, int n_jobs,
                                                              int slots, unsigned *counter) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -671,8 +709,74 @@ __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_persistent_kernel(const 
         if (lane == 0) v = atomicAdd(counter, 1u);
         const int w = __builtin_amdgcn_readfirstlane((int)v);
         if (w >= slots) break;
-        sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
+        sum_slot<Real, SL, COMP, DD, PIPE>(jobs, n_jobs, w);
     }
+}
+
+// ===========================================================================
+// Mode selector (Sec. III D): per knot, order the modes by decreasing power
+// |A|^2 (ties by increasing index), sum the powers sequentially in that order,
+// and keep the shortest prefix that reaches (1 - eps) of the knot's total (at
+// least the top mode).  The selection is the union over knots.  One workgroup
+// per knot; bitonic sort of (power, index) in LDS; one lane forms the partial
+// sums in the sorted order so every threshold decision is reproducible.
+// ===========================================================================
+__device__ __forceinline__ bool sel_before(double ka, int ia, double kb, int ib) {
+    return ka > kb || (ka == kb && ia < ib);
+}
+
+__global__ __launch_bounds__(256) void select_kernel(const double *amp, int M, int N,
+                                                     double one_minus_eps, int *keep) {
+    extern __shared__ double sel_lds[];
+    double *key = sel_lds;
+    int *idx = (int *)(sel_lds + N);
+    __shared__ int cut;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const size_t k = blockIdx.x;
+    for (int j = tid; j < N; j += bs) {
+        if (j < M) {
+            const double re = amp[(k * M + j) * 2], im = amp[(k * M + j) * 2 + 1];
+            key[j] = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+            idx[j] = j;
+        } else {
+            key[j] = -1.0;          // below every power
+            idx[j] = INT_MAX;
+        }
+    }
+    __syncthreads();
+    for (int size = 2; size <= N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < N; i += bs) {
+                const int l = i ^ stride;
+                if (l > i) {
+                    const bool up = (i & size) == 0;
+                    const double ki = key[i], kl = key[l];
+                    const int ii = idx[i], il = idx[l];
+                    const bool swap = up ? sel_before(kl, il, ki, ii) : sel_before(ki, ii, kl, il);
+                    if (swap) {
+                        key[i] = kl; key[l] = ki;
+                        idx[i] = il; idx[l] = ii;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        double total = 0.0;
+        for (int j = 0; j < M; ++j) total = __dadd_rn(total, key[j]);
+        const double thr = __dmul_rn(one_minus_eps, total);
+        double before = 0.0;
+        int J = 0;
+        for (int j = 0; j < M; ++j) {
+            if (!(before < thr)) break;
+            J = j + 1;
+            before = __dadd_rn(before, key[j]);
+        }
+        cut = J > 0 ? J : 1;
+    }
+    __syncthreads();
+    for (int j = tid; j < cut; j += bs) keep[idx[j]] = 1;
 }
 
 __global__ void zero_u32_kernel(unsigned *p, int n) {
@@ -734,10 +838,10 @@ hipError_t launch_sum(const SumJob &job, int wave_slots, bool fp32, hipStream_t 
     const int waves_per_block = 256 / kWave;
     dim3 grid(round_up8((wave_slots + waves_per_block - 1) / waves_per_block));
     if (fp32)
-        hipLaunchKernelGGL((sum_kernel<float, kSamplesPerLaneF32, true, false>), grid, dim3(256),
+        hipLaunchKernelGGL((sum_kernel<float, kSamplesPerLaneF32, true, false, kPipeF32>), grid, dim3(256),
                            0, stream, job, wave_slots);
     else
-        hipLaunchKernelGGL((sum_kernel<double, kSamplesPerLaneF64, false, true>), grid, dim3(256),
+        hipLaunchKernelGGL((sum_kernel<double, kSamplesPerLaneF64, false, true, kPipeF64>), grid, dim3(256),
                            0, stream, job, wave_slots);
     return hipGetLastError();
 }
@@ -748,10 +852,10 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_s
     if (!persistent) {
         dim3 grid(round_up8((total_wave_slots + waves_per_block - 1) / waves_per_block));
         if (fp32)
-            hipLaunchKernelGGL((sum_batch_kernel<float, kSamplesPerLaneF32, true, false>), grid,
+            hipLaunchKernelGGL((sum_batch_kernel<float, kSamplesPerLaneF32, true, false, kPipeF32>), grid,
                                dim3(256), 0, stream, jobs_dev, n_jobs, total_wave_slots);
         else
-            hipLaunchKernelGGL((sum_batch_kernel<double, kSamplesPerLaneF64, false, true>), grid,
+            hipLaunchKernelGGL((sum_batch_kernel<double, kSamplesPerLaneF64, false, true, kPipeF64>), grid,
                                dim3(256), 0, stream, jobs_dev, n_jobs, total_wave_slots);
         return hipGetLastError();
     }
@@ -761,13 +865,27 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_s
     if (blocks > needed) blocks = needed > 0 ? needed : 1;
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, counter_dev, 1);
     if (fp32)
-        hipLaunchKernelGGL((sum_persistent_kernel<float, kSamplesPerLaneF32, true, false>),
+        hipLaunchKernelGGL((sum_persistent_kernel<float, kSamplesPerLaneF32, true, false, kPipeF32>),
                            dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs,
                            total_wave_slots, counter_dev);
     else
-        hipLaunchKernelGGL((sum_persistent_kernel<double, kSamplesPerLaneF64, false, true>),
+        hipLaunchKernelGGL((sum_persistent_kernel<double, kSamplesPerLaneF64, false, true, kPipeF64>),
                            dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs,
                            total_wave_slots, counter_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const double *amp, int K, int M, double eps, int *keep,
+                         hipStream_t stream) {
+    int N = 1;
+    while (N < M) N <<= 1;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((M + 255) / 256), dim3(256), 0, stream,
+                       (unsigned *)keep, M);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)N;
+    hipLaunchKernelGGL(select_kernel, dim3(K), dim3(256), lds, stream, amp, M, N, 1.0 - eps,
+                       keep);
     return hipGetLastError();
 }
 

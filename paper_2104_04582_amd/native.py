@@ -32,7 +32,8 @@ FEW_FLAG_TIMING = 1
 
 EXPORTED = [
     "few_plan_create", "few_plan_destroy", "few_spline_fit", "few_spline_free",
-    "few_spline_coefs", "few_mode_sum", "few_batch", "few_submit", "few_poll", "few_wait",
+    "few_spline_coefs", "few_mode_sum", "few_mode_select", "few_batch", "few_submit",
+    "few_poll", "few_wait",
     "few_plan_timing", "few_last_error", "few_host_terms", "few_host_interval_starts",
     "few_host_request_bytes",
 ]
@@ -93,6 +94,7 @@ def load() -> ctypes.CDLL:
     lib.few_spline_coefs.argtypes = [vp, i32, vp]
     lib.few_mode_sum.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp]
     lib.few_batch.argtypes = [vp, i32, P(Request)]
+    lib.few_mode_select.argtypes = [vp, i32, i32, vp, dbl, vp]
     lib.few_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
     lib.few_poll.argtypes = [vp, ctypes.c_uint64]
     lib.few_wait.argtypes = [vp, ctypes.c_uint64]
@@ -240,6 +242,19 @@ class Plan:
                     t_start=float(t_start), dt=float(dt), n_samples=int(n_samples),
                     out=_dev_ptr(out, self.out_dtype, (n_samples,), "out"))
         return r, (t, lm)
+
+    def mode_select(self, amp, eps: float, keep=None):
+        """few_mode_select: int32 device mask [M] of the modes kept at any knot."""
+        import torch
+        if amp.dim() != 3 or amp.shape[2] != 2:
+            raise ValueError("amp must have shape [K, M, 2]")
+        K, M = int(amp.shape[0]), int(amp.shape[1])
+        ap = _dev_ptr(amp, torch.float64, (K, M, 2), "amp")
+        if keep is None:
+            keep = torch.empty(M, dtype=torch.int32, device=amp.device)
+        kp = _dev_ptr(keep, torch.int32, (M,), "keep")
+        _check(load().few_mode_select(self.handle, K, M, ap, float(eps), kp))
+        return keep
 
     def batch(self, requests) -> None:
         """few_batch: each item is a dict of submit() keyword arguments."""
