@@ -23,15 +23,6 @@ constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 #endif
 constexpr int kSamplesPerLaneF32 = FEW_SL_F32;
 constexpr int kSamplesPerLaneF64 = FEW_SL_F64;
-// Software-pipelined coefficient loads in the summation loop.
-#ifndef FEW_PIPE_F32
-#define FEW_PIPE_F32 0
-#endif
-#ifndef FEW_PIPE_F64
-#define FEW_PIPE_F64 0
-#endif
-constexpr bool kPipeF32 = FEW_PIPE_F32 != 0;
-constexpr bool kPipeF64 = FEW_PIPE_F64 != 0;
 
 inline int tile_samples(bool fp32) {
     return kWave * (fp32 ? kSamplesPerLaneF32 : kSamplesPerLaneF64);

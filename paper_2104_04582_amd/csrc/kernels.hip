@@ -474,7 +474,7 @@ __device__ __forceinline__ void phase_eval(const FEW_AS4 double *pc, dd x, doubl
 }
 
 // One wave tile: samples [j0, j1) of knot interval iv, SL samples per lane.
-template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
+template <typename Real, int SL, bool COMP, bool DD>
 __device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
     const int lane = threadIdx.x & (kWave - 1);
     const int K = jb.K;
@@ -560,63 +560,25 @@ __device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
         for (int s = 0; s < SL; ++s) sr[s] = si[s] = (Real)0;
         const FEW_AS4 Real *cp = tab + (size_t)(S.w + S.z - 1) * 8;
         const int len = S.z;
-        if (PIPE) {
-            // Software pipeline for wide coefficients: the next term's scalar
-            // load is issued right after the first FMA of the current term,
-            // which forces the wait for the current one; the scheduling
-            // barrier keeps the load behind that FMA, so the next wait only
-            // covers a load issued one term earlier.
-            Real c[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) c[k] = cp[k];
 #pragma unroll 2
-            for (int q = 0; q < len; ++q) {
-                Real nr0 = fmar(sr[0], fr[0], c[0]);
-                __builtin_amdgcn_sched_barrier(0);
-                const FEW_AS4 Real *np = (q + 1 < len) ? cp - 8 : cp;
-                Real nx[8];
+        for (int q = 0; q < len; ++q) {
+            const Real c0r = cp[0], c0i = cp[1], c1r = cp[2], c1i = cp[3];
+            const Real c2r = cp[4], c2i = cp[5], c3r = cp[6], c3i = cp[7];
+            cp -= 8;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) nx[k] = np[k];
-#pragma unroll
-                for (int s = 0; s < SL; ++s) {
-                    Real nr = (s == 0) ? nr0 : fmar(sr[s], fr[s], c[0]);
-                    nr = fmar(-si[s], fi[s], nr);
-                    nr = fmar(u[s], c[2], nr);
-                    nr = fmar(u2[s], c[4], nr);
-                    nr = fmar(u3[s], c[6], nr);
-                    Real ni = fmar(sr[s], fi[s], c[1]);
-                    ni = fmar(si[s], fr[s], ni);
-                    ni = fmar(u[s], c[3], ni);
-                    ni = fmar(u2[s], c[5], ni);
-                    ni = fmar(u3[s], c[7], ni);
-                    sr[s] = nr;
-                    si[s] = ni;
-                }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) c[k] = nx[k];
-                cp = np;
-            }
-        } else {
-#pragma unroll 2
-            for (int q = 0; q < len; ++q) {
-                const Real c0r = cp[0], c0i = cp[1], c1r = cp[2], c1i = cp[3];
-                const Real c2r = cp[4], c2i = cp[5], c3r = cp[6], c3i = cp[7];
-                cp -= 8;
-#pragma unroll
-                for (int s = 0; s < SL; ++s) {
-                    Real nr = fmar(sr[s], fr[s], c0r);
-                    nr = fmar(-si[s], fi[s], nr);
-                    nr = fmar(u[s], c1r, nr);
-                    nr = fmar(u2[s], c2r, nr);
-                    nr = fmar(u3[s], c3r, nr);
-                    Real ni = fmar(sr[s], fi[s], c0i);
-                    ni = fmar(si[s], fr[s], ni);
-                    ni = fmar(u[s], c1i, ni);
-                    ni = fmar(u2[s], c2i, ni);
-                    ni = fmar(u3[s], c3i, ni);
-                    sr[s] = nr;
-                    si[s] = ni;
-                }
+            for (int s = 0; s < SL; ++s) {
+                Real nr = fmar(sr[s], fr[s], c0r);
+                nr = fmar(-si[s], fi[s], nr);
+                nr = fmar(u[s], c1r, nr);
+                nr = fmar(u2[s], c2r, nr);
+                nr = fmar(u3[s], c3r, nr);
+                Real ni = fmar(sr[s], fi[s], c0i);
+                ni = fmar(si[s], fr[s], ni);
+                ni = fmar(u[s], c1i, ni);
+                ni = fmar(u2[s], c2i, ni);
+                ni = fmar(u3[s], c3i, ni);
+                sr[s] = nr;
+                si[s] = ni;
             }
         }
         // h += seed * S
@@ -665,11 +627,11 @@ __device__ __forceinline__ int xcd_wave_id() {
     return bb * (blockDim.x / kWave) + (threadIdx.x / kWave);
 }
 
-template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
+template <typename Real, int SL, bool COMP, bool DD>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_kernel(SumJob jb, int slots) {
     const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
     if (w >= slots) return;
-    sum_tile<Real, SL, COMP, DD, PIPE>(jb, w);
+    sum_tile<Real, SL, COMP, DD>(jb, w);
 }
 
 // Batched launch: job j owns global wave slots [wave_base_j, wave_base_{j+1}).
@@ -683,24 +645,24 @@ __device__ __forceinline__ int find_job(const SumJob *jobs, int n_jobs, int w) {
     return lo;
 }
 
-template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
+template <typename Real, int SL, bool COMP, bool DD>
 __device__ __forceinline__ void sum_slot(const SumJob *jobs, int n_jobs, int w) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, w));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_tile<Real, SL, COMP, DD, PIPE>(jb, w - jb.wave_base);
+    sum_tile<Real, SL, COMP, DD>(jb, w - jb.wave_base);
 }
 
-template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
+template <typename Real, int SL, bool COMP, bool DD>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_batch_kernel(const SumJob *jobs, int n_jobs,
                                                         int slots) {
     const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
     if (w >= slots) return;
-    sum_slot<Real, SL, COMP, DD, PIPE>(jobs, n_jobs, w);
+    sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
 }
 
 // Persistent variant: a fixed grid of waves pulls wave slots from one atomic
 // counter until all `slots` are handed out; every wave then exits.
-template <typename Real, int SL, bool COMP, bool DD, bool PIPE>
+template <typename Real, int SL, bool COMP, bool DD>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_persistent_kernel(const SumJob *jobs, int n_jobs,
                                                              int slots, unsigned *counter) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -709,7 +671,7 @@ __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_persistent_kernel(const 
         if (lane == 0) v = atomicAdd(counter, 1u);
         const int w = __builtin_amdgcn_readfirstlane((int)v);
         if (w >= slots) break;
-        sum_slot<Real, SL, COMP, DD, PIPE>(jobs, n_jobs, w);
+        sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
     }
 }
 
@@ -838,10 +800,10 @@ hipError_t launch_sum(const SumJob &job, int wave_slots, bool fp32, hipStream_t 
     const int waves_per_block = 256 / kWave;
     dim3 grid(round_up8((wave_slots + waves_per_block - 1) / waves_per_block));
     if (fp32)
-        hipLaunchKernelGGL((sum_kernel<float, kSamplesPerLaneF32, true, false, kPipeF32>), grid, dim3(256),
+        hipLaunchKernelGGL((sum_kernel<float, kSamplesPerLaneF32, true, false>), grid, dim3(256),
                            0, stream, job, wave_slots);
     else
-        hipLaunchKernelGGL((sum_kernel<double, kSamplesPerLaneF64, false, true, kPipeF64>), grid, dim3(256),
+        hipLaunchKernelGGL((sum_kernel<double, kSamplesPerLaneF64, false, true>), grid, dim3(256),
                            0, stream, job, wave_slots);
     return hipGetLastError();
 }
@@ -852,10 +814,10 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_s
     if (!persistent) {
         dim3 grid(round_up8((total_wave_slots + waves_per_block - 1) / waves_per_block));
         if (fp32)
-            hipLaunchKernelGGL((sum_batch_kernel<float, kSamplesPerLaneF32, true, false, kPipeF32>), grid,
+            hipLaunchKernelGGL((sum_batch_kernel<float, kSamplesPerLaneF32, true, false>), grid,
                                dim3(256), 0, stream, jobs_dev, n_jobs, total_wave_slots);
         else
-            hipLaunchKernelGGL((sum_batch_kernel<double, kSamplesPerLaneF64, false, true, kPipeF64>), grid,
+            hipLaunchKernelGGL((sum_batch_kernel<double, kSamplesPerLaneF64, false, true>), grid,
                                dim3(256), 0, stream, jobs_dev, n_jobs, total_wave_slots);
         return hipGetLastError();
     }
@@ -865,11 +827,11 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_s
     if (blocks > needed) blocks = needed > 0 ? needed : 1;
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, counter_dev, 1);
     if (fp32)
-        hipLaunchKernelGGL((sum_persistent_kernel<float, kSamplesPerLaneF32, true, false, kPipeF32>),
+        hipLaunchKernelGGL((sum_persistent_kernel<float, kSamplesPerLaneF32, true, false>),
                            dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs,
                            total_wave_slots, counter_dev);
     else
-        hipLaunchKernelGGL((sum_persistent_kernel<double, kSamplesPerLaneF64, false, true, kPipeF64>),
+        hipLaunchKernelGGL((sum_persistent_kernel<double, kSamplesPerLaneF64, false, true>),
                            dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs,
                            total_wave_slots, counter_dev);
     return hipGetLastError();
