@@ -204,6 +204,7 @@ void stage_upload(const HostReq &r, char *dst) {
     std::memcpy(dst + r.L.off_segs, r.terms.segs, sizeof(int) * 4 * r.terms.n_segs);
     std::memcpy(dst + r.L.off_term_ptr, r.terms.term_ptr, sizeof(int) * (r.terms.n_terms + 1));
     std::memcpy(dst + r.L.off_term_src, r.terms.term_src, sizeof(int) * 2 * r.terms.n_src);
+    std::memcpy(dst + r.L.off_chunks, r.terms.chunks, sizeof(int) * (r.terms.n_chunks + 1));
 }
 
 // Recently used term layouts, keyed by the full mode list (an MCMC client
@@ -253,13 +254,16 @@ class LayoutCache {
         b->n_segs = a.n_segs;
         b->n_terms = a.n_terms;
         b->n_src = a.n_src;
+        b->n_chunks = a.n_chunks;
         b->segs = (int *)std::malloc(sizeof(int) * 4 * (size_t)a.n_segs);
         b->term_ptr = (int *)std::malloc(sizeof(int) * (size_t)(a.n_terms + 1));
         b->term_src = (int *)std::malloc(sizeof(int) * 2 * (size_t)std::max(a.n_src, 1));
-        if (!b->segs || !b->term_ptr || !b->term_src) {
+        b->chunks = (int *)std::malloc(sizeof(int) * (size_t)(a.n_chunks + 1));
+        if (!b->segs || !b->term_ptr || !b->term_src || !b->chunks) {
             free_term_layout(b);
             return FEW_E_NOMEM;
         }
+        std::memcpy(b->chunks, a.chunks, sizeof(int) * (size_t)(a.n_chunks + 1));
         std::memcpy(b->segs, a.segs, sizeof(int) * 4 * (size_t)a.n_segs);
         std::memcpy(b->term_ptr, a.term_ptr, sizeof(int) * (size_t)(a.n_terms + 1));
         std::memcpy(b->term_src, a.term_src, sizeof(int) * 2 * (size_t)a.n_src);
@@ -276,7 +280,8 @@ int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, 
     r->t.assign(t, t + K);
     int rc = cache->get(M, lmn, &r->terms);
     if (rc) return fail(rc, "mode list rejected while building the term layout");
-    r->L = request_layout(fp32, K, M, r->terms.n_segs, r->terms.n_terms, r->terms.n_src);
+    r->L = request_layout(fp32, K, M, r->terms.n_segs, r->terms.n_terms, r->terms.n_src,
+                          r->terms.n_chunks);
     r->upload_bytes = r->L.upload_end;
     return FEW_OK;
 }
@@ -296,8 +301,18 @@ FitJob fit_job(const HostReq &r, char *base, const double *pp, const double *pr,
     return j;
 }
 
+// First sample of the short-tile region of a single-request launch (binary32):
+// the last FEW_SHORT_QUARTERS / 4 rounds of long tiles over `resident`
+// workgroups.  n means no short tiles (binary64, batched launches).
+long long short_tiles_from(int64_t n, bool fp32, int resident) {
+    if (!fp32 || resident <= 0) return n;
+    const long long region =
+        (long long)resident * tile_samples(true) * FEW_SHORT_QUARTERS / 4;
+    return n > region ? n - region : 0;
+}
+
 PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double scale,
-                 double t_start, double dt, int64_t n, bool fp32) {
+                 double t_start, double dt, int64_t n, bool fp32, long long short_from) {
     PrepJob j{};
     j.t = (const double *)(base + r.L.off_t);
     j.acoef = (const double *)(base + r.L.off_acoef);
@@ -318,17 +333,21 @@ PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double 
     j.n_terms = r.terms.n_terms;
     j.n_src = r.terms.n_src;
     j.tile = tile_samples(fp32);
+    j.short_tile = fp32 ? short_tile_samples() : j.tile;
+    j.short_from = short_from;
     j.src_blocks = (r.terms.n_src + 255) / 256;
     j.fold_blocks = (int)(((long long)(r.K - 1) * r.terms.n_terms + 255) / 256);
     return j;
 }
 
-SumJob sum_job(const HostReq &r, char *base, double t_start, double dt, int64_t n, void *out) {
+SumJob sum_job(const HostReq &r, char *base, double t_start, double dt, int64_t n, void *out,
+               long long short_from) {
     SumJob j{};
     j.t = (const double *)(base + r.L.off_t);
     j.pcoef = (const double *)(base + r.L.off_pcoef);
     j.table = base + r.L.off_table;
     j.segs = (const int4 *)(base + r.L.off_segs);
+    j.chunks = (const int *)(base + r.L.off_chunks);
     j.starts = (const long long *)(base + r.L.off_starts);
     j.tile_pref = (const int *)(base + r.L.off_tile_pref);
     j.out = out;
@@ -338,6 +357,8 @@ SumJob sum_job(const HostReq &r, char *base, double t_start, double dt, int64_t 
     j.K = r.K;
     j.n_terms = r.terms.n_terms;
     j.n_segs = r.terms.n_segs;
+    j.n_chunks = r.terms.n_chunks;
+    j.short_from = short_from;
     j.wave_base = 0;
     return j;
 }
@@ -368,6 +389,7 @@ struct few_plan_s {
     hipStream_t stream = nullptr;
     bool fp32 = false;
     int max_knots = kMaxKnots, max_modes = 65536, max_inflight = 2;
+    int resident_wg = 0;        // binary32 summation workgroups resident at once
     uint64_t budget = 0;
     int flags = 0;
     char *arena_base = nullptr;
@@ -515,6 +537,7 @@ int32_t few_plan_create(const few_plan_desc *desc, few_plan *out) {
         p->device = desc->device;
         p->stream = (hipStream_t)desc->stream;
         p->fp32 = desc->precision == FEW_MIXED;
+        p->resident_wg = p->fp32 ? sum_resident_workgroups() : 0;
         p->max_knots = desc->max_knots ? desc->max_knots : kMaxKnots;
         p->max_modes = desc->max_modes ? desc->max_modes : 65536;
         p->max_inflight = desc->max_inflight ? desc->max_inflight : 2;
@@ -671,12 +694,15 @@ int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double 
         std::lock_guard<std::mutex> g(p->sync_mu);
         HIP_TRY(hipSetDevice(p->device));
         char *base = p->arena.ptr(s->arena_off);
-        PrepJob pj = prep_job(s->h, base, theta, phi, scale, t_start, dt, n, p->fp32);
+        const long long short_from = short_tiles_from(n, p->fp32, p->resident_wg);
+        PrepJob pj = prep_job(s->h, base, theta, phi, scale, t_start, dt, n, p->fp32, short_from);
         rc = timed_launch(p, ST_PREP, p->stream,
                           [&] { return launch_prepare(pj, p->fp32, p->stream); });
         if (rc) return rc;
-        SumJob sj = sum_job(s->h, base, t_start, dt, n, out);
-        long long slots = tile_upper_bound(n, s->h.K, tile_samples(p->fp32));
+        SumJob sj = sum_job(s->h, base, t_start, dt, n, out, short_from);
+        long long slots = tile_upper_bound2(n, short_from, s->h.K, tile_samples(p->fp32),
+                                            pj.short_tile);
+        if (slots > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
         return timed_launch(p, ST_SUM, p->stream, [&] {
             return launch_sum(sj, (int)slots, p->fp32, p->stream);
         });
@@ -909,8 +935,9 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         stage_upload(r->h, host + req_off[i]);
         fj[i] = fit_job(r->h, rb, r->r.phi_phi, r->r.phi_r, r->r.amp);
         pj[i] = prep_job(r->h, rb, r->r.theta, r->r.phi, r->r.scale, r->r.t_start, r->r.dt,
-                         r->r.n_samples, fp32);
-        sj[i] = sum_job(r->h, rb, r->r.t_start, r->r.dt, r->r.n_samples, r->r.out);
+                         r->r.n_samples, fp32, r->r.n_samples);
+        sj[i] = sum_job(r->h, rb, r->r.t_start, r->r.dt, r->r.n_samples, r->r.out,
+                        r->r.n_samples);
         sj[i].wave_base = (int)waves;
         waves += tile_upper_bound(r->r.n_samples, r->h.K, tile);
         max_amp_blocks = std::max(max_amp_blocks, fj[i].amp_blocks);

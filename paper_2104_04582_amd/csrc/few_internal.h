@@ -13,10 +13,17 @@ constexpr int kMaxL = 30;             // Wigner-d sum stays well conditioned in 
 constexpr int kMaxAbsN = 1000;
 constexpr int kWave = 64;
 constexpr int kMaxGap = 4;            // zero terms filled inside one segment
+#ifndef FEW_SEG_UNROLL
+#define FEW_SEG_UNROLL 2
+#endif
+#ifndef FEW_CHUNK_TERMS
+#define FEW_CHUNK_TERMS 1024
+#endif
+constexpr int kChunkTerms = FEW_CHUNK_TERMS;   // terms staged in LDS at once (binary32: 32 B each)
 
 // Samples per lane in one wave tile of the summation kernel.
 #ifndef FEW_SL_F32
-#define FEW_SL_F32 2
+#define FEW_SL_F32 4
 #endif
 #ifndef FEW_SL_F64
 #define FEW_SL_F64 2
@@ -24,9 +31,22 @@ constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 constexpr int kSamplesPerLaneF32 = FEW_SL_F32;
 constexpr int kSamplesPerLaneF64 = FEW_SL_F64;
 
+// Samples per tile: a workgroup of 4 waves (binary32) or one wave (binary64).
 inline int tile_samples(bool fp32) {
-    return kWave * (fp32 ? kSamplesPerLaneF32 : kSamplesPerLaneF64);
+    return fp32 ? 4 * kWave * kSamplesPerLaneF32 : kWave * kSamplesPerLaneF64;
 }
+
+// binary32: the last samples of a request are cut into short tiles (half the
+// samples per lane) so the end of a launch drains evenly.  The short-tile region holds
+// FEW_SHORT_QUARTERS / 4 of one round of long tiles over the resident workgroups.
+#ifndef FEW_SL_SHORT
+#define FEW_SL_SHORT 2
+#endif
+#ifndef FEW_SHORT_QUARTERS
+#define FEW_SHORT_QUARTERS 2
+#endif
+constexpr int kSamplesPerLaneShort = FEW_SL_SHORT;
+inline int short_tile_samples() { return 4 * kWave * kSamplesPerLaneShort; }
 
 // ---------------------------------------------------------------------------
 // Device-side job descriptors.  Pointers are device addresses in the plan
@@ -57,8 +77,10 @@ struct PrepJob {
     int *tile_pref;         // [K]
     double theta, phi, scale, t_start, dt;
     long long n;
+    long long short_from;   // first sample cut into short tiles (n: none)
     int K, M, n_terms, n_src;
-    int tile;               // samples per wave tile
+    int tile;               // samples per tile
+    int short_tile;         // samples per short tile
     int src_blocks;         // workgroups of the harmonic pass
     int fold_blocks;        // workgroups of the fold pass
 };
@@ -69,16 +91,20 @@ struct SumJob {
     const double *pcoef;
     const void *table;
     const int4 *segs;       // [n_segs]: (m, n_lo, length, first term)
+    const int *chunks;      // [n_chunks + 1]: first segment of each LDS chunk
     const long long *starts;
     const int *tile_pref;
     void *out;
     double t_start, dt;
     long long n;
-    int K, n_terms, n_segs;
-    int wave_base;          // first global wave slot of this job (batched launch)
+    long long short_from;   // first sample cut into short tiles (n: none)
+    int K, n_terms, n_segs, n_chunks;
+    int wave_base;          // first global tile slot of this job (batched launch)
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
+// Binary32 summation workgroups resident at once on the current device.
+int sum_resident_workgroups();
 hipError_t launch_fit(const FitJob &job, hipStream_t stream);
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream);
@@ -98,10 +124,11 @@ constexpr int kMaxSelectModes = 4096;   // LDS: (binary64 key + int index) per p
 // Host core (host_core.cpp): no device work.
 // ---------------------------------------------------------------------------
 struct TermLayout {
-    int n_segs = 0, n_terms = 0, n_src = 0;
+    int n_segs = 0, n_terms = 0, n_src = 0, n_chunks = 0;
     int *segs = nullptr;       // 4 * n_segs
     int *term_ptr = nullptr;   // n_terms + 1
     int *term_src = nullptr;   // 2 * n_src
+    int *chunks = nullptr;     // n_chunks + 1: first segment of each chunk of <= kChunkTerms terms
 };
 
 // Build the folded term layout; returns 0 or a few_status error code.
@@ -117,12 +144,22 @@ inline long long tile_upper_bound(long long n, int K, int tile) {
     return (n + tile - 1) / tile + (K - 1);
 }
 
+// Tiles of a request whose samples from short_from on use short tiles: each
+// interval adds at most one partial tile of each kind.
+inline long long tile_upper_bound2(long long n, long long short_from, int K, int tile,
+                                   int short_tile) {
+    if (short_from >= n) return tile_upper_bound(n, K, tile);
+    return (short_from + tile - 1) / tile + (n - short_from + short_tile - 1) / short_tile +
+           2LL * (K - 1);
+}
+
 // Arena layout of one request's resident state.
 struct ReqLayout {
-    size_t off_t, off_segs, off_term_ptr, off_term_src, upload_end;   // host-staged
+    size_t off_t, off_segs, off_term_ptr, off_term_src, off_chunks, upload_end;   // host-staged
     size_t off_pcoef, off_acoef, off_ybuf, off_table, off_starts, off_tile_pref, total;
 };
-ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src);
+ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
+                         int n_chunks);
 
 // Binary64 sample time exactly as written: t_start + j * dt, no contraction.
 double sample_time(double t_start, double dt, long long j);

@@ -45,6 +45,7 @@ void free_term_layout(TermLayout *t) {
     std::free(t->segs);
     std::free(t->term_ptr);
     std::free(t->term_src);
+    std::free(t->chunks);
     *t = TermLayout{};
 }
 
@@ -85,6 +86,8 @@ int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
         while (q < e.size() && e[q].m == m) {
             int n = e[q].n;
             if (n > n_prev + 1 + max_gap && q != p) break;
+            // no segment longer than one LDS chunk
+            if (q != p && (term - first) + (n - n_prev) > kChunkTerms) break;
             // fill zero terms between n_prev and n
             for (int z = n_prev + 1; z < n; ++z) {
                 term_ptr.push_back((int)src.size() / 2);
@@ -106,25 +109,43 @@ int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
         p = q;
     }
     term_ptr.push_back((int)src.size() / 2);
+    // chunks: runs of whole segments with at most kChunkTerms terms
+    std::vector<int> chunks;
+    chunks.push_back(0);
+    const int n_seg = (int)segs.size() / 4;
+    int run = 0;
+    for (int g = 0; g < n_seg; ++g) {
+        const int len = segs[4 * g + 2];
+        if (run > 0 && run + len > kChunkTerms) {
+            chunks.push_back(g);
+            run = 0;
+        }
+        run += len;
+    }
+    chunks.push_back(n_seg);
+    out->n_chunks = (int)chunks.size() - 1;
     out->n_segs = (int)segs.size() / 4;
     out->n_terms = term;
     out->n_src = (int)src.size() / 2;
     out->segs = (int *)std::malloc(sizeof(int) * segs.size());
     out->term_ptr = (int *)std::malloc(sizeof(int) * term_ptr.size());
     out->term_src = (int *)std::malloc(sizeof(int) * std::max<size_t>(src.size(), 2));
-    if (!out->segs || !out->term_ptr || !out->term_src) {
+    out->chunks = (int *)std::malloc(sizeof(int) * chunks.size());
+    if (!out->segs || !out->term_ptr || !out->term_src || !out->chunks) {
         free_term_layout(out);
         return FEW_E_NOMEM;
     }
     std::memcpy(out->segs, segs.data(), sizeof(int) * segs.size());
     std::memcpy(out->term_ptr, term_ptr.data(), sizeof(int) * term_ptr.size());
     std::memcpy(out->term_src, src.data(), sizeof(int) * src.size());
+    std::memcpy(out->chunks, chunks.data(), sizeof(int) * chunks.size());
     return FEW_OK;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src) {
+ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
+                         int n_chunks) {
     ReqLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -137,7 +158,8 @@ ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n
     L.off_segs = take(sizeof(int) * 4 * (size_t)n_segs);
     L.off_term_ptr = take(sizeof(int) * (size_t)(n_terms + 1));
     L.off_term_src = take(sizeof(int) * 2 * (size_t)std::max(n_src, 1));
-    L.upload_end = L.off_term_src + sizeof(int) * 2 * (size_t)n_src;
+    L.off_chunks = take(sizeof(int) * (size_t)(n_chunks + 1));
+    L.upload_end = L.off_chunks + sizeof(int) * (size_t)(n_chunks + 1);
     // device-produced arrays
     L.off_pcoef = take(sizeof(double) * 16 * (size_t)(K - 1));
     L.off_acoef = take(sizeof(double) * 8 * (size_t)(K - 1) * M);
@@ -188,6 +210,6 @@ extern "C" uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t
                                            int32_t n_terms) {
     if (K < 4 || M < 1 || n_terms < 1) return 0;
     // n_src <= 2M, n_segs <= n_terms
-    ReqLayout L = request_layout(precision == FEW_MIXED, K, M, n_terms, n_terms, 2 * M);
+    ReqLayout L = request_layout(precision == FEW_MIXED, K, M, n_terms, n_terms, 2 * M, n_terms);
     return (uint64_t)L.total;
 }

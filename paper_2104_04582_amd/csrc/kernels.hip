@@ -324,6 +324,15 @@ __device__ long long dev_interval_start(double ti, double t_start, double dt, lo
     return j;
 }
 
+// Tiles of interval i: samples before short_from in long tiles, the rest in
+// short tiles (every tile lies inside one interval).
+__device__ int interval_tiles(const PrepJob &jb, int i) {
+    const long long a = jb.starts[i], e = jb.starts[i + 1];
+    const long long split = min(e, max(a, jb.short_from));
+    return (int)((split - a + jb.tile - 1) / jb.tile +
+                 (e - split + jb.short_tile - 1) / jb.short_tile);
+}
+
 __device__ void prep_intervals(const PrepJob &jb) {
     __shared__ int part[256];
     const int tid = threadIdx.x, bs = blockDim.x;
@@ -341,10 +350,7 @@ __device__ void prep_intervals(const PrepJob &jb) {
     const int per = (P + bs - 1) / bs;
     const int a = tid * per, b = min(a + per, P);
     int local = 0;
-    for (int i = a; i < b; ++i) {
-        long long cnt = jb.starts[i + 1] - jb.starts[i];
-        local += (int)((cnt + jb.tile - 1) / jb.tile);
-    }
+    for (int i = a; i < b; ++i) local += interval_tiles(jb, i);
     // inclusive block scan of the per-lane counts (Hillis-Steele in LDS)
     part[tid] = local;
     __syncthreads();
@@ -358,8 +364,7 @@ __device__ void prep_intervals(const PrepJob &jb) {
     int run = part[tid] - local;
     for (int i = a; i < b; ++i) {
         jb.tile_pref[i] = run;
-        long long cnt = jb.starts[i + 1] - jb.starts[i];
-        run += (int)((cnt + jb.tile - 1) / jb.tile);
+        run += interval_tiles(jb, i);
     }
 }
 
@@ -445,8 +450,10 @@ __global__ __launch_bounds__(256) void fold_batch_kernel(const PrepJob *jobs) {
 }
 
 // ===========================================================================
-// Summation stage.
+// Summation stage.  No contraction: every sample goes through the same rounded
+// operations whatever the tile shape, so results do not depend on tiling.
 // ===========================================================================
+#pragma clang fp contract(off)
 
 // Reduced phases at one sample (both in [-pi, pi]).  pc: the interval's
 // [2][4][2] double-double phase cubic.
@@ -473,168 +480,269 @@ __device__ __forceinline__ void phase_eval(const FEW_AS4 double *pc, dd x, doubl
     }
 }
 
-// One wave tile: samples [j0, j1) of knot interval iv, SL samples per lane.
-template <typename Real, int SL, bool COMP, bool DD>
-__device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int K = jb.K;
+// Per-lane state of SL samples of one tile.
+template <typename Real, int SL>
+struct LaneState {
+    Real u[SL], fr[SL], fi[SL], er[SL], ei[SL];
+    double pf[SL], pr[SL];
+    long long jj[SL];
+    Real hr[SL], hq[SL], cr[SL], cq[SL], zr[SL], zi[SL];
+    int pm, pn;
+};
+
+// Knot interval of tile `local` (tile_pref holds tiles before each interval).
+__device__ __forceinline__ int tile_interval(const SumJob &jb, int local) {
     const FEW_AS4 int *tp = cptr(jb.tile_pref);
-    const int total = tp[K - 1];
-    if (local >= total) return;
-    int lo = 0, hi = K - 2;
+    int lo = 0, hi = jb.K - 2;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (tp[mid] <= local) lo = mid; else hi = mid - 1;
     }
-    const int iv = lo;
-    const FEW_AS4 long long *st = cptr(jb.starts);
-    constexpr int TILE = kWave * SL;
-    const long long j0 = st[iv] + (long long)(local - tp[iv]) * TILE;
-    const long long j1 = min(j0 + (long long)TILE, st[iv + 1]);
+    return lo;
+}
+
+// Per-sample setup: samples j0 + s * 64 + lane (s < SL), valid below j1.
+template <typename Real, int SL, bool DD>
+__device__ __forceinline__ void lane_setup(LaneState<Real, SL> &L, const SumJob &jb, int iv,
+                                           long long j0, long long j1) {
+    const int lane = threadIdx.x & (kWave - 1);
     const FEW_AS4 double *tk = cptr(jb.t);
     const double ti = tk[iv];
     const double inv_h = 1.0 / (tk[iv + 1] - ti);
     const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 16;
-
-    Real u[SL], u2[SL], u3[SL], fr[SL], fi[SL], er[SL], ei[SL];
-    double pf[SL], pr[SL];
-    long long jj[SL];
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
         long long j = j0 + s * kWave + lane;
-        jj[s] = j;
+        L.jj[s] = j;
         if (j >= j1) j = j1 - 1;
         const double tj = dev_sample_time(jb.t_start, jb.dt, j);
         const dd x = two_sum(tj, -ti);
-        phase_eval<DD>(pc, x, &pf[s], &pr[s]);
-        const Real uu = (Real)(x.hi * inv_h);
-        u[s] = uu;
-        u2[s] = uu * uu;
-        u3[s] = u2[s] * uu;
+        phase_eval<DD>(pc, x, &L.pf[s], &L.pr[s]);
+        L.u[s] = (Real)(x.hi * inv_h);
         double sn, cs;
-        sincos(pf[s], &sn, &cs);
-        er[s] = (Real)cs;
-        ei[s] = (Real)(-sn);
-        sincos(pr[s], &sn, &cs);
-        fr[s] = (Real)cs;
-        fi[s] = (Real)(-sn);
+        sincos(L.pf[s], &sn, &cs);
+        L.er[s] = (Real)cs;
+        L.ei[s] = (Real)(-sn);
+        sincos(L.pr[s], &sn, &cs);
+        L.fr[s] = (Real)cs;
+        L.fi[s] = (Real)(-sn);
+        L.hr[s] = L.hq[s] = L.cr[s] = L.cq[s] = (Real)0;
+        L.zr[s] = L.zi[s] = (Real)0;
     }
+    L.pm = INT_MIN / 2;
+    L.pn = INT_MIN / 2;
+}
 
-    Real hr[SL], hq[SL], cr[SL], cq[SL], zr[SL], zi[SL];
+// The 8 coefficients of one term: scalar loads from the constant address space,
+// or two 16-byte LDS reads (every lane of a wave reads the same address, so the
+// LDS broadcasts).
+template <typename Real>
+__device__ __forceinline__ void load_term(const FEW_AS4 Real *cp, Real *c) {
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-        hr[s] = hq[s] = cr[s] = cq[s] = (Real)0;
-        zr[s] = zi[s] = (Real)0;
-    }
+    for (int i = 0; i < 8; ++i) c[i] = cp[i];
+}
 
-    const FEW_AS4 Real *tab = cptr((const Real *)jb.table) + (size_t)iv * jb.n_terms * 8;
-    int pm = INT_MIN / 2, pn = INT_MIN / 2;
-    const int n_segs = jb.n_segs;
-    for (int g = 0; g < n_segs; ++g) {
-        const int4 S = load_uniform(jb.segs + g);
-        if (S.x == pm + 1 && S.y == pn) {
-            // e^{-i((m+1) Phi_phi + n_lo Phi_r)} = seed * e^{-i Phi_phi}
-#pragma unroll
-            for (int s = 0; s < SL; ++s) {
-                const Real a = zr[s] * er[s] - zi[s] * ei[s];
-                const Real b = zr[s] * ei[s] + zi[s] * er[s];
-                zr[s] = a;
-                zi[s] = b;
-            }
-        } else {
-#pragma unroll
-            for (int s = 0; s < SL; ++s) {
-                const double a = d_reduce_2pi((double)S.x * pf[s] + (double)S.y * pr[s]);
-                double sn, cs;
-                sincos(a, &sn, &cs);
-                zr[s] = (Real)cs;
-                zi[s] = (Real)(-sn);
-            }
-        }
-        pm = S.x;
-        pn = S.y;
-        // Horner over the segment's terms in f = e^{-i Phi_r}, highest n first:
-        //   S <- S f + C_n(u),  C_n(u) = c0 + c1 u + c2 u^2 + c3 u^3.
-        Real sr[SL], si[SL];
-#pragma unroll
-        for (int s = 0; s < SL; ++s) sr[s] = si[s] = (Real)0;
-        const FEW_AS4 Real *cp = tab + (size_t)(S.w + S.z - 1) * 8;
-        const int len = S.z;
-#pragma unroll 2
-        for (int q = 0; q < len; ++q) {
-            const Real c0r = cp[0], c0i = cp[1], c1r = cp[2], c1i = cp[3];
-            const Real c2r = cp[4], c2i = cp[5], c3r = cp[6], c3i = cp[7];
-            cp -= 8;
-#pragma unroll
-            for (int s = 0; s < SL; ++s) {
-                Real nr = fmar(sr[s], fr[s], c0r);
-                nr = fmar(-si[s], fi[s], nr);
-                nr = fmar(u[s], c1r, nr);
-                nr = fmar(u2[s], c2r, nr);
-                nr = fmar(u3[s], c3r, nr);
-                Real ni = fmar(sr[s], fi[s], c0i);
-                ni = fmar(si[s], fr[s], ni);
-                ni = fmar(u[s], c1i, ni);
-                ni = fmar(u2[s], c2i, ni);
-                ni = fmar(u3[s], c3i, ni);
-                sr[s] = nr;
-                si[s] = ni;
-            }
-        }
-        // h += seed * S
+__device__ __forceinline__ void load_term(const float *cp, float *c) {
+    const float4 a = *(const float4 *)cp;
+    const float4 b = *(const float4 *)(cp + 4);
+    c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
+    c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+}
+
+// One segment: seed e^{-i(m Phi_phi + n_lo Phi_r)} (chained by e^{-i Phi_phi}
+// when m steps by one at the same n_lo), Horner over its terms in
+// f = e^{-i Phi_r} from the highest n down,
+//   S <- S f + C_n(u),  C_n(u) = c0 + u (c1 + u (c2 + u c3)),
+// then h += seed * S (Kahan-compensated when COMP).  C_n(u) does not depend on
+// S, so only two dependent FMAs per term lie on the recurrence.  `last` points at the
+// 8 values (c0r, c0i, ..., c3i) of the segment's highest-n term; earlier terms
+// precede it at a stride of 8.
+template <typename Real, int SL, bool COMP, typename Ptr>
+__device__ __forceinline__ void seg_step(LaneState<Real, SL> &L, const int4 S, Ptr last) {
+    if (S.x == L.pm + 1 && S.y == L.pn) {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
-            const Real vr = zr[s] * sr[s] - zi[s] * si[s];
-            const Real vi = zr[s] * si[s] + zi[s] * sr[s];
-            if (COMP) {
-                // Kahan-compensated binary32 accumulation across segments
-                const Real yr = vr - cr[s];
-                const Real tr = hr[s] + yr;
-                cr[s] = (tr - hr[s]) - yr;
-                hr[s] = tr;
-                const Real yi = vi - cq[s];
-                const Real ti2 = hq[s] + yi;
-                cq[s] = (ti2 - hq[s]) - yi;
-                hq[s] = ti2;
-            } else {
-                hr[s] += vr;
-                hq[s] += vi;
-            }
+            const Real a = L.zr[s] * L.er[s] - L.zi[s] * L.ei[s];
+            const Real b = L.zr[s] * L.ei[s] + L.zi[s] * L.er[s];
+            L.zr[s] = a;
+            L.zi[s] = b;
         }
+    } else {
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const double a = d_reduce_2pi((double)S.x * L.pf[s] + (double)S.y * L.pr[s]);
+            double sn, cs;
+            sincos(a, &sn, &cs);
+            L.zr[s] = (Real)cs;
+            L.zi[s] = (Real)(-sn);
+        }
+    }
+    L.pm = S.x;
+    L.pn = S.y;
+    Real sr[SL], si[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) sr[s] = si[s] = (Real)0;
+    // the next term's coefficients are loaded while the current one is used
+    // (the last prefetch re-reads the first term, so it stays in bounds)
+    Ptr cp = last;
+    const int len = S.z;
+    Real c[8];
+    load_term(cp, c);
+#pragma unroll FEW_SEG_UNROLL
+    for (int q = 0; q < len; ++q) {
+        const Ptr np = (q + 1 < len) ? cp - 8 : cp;
+        Real cn[8];
+        load_term(np, cn);
+        const Real c0r = c[0], c0i = c[1], c1r = c[2], c1i = c[3];
+        const Real c2r = c[4], c2i = c[5], c3r = c[6], c3i = c[7];
+        cp = np;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const Real u = L.u[s];
+            const Real pr = fmar(fmar(fmar(c3r, u, c2r), u, c1r), u, c0r);
+            const Real pi = fmar(fmar(fmar(c3i, u, c2i), u, c1i), u, c0i);
+            const Real nr = fmar(sr[s], L.fr[s], fmar(-si[s], L.fi[s], pr));
+            const Real ni = fmar(sr[s], L.fi[s], fmar(si[s], L.fr[s], pi));
+            sr[s] = nr;
+            si[s] = ni;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) c[i] = cn[i];
     }
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
-        if (jj[s] < j1) {
-            Real *o = (Real *)jb.out + 2 * jj[s];
+        const Real vr = L.zr[s] * sr[s] - L.zi[s] * si[s];
+        const Real vi = L.zr[s] * si[s] + L.zi[s] * sr[s];
+        if (COMP) {
+            const Real yr = vr - L.cr[s];
+            const Real tr = L.hr[s] + yr;
+            L.cr[s] = (tr - L.hr[s]) - yr;
+            L.hr[s] = tr;
+            const Real yi = vi - L.cq[s];
+            const Real ti2 = L.hq[s] + yi;
+            L.cq[s] = (ti2 - L.hq[s]) - yi;
+            L.hq[s] = ti2;
+        } else {
+            L.hr[s] += vr;
+            L.hq[s] += vi;
+        }
+    }
+}
+
+template <typename Real, int SL, bool COMP>
+__device__ __forceinline__ void lane_store(const LaneState<Real, SL> &L, const SumJob &jb,
+                                           long long j1) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        if (L.jj[s] < j1) {
+            Real *o = (Real *)jb.out + 2 * L.jj[s];
             if (COMP) {
-                o[0] = hr[s] - cr[s];
-                o[1] = hq[s] - cq[s];
+                o[0] = L.hr[s] - L.cr[s];
+                o[1] = L.hq[s] - L.cq[s];
             } else {
-                o[0] = hr[s];
-                o[1] = hq[s];
+                o[0] = L.hr[s];
+                o[1] = L.hq[s];
             }
         }
     }
 }
 
-// Waves are numbered so that each of the 8 XCDs (which receive workgroups
-// round-robin) works on one contiguous eighth of the wave range, i.e. on a
-// few knot intervals whose coefficient tables stay in its own L2.
-__device__ __forceinline__ int xcd_wave_id() {
+// Wave tile (binary64 path): 64 x SL consecutive samples of one interval,
+// coefficients read by scalar loads straight into SGPR operands.
+template <typename Real, int SL, bool COMP, bool DD>
+__device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
+    const FEW_AS4 int *tp = cptr(jb.tile_pref);
+    if (local >= tp[jb.K - 1]) return;
+    const int iv = tile_interval(jb, local);
+    const FEW_AS4 long long *st = cptr(jb.starts);
+    constexpr int TILE = kWave * SL;
+    const long long j0 = st[iv] + (long long)(local - tp[iv]) * TILE;
+    const long long j1 = min(j0 + (long long)TILE, st[iv + 1]);
+    LaneState<Real, SL> L;
+    lane_setup<Real, SL, DD>(L, jb, iv, j0, j1);
+    const FEW_AS4 Real *tab = cptr((const Real *)jb.table) + (size_t)iv * jb.n_terms * 8;
+    for (int g = 0; g < jb.n_segs; ++g) {
+        const int4 S = load_uniform(jb.segs + g);
+        seg_step<Real, SL, COMP>(L, S, tab + (size_t)(S.w + S.z - 1) * 8);
+    }
+    lane_store<Real, SL, COMP>(L, jb, j1);
+}
+
+// Workgroup tile (binary32 path): 4 waves x 64 x SL consecutive samples
+// [base, j1) of interval iv.  The workgroup stages the interval's coefficients
+// in LDS, one chunk of whole segments (at most kChunkTerms terms) at a time, and
+// every wave reads each term with broadcast LDS loads into VGPRs: FMAs without
+// scalar operands issue at twice the rate on gfx950.  Every lane of the
+// workgroup reaches every barrier.
+template <typename Real, int SL, bool COMP, bool DD>
+__device__ __forceinline__ void sum_wg_run(const SumJob &jb, int iv, long long base,
+                                           long long j1, Real *buf) {
+    constexpr int WT = kWave * SL;                  // samples per wave
+    const int wave = threadIdx.x / kWave;
+    // a wave past the end of a partial tile only helps stage coefficients
+    const bool busy = base + (long long)wave * WT < j1;
+    LaneState<Real, SL> L;
+    if (busy) lane_setup<Real, SL, DD>(L, jb, iv, base + (long long)wave * WT, j1);
+    const Real *tab = (const Real *)jb.table + (size_t)iv * jb.n_terms * 8;
+    const FEW_AS4 int *ch = cptr(jb.chunks);
+    for (int c = 0; c < jb.n_chunks; ++c) {
+        const int g0 = ch[c], g1 = ch[c + 1];
+        const int t0 = load_uniform(jb.segs + g0).w;
+        const int4 Sl = load_uniform(jb.segs + g1 - 1);
+        const int nv = (Sl.w + Sl.z - t0) * 8 * (int)sizeof(Real) / 16;
+        __syncthreads();                            // previous chunk fully consumed
+        const float4 *src = (const float4 *)(tab + (size_t)t0 * 8);
+        float4 *dst = (float4 *)buf;
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
+        __syncthreads();
+        if (busy) {
+            for (int g = g0; g < g1; ++g) {
+                const int4 S = load_uniform(jb.segs + g);
+                seg_step<Real, SL, COMP>(L, S, buf + (S.w - t0 + S.z - 1) * 8);
+            }
+        }
+    }
+    if (busy) lane_store<Real, SL, COMP>(L, jb, j1);
+}
+
+// Tile `local` of a request: inside its interval [a, e), long tiles cover
+// [a, split) and short tiles [split, e), split = clamp(short_from, a, e).  The
+// branch is uniform per workgroup.
+template <typename Real, bool COMP, bool DD>
+__device__ __forceinline__ void sum_wg_tile(const SumJob &jb, int local, Real *buf) {
+    const FEW_AS4 int *tp = cptr(jb.tile_pref);
+    if (local >= tp[jb.K - 1]) return;
+    const int iv = tile_interval(jb, local);
+    const FEW_AS4 long long *st = cptr(jb.starts);
+    const long long a = st[iv], e = st[iv + 1];
+    const long long split = min(e, max(a, jb.short_from));
+    constexpr int LT = 4 * kWave * kSamplesPerLaneF32;
+    constexpr int ST = 4 * kWave * kSamplesPerLaneShort;
+    const int n_long = (int)((split - a + LT - 1) / LT);
+    const int r = local - tp[iv];
+    if (r < n_long) {
+        const long long base = a + (long long)r * LT;
+        sum_wg_run<Real, kSamplesPerLaneF32, COMP, DD>(jb, iv, base, min(base + LT, split), buf);
+    } else {
+        const long long base = split + (long long)(r - n_long) * ST;
+        sum_wg_run<Real, kSamplesPerLaneShort, COMP, DD>(jb, iv, base, min(base + ST, e), buf);
+    }
+}
+
+// Workgroups are numbered so that each of the 8 XCDs (which receive workgroups
+// round-robin) works on one contiguous eighth of the range, i.e. on a few knot
+// intervals whose coefficient tables stay in its own L2.
+__device__ __forceinline__ int xcd_block_id() {
     const int nb = gridDim.x;                       // multiple of 8
     const int b = blockIdx.x;
-    const int bb = (b & 7) * (nb >> 3) + (b >> 3);
-    return bb * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-template <typename Real, int SL, bool COMP, bool DD>
-__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_kernel(SumJob jb, int slots) {
-    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
-    if (w >= slots) return;
-    sum_tile<Real, SL, COMP, DD>(jb, w);
+__device__ __forceinline__ int xcd_wave_id() {
+    return xcd_block_id() * (blockDim.x / kWave) + (threadIdx.x / kWave);
 }
 
-// Batched launch: job j owns global wave slots [wave_base_j, wave_base_{j+1}).
+// Batched launch: job j owns slots [wave_base_j, wave_base_{j+1}).
 __device__ __forceinline__ int find_job(const SumJob *jobs, int n_jobs, int w) {
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -643,6 +751,14 @@ __device__ __forceinline__ int find_job(const SumJob *jobs, int n_jobs, int w) {
         if (base <= w) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// ---- binary64: one wave per tile -------------------------------------------
+template <typename Real, int SL, bool COMP, bool DD>
+__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_kernel(SumJob jb, int slots) {
+    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
+    if (w >= slots) return;
+    sum_tile<Real, SL, COMP, DD>(jb, w);
 }
 
 template <typename Real, int SL, bool COMP, bool DD>
@@ -674,6 +790,54 @@ __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_persistent_kernel(const 
         sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
     }
 }
+
+// ---- binary32: one workgroup per tile ---------------------------------------
+// One request: workgroups take tiles in dispatch order, so the short tiles at
+// the end of the request fill the machine while the last long tiles finish.
+// (Every XCD sees every interval; the coefficient tables are small next to L2.)
+template <typename Real, bool COMP, bool DD>
+__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_kernel(SumJob jb, int slots) {
+    extern __shared__ float4 sum_lds[];
+    const int b = blockIdx.x;
+    if (b >= slots) return;
+    sum_wg_tile<Real, COMP, DD>(jb, b, (Real *)sum_lds);
+}
+
+template <typename Real, bool COMP, bool DD>
+__device__ __forceinline__ void sum_wg_slot(const SumJob *jobs, int n_jobs, int b, Real *buf) {
+    const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, b));
+    const SumJob jb = load_uniform(jobs + jx);
+    sum_wg_tile<Real, COMP, DD>(jb, b - jb.wave_base, buf);
+}
+
+template <typename Real, bool COMP, bool DD>
+__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_batch_kernel(const SumJob *jobs, int n_jobs,
+                                                           int slots) {
+    extern __shared__ float4 sum_lds[];
+    const int b = xcd_block_id();
+    if (b >= slots) return;
+    sum_wg_slot<Real, COMP, DD>(jobs, n_jobs, b, (Real *)sum_lds);
+}
+
+// Persistent variant: workgroups pull tile slots from one atomic counter
+// (lane 0 draws, the slot is broadcast through LDS) until all are handed out.
+template <typename Real, bool COMP, bool DD>
+__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_persistent_kernel(const SumJob *jobs,
+                                                                int n_jobs, int slots,
+                                                                unsigned *counter) {
+    extern __shared__ float4 sum_lds[];
+    __shared__ int slot;
+    for (;;) {
+        if (threadIdx.x == 0) slot = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int b = slot;
+        __syncthreads();
+        if (b >= slots) break;
+        sum_wg_slot<Real, COMP, DD>(jobs, n_jobs, b, (Real *)sum_lds);
+    }
+}
+
+#pragma clang fp contract(on)
 
 // ===========================================================================
 // Mode selector (Sec. III D): per knot, order the modes by decreasing power
@@ -796,44 +960,63 @@ hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_src
     return hipGetLastError();
 }
 
-hipError_t launch_sum(const SumJob &job, int wave_slots, bool fp32, hipStream_t stream) {
-    const int waves_per_block = 256 / kWave;
-    dim3 grid(round_up8((wave_slots + waves_per_block - 1) / waves_per_block));
-    if (fp32)
-        hipLaunchKernelGGL((sum_kernel<float, kSamplesPerLaneF32, true, false>), grid, dim3(256),
-                           0, stream, job, wave_slots);
-    else
+static inline size_t sum_lds_bytes() { return sizeof(float) * 8 * (size_t)kChunkTerms; }
+
+int sum_resident_workgroups() {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, (const void *)sum_wg_kernel<float, true, false>, 256, sum_lds_bytes()) !=
+        hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+hipError_t launch_sum(const SumJob &job, int slots, bool fp32, hipStream_t stream) {
+    if (fp32) {
+        hipLaunchKernelGGL((sum_wg_kernel<float, true, false>),
+                           dim3(round_up8(slots)), dim3(256), sum_lds_bytes(), stream, job, slots);
+    } else {
+        const int waves_per_block = 256 / kWave;
+        dim3 grid(round_up8((slots + waves_per_block - 1) / waves_per_block));
         hipLaunchKernelGGL((sum_kernel<double, kSamplesPerLaneF64, false, true>), grid, dim3(256),
-                           0, stream, job, wave_slots);
+                           0, stream, job, slots);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_slots, bool fp32,
+hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_slots, bool fp32,
                             bool persistent, unsigned *counter_dev, hipStream_t stream) {
     const int waves_per_block = 256 / kWave;
     if (!persistent) {
-        dim3 grid(round_up8((total_wave_slots + waves_per_block - 1) / waves_per_block));
         if (fp32)
-            hipLaunchKernelGGL((sum_batch_kernel<float, kSamplesPerLaneF32, true, false>), grid,
-                               dim3(256), 0, stream, jobs_dev, n_jobs, total_wave_slots);
+            hipLaunchKernelGGL((sum_wg_batch_kernel<float, true, false>),
+                               dim3(round_up8(total_slots)), dim3(256), sum_lds_bytes(), stream,
+                               jobs_dev, n_jobs, total_slots);
         else
-            hipLaunchKernelGGL((sum_batch_kernel<double, kSamplesPerLaneF64, false, true>), grid,
-                               dim3(256), 0, stream, jobs_dev, n_jobs, total_wave_slots);
+            hipLaunchKernelGGL((sum_batch_kernel<double, kSamplesPerLaneF64, false, true>),
+                               dim3(round_up8((total_slots + waves_per_block - 1) / waves_per_block)),
+                               dim3(256), 0, stream, jobs_dev, n_jobs, total_slots);
         return hipGetLastError();
     }
-    // one resident grid: 256 CUs x 8 workgroups of 4 waves
-    int blocks = 256 * 8;
-    const int needed = (total_wave_slots + waves_per_block - 1) / waves_per_block;
-    if (blocks > needed) blocks = needed > 0 ? needed : 1;
+    // one resident grid: 256 CUs x 4 workgroups of 4 waves
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, counter_dev, 1);
-    if (fp32)
-        hipLaunchKernelGGL((sum_persistent_kernel<float, kSamplesPerLaneF32, true, false>),
-                           dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs,
-                           total_wave_slots, counter_dev);
-    else
+    if (fp32) {
+        int blocks = 256 * 4;
+        if (blocks > total_slots) blocks = total_slots > 0 ? total_slots : 1;
+        hipLaunchKernelGGL((sum_wg_persistent_kernel<float, true, false>),
+                           dim3(blocks), dim3(256), sum_lds_bytes(), stream, jobs_dev, n_jobs,
+                           total_slots, counter_dev);
+    } else {
+        int blocks = 256 * 8;
+        const int needed = (total_slots + waves_per_block - 1) / waves_per_block;
+        if (blocks > needed) blocks = needed > 0 ? needed : 1;
         hipLaunchKernelGGL((sum_persistent_kernel<double, kSamplesPerLaneF64, false, true>),
-                           dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs,
-                           total_wave_slots, counter_dev);
+                           dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs, total_slots,
+                           counter_dev);
+    }
     return hipGetLastError();
 }
 
