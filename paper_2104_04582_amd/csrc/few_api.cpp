@@ -301,18 +301,25 @@ FitJob fit_job(const HostReq &r, char *base, const double *pp, const double *pr,
     return j;
 }
 
-// First sample of the short-tile region of a single-request launch (binary32):
-// the last FEW_SHORT_QUARTERS / 4 rounds of long tiles over `resident`
-// workgroups.  n means no short tiles (binary64, batched launches).
-long long short_tiles_from(int64_t n, bool fp32, int resident) {
-    if (!fp32 || resident <= 0) return n;
-    const long long region =
-        (long long)resident * tile_samples(true) * FEW_SHORT_QUARTERS / 4;
-    return n > region ? n - region : 0;
+// How a launch cuts a request into tiles: `parts` contiguous sample parts and
+// the short-tile region at the end of each.
+struct Tiling {
+    int parts;
+    long long short_len;
+};
+
+// Single-request launch: one part per XCD; binary32 parts end in short tiles
+// worth FEW_SHORT_QUARTERS / 4 of one round of long tiles over the `resident`
+// workgroups.  Batched launches use Tiling{1, 0}.
+Tiling single_tiling(bool fp32, int resident) {
+    Tiling t{kParts, 0};
+    if (fp32 && resident > 0)
+        t.short_len = (long long)resident * tile_samples(true) * FEW_SHORT_QUARTERS / 4 / kParts;
+    return t;
 }
 
 PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double scale,
-                 double t_start, double dt, int64_t n, bool fp32, long long short_from) {
+                 double t_start, double dt, int64_t n, bool fp32, Tiling tl) {
     PrepJob j{};
     j.t = (const double *)(base + r.L.off_t);
     j.acoef = (const double *)(base + r.L.off_acoef);
@@ -333,15 +340,16 @@ PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double 
     j.n_terms = r.terms.n_terms;
     j.n_src = r.terms.n_src;
     j.tile = tile_samples(fp32);
-    j.short_tile = fp32 ? short_tile_samples() : j.tile;
-    j.short_from = short_from;
+    j.short_tile = short_tile_samples(fp32);
+    j.short_len = tl.short_len;
+    j.parts = tl.parts;
     j.src_blocks = (r.terms.n_src + 255) / 256;
     j.fold_blocks = (int)(((long long)(r.K - 1) * r.terms.n_terms + 255) / 256);
     return j;
 }
 
 SumJob sum_job(const HostReq &r, char *base, double t_start, double dt, int64_t n, void *out,
-               long long short_from) {
+               Tiling tl) {
     SumJob j{};
     j.t = (const double *)(base + r.L.off_t);
     j.pcoef = (const double *)(base + r.L.off_pcoef);
@@ -358,7 +366,8 @@ SumJob sum_job(const HostReq &r, char *base, double t_start, double dt, int64_t 
     j.n_terms = r.terms.n_terms;
     j.n_segs = r.terms.n_segs;
     j.n_chunks = r.terms.n_chunks;
-    j.short_from = short_from;
+    j.short_len = tl.short_len;
+    j.parts = tl.parts;
     j.wave_base = 0;
     return j;
 }
@@ -694,15 +703,16 @@ int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double 
         std::lock_guard<std::mutex> g(p->sync_mu);
         HIP_TRY(hipSetDevice(p->device));
         char *base = p->arena.ptr(s->arena_off);
-        const long long short_from = short_tiles_from(n, p->fp32, p->resident_wg);
-        PrepJob pj = prep_job(s->h, base, theta, phi, scale, t_start, dt, n, p->fp32, short_from);
+        const Tiling tl = single_tiling(p->fp32, p->resident_wg);
+        PrepJob pj = prep_job(s->h, base, theta, phi, scale, t_start, dt, n, p->fp32, tl);
         rc = timed_launch(p, ST_PREP, p->stream,
                           [&] { return launch_prepare(pj, p->fp32, p->stream); });
         if (rc) return rc;
-        SumJob sj = sum_job(s->h, base, t_start, dt, n, out, short_from);
-        long long slots = tile_upper_bound2(n, short_from, s->h.K, tile_samples(p->fp32),
-                                            pj.short_tile);
-        if (slots > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
+        SumJob sj = sum_job(s->h, base, t_start, dt, n, out, tl);
+        // tiles per part; the grid holds parts x slots tiles
+        long long slots = part_tile_bound(n, tl.parts, tl.short_len, s->h.K,
+                                          tile_samples(p->fp32), pj.short_tile);
+        if (slots * tl.parts > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
         return timed_launch(p, ST_SUM, p->stream, [&] {
             return launch_sum(sj, (int)slots, p->fp32, p->stream);
         });
@@ -935,9 +945,9 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         stage_upload(r->h, host + req_off[i]);
         fj[i] = fit_job(r->h, rb, r->r.phi_phi, r->r.phi_r, r->r.amp);
         pj[i] = prep_job(r->h, rb, r->r.theta, r->r.phi, r->r.scale, r->r.t_start, r->r.dt,
-                         r->r.n_samples, fp32, r->r.n_samples);
+                         r->r.n_samples, fp32, Tiling{1, 0});
         sj[i] = sum_job(r->h, rb, r->r.t_start, r->r.dt, r->r.n_samples, r->r.out,
-                        r->r.n_samples);
+                        Tiling{1, 0});
         sj[i].wave_base = (int)waves;
         waves += tile_upper_bound(r->r.n_samples, r->h.K, tile);
         max_amp_blocks = std::max(max_amp_blocks, fj[i].amp_blocks);

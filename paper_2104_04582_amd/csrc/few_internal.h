@@ -36,9 +36,11 @@ inline int tile_samples(bool fp32) {
     return fp32 ? 4 * kWave * kSamplesPerLaneF32 : kWave * kSamplesPerLaneF64;
 }
 
-// binary32: the last samples of a request are cut into short tiles (half the
-// samples per lane) so the end of a launch drains evenly.  The short-tile region holds
-// FEW_SHORT_QUARTERS / 4 of one round of long tiles over the resident workgroups.
+// Binary32: the last samples of a single-request launch are cut into short
+// tiles (half the samples per lane) so the end of the launch drains evenly.
+// The short-tile region holds FEW_SHORT_QUARTERS / 4 of one round of long tiles
+// over the resident workgroups.  (Binary64 tiles read their coefficients with
+// scalar loads, which short tiles amortise poorly: long tiles only.)
 #ifndef FEW_SL_SHORT
 #define FEW_SL_SHORT 2
 #endif
@@ -46,7 +48,9 @@ inline int tile_samples(bool fp32) {
 #define FEW_SHORT_QUARTERS 2
 #endif
 constexpr int kSamplesPerLaneShort = FEW_SL_SHORT;
-inline int short_tile_samples() { return 4 * kWave * kSamplesPerLaneShort; }
+inline int short_tile_samples(bool fp32) {
+    return fp32 ? 4 * kWave * kSamplesPerLaneShort : kWave * kSamplesPerLaneF64;
+}
 
 // ---------------------------------------------------------------------------
 // Device-side job descriptors.  Pointers are device addresses in the plan
@@ -74,10 +78,11 @@ struct PrepJob {
     double2 *ybuf;          // [n_src] harmonic weight of each contributor
     void *table;            // [K-1][n_terms][8] binary32 or binary64
     long long *starts;      // [K]
-    int *tile_pref;         // [K]
+    int *tile_pref;         // [parts][K]: tiles before each interval, per part
     double theta, phi, scale, t_start, dt;
     long long n;
-    long long short_from;   // first sample cut into short tiles (n: none)
+    long long short_len;    // samples at the end of each part cut into short tiles
+    int parts;              // contiguous sample parts (one per XCD) or 1
     int K, M, n_terms, n_src;
     int tile;               // samples per tile
     int short_tile;         // samples per short tile
@@ -97,7 +102,8 @@ struct SumJob {
     void *out;
     double t_start, dt;
     long long n;
-    long long short_from;   // first sample cut into short tiles (n: none)
+    long long short_len;    // samples at the end of each part cut into short tiles
+    int parts;              // contiguous sample parts (one per XCD) or 1
     int K, n_terms, n_segs, n_chunks;
     int wave_base;          // first global tile slot of this job (batched launch)
 };
@@ -144,13 +150,24 @@ inline long long tile_upper_bound(long long n, int K, int tile) {
     return (n + tile - 1) / tile + (K - 1);
 }
 
-// Tiles of a request whose samples from short_from on use short tiles: each
-// interval adds at most one partial tile of each kind.
-inline long long tile_upper_bound2(long long n, long long short_from, int K, int tile,
-                                   int short_tile) {
-    if (short_from >= n) return tile_upper_bound(n, K, tile);
-    return (short_from + tile - 1) / tile + (n - short_from + short_tile - 1) / short_tile +
-           2LL * (K - 1);
+// Single-request launches split the samples into kParts contiguous parts,
+// [floor(p n / kParts), floor((p + 1) n / kParts)), one per XCD, so each XCD
+// reads the coefficient tables of its own intervals only.
+constexpr int kParts = 8;
+
+__host__ __device__ inline long long part_begin(long long n, int parts, int p) {
+    return n * p / parts;
+}
+
+// Tiles of one part (at most ceil(n / parts) samples) whose last short_len
+// samples use short tiles: each interval adds at most one partial tile of
+// each kind.
+inline long long part_tile_bound(long long n, int parts, long long short_len, int K, int tile,
+                                 int short_tile) {
+    const long long len = (n + parts - 1) / parts;
+    if (short_len <= 0) return tile_upper_bound(len, K, tile);
+    const long long s = short_len < len ? short_len : len;
+    return (len + tile - 1) / tile + (s + short_tile - 1) / short_tile + 2LL * (K - 1);
 }
 
 // Arena layout of one request's resident state.

@@ -166,7 +166,7 @@ ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n
     L.off_ybuf = take(sizeof(double) * 2 * (size_t)std::max(n_src, 1));
     L.off_table = take((fp32 ? 4 : 8) * 8 * (size_t)(K - 1) * n_terms);
     L.off_starts = take(sizeof(long long) * K);
-    L.off_tile_pref = take(sizeof(int) * K);
+    L.off_tile_pref = take(sizeof(int) * kParts * (size_t)K);
     L.total = o;
     return L;
 }

@@ -27,12 +27,20 @@ namespace few {
 
 #define FEW_AS4 __attribute__((address_space(4)))
 
-// Optional minimum waves per SIMD for the summation kernels (register cap).
+// Optional minimum waves per SIMD (register cap) for the binary32 and the
+// binary64 summation kernels.
 #ifdef FEW_SUM_WAVES
 #define FEW_SUM_ATTR __attribute__((amdgpu_waves_per_eu(FEW_SUM_WAVES)))
 #else
 #define FEW_SUM_ATTR
 #endif
+// Binary64: the five-FMA chains per component need more waves in flight than
+// the register count alone allows (4 per SIMD); 5 costs one spill outside the
+// term loop.
+#ifndef FEW_F64_WAVES
+#define FEW_F64_WAVES 5
+#endif
+#define FEW_F64_ATTR __attribute__((amdgpu_waves_per_eu(FEW_F64_WAVES)))
 
 // Wave-uniform read-only data: the constant address space makes the compiler
 // use scalar loads (SGPR destinations) for uniform addresses.
@@ -324,13 +332,28 @@ __device__ long long dev_interval_start(double ti, double t_start, double dt, lo
     return j;
 }
 
-// Tiles of interval i: samples before short_from in long tiles, the rest in
-// short tiles (every tile lies inside one interval).
-__device__ int interval_tiles(const PrepJob &jb, int i) {
-    const long long a = jb.starts[i], e = jb.starts[i + 1];
-    const long long split = min(e, max(a, jb.short_from));
-    return (int)((split - a + jb.tile - 1) / jb.tile +
-                 (e - split + jb.short_tile - 1) / jb.short_tile);
+// Samples of part p that lie in interval i, [lo, hi), and where its short
+// tiles start (every tile lies inside one interval and one part).
+struct PieceRange {
+    long long lo, hi, split;
+};
+
+__device__ __forceinline__ PieceRange piece_range(long long a, long long e, long long n,
+                                                  int parts, int p, long long short_len) {
+    const long long b0 = part_begin(n, parts, p), b1 = part_begin(n, parts, p + 1);
+    PieceRange r;
+    r.lo = max(a, b0);
+    r.hi = max(r.lo, min(e, b1));
+    const long long s0 = b1 - min(b1 - b0, short_len);
+    r.split = min(r.hi, max(r.lo, s0));
+    return r;
+}
+
+__device__ int piece_tiles(const PrepJob &jb, int p, int i) {
+    const PieceRange r = piece_range(jb.starts[i], jb.starts[i + 1], jb.n, jb.parts, p,
+                                     jb.short_len);
+    return (int)((r.split - r.lo + jb.tile - 1) / jb.tile +
+                 (r.hi - r.split + jb.short_tile - 1) / jb.short_tile);
 }
 
 __device__ void prep_intervals(const PrepJob &jb) {
@@ -345,26 +368,30 @@ __device__ void prep_intervals(const PrepJob &jb) {
         jb.starts[i] = s;
     }
     __syncthreads();
-    // tiles per interval, exclusive prefix by runs of consecutive intervals
+    // per part: tiles per interval, exclusive prefix by runs of intervals
     const int P = K - 1;
     const int per = (P + bs - 1) / bs;
     const int a = tid * per, b = min(a + per, P);
-    int local = 0;
-    for (int i = a; i < b; ++i) local += interval_tiles(jb, i);
-    // inclusive block scan of the per-lane counts (Hillis-Steele in LDS)
-    part[tid] = local;
-    __syncthreads();
-    for (int off = 1; off < bs; off <<= 1) {
-        const int v = (tid >= off) ? part[tid - off] : 0;
+    for (int pt = 0; pt < jb.parts; ++pt) {
+        int *tp = jb.tile_pref + (size_t)pt * K;
+        int local = 0;
+        for (int i = a; i < b; ++i) local += piece_tiles(jb, pt, i);
+        // inclusive block scan of the per-lane counts (Hillis-Steele in LDS)
         __syncthreads();
-        part[tid] += v;
+        part[tid] = local;
         __syncthreads();
-    }
-    if (tid == bs - 1) jb.tile_pref[P] = part[tid];
-    int run = part[tid] - local;
-    for (int i = a; i < b; ++i) {
-        jb.tile_pref[i] = run;
-        run += interval_tiles(jb, i);
+        for (int off = 1; off < bs; off <<= 1) {
+            const int v = (tid >= off) ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += v;
+            __syncthreads();
+        }
+        if (tid == bs - 1) tp[P] = part[tid];
+        int run = part[tid] - local;
+        for (int i = a; i < b; ++i) {
+            tp[i] = run;
+            run += piece_tiles(jb, pt, i);
+        }
     }
 }
 
@@ -490,10 +517,9 @@ struct LaneState {
     int pm, pn;
 };
 
-// Knot interval of tile `local` (tile_pref holds tiles before each interval).
-__device__ __forceinline__ int tile_interval(const SumJob &jb, int local) {
-    const FEW_AS4 int *tp = cptr(jb.tile_pref);
-    int lo = 0, hi = jb.K - 2;
+// Knot interval of tile `local` (tp: tiles before each interval of one part).
+__device__ __forceinline__ int tile_interval(const FEW_AS4 int *tp, int K, int local) {
+    int lo = 0, hi = K - 2;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (tp[mid] <= local) lo = mid; else hi = mid - 1;
@@ -552,11 +578,13 @@ __device__ __forceinline__ void load_term(const float *cp, float *c) {
 // One segment: seed e^{-i(m Phi_phi + n_lo Phi_r)} (chained by e^{-i Phi_phi}
 // when m steps by one at the same n_lo), Horner over its terms in
 // f = e^{-i Phi_r} from the highest n down,
-//   S <- S f + C_n(u),  C_n(u) = c0 + u (c1 + u (c2 + u c3)),
-// then h += seed * S (Kahan-compensated when COMP).  C_n(u) does not depend on
-// S, so only two dependent FMAs per term lie on the recurrence.  `last` points at the
-// 8 values (c0r, c0i, ..., c3i) of the segment's highest-n term; earlier terms
-// precede it at a stride of 8.
+//   S <- S f + C_n(u),  C_n(u) = c0 + c1 u + c2 u^2 + c3 u^3,
+// then h += seed * S (Kahan-compensated when COMP).  `last` points at the 8
+// values (c0r, c0i, ..., c3i) of the segment's highest-n term; earlier terms
+// precede it at a stride of 8.  Binary32 (coefficients in VGPRs) evaluates
+// C_n(u) by Horner in u apart from the recurrence, leaving two dependent FMAs
+// per term on it; binary64 (coefficients in SGPRs, one scalar operand per
+// instruction) chains all five FMAs of each component into the recurrence.
 template <typename Real, int SL, bool COMP, typename Ptr>
 __device__ __forceinline__ void seg_step(LaneState<Real, SL> &L, const int4 S, Ptr last) {
     if (S.x == L.pm + 1 && S.y == L.pn) {
@@ -599,10 +627,27 @@ __device__ __forceinline__ void seg_step(LaneState<Real, SL> &L, const int4 S, P
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const Real u = L.u[s];
-            const Real pr = fmar(fmar(fmar(c3r, u, c2r), u, c1r), u, c0r);
-            const Real pi = fmar(fmar(fmar(c3i, u, c2i), u, c1i), u, c0i);
-            const Real nr = fmar(sr[s], L.fr[s], fmar(-si[s], L.fi[s], pr));
-            const Real ni = fmar(sr[s], L.fi[s], fmar(si[s], L.fr[s], pi));
+            Real nr, ni;
+            if constexpr (sizeof(Real) == 4) {
+                // coefficients in VGPRs: cubic first, two FMAs on the recurrence
+                const Real pr = fmar(fmar(fmar(c3r, u, c2r), u, c1r), u, c0r);
+                const Real pi = fmar(fmar(fmar(c3i, u, c2i), u, c1i), u, c0i);
+                nr = fmar(sr[s], L.fr[s], fmar(-si[s], L.fi[s], pr));
+                ni = fmar(sr[s], L.fi[s], fmar(si[s], L.fr[s], pi));
+            } else {
+                // coefficients in SGPRs: one scalar operand per FMA
+                const Real u2 = u * u, u3 = u2 * u;
+                nr = fmar(sr[s], L.fr[s], c0r);
+                nr = fmar(-si[s], L.fi[s], nr);
+                nr = fmar(u, c1r, nr);
+                nr = fmar(u2, c2r, nr);
+                nr = fmar(u3, c3r, nr);
+                ni = fmar(sr[s], L.fi[s], c0i);
+                ni = fmar(si[s], L.fr[s], ni);
+                ni = fmar(u, c1i, ni);
+                ni = fmar(u2, c2i, ni);
+                ni = fmar(u3, c3i, ni);
+            }
             sr[s] = nr;
             si[s] = ni;
         }
@@ -647,17 +692,11 @@ __device__ __forceinline__ void lane_store(const LaneState<Real, SL> &L, const S
     }
 }
 
-// Wave tile (binary64 path): 64 x SL consecutive samples of one interval,
-// coefficients read by scalar loads straight into SGPR operands.
+// Wave tile (binary64 path): 64 x SL consecutive samples [j0, j1) of interval
+// iv, coefficients read by scalar loads straight into SGPR operands.
 template <typename Real, int SL, bool COMP, bool DD>
-__device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
-    const FEW_AS4 int *tp = cptr(jb.tile_pref);
-    if (local >= tp[jb.K - 1]) return;
-    const int iv = tile_interval(jb, local);
-    const FEW_AS4 long long *st = cptr(jb.starts);
-    constexpr int TILE = kWave * SL;
-    const long long j0 = st[iv] + (long long)(local - tp[iv]) * TILE;
-    const long long j1 = min(j0 + (long long)TILE, st[iv + 1]);
+__device__ __forceinline__ void sum_wave_run(const SumJob &jb, int iv, long long j0,
+                                             long long j1) {
     LaneState<Real, SL> L;
     lane_setup<Real, SL, DD>(L, jb, iv, j0, j1);
     const FEW_AS4 Real *tab = cptr((const Real *)jb.table) + (size_t)iv * jb.n_terms * 8;
@@ -666,6 +705,20 @@ __device__ __forceinline__ void sum_tile(const SumJob &jb, int local) {
         seg_step<Real, SL, COMP>(L, S, tab + (size_t)(S.w + S.z - 1) * 8);
     }
     lane_store<Real, SL, COMP>(L, jb, j1);
+}
+
+// Wave tile `local` of part `pt` of a request (binary64 launches use long
+// tiles only).
+template <typename Real, bool COMP, bool DD>
+__device__ __forceinline__ void sum_tile(const SumJob &jb, int pt, int local) {
+    const FEW_AS4 int *tp = cptr(jb.tile_pref) + (size_t)pt * jb.K;
+    if (local >= tp[jb.K - 1]) return;
+    const int iv = tile_interval(tp, jb.K, local);
+    const FEW_AS4 long long *st = cptr(jb.starts);
+    const PieceRange pr = piece_range(st[iv], st[iv + 1], jb.n, jb.parts, pt, 0);
+    constexpr int LT = kWave * kSamplesPerLaneF64;
+    const long long j0 = pr.lo + (long long)(local - tp[iv]) * LT;
+    sum_wave_run<Real, kSamplesPerLaneF64, COMP, DD>(jb, iv, j0, min(j0 + LT, pr.hi));
 }
 
 // Workgroup tile (binary32 path): 4 waves x 64 x SL consecutive samples
@@ -705,27 +758,28 @@ __device__ __forceinline__ void sum_wg_run(const SumJob &jb, int iv, long long b
     if (busy) lane_store<Real, SL, COMP>(L, jb, j1);
 }
 
-// Tile `local` of a request: inside its interval [a, e), long tiles cover
-// [a, split) and short tiles [split, e), split = clamp(short_from, a, e).  The
-// branch is uniform per workgroup.
+// Tile `local` of part `pt` of a request: the part's samples in its interval,
+// [lo, hi), are covered by long tiles up to `split` and short tiles after it.
+// The branch is uniform per workgroup.
 template <typename Real, bool COMP, bool DD>
-__device__ __forceinline__ void sum_wg_tile(const SumJob &jb, int local, Real *buf) {
-    const FEW_AS4 int *tp = cptr(jb.tile_pref);
+__device__ __forceinline__ void sum_wg_tile(const SumJob &jb, int pt, int local, Real *buf) {
+    const FEW_AS4 int *tp = cptr(jb.tile_pref) + (size_t)pt * jb.K;
     if (local >= tp[jb.K - 1]) return;
-    const int iv = tile_interval(jb, local);
+    const int iv = tile_interval(tp, jb.K, local);
     const FEW_AS4 long long *st = cptr(jb.starts);
-    const long long a = st[iv], e = st[iv + 1];
-    const long long split = min(e, max(a, jb.short_from));
+    const PieceRange pr = piece_range(st[iv], st[iv + 1], jb.n, jb.parts, pt, jb.short_len);
     constexpr int LT = 4 * kWave * kSamplesPerLaneF32;
     constexpr int ST = 4 * kWave * kSamplesPerLaneShort;
-    const int n_long = (int)((split - a + LT - 1) / LT);
+    const int n_long = (int)((pr.split - pr.lo + LT - 1) / LT);
     const int r = local - tp[iv];
     if (r < n_long) {
-        const long long base = a + (long long)r * LT;
-        sum_wg_run<Real, kSamplesPerLaneF32, COMP, DD>(jb, iv, base, min(base + LT, split), buf);
+        const long long base = pr.lo + (long long)r * LT;
+        sum_wg_run<Real, kSamplesPerLaneF32, COMP, DD>(jb, iv, base, min(base + LT, pr.split),
+                                                       buf);
     } else {
-        const long long base = split + (long long)(r - n_long) * ST;
-        sum_wg_run<Real, kSamplesPerLaneShort, COMP, DD>(jb, iv, base, min(base + ST, e), buf);
+        const long long base = pr.split + (long long)(r - n_long) * ST;
+        sum_wg_run<Real, kSamplesPerLaneShort, COMP, DD>(jb, iv, base, min(base + ST, pr.hi),
+                                                         buf);
     }
 }
 
@@ -754,32 +808,38 @@ __device__ __forceinline__ int find_job(const SumJob *jobs, int n_jobs, int w) {
 }
 
 // ---- binary64: one wave per tile -------------------------------------------
-template <typename Real, int SL, bool COMP, bool DD>
-__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_kernel(SumJob jb, int slots) {
-    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
+// One request: workgroup b runs on XCD b mod 8 (workgroups are dealt to the
+// XCDs in turn), so part b mod parts is that XCD's; its waves take the part's
+// tiles in dispatch order.  `slots`: wave tiles per part.
+template <typename Real, bool COMP, bool DD>
+__global__ __launch_bounds__(256) FEW_F64_ATTR void sum_kernel(SumJob jb, int slots) {
+    const int b = blockIdx.x;
+    const int pt = b % jb.parts;
+    const int w = __builtin_amdgcn_readfirstlane(
+        (int)((b / jb.parts) * (blockDim.x / kWave) + threadIdx.x / kWave));
     if (w >= slots) return;
-    sum_tile<Real, SL, COMP, DD>(jb, w);
+    sum_tile<Real, COMP, DD>(jb, pt, w);
 }
 
-template <typename Real, int SL, bool COMP, bool DD>
+template <typename Real, bool COMP, bool DD>
 __device__ __forceinline__ void sum_slot(const SumJob *jobs, int n_jobs, int w) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, w));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_tile<Real, SL, COMP, DD>(jb, w - jb.wave_base);
+    sum_tile<Real, COMP, DD>(jb, 0, w - jb.wave_base);
 }
 
-template <typename Real, int SL, bool COMP, bool DD>
-__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_batch_kernel(const SumJob *jobs, int n_jobs,
+template <typename Real, bool COMP, bool DD>
+__global__ __launch_bounds__(256) FEW_F64_ATTR void sum_batch_kernel(const SumJob *jobs, int n_jobs,
                                                         int slots) {
     const int w = __builtin_amdgcn_readfirstlane(xcd_wave_id());
     if (w >= slots) return;
-    sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
+    sum_slot<Real, COMP, DD>(jobs, n_jobs, w);
 }
 
 // Persistent variant: a fixed grid of waves pulls wave slots from one atomic
 // counter until all `slots` are handed out; every wave then exits.
-template <typename Real, int SL, bool COMP, bool DD>
-__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_persistent_kernel(const SumJob *jobs, int n_jobs,
+template <typename Real, bool COMP, bool DD>
+__global__ __launch_bounds__(256) FEW_F64_ATTR void sum_persistent_kernel(const SumJob *jobs, int n_jobs,
                                                              int slots, unsigned *counter) {
     const int lane = threadIdx.x & (kWave - 1);
     for (;;) {
@@ -787,27 +847,29 @@ __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_persistent_kernel(const 
         if (lane == 0) v = atomicAdd(counter, 1u);
         const int w = __builtin_amdgcn_readfirstlane((int)v);
         if (w >= slots) break;
-        sum_slot<Real, SL, COMP, DD>(jobs, n_jobs, w);
+        sum_slot<Real, COMP, DD>(jobs, n_jobs, w);
     }
 }
 
 // ---- binary32: one workgroup per tile ---------------------------------------
-// One request: workgroups take tiles in dispatch order, so the short tiles at
-// the end of the request fill the machine while the last long tiles finish.
-// (Every XCD sees every interval; the coefficient tables are small next to L2.)
+// One request: workgroup b runs on XCD b mod 8, takes part b mod parts and
+// that part's tiles in dispatch order, so each XCD reads the coefficients of its
+// own intervals and ends on its short tiles while its last long tiles finish.
+// `slots`: tiles per part.
 template <typename Real, bool COMP, bool DD>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_kernel(SumJob jb, int slots) {
     extern __shared__ float4 sum_lds[];
     const int b = blockIdx.x;
-    if (b >= slots) return;
-    sum_wg_tile<Real, COMP, DD>(jb, b, (Real *)sum_lds);
+    const int local = b / jb.parts;
+    if (local >= slots) return;
+    sum_wg_tile<Real, COMP, DD>(jb, b % jb.parts, local, (Real *)sum_lds);
 }
 
 template <typename Real, bool COMP, bool DD>
 __device__ __forceinline__ void sum_wg_slot(const SumJob *jobs, int n_jobs, int b, Real *buf) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, b));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_wg_tile<Real, COMP, DD>(jb, b - jb.wave_base, buf);
+    sum_wg_tile<Real, COMP, DD>(jb, 0, b - jb.wave_base, buf);
 }
 
 template <typename Real, bool COMP, bool DD>
@@ -975,14 +1037,15 @@ int sum_resident_workgroups() {
 }
 
 hipError_t launch_sum(const SumJob &job, int slots, bool fp32, hipStream_t stream) {
+    const long long parts = job.parts;
     if (fp32) {
-        hipLaunchKernelGGL((sum_wg_kernel<float, true, false>),
-                           dim3(round_up8(slots)), dim3(256), sum_lds_bytes(), stream, job, slots);
+        hipLaunchKernelGGL((sum_wg_kernel<float, true, false>), dim3((unsigned)(parts * slots)),
+                           dim3(256), sum_lds_bytes(), stream, job, slots);
     } else {
         const int waves_per_block = 256 / kWave;
-        dim3 grid(round_up8((slots + waves_per_block - 1) / waves_per_block));
-        hipLaunchKernelGGL((sum_kernel<double, kSamplesPerLaneF64, false, true>), grid, dim3(256),
-                           0, stream, job, slots);
+        const long long blocks = (slots + waves_per_block - 1) / waves_per_block;
+        hipLaunchKernelGGL((sum_kernel<double, false, true>), dim3((unsigned)(parts * blocks)),
+                           dim3(256), 0, stream, job, slots);
     }
     return hipGetLastError();
 }
@@ -996,7 +1059,7 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_slots,
                                dim3(round_up8(total_slots)), dim3(256), sum_lds_bytes(), stream,
                                jobs_dev, n_jobs, total_slots);
         else
-            hipLaunchKernelGGL((sum_batch_kernel<double, kSamplesPerLaneF64, false, true>),
+            hipLaunchKernelGGL((sum_batch_kernel<double, false, true>),
                                dim3(round_up8((total_slots + waves_per_block - 1) / waves_per_block)),
                                dim3(256), 0, stream, jobs_dev, n_jobs, total_slots);
         return hipGetLastError();
@@ -1013,7 +1076,7 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_slots,
         int blocks = 256 * 8;
         const int needed = (total_slots + waves_per_block - 1) / waves_per_block;
         if (blocks > needed) blocks = needed > 0 ? needed : 1;
-        hipLaunchKernelGGL((sum_persistent_kernel<double, kSamplesPerLaneF64, false, true>),
+        hipLaunchKernelGGL((sum_persistent_kernel<double, false, true>),
                            dim3(blocks), dim3(256), 0, stream, jobs_dev, n_jobs, total_slots,
                            counter_dev);
     }
