@@ -135,15 +135,25 @@ def host_threads() -> int:
     return max(1, min(n, 16))
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_2104_04582_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2104_04582_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sum_kernel_traffic.txt")
+
+
+def sources_digest() -> str:
+    """sha256 over the native sources (file names and contents, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per launch of the summation kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that summary was
-    taken on a different kernel source than the one built now."""
-    import hashlib
+    taken on different native sources than the ones built now."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
@@ -151,8 +161,7 @@ def measured_traffic():
         if ":" in line and not line.lstrip().startswith("#"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if fields.get("kernels_sha256") != digest:
+    if fields.get("sources_sha256") != sources_digest():
         return None
     try:
         return float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])
@@ -351,7 +360,7 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VALU,
                      "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU,
                      "traffic": measured_traffic(),
-                     "kernel": "sum_kernel<float>",
+                     "kernel": "sum_wg_kernel<float>",
                      "flop_per_launch": flops, "launch_ms": m["sum_ms"]},
         "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
                  "sum_ms": res["fp64"]["sum_ms"], "sum_tflops": res["fp64"]["sum_tflops"],
