@@ -208,7 +208,9 @@ void stage_upload(const HostReq &r, char *dst) {
 }
 
 // Recently used term layouts, keyed by the full mode list (an MCMC client
-// resubmits the same mode set many times; sorting it costs ~1 ms per call).
+// resubmits the same mode sets many times; building a layout costs ~0.1 ms at
+// 3843 modes).  Most recently used first; entries are matched by a hash of the
+// list, then by the list itself.
 class LayoutCache {
   public:
     ~LayoutCache() {
@@ -216,10 +218,11 @@ class LayoutCache {
     }
     // Fill *out with an owned copy of the layout of (M, lmn).
     int get(int M, const int32_t *lmn, TermLayout *out) {
+        const uint64_t h = hash(M, lmn);
         std::lock_guard<std::mutex> g(mu_);
         for (size_t i = 0; i < entries_.size(); ++i) {
             Entry &e = entries_[i];
-            if ((int)e.lmn.size() == 3 * M &&
+            if (e.hash == h && (int)e.lmn.size() == 3 * M &&
                 std::memcmp(e.lmn.data(), lmn, sizeof(int32_t) * 3 * (size_t)M) == 0) {
                 int rc = copy(e.layout, out);
                 if (!rc && i != 0) std::rotate(entries_.begin(), entries_.begin() + i,
@@ -239,16 +242,27 @@ class LayoutCache {
             free_term_layout(&entries_.back().layout);
             entries_.pop_back();
         }
-        entries_.insert(entries_.begin(), Entry{std::vector<int32_t>(lmn, lmn + 3 * (size_t)M), L});
+        entries_.insert(entries_.begin(),
+                        Entry{h, std::vector<int32_t>(lmn, lmn + 3 * (size_t)M), L});
         return FEW_OK;
     }
 
   private:
-    static constexpr size_t kCap = 8;
+    static constexpr size_t kCap = 256;
     struct Entry {
+        uint64_t hash;
         std::vector<int32_t> lmn;
         TermLayout layout;
     };
+    // FNV-1a over the 32-bit words of the list
+    static uint64_t hash(int M, const int32_t *lmn) {
+        uint64_t h = 1469598103934665603ULL;
+        for (size_t i = 0; i < 3 * (size_t)M; ++i) {
+            h ^= (uint32_t)lmn[i];
+            h *= 1099511628211ULL;
+        }
+        return h;
+    }
     static int copy(const TermLayout &a, TermLayout *b) {
         *b = TermLayout{};
         b->n_segs = a.n_segs;
@@ -286,15 +300,36 @@ int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, 
     return FEW_OK;
 }
 
-FitJob fit_job(const HostReq &r, char *base, const double *pp, const double *pr,
+// Where one request's arrays live on the device: the host-uploaded arrays
+// ([0, dev_begin) of its layout) at `up`, the device-produced ones at `dev`.
+// A request in one block has dev = up + dev_begin; a batch packs every
+// request's upload region together so one small copy stages them all.
+struct ReqBase {
+    char *up, *dev;
+};
+
+ReqBase one_block(const HostReq &r, char *base) { return {base, base + r.L.dev_begin}; }
+
+template <class T>
+T *at_up(const HostReq &r, ReqBase b, size_t off) {
+    (void)r;
+    return (T *)(b.up + off);
+}
+
+template <class T>
+T *at_dev(const HostReq &r, ReqBase b, size_t off) {
+    return (T *)(b.dev + (off - r.L.dev_begin));
+}
+
+FitJob fit_job(const HostReq &r, ReqBase base, const double *pp, const double *pr,
                const double *amp) {
     FitJob j{};
-    j.t = (const double *)(base + r.L.off_t);
+    j.t = at_up<const double>(r, base, r.L.off_t);
     j.phi_phi = pp;
     j.phi_r = pr;
     j.amp = amp;
-    j.pcoef = (double *)(base + r.L.off_pcoef);
-    j.acoef = (double *)(base + r.L.off_acoef);
+    j.pcoef = at_dev<double>(r, base, r.L.off_pcoef);
+    j.acoef = at_dev<double>(r, base, r.L.off_acoef);
     j.K = r.K;
     j.M = r.M;
     j.amp_blocks = (2 * r.M + 255) / 256;
@@ -318,17 +353,17 @@ Tiling single_tiling(bool fp32, int resident) {
     return t;
 }
 
-PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double scale,
+PrepJob prep_job(const HostReq &r, ReqBase base, double theta, double phi, double scale,
                  double t_start, double dt, int64_t n, bool fp32, Tiling tl) {
     PrepJob j{};
-    j.t = (const double *)(base + r.L.off_t);
-    j.acoef = (const double *)(base + r.L.off_acoef);
-    j.term_ptr = (const int *)(base + r.L.off_term_ptr);
-    j.term_src = (const int2 *)(base + r.L.off_term_src);
-    j.ybuf = (double2 *)(base + r.L.off_ybuf);
-    j.table = base + r.L.off_table;
-    j.starts = (long long *)(base + r.L.off_starts);
-    j.tile_pref = (int *)(base + r.L.off_tile_pref);
+    j.t = at_up<const double>(r, base, r.L.off_t);
+    j.acoef = at_dev<const double>(r, base, r.L.off_acoef);
+    j.term_ptr = at_up<const int>(r, base, r.L.off_term_ptr);
+    j.term_src = at_up<const int2>(r, base, r.L.off_term_src);
+    j.ybuf = at_dev<double2>(r, base, r.L.off_ybuf);
+    j.table = at_dev<char>(r, base, r.L.off_table);
+    j.starts = at_dev<long long>(r, base, r.L.off_starts);
+    j.tile_pref = at_dev<int>(r, base, r.L.off_tile_pref);
     j.theta = theta;
     j.phi = phi;
     j.scale = scale;
@@ -348,16 +383,16 @@ PrepJob prep_job(const HostReq &r, char *base, double theta, double phi, double 
     return j;
 }
 
-SumJob sum_job(const HostReq &r, char *base, double t_start, double dt, int64_t n, void *out,
+SumJob sum_job(const HostReq &r, ReqBase base, double t_start, double dt, int64_t n, void *out,
                Tiling tl) {
     SumJob j{};
-    j.t = (const double *)(base + r.L.off_t);
-    j.pcoef = (const double *)(base + r.L.off_pcoef);
-    j.table = base + r.L.off_table;
-    j.segs = (const int4 *)(base + r.L.off_segs);
-    j.chunks = (const int *)(base + r.L.off_chunks);
-    j.starts = (const long long *)(base + r.L.off_starts);
-    j.tile_pref = (const int *)(base + r.L.off_tile_pref);
+    j.t = at_up<const double>(r, base, r.L.off_t);
+    j.pcoef = at_dev<const double>(r, base, r.L.off_pcoef);
+    j.table = at_dev<char>(r, base, r.L.off_table);
+    j.segs = at_up<const int4>(r, base, r.L.off_segs);
+    j.chunks = at_up<const int>(r, base, r.L.off_chunks);
+    j.starts = at_dev<const long long>(r, base, r.L.off_starts);
+    j.tile_pref = at_dev<const int>(r, base, r.L.off_tile_pref);
     j.out = out;
     j.t_start = t_start;
     j.dt = dt;
@@ -645,7 +680,7 @@ int32_t few_spline_fit(few_plan p, int32_t K, const double *t_knots, const doubl
         char *base = p->arena.ptr(s->arena_off);
         rc = sync_upload(p, s->h, base);
         if (!rc) {
-            FitJob job = fit_job(s->h, base, phi_phi, phi_r, amp);
+            FitJob job = fit_job(s->h, one_block(s->h, base), phi_phi, phi_r, amp);
             rc = timed_launch(p, ST_FIT, p->stream, [&] { return launch_fit(job, p->stream); });
         }
         if (rc) {
@@ -704,11 +739,12 @@ int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double 
         HIP_TRY(hipSetDevice(p->device));
         char *base = p->arena.ptr(s->arena_off);
         const Tiling tl = single_tiling(p->fp32, p->resident_wg);
-        PrepJob pj = prep_job(s->h, base, theta, phi, scale, t_start, dt, n, p->fp32, tl);
+        PrepJob pj = prep_job(s->h, one_block(s->h, base), theta, phi, scale, t_start, dt, n,
+                              p->fp32, tl);
         rc = timed_launch(p, ST_PREP, p->stream,
                           [&] { return launch_prepare(pj, p->fp32, p->stream); });
         if (rc) return rc;
-        SumJob sj = sum_job(s->h, base, t_start, dt, n, out, tl);
+        SumJob sj = sum_job(s->h, one_block(s->h, base), t_start, dt, n, out, tl);
         // tiles per part; the grid holds parts x slots tiles
         long long slots = part_tile_bound(n, tl.parts, tl.short_len, s->h.K,
                                           tile_samples(p->fp32), pj.short_tile);
@@ -915,19 +951,24 @@ namespace {
 // Build and launch one batch on stream slot `slot`.  Called without p->mu held.
 int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
     const int n = (int)b->reqs.size();
-    // arena block: [FitJob[n] | PrepJob[n] | SumJob[n] | per-request uploads | rest]
+    // arena block: [FitJob[n] | PrepJob[n] | SumJob[n] | upload region of every
+    // request | device-produced region of every request]; one copy stages the
+    // job arrays and all upload regions
     size_t off_fit = 0;
     size_t off_prep = (off_fit + sizeof(FitJob) * n + 255) & ~(size_t)255;
     size_t off_sum = (off_prep + sizeof(PrepJob) * n + 255) & ~(size_t)255;
     size_t cur = (off_sum + sizeof(SumJob) * n + 255) & ~(size_t)255;
-    std::vector<size_t> req_off(n);
+    std::vector<size_t> up_off(n), dev_off(n);
     for (int i = 0; i < n; ++i) {
-        req_off[i] = cur;
-        cur += (b->reqs[i]->h.L.total + 255) & ~(size_t)255;
+        up_off[i] = cur;
+        cur += (b->reqs[i]->h.L.dev_begin + 255) & ~(size_t)255;
     }
-    // only the job arrays and each request's upload region are copied; the
-    // whole staged image is sent in one copy up to the last upload region
-    size_t upload_end = n ? req_off[n - 1] + b->reqs[n - 1]->h.upload_bytes : off_sum;
+    const size_t upload_end = cur;
+    for (int i = 0; i < n; ++i) {
+        dev_off[i] = cur;
+        const HostReq &h = b->reqs[i]->h;
+        cur += (h.L.total - h.L.dev_begin + 255) & ~(size_t)255;
+    }
     char *dev = p->arena.ptr(b->arena_off);
     b->pinned = p->pinned.get(upload_end);
     if (!b->pinned) return fail(FEW_E_NOMEM, "pinned staging allocation failed");
@@ -941,8 +982,8 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
     long long waves = 0;
     for (int i = 0; i < n; ++i) {
         ServedReq *r = b->reqs[i];
-        char *rb = dev + req_off[i];
-        stage_upload(r->h, host + req_off[i]);
+        const ReqBase rb{dev + up_off[i], dev + dev_off[i]};
+        stage_upload(r->h, host + up_off[i]);
         fj[i] = fit_job(r->h, rb, r->r.phi_phi, r->r.phi_r, r->r.amp);
         pj[i] = prep_job(r->h, rb, r->r.theta, r->r.phi, r->r.scale, r->r.t_start, r->r.dt,
                          r->r.n_samples, fp32, Tiling{1, 0});
@@ -973,7 +1014,10 @@ size_t batch_bytes(const std::vector<ServedReq *> &reqs) {
     cur = (cur + sizeof(FitJob) * n + 255) & ~(size_t)255;
     cur = (cur + sizeof(PrepJob) * n + 255) & ~(size_t)255;
     cur = (cur + sizeof(SumJob) * n + 255) & ~(size_t)255;
-    for (ServedReq *r : reqs) cur += (r->h.L.total + 255) & ~(size_t)255;
+    for (ServedReq *r : reqs) {
+        cur += (r->h.L.dev_begin + 255) & ~(size_t)255;
+        cur += (r->h.L.total - r->h.L.dev_begin + 255) & ~(size_t)255;
+    }
     return cur;
 }
 

@@ -174,6 +174,7 @@ inline long long part_tile_bound(long long n, int parts, long long short_len, in
 struct ReqLayout {
     size_t off_t, off_segs, off_term_ptr, off_term_src, off_chunks, upload_end;   // host-staged
     size_t off_pcoef, off_acoef, off_ybuf, off_table, off_starts, off_tile_pref, total;
+    size_t dev_begin;       // first device-produced offset (== off_pcoef)
 };
 ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
                          int n_chunks);

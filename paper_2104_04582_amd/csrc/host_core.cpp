@@ -56,25 +56,47 @@ void free_term_layout(TermLayout *t) {
 int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
     *out = TermLayout{};
     if (M < 1 || !lmn) return FEW_E_ARG;
-    std::vector<Entry> e;
-    e.reserve(2 * (size_t)M);
+    // order by (m, n, k, mirror): entries are generated in (k, mirror) order,
+    // then a stable two-pass radix sort on the 18-bit key (m, n) keeps that
+    // order inside each (m, n)
+    // (scratch vectors are reused per thread: fresh large blocks would be
+    // mapped and faulted in on every call)
+    thread_local std::vector<Entry> gen, e;
+    thread_local std::vector<uint32_t> key, idx, tmp;
+    thread_local std::vector<int> segs, term_ptr, src, chunks;
+    gen.clear();
+    key.clear();
     for (int k = 0; k < M; ++k) {
         int l = lmn[3 * k], m = lmn[3 * k + 1], n = lmn[3 * k + 2];
         if (l < 2 || l > kMaxL || m < 0 || m > l || n < -kMaxAbsN || n > kMaxAbsN)
             return FEW_E_MODES;
-        e.push_back({m, n, k, l, m, 0});
-        if (m > 0) e.push_back({-m, -n, k, l, m, 1});
+        gen.push_back({m, n, k, l, m, 0});
+        key.push_back((uint32_t)((m + kMaxL) << 12 | (n + kMaxAbsN)));
+        if (m > 0) {
+            gen.push_back({-m, -n, k, l, m, 1});
+            key.push_back((uint32_t)((-m + kMaxL) << 12 | (-n + kMaxAbsN)));
+        }
     }
-    std::sort(e.begin(), e.end(), [](const Entry &a, const Entry &b) {
-        if (a.m != b.m) return a.m < b.m;
-        if (a.n != b.n) return a.n < b.n;
-        if (a.k != b.k) return a.k < b.k;
-        return a.mirror < b.mirror;
-    });
-    // segments over distinct (m, n)
-    std::vector<int> segs;              // m, n_lo, len, first
-    std::vector<int> term_ptr;          // per term: first entry
-    std::vector<int> src;
+    const size_t ne = gen.size();
+    idx.resize(ne);
+    tmp.resize(ne);
+    for (size_t q = 0; q < ne; ++q) idx[q] = (uint32_t)q;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int shift = 9 * pass;
+        uint32_t count[513] = {0};
+        for (size_t q = 0; q < ne; ++q) ++count[((key[idx[q]] >> shift) & 511) + 1];
+        for (int b = 0; b < 512; ++b) count[b + 1] += count[b];
+        for (size_t q = 0; q < ne; ++q) tmp[count[(key[idx[q]] >> shift) & 511]++] = idx[q];
+        idx.swap(tmp);
+    }
+    e.resize(ne);
+    for (size_t q = 0; q < ne; ++q) e[q] = gen[idx[q]];
+
+    // segments over distinct (m, n): segs (m, n_lo, len, first), term_ptr
+    // (first contributor of each term), src (contributors)
+    segs.clear();
+    term_ptr.clear();
+    src.clear();
     size_t p = 0;
     int term = 0;
     while (p < e.size()) {
@@ -110,7 +132,7 @@ int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
     }
     term_ptr.push_back((int)src.size() / 2);
     // chunks: runs of whole segments with at most kChunkTerms terms
-    std::vector<int> chunks;
+    chunks.clear();
     chunks.push_back(0);
     const int n_seg = (int)segs.size() / 4;
     int run = 0;
@@ -162,6 +184,7 @@ ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n
     L.upload_end = L.off_chunks + sizeof(int) * (size_t)(n_chunks + 1);
     // device-produced arrays
     L.off_pcoef = take(sizeof(double) * 16 * (size_t)(K - 1));
+    L.dev_begin = L.off_pcoef;
     L.off_acoef = take(sizeof(double) * 8 * (size_t)(K - 1) * M);
     L.off_ybuf = take(sizeof(double) * 2 * (size_t)std::max(n_src, 1));
     L.off_table = take((fp32 ? 4 : 8) * 8 * (size_t)(K - 1) * n_terms);

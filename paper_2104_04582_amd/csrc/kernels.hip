@@ -507,6 +507,24 @@ __device__ __forceinline__ void phase_eval(const FEW_AS4 double *pc, dd x, doubl
     }
 }
 
+// e^{-i a} for a reduced phase a in [-pi, pi] (binary64): the binary32 path
+// rounds a to binary32 and takes the binary32 sincos (harmonics are binary32
+// there), the binary64 path the binary64 one.
+template <typename Real>
+__device__ __forceinline__ void unit_phasor(double a, Real *re, Real *im) {
+    if constexpr (sizeof(Real) == 4) {
+        float sn, cs;
+        sincosf((float)a, &sn, &cs);
+        *re = cs;
+        *im = -sn;
+    } else {
+        double sn, cs;
+        sincos(a, &sn, &cs);
+        *re = cs;
+        *im = -sn;
+    }
+}
+
 // Per-lane state of SL samples of one tile.
 template <typename Real, int SL>
 struct LaneState {
@@ -545,13 +563,8 @@ __device__ __forceinline__ void lane_setup(LaneState<Real, SL> &L, const SumJob 
         const dd x = two_sum(tj, -ti);
         phase_eval<DD>(pc, x, &L.pf[s], &L.pr[s]);
         L.u[s] = (Real)(x.hi * inv_h);
-        double sn, cs;
-        sincos(L.pf[s], &sn, &cs);
-        L.er[s] = (Real)cs;
-        L.ei[s] = (Real)(-sn);
-        sincos(L.pr[s], &sn, &cs);
-        L.fr[s] = (Real)cs;
-        L.fi[s] = (Real)(-sn);
+        unit_phasor<Real>(L.pf[s], &L.er[s], &L.ei[s]);
+        unit_phasor<Real>(L.pr[s], &L.fr[s], &L.fi[s]);
         L.hr[s] = L.hq[s] = L.cr[s] = L.cq[s] = (Real)0;
         L.zr[s] = L.zi[s] = (Real)0;
     }
@@ -599,10 +612,7 @@ __device__ __forceinline__ void seg_step(LaneState<Real, SL> &L, const int4 S, P
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const double a = d_reduce_2pi((double)S.x * L.pf[s] + (double)S.y * L.pr[s]);
-            double sn, cs;
-            sincos(a, &sn, &cs);
-            L.zr[s] = (Real)cs;
-            L.zi[s] = (Real)(-sn);
+            unit_phasor<Real>(a, &L.zr[s], &L.zi[s]);
         }
     }
     L.pm = S.x;
