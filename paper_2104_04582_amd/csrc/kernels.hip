@@ -916,65 +916,161 @@ __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_persistent_kernel(con
 // |A|^2 (ties by increasing index), sum the powers sequentially in that order,
 // and keep the shortest prefix that reaches (1 - eps) of the knot's total (at
 // least the top mode).  The selection is the union over knots.  One workgroup
-// per knot; bitonic sort of (power, index) in LDS; one lane forms the partial
-// sums in the sorted order so every threshold decision is reproducible.
+// of 1024 lanes per knot: bitonic sort of (power, index) held in registers;
+// one wave forms the binary64 partial sums in sorted order (values broadcast 64
+// at a time, so only the chain of adds is serial) and every threshold decision
+// is taken on exactly those sums.
 // ===========================================================================
 __device__ __forceinline__ bool sel_before(double ka, int ia, double kb, int ib) {
     return ka > kb || (ka == kb && ia < ib);
 }
 
-__global__ __launch_bounds__(256) void select_kernel(const double *amp, int M, int N,
-                                                     double one_minus_eps, int *keep) {
+constexpr int kSelectThreads = 1024;
+
+// One compare-exchange of the bitonic network from the side of the element at
+// position p, whose partner (position p ^ stride) holds (kq, iq).
+__device__ __forceinline__ void sel_exchange(double &kv, int &iv, double kq, int iq, int p,
+                                             int stride, int size) {
+    const bool lower = (p & stride) == 0;
+    const int low = lower ? p : (p ^ stride);
+    const bool up = (low & size) == 0;             // this run sorts in "before" order
+    const bool mine_first = sel_before(kv, iv, kq, iq);
+    if (mine_first != (lower == up)) {
+        kv = kq;
+        iv = iq;
+    }
+}
+
+// N = 1024 R positions (R = 1, 2 or 4); lane t holds positions t + 1024 r in
+// registers.  Partners closer than a wave are exchanged by shuffles, partners
+// 1024 or more apart are in the lane's own registers, the rest go through LDS.
+__global__ __launch_bounds__(kSelectThreads) void select_kernel(const double *amp, int M, int N,
+                                                                double one_minus_eps,
+                                                                int *keep) {
     extern __shared__ double sel_lds[];
     double *key = sel_lds;
     int *idx = (int *)(sel_lds + N);
-    __shared__ int cut;
-    const int tid = threadIdx.x, bs = blockDim.x;
+    __shared__ double total;
+    __shared__ int below;
+    const int tid = threadIdx.x;
+    const int R = N / kSelectThreads;
     const size_t k = blockIdx.x;
-    for (int j = tid; j < N; j += bs) {
-        if (j < M) {
-            const double re = amp[(k * M + j) * 2], im = amp[(k * M + j) * 2 + 1];
-            key[j] = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
-            idx[j] = j;
+    double kv[4];
+    int iv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = tid + kSelectThreads * r;
+        if (r < R && p < M) {
+            const double re = amp[(k * M + p) * 2], im = amp[(k * M + p) * 2 + 1];
+            kv[r] = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+            iv[r] = p;
         } else {
-            key[j] = -1.0;          // below every power
-            idx[j] = INT_MAX;
+            kv[r] = -1.0;           // below every power
+            iv[r] = INT_MAX;
         }
     }
-    __syncthreads();
     for (int size = 2; size <= N; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = tid; i < N; i += bs) {
-                const int l = i ^ stride;
-                if (l > i) {
-                    const bool up = (i & size) == 0;
-                    const double ki = key[i], kl = key[l];
-                    const int ii = idx[i], il = idx[l];
-                    const bool swap = up ? sel_before(kl, il, ki, ii) : sel_before(ki, ii, kl, il);
-                    if (swap) {
-                        key[i] = kl; key[l] = ki;
-                        idx[i] = il; idx[l] = ii;
+            if (stride >= kSelectThreads) {
+                const int rs = stride / kSelectThreads;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r < R && (r & rs) == 0) {
+                        const int r2 = r | rs;
+                        const int p = tid + kSelectThreads * r;
+                        const bool up = (p & size) == 0;
+                        const bool sw = up ? sel_before(kv[r2], iv[r2], kv[r], iv[r])
+                                           : sel_before(kv[r], iv[r], kv[r2], iv[r2]);
+                        if (sw) {
+                            const double tk = kv[r]; kv[r] = kv[r2]; kv[r2] = tk;
+                            const int ti = iv[r]; iv[r] = iv[r2]; iv[r2] = ti;
+                        }
+                    }
+                }
+            } else if (stride >= kWave) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r < R) {
+                        key[tid + kSelectThreads * r] = kv[r];
+                        idx[tid + kSelectThreads * r] = iv[r];
+                    }
+                }
+                __syncthreads();
+                double kq[4];
+                int iq[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r < R) {
+                        const int q = (tid + kSelectThreads * r) ^ stride;
+                        kq[r] = key[q];
+                        iq[r] = idx[q];
+                    }
+                }
+                __syncthreads();                    // reads done before the next writes
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < R)
+                        sel_exchange(kv[r], iv[r], kq[r], iq[r], tid + kSelectThreads * r,
+                                     stride, size);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r < R) {
+                        const double kq = __shfl_xor(kv[r], stride);
+                        const int iq = __shfl_xor(iv[r], stride);
+                        sel_exchange(kv[r], iv[r], kq, iq, tid + kSelectThreads * r, stride,
+                                     size);
                     }
                 }
             }
-            __syncthreads();
         }
     }
-    if (tid == 0) {
-        double total = 0.0;
-        for (int j = 0; j < M; ++j) total = __dadd_rn(total, key[j]);
-        const double thr = __dmul_rn(one_minus_eps, total);
-        double before = 0.0;
-        int J = 0;
-        for (int j = 0; j < M; ++j) {
-            if (!(before < thr)) break;
-            J = j + 1;
-            before = __dadd_rn(before, key[j]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r < R) {
+            key[tid + kSelectThreads * r] = kv[r];
+            idx[tid + kSelectThreads * r] = iv[r];
         }
-        cut = J > 0 ? J : 1;
     }
     __syncthreads();
-    for (int j = tid; j < cut; j += bs) keep[idx[j]] = 1;
+    // sequential partial sums: key[j] becomes the sum of the powers before j.
+    // One lane walks the sorted powers in blocks of 32 held in its registers,
+    // so the serial part is the chain of binary64 adds alone.
+    if (tid == 0) {
+        constexpr int B = 32;
+        double run = 0.0;
+        int j = 0;
+        for (; j + B <= M; j += B) {
+            double v[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) v[q] = key[j + q];
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const double before = run;
+                run = __dadd_rn(run, v[q]);
+                v[q] = before;
+            }
+#pragma unroll
+            for (int q = 0; q < B; ++q) key[j + q] = v[q];
+        }
+        for (; j < M; ++j) {
+            const double before = run;
+            run = __dadd_rn(run, key[j]);
+            key[j] = before;
+        }
+        total = run;
+        below = 0;
+    }
+    __syncthreads();
+    // kept: the modes whose preceding sum is below (1 - eps) total, a prefix
+    // since the sums do not decrease; at least the top mode
+    const double thr = __dmul_rn(one_minus_eps, total);
+    int local = 0;
+    for (int j = tid; j < M; j += kSelectThreads) local += key[j] < thr ? 1 : 0;
+    if (local) atomicAdd(&below, local);
+    __syncthreads();
+    const int cut = below > 0 ? below : 1;
+    for (int j = tid; j < cut; j += kSelectThreads) keep[idx[j]] = 1;
 }
 
 __global__ void zero_u32_kernel(unsigned *p, int n) {
@@ -1095,15 +1191,15 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_slots,
 
 hipError_t launch_select(const double *amp, int K, int M, double eps, int *keep,
                          hipStream_t stream) {
-    int N = 1;
+    int N = kSelectThreads;                 // 1024, 2048 or 4096 sort positions
     while (N < M) N <<= 1;
     hipLaunchKernelGGL(zero_u32_kernel, dim3((M + 255) / 256), dim3(256), 0, stream,
                        (unsigned *)keep, M);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)N;
-    hipLaunchKernelGGL(select_kernel, dim3(K), dim3(256), lds, stream, amp, M, N, 1.0 - eps,
-                       keep);
+    hipLaunchKernelGGL(select_kernel, dim3(K), dim3(kSelectThreads), lds, stream, amp, M, N,
+                       1.0 - eps, keep);
     return hipGetLastError();
 }
 

@@ -50,6 +50,10 @@ def test_limits(env):
     np.testing.assert_array_equal(gpu_select(env, amp, 1e-3), mode_select(amp, 1e-3))
     one = np.array([[[0.3, 0.4]]])
     np.testing.assert_array_equal(gpu_select(env, one, 0.5), [1])
+    # no power at any knot: only the first mode (ties go to the lower index)
+    zero = np.zeros((3, 65, 2))
+    np.testing.assert_array_equal(gpu_select(env, zero, 0.1), mode_select(zero, 0.1))
+    assert mode_select(zero, 0.1).tolist() == [1] + [0] * 64
     with native.Plan(0, "fp64") as plan:
         a = torch.zeros((2, 4097, 2), dtype=torch.float64, device=dev)
         with pytest.raises(native.FewError) as e:
