@@ -28,6 +28,16 @@
  * (~1e-12 rad at 5e5 rad of accumulated phase) near the tolerance it is used
  * to check.
  *
+ * Generic-Kerr spherical-projected sum (Sec. VII, Eq. (spherical projection)
+ * of the waveform, with the amplitude symmetry of Eq. (9) for general k):
+ *
+ *   h = scale * sum_{listed (l,m,k,n)} [ A Y+_lm + [m>0] conj(A) Y-_lmk ]
+ *                                     * e^{-i (m Phi_phi + k Phi_theta + n Phi_r)}
+ *
+ * with A_{l,-m,-k,-n} = (-1)^{l+k} conj(A_lmkn), i.e. Y-_lmk = (-1)^{l+k}
+ * -2Y_{l,-m}; a third phase Phi_theta is splined like the other two.  The
+ * Schwarzschild sum above is the case k = 0 without Phi_theta.
+ *
  * Plain and slow on purpose: dense LU with partial pivoting for the spline
  * system, a binary search per sample, libm sincosl per mode and sample,
  * Neumaier-compensated accumulation.  OpenMP over samples only.
@@ -313,15 +323,19 @@ static void neum_add(neum_t *a, ld v) {
 
 /*
  * h at the samples j = idx[q] (q < n_out), or j = q when idx is NULL.
- * amp is knot-major [K][M][2]; lmn is [M][3] with l >= 2, 0 <= m <= l.
- * out is complex128 interleaved (re = h_plus, im = -h_cross).
+ * amp is knot-major [K][M][2].  Modes: `mode` is [M][width], width 3 for
+ * (l, m, n) (k = 0, phi_theta unused) or 4 for (l, m, k, n) with phi_theta
+ * given; l >= 2, 0 <= m <= l.  out is complex128 interleaved
+ * (re = h_plus, im = -h_cross).
  */
-int few_oracle_sum(int K, const double *t, const double *phi_phi, const double *phi_r,
-                   int M, const int32_t *lmn, const double *amp,
-                   double theta, double phi, double scale,
-                   double t_start, double dt, int64_t n_samples,
-                   const int64_t *idx, int64_t n_out, double *out, int n_threads) {
-    if (!t || !phi_phi || !phi_r || !lmn || !amp || !out || M < 1 || n_samples < 1)
+static int sum_general(int K, const double *t, const double *phi_phi,
+                       const double *phi_theta, const double *phi_r, int M,
+                       const int32_t *mode, int width, const double *amp, double theta,
+                       double phi, double scale, double t_start, double dt, int64_t n_samples,
+                       const int64_t *idx, int64_t n_out, double *out, int n_threads) {
+    const int kerr = width == 4;
+    if (!t || !phi_phi || !phi_r || (kerr && !phi_theta) || !mode || !amp || !out || M < 1 ||
+        n_samples < 1)
         return OR_E_ARG;
     if (!(dt > 0.0) || !isfinite(dt) || !isfinite(t_start) || !isfinite(theta) ||
         !isfinite(phi) || !isfinite(scale))
@@ -329,7 +343,7 @@ int few_oracle_sum(int K, const double *t, const double *phi_phi, const double *
     int rc = check_knots(K, t);
     if (rc) return rc;
     for (int k = 0; k < M; ++k) {
-        int l = lmn[3 * k], m = lmn[3 * k + 1];
+        int l = mode[width * k], m = mode[width * k + 1];
         if (l < 2 || m < 0 || m > l) return OR_E_MODES;
     }
     if (!(t_start >= t[0]) || !(sample_time(t_start, dt, n_samples - 1) <= t[K - 1]))
@@ -339,11 +353,12 @@ int few_oracle_sum(int K, const double *t, const double *phi_phi, const double *
             if (idx[q] < 0 || idx[q] >= n_samples) return OR_E_RANGE;
     if (!idx) n_out = n_samples;
 
-    /* Splines of every series: Phi_phi, Phi_r, then Re/Im of each mode. */
-    const int S = 2 + 2 * M;
+    /* Splines of every series: Phi_phi, Phi_r, Phi_theta, then Re/Im of each
+     * mode (Phi_theta is all zero in the width-3 case and never used). */
+    const int S = 3 + 2 * M;
     double *y = malloc(sizeof(double) * (size_t)K * S);
     ld *c = malloc(sizeof(ld) * (size_t)(K - 1) * S * 4);
-    ld *red = malloc(sizeof(ld) * (size_t)(K - 1) * 2);
+    ld *red = malloc(sizeof(ld) * (size_t)(K - 1) * 3);
     ld *yp = malloc(sizeof(ld) * (size_t)M * 2), *ym = malloc(sizeof(ld) * (size_t)M * 2);
     if (!y || !c || !red || !yp || !ym) {
         free(y); free(c); free(red); free(yp); free(ym);
@@ -352,23 +367,26 @@ int few_oracle_sum(int K, const double *t, const double *phi_phi, const double *
     for (int i = 0; i < K; ++i) {
         y[(size_t)i * S + 0] = phi_phi[i];
         y[(size_t)i * S + 1] = phi_r[i];
-        for (int k = 0; k < 2 * M; ++k) y[(size_t)i * S + 2 + k] = amp[(size_t)i * 2 * M + k];
+        y[(size_t)i * S + 2] = kerr ? phi_theta[i] : 0.0;
+        for (int k = 0; k < 2 * M; ++k) y[(size_t)i * S + 3 + k] = amp[(size_t)i * 2 * M + k];
     }
     rc = spline_ld(K, t, S, y, c);
     if (rc) { free(y); free(c); free(red); free(yp); free(ym); return rc; }
     /* Constant term of each phase cubic, reduced mod 2 pi (exact identity). */
     for (int i = 0; i + 1 < K; ++i) {
-        red[2 * i + 0] = reduce_q((__float128)phi_phi[i]);
-        red[2 * i + 1] = reduce_q((__float128)phi_r[i]);
+        red[3 * i + 0] = reduce_q((__float128)phi_phi[i]);
+        red[3 * i + 1] = reduce_q((__float128)phi_r[i]);
+        red[3 * i + 2] = kerr ? reduce_q((__float128)phi_theta[i]) : 0.0L;
     }
-    /* Harmonics: Y+ = -2Y_lm; Y- = (-1)^l -2Y_{l,-m} for m > 0 (Eq. (9)). */
+    /* Harmonics: Y+ = -2Y_lm; Y- = (-1)^{l+k} -2Y_{l,-m} for m > 0 (Eq. (9)). */
     for (int k = 0; k < M; ++k) {
-        int l = lmn[3 * k], m = lmn[3 * k + 1];
+        int l = mode[width * k], m = mode[width * k + 1];
+        int kk = kerr ? mode[width * k + 2] : 0;
         swsh_ld(-2, l, m, (ld)theta, (ld)phi, &yp[2 * k], &yp[2 * k + 1]);
         if (m > 0) {
             ld r, i;
             swsh_ld(-2, l, -m, (ld)theta, (ld)phi, &r, &i);
-            ld sg = (l & 1) ? -1.0L : 1.0L;
+            ld sg = ((l + kk) & 1) ? -1.0L : 1.0L;
             ym[2 * k] = sg * r;
             ym[2 * k + 1] = sg * i;
         } else {
@@ -385,16 +403,20 @@ int few_oracle_sum(int K, const double *t, const double *phi_phi, const double *
         ld x = (ld)tj - (ld)t[i];
         const ld *cf = c + ((size_t)i * S + 0) * 4;
         const ld *cr = c + ((size_t)i * S + 1) * 4;
-        ld pf = reduce_q((__float128)(red[2 * i] + x * (cf[1] + x * (cf[2] + x * cf[3]))));
-        ld pr = reduce_q((__float128)(red[2 * i + 1] + x * (cr[1] + x * (cr[2] + x * cr[3]))));
+        const ld *ct = c + ((size_t)i * S + 2) * 4;
+        ld pf = reduce_q((__float128)(red[3 * i] + x * (cf[1] + x * (cf[2] + x * cf[3]))));
+        ld pr = reduce_q((__float128)(red[3 * i + 1] + x * (cr[1] + x * (cr[2] + x * cr[3]))));
+        ld pt = kerr ? reduce_q((__float128)(red[3 * i + 2] + x * (ct[1] + x * (ct[2] + x * ct[3]))))
+                     : 0.0L;
         neum_t hr = {0.0L, 0.0L}, hi = {0.0L, 0.0L};
         for (int k = 0; k < M; ++k) {
-            int m = lmn[3 * k + 1], n = lmn[3 * k + 2];
-            const ld *ar = c + ((size_t)i * S + 2 + 2 * k) * 4;
-            const ld *ai = c + ((size_t)i * S + 3 + 2 * k) * 4;
+            int m = mode[width * k + 1], n = mode[width * k + width - 1];
+            int kk = kerr ? mode[width * k + 2] : 0;
+            const ld *ar = c + ((size_t)i * S + 3 + 2 * k) * 4;
+            const ld *ai = c + ((size_t)i * S + 4 + 2 * k) * 4;
             ld a_r = ar[0] + x * (ar[1] + x * (ar[2] + x * ar[3]));
             ld a_i = ai[0] + x * (ai[1] + x * (ai[2] + x * ai[3]));
-            ld psi = (ld)m * pf + (ld)n * pr;
+            ld psi = (ld)m * pf + (ld)kk * pt + (ld)n * pr;
             ld sn, cs;
             sincosl(psi, &sn, &cs);
             /* z = A e^{-i psi} */
@@ -414,4 +436,24 @@ int few_oracle_sum(int K, const double *t, const double *phi_phi, const double *
     }
     free(y); free(c); free(red); free(yp); free(ym);
     return OR_OK;
+}
+
+/* Schwarzschild eccentric sum (Eq. (10)); lmn is [M][3]. */
+int few_oracle_sum(int K, const double *t, const double *phi_phi, const double *phi_r,
+                   int M, const int32_t *lmn, const double *amp,
+                   double theta, double phi, double scale,
+                   double t_start, double dt, int64_t n_samples,
+                   const int64_t *idx, int64_t n_out, double *out, int n_threads) {
+    return sum_general(K, t, phi_phi, NULL, phi_r, M, lmn, 3, amp, theta, phi, scale, t_start,
+                       dt, n_samples, idx, n_out, out, n_threads);
+}
+
+/* Generic-Kerr spherical-projected sum; lmkn is [M][4] = (l, m, k, n). */
+int few_oracle_sum_kerr(int K, const double *t, const double *phi_phi, const double *phi_theta,
+                        const double *phi_r, int M, const int32_t *lmkn, const double *amp,
+                        double theta, double phi, double scale,
+                        double t_start, double dt, int64_t n_samples,
+                        const int64_t *idx, int64_t n_out, double *out, int n_threads) {
+    return sum_general(K, t, phi_phi, phi_theta, phi_r, M, lmkn, 4, amp, theta, phi, scale,
+                       t_start, dt, n_samples, idx, n_out, out, n_threads);
 }

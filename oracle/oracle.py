@@ -55,6 +55,12 @@ def load():
                                        ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                        i64p, ctypes.c_int64, dp, ctypes.c_int]
         lib.few_oracle_sum.restype = ctypes.c_int
+        lib.few_oracle_sum_kerr.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, i32p,
+                                            dp, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_int64, i64p,
+                                            ctypes.c_int64, dp, ctypes.c_int]
+        lib.few_oracle_sum_kerr.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -109,10 +115,13 @@ def phase(t: Sequence[float], y: Sequence[float], tq: Sequence[float]) -> np.nda
 
 def mode_sum(t_knots, phi_phi, phi_r, lmn, amp, theta, phi, dt, n_samples,
              t_start: float = 0.0, scale: float = 1.0,
-             idx: Optional[np.ndarray] = None, n_threads: Optional[int] = None) -> np.ndarray:
+             idx: Optional[np.ndarray] = None, n_threads: Optional[int] = None,
+             phi_theta=None) -> np.ndarray:
     """h = h_plus - i h_cross at the samples (all, or the indices idx).
 
-    amp: [K, M, 2] knot-major (re, im); lmn: [M, 3].  Returns complex128.
+    amp: [K, M, 2] knot-major (re, im); lmn: [M, 3] (l, m, n), or [M, 4]
+    (l, m, k, n) for the generic-Kerr sum, which also needs phi_theta [K].
+    Returns complex128.
     """
     t = _f64(t_knots)
     pp = _f64(phi_phi)
@@ -121,6 +130,9 @@ def mode_sum(t_knots, phi_phi, phi_r, lmn, amp, theta, phi, dt, n_samples,
     amp = _f64(amp)
     K = t.shape[0]
     M = lmn.shape[0]
+    kerr = lmn.ndim == 2 and lmn.shape[1] == 4
+    if kerr and phi_theta is None:
+        raise OracleError("the (l, m, k, n) sum needs phi_theta")
     if amp.shape != (K, M, 2):
         raise OracleError(f"amp shape {amp.shape} != {(K, M, 2)}")
     if idx is not None:
@@ -133,11 +145,18 @@ def mode_sum(t_knots, phi_phi, phi_r, lmn, amp, theta, phi, dt, n_samples,
     out = np.empty(2 * n_out, dtype=np.float64)
     if n_threads is None:
         n_threads = os.cpu_count() or 1
-    rc = load().few_oracle_sum(K, _dp(t), _dp(pp), _dp(pr), M,
-                               lmn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                               _dp(amp), float(theta), float(phi), float(scale),
-                               float(t_start), float(dt), int(n_samples), ip, n_out,
-                               _dp(out), int(n_threads))
+    mp = lmn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    if kerr:
+        pt = _f64(phi_theta)
+        rc = load().few_oracle_sum_kerr(K, _dp(t), _dp(pp), _dp(pt), _dp(pr), M, mp,
+                                        _dp(amp), float(theta), float(phi), float(scale),
+                                        float(t_start), float(dt), int(n_samples), ip, n_out,
+                                        _dp(out), int(n_threads))
+    else:
+        rc = load().few_oracle_sum(K, _dp(t), _dp(pp), _dp(pr), M, mp,
+                                   _dp(amp), float(theta), float(phi), float(scale),
+                                   float(t_start), float(dt), int(n_samples), ip, n_out,
+                                   _dp(out), int(n_threads))
     _check(rc, "mode_sum")
     return out.view(np.complex128)
 
@@ -147,4 +166,4 @@ def mode_sum_waveform(w, idx: Optional[np.ndarray] = None,
     """Convenience: oracle sum of a synth.Waveform."""
     return mode_sum(w.t_knots, w.phi_phi, w.phi_r, w.lmn, w.amp, w.theta, w.phi, w.dt,
                     w.n_samples, t_start=w.t_start, scale=w.scale, idx=idx,
-                    n_threads=n_threads)
+                    n_threads=n_threads, phi_theta=getattr(w, "phi_theta", None))

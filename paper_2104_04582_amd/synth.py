@@ -17,6 +17,11 @@ RomanNet amplitudes need data that is not available, so:
 * amplitudes are random complex cubics in t/T with a weight
   exp(-|n|/5) exp(-(l-2)) on the coefficients;
 * knots are log-spaced in time to coalescence (densest near the end).
+
+Generic-Kerr inputs (Sec. VII, spherical projection) add the polar index k
+and a third phase: Phi_theta = kappa_theta Phi_phi, kappa_theta in
+[0.85, 0.98], amplitude weight exp(-|n|/5) exp(-|k|/2) exp(-(l-2)); the mode
+list is (l, m, k, n) with l 2..l_max, m 0..l, |k| <= k_max, |n| <= n_max.
 """
 from __future__ import annotations
 
@@ -75,6 +80,8 @@ class Waveform:
     n_samples: int
     t_start: float = 0.0
     scale: float = 1.0
+    # generic-Kerr requests: lmn is [M, 4] = (l, m, k, n) and Phi_theta [K]
+    phi_theta: Optional[np.ndarray] = None
     # generator bookkeeping (used by tests that pin exact polynomials)
     amp_poly: Optional[np.ndarray] = None   # [M, 4, 2] coefficients in (t/T)^p
     T: float = 0.0
@@ -97,8 +104,11 @@ class Waveform:
 
 def _amp_weights(lmn: np.ndarray) -> np.ndarray:
     l = lmn[:, 0].astype(np.float64)
-    n = lmn[:, 2].astype(np.float64)
-    return np.exp(-np.abs(n) / 5.0) * np.exp(-(l - 2.0))
+    n = lmn[:, -1].astype(np.float64)
+    w = np.exp(-np.abs(n) / 5.0) * np.exp(-(l - 2.0))
+    if lmn.shape[1] == 4:
+        w = w * np.exp(-np.abs(lmn[:, 2].astype(np.float64)) / 2.0)
+    return w
 
 
 def _amp_at_knots(poly: np.ndarray, t: np.ndarray, T: float) -> np.ndarray:
@@ -124,6 +134,76 @@ def draw_waveform(rng: np.random.Generator, lmn: np.ndarray, T: float, K: int,
                     amp=_amp_at_knots(poly, t, T), theta=math.acos(cos_t),
                     phi=phi, dt=dt, n_samples=n_samples_for(T, dt),
                     amp_poly=poly, T=T, f0=f0, kappa=kappa, tc=tc)
+
+
+def mode_list_kerr(l_min: int, l_max: int, k_max: int, n_max: int) -> np.ndarray:
+    """All (l, m, k, n) with l_min <= l <= l_max, 0 <= m <= l, |k| <= k_max,
+    |n| <= n_max.  Order: l, then m, then k, then n ascending.  int32 [M, 4]."""
+    rows = [(l, m, k, n)
+            for l in range(l_min, l_max + 1)
+            for m in range(0, l + 1)
+            for k in range(-k_max, k_max + 1)
+            for n in range(-n_max, n_max + 1)]
+    return np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+
+
+def draw_kerr(rng: np.random.Generator, lmkn: np.ndarray, T: float, K: int,
+              dt: float) -> Waveform:
+    """Generic-Kerr draw: f0, kappa, kappa_theta, cos(theta), phi, then the
+    amplitude cubics, in that order."""
+    f0 = rng.uniform(5e-4, 2e-3)
+    kappa = rng.uniform(0.6, 0.9)
+    kappa_t = rng.uniform(0.85, 0.98)
+    cos_t = rng.uniform(-1.0, 1.0)
+    phi = rng.uniform(0.0, 2.0 * math.pi)
+    M = lmkn.shape[0]
+    poly = rng.standard_normal((M, 4, 2)) * _amp_weights(lmkn)[:, None, None]
+    tc = 1.2 * T
+    t = knot_times(T, K, tc)
+    pp = chirp_phase(t, f0, tc)
+    return Waveform(t_knots=t, phi_phi=pp, phi_r=kappa * pp, lmn=lmkn.copy(),
+                    amp=_amp_at_knots(poly, t, T), theta=math.acos(cos_t),
+                    phi=phi, dt=dt, n_samples=n_samples_for(T, dt),
+                    phi_theta=kappa_t * pp, amp_poly=poly, T=T, f0=f0, kappa=kappa,
+                    tc=tc)
+
+
+def kerr_small(seed: int = 0) -> Waveform:
+    """Small generic-Kerr case: l 2..4, |k| <= 2, |n| <= 5 (660 modes), 40 knots
+    over 1 day, dt 10 s."""
+    return draw_kerr(np.random.default_rng(seed), mode_list_kerr(2, 4, 2, 5),
+                     DAY_S, 40, 10.0)
+
+
+def kerr_full(seed: int = 0) -> Waveform:
+    """Full generic-Kerr case: l 2..10, |k| <= 4, |n| <= 30 (34,587 modes, about
+    nine times the Schwarzschild set), 100 knots over 1 yr, dt 10 s."""
+    return draw_kerr(np.random.default_rng(seed), mode_list_kerr(2, 10, 4, 30),
+                     YEAR_S, 100, 10.0)
+
+
+def tiny_kerr(seed: int, K: int = 5, M: int = 4, n_samples: int = 40, l_max: int = 3,
+              k_max: int = 2, n_max: int = 2, T: float = 1000.0,
+              phase_scale: float = 30.0) -> Waveform:
+    """A small random generic-Kerr instance with arbitrary knot data (modes
+    drawn at random, repeats possible, from l 2..l_max, |k| <= k_max,
+    |n| <= n_max)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.uniform(0.3, 1.0, K - 1)
+    t = np.concatenate([[0.0], np.cumsum(gaps)])
+    t = t / t[-1] * T
+    t[-1] = T
+    pp = np.cumsum(rng.uniform(0.0, phase_scale, K))
+    pt = np.cumsum(rng.uniform(0.0, phase_scale * 0.9, K))
+    pr = np.cumsum(rng.uniform(0.0, phase_scale * 0.7, K))
+    modes = mode_list_kerr(2, l_max, k_max, n_max)
+    lmkn = modes[rng.integers(0, modes.shape[0], M)]
+    amp = rng.standard_normal((K, M, 2))
+    dt = T / n_samples
+    return Waveform(t_knots=t, phi_phi=pp, phi_r=pr, lmn=lmkn, amp=amp,
+                    theta=math.acos(rng.uniform(-1, 1)),
+                    phi=rng.uniform(0, 2 * math.pi), dt=dt,
+                    n_samples=n_samples_for(T, dt), phi_theta=pt, T=T)
 
 
 def config0(seed: int = 0) -> Waveform:
