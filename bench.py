@@ -75,6 +75,47 @@ def time_path(native, plan, w, dev, steps: int, warmup: int):
     return elapsed / steps, tm, out
 
 
+def kerr_run(native, dev, steps: int = 5, warmup: int = 1):
+    """Generic-Kerr sum (34,587 modes, 1 yr): fit + sum per step, both precisions."""
+    import torch
+    from paper_2104_04582_amd import synth
+    w = synth.kerr_full()
+    segs, tp, _ = native.host_terms(w.lmn)
+    n_terms, n_segs = tp.shape[0] - 1, segs.shape[0]
+    flops = algorithmic_flops(n_terms, n_segs, w.n_samples)
+    ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+           for a in (w.phi_phi, w.phi_theta, w.phi_r, w.amp)]
+    res = {"workload": "generic-Kerr spherical-projected sum, 34,587 modes (l 2..10, m 0..l, "
+                       "k -4..4, n -30..30), 100 knots, 1 yr at dt 10 s",
+           "modes": w.M, "samples": w.n_samples, "folded_terms": n_terms, "segments": n_segs}
+    for prec in ("mixed", "fp64"):
+        with native.Plan(0, prec, timing=True, hbm_budget_bytes=4 << 30) as plan:
+            out = torch.empty(w.n_samples, dtype=plan.out_dtype, device=dev)
+
+            def step():
+                sp = plan.spline_fit_kerr(w.t_knots, *ins[:3], w.lmn, ins[3])
+                plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples, out=out)
+                sp.free()
+
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            plan.timing(reset=True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+            tm = plan.timing(reset=True)
+        sum_ms = tm["sum_ms"] / max(tm["sum_launches"], 1)
+        res[prec] = {"value": w.mode_samples / sec, "ms_per_step": sec * 1e3,
+                     "spline_ms": tm["spline_ms"] / max(tm["spline_launches"], 1),
+                     "sum_ms": sum_ms, "sum_tflops": flops / (sum_ms * 1e-3) / 1e12}
+    del ins
+    torch.cuda.empty_cache()
+    return res
+
+
 def select_timing(native, w, dev, eps: float = 1e-5, reps: int = 20):
     """Mode selector on the benchmark amplitudes: kept modes and mean time."""
     import torch
@@ -259,6 +300,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-kerr", action="store_true", help="skip the generic-Kerr line")
     ap.add_argument("--batch", type=int, default=128, help="uneven instances in one launch")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
@@ -318,6 +360,12 @@ def main() -> int:
     sel = select_timing(native, w, dev)
     log(f"[bench] mode select: {json.dumps(sel)}")
 
+    kerr = None
+    if not args.no_kerr:
+        log("[bench] generic-Kerr sum")
+        kerr = kerr_run(native, dev)
+        log(f"[bench] kerr: {json.dumps(kerr)}")
+
     batch = {}
     if args.batch > 0:
         for prec in ("mixed", "fp64"):
@@ -370,6 +418,7 @@ def main() -> int:
         "canonical_32flop_tflops": {p: res[p]["canonical_tflops"] for p in res},
         "mixed_vs_fp64": {"mismatch": mm, "max_rel_error": mx},
         "mode_select": sel,
+        "kerr": kerr,
         "batched": batch or None,
         "served": serve or None,
         "cpu_baseline": cpu,

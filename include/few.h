@@ -144,6 +144,24 @@ int32_t few_spline_fit(few_plan plan, int32_t K, const double *t_knots,
                        int32_t M, const int32_t *lmn, const double *amp,
                        few_spline *out);
 
+/*
+ * Generic-Kerr spherical-projected sum (Sec. VII, spherical projection of the
+ * spheroidal harmonics): modes (l, m, k, n) with phase
+ * m Phi_phi + k Phi_theta + n Phi_r, and the amplitude symmetry of Eq. (9)
+ * with general k, A_{l,-m,-k,-n} = (-1)^{l+k} conj(A_lmkn).  Same as
+ * few_spline_fit plus:
+ *   phi_theta  device [K]    polar orbital phase at the knots
+ *   lmkn       host [M][4]   (l, m, k, n); 2 <= l <= 30, 0 <= m <= l,
+ *                            |k| <= 30, |n| <= 1000 (FEW_E_MODES otherwise);
+ *                            m = 0 modes are not mirrored
+ * The resulting spline is summed by few_mode_sum like any other.  The batched
+ * and served entry points take (l, m, n) requests only.
+ */
+int32_t few_spline_fit_kerr(few_plan plan, int32_t K, const double *t_knots,
+                            const double *phi_phi, const double *phi_theta,
+                            const double *phi_r, int32_t M, const int32_t *lmkn,
+                            const double *amp, few_spline *out);
+
 /* Release a spline's arena memory (stream-ordered: safe while work using it is queued). */
 int32_t few_spline_free(few_spline spline);
 
@@ -151,9 +169,10 @@ int32_t few_spline_free(few_spline spline);
  * Copy a fitted spline's coefficients into device memory `dst` (plan stream):
  *   which = 0: amplitudes, float64 [K-1][M][4][2]: coefficient of x^p (x = t - t_i)
  *              of Re/Im A_k on interval i at dst[((i*M + k)*4 + p)*2 + re/im].
- *   which = 1: phases, float64 [K-1][2][4][2]: coefficient p of Phi_phi (0) /
- *              Phi_r (1) as a double-double (hi, lo); p = 0 holds the knot value
- *              reduced to [-pi, pi) (adding 2 pi k leaves e^{-i psi} unchanged).
+ *   which = 1: phases, float64 [K-1][P][4][2]: coefficient p of Phi_phi (0) /
+ *              Phi_r (1) / Phi_theta (2, generic-Kerr splines; P = 3, else 2)
+ *              as a double-double (hi, lo); p = 0 holds the knot value reduced
+ *              to [-pi, pi) (adding 2 pi k leaves e^{-i psi} unchanged).
  */
 int32_t few_spline_coefs(few_spline spline, int32_t which, void *dst);
 
@@ -232,13 +251,27 @@ const char *few_last_error(void);
  * into segments of one signed m and a contiguous n range (gaps of at most
  * `max_gap` zero terms are filled).  Writes up to cap_* entries:
  *   segs[4*s + 0..3] = (m, n_lo, length, first term index)
- *   term_ptr[n_terms + 1], term_src[2*e + 0/1] = (mode index, l | m << 8 | mirror << 16)
+ *   term_ptr[n_terms + 1], term_src[2*e + 0/1] = (mode index,
+ *     l | m << 8 | mirror << 16 | 64 << 17)
  * and the counts.  Returns FEW_E_ARG if a capacity is too small.
  */
 int32_t few_host_terms(int32_t M, const int32_t *lmn, int32_t max_gap,
                        int32_t cap_segs, int32_t *segs, int32_t *n_segs,
                        int32_t cap_terms, int32_t *term_ptr, int32_t *n_terms,
                        int32_t cap_src, int32_t *term_src, int32_t *n_src);
+
+/*
+ * The same for generic-Kerr modes lmkn [M][4] = (l, m, k, n): one complex cubic
+ * per signed (m, k, n), mirrors weighted by (-1)^{l+k} -2Y_{l,-m}; segments of
+ * one signed (m, k) with contiguous n, in (m, k, n) order;
+ *   segs[4*s + 0] = m + 256 k
+ *   term_src[2*e + 1] = l | m << 8 | mirror << 16 | (k + 64) << 17
+ * (few_host_terms writes the same fields with k = 0).
+ */
+int32_t few_host_terms_kerr(int32_t M, const int32_t *lmkn, int32_t max_gap,
+                            int32_t cap_segs, int32_t *segs, int32_t *n_segs,
+                            int32_t cap_terms, int32_t *term_ptr, int32_t *n_terms,
+                            int32_t cap_src, int32_t *term_src, int32_t *n_src);
 
 /*
  * First sample of each knot interval: starts[i] = min{ j in [0, n] :

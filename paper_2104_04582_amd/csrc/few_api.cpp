@@ -156,6 +156,8 @@ enum Stage { ST_FIT = 0, ST_PREP = 1, ST_SUM = 2 };
 // One request's host-side description and arena placement.
 struct HostReq {
     int K = 0, M = 0;
+    int width = 3;             // modes (l, m, n), or (l, m, k, n) for generic Kerr
+    int n_ph = 2;              // splined phases: Phi_phi, Phi_r (+ Phi_theta)
     std::vector<double> t;
     TermLayout terms;
     ReqLayout L{};
@@ -164,8 +166,10 @@ struct HostReq {
 };
 
 int validate_fit_args(int K, const double *t, int M, const int32_t *lmn, const void *pp,
-                      const void *pr, const void *amp, int max_knots, int max_modes) {
-    if (!t || !lmn || !pp || !pr || !amp) return fail(FEW_E_ARG, "null pointer argument");
+                      const void *pr, const void *amp, int max_knots, int max_modes,
+                      int width = 3, const void *pt = nullptr) {
+    if (!t || !lmn || !pp || !pr || !amp || (width == 4 && !pt))
+        return fail(FEW_E_ARG, "null pointer argument");
     if (K < 4 || K > max_knots)
         return fail(FEW_E_KNOTS, "K = %d outside [4, %d]", K, max_knots);
     for (int i = 0; i < K; ++i)
@@ -175,10 +179,14 @@ int validate_fit_args(int K, const double *t, int M, const int32_t *lmn, const v
             return fail(FEW_E_KNOTS, "knots not strictly increasing at %d", i);
     if (M < 1 || M > max_modes) return fail(FEW_E_MODES, "M = %d outside [1, %d]", M, max_modes);
     for (int k = 0; k < M; ++k) {
-        int l = lmn[3 * k], m = lmn[3 * k + 1], n = lmn[3 * k + 2];
-        if (l < 2 || l > kMaxL || m < 0 || m > l || n < -kMaxAbsN || n > kMaxAbsN)
-            return fail(FEW_E_MODES, "mode %d = (%d,%d,%d) invalid (2<=l<=%d, 0<=m<=l, |n|<=%d)",
-                        k, l, m, n, kMaxL, kMaxAbsN);
+        const int32_t *md = lmn + (size_t)width * k;
+        int l = md[0], m = md[1], kp = width == 4 ? md[2] : 0, n = md[width - 1];
+        if (l < 2 || l > kMaxL || m < 0 || m > l || n < -kMaxAbsN || n > kMaxAbsN ||
+            kp < -kMaxAbsK || kp > kMaxAbsK)
+            return fail(FEW_E_MODES,
+                        "mode %d = (l %d, m %d, k %d, n %d) invalid (2<=l<=%d, 0<=m<=l, |k|<=%d, "
+                        "|n|<=%d)",
+                        k, l, m, kp, n, kMaxL, kMaxAbsK, kMaxAbsN);
     }
     return FEW_OK;
 }
@@ -216,14 +224,15 @@ class LayoutCache {
     ~LayoutCache() {
         for (auto &e : entries_) free_term_layout(&e.layout);
     }
-    // Fill *out with an owned copy of the layout of (M, lmn).
-    int get(int M, const int32_t *lmn, TermLayout *out) {
-        const uint64_t h = hash(M, lmn);
+    // Fill *out with an owned copy of the layout of M modes of `width` ints.
+    int get(int M, const int32_t *lmn, int width, TermLayout *out) {
+        const size_t words = (size_t)width * M;
+        const uint64_t h = hash(words, lmn) ^ (uint64_t)width;
         std::lock_guard<std::mutex> g(mu_);
         for (size_t i = 0; i < entries_.size(); ++i) {
             Entry &e = entries_[i];
-            if (e.hash == h && (int)e.lmn.size() == 3 * M &&
-                std::memcmp(e.lmn.data(), lmn, sizeof(int32_t) * 3 * (size_t)M) == 0) {
+            if (e.hash == h && e.width == width && e.lmn.size() == words &&
+                std::memcmp(e.lmn.data(), lmn, sizeof(int32_t) * words) == 0) {
                 int rc = copy(e.layout, out);
                 if (!rc && i != 0) std::rotate(entries_.begin(), entries_.begin() + i,
                                                entries_.begin() + i + 1);
@@ -231,7 +240,7 @@ class LayoutCache {
             }
         }
         TermLayout L;
-        int rc = build_term_layout(M, lmn, kMaxGap, &L);
+        int rc = build_term_layout(M, lmn, width, kMaxGap, &L);
         if (rc) return rc;
         rc = copy(L, out);
         if (rc) {
@@ -243,7 +252,7 @@ class LayoutCache {
             entries_.pop_back();
         }
         entries_.insert(entries_.begin(),
-                        Entry{h, std::vector<int32_t>(lmn, lmn + 3 * (size_t)M), L});
+                        Entry{h, width, std::vector<int32_t>(lmn, lmn + words), L});
         return FEW_OK;
     }
 
@@ -251,13 +260,14 @@ class LayoutCache {
     static constexpr size_t kCap = 256;
     struct Entry {
         uint64_t hash;
+        int width;
         std::vector<int32_t> lmn;
         TermLayout layout;
     };
     // FNV-1a over the 32-bit words of the list
-    static uint64_t hash(int M, const int32_t *lmn) {
+    static uint64_t hash(size_t words, const int32_t *lmn) {
         uint64_t h = 1469598103934665603ULL;
-        for (size_t i = 0; i < 3 * (size_t)M; ++i) {
+        for (size_t i = 0; i < words; ++i) {
             h ^= (uint32_t)lmn[i];
             h *= 1099511628211ULL;
         }
@@ -288,14 +298,16 @@ class LayoutCache {
 };
 
 int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, HostReq *r,
-                  LayoutCache *cache) {
+                  LayoutCache *cache, int width = 3) {
     r->K = K;
     r->M = M;
+    r->width = width;
+    r->n_ph = width == 4 ? 3 : 2;
     r->t.assign(t, t + K);
-    int rc = cache->get(M, lmn, &r->terms);
+    int rc = cache->get(M, lmn, width, &r->terms);
     if (rc) return fail(rc, "mode list rejected while building the term layout");
     r->L = request_layout(fp32, K, M, r->terms.n_segs, r->terms.n_terms, r->terms.n_src,
-                          r->terms.n_chunks);
+                          r->terms.n_chunks, r->n_ph);
     r->upload_bytes = r->L.upload_end;
     return FEW_OK;
 }
@@ -322,11 +334,13 @@ T *at_dev(const HostReq &r, ReqBase b, size_t off) {
 }
 
 FitJob fit_job(const HostReq &r, ReqBase base, const double *pp, const double *pr,
-               const double *amp) {
+               const double *amp, const double *pt = nullptr) {
     FitJob j{};
     j.t = at_up<const double>(r, base, r.L.off_t);
     j.phi_phi = pp;
     j.phi_r = pr;
+    j.phi_theta = pt;
+    j.n_ph = r.n_ph;
     j.amp = amp;
     j.pcoef = at_dev<double>(r, base, r.L.off_pcoef);
     j.acoef = at_dev<double>(r, base, r.L.off_acoef);
@@ -401,6 +415,7 @@ SumJob sum_job(const HostReq &r, ReqBase base, double t_start, double dt, int64_
     j.n_terms = r.terms.n_terms;
     j.n_segs = r.terms.n_segs;
     j.n_chunks = r.terms.n_chunks;
+    j.n_ph = r.n_ph;
     j.short_len = tl.short_len;
     j.parts = tl.parts;
     j.wave_base = 0;
@@ -434,6 +449,7 @@ struct few_plan_s {
     bool fp32 = false;
     int max_knots = kMaxKnots, max_modes = 65536, max_inflight = 2;
     int resident_wg = 0;        // binary32 summation workgroups resident at once
+    int resident_wg3 = 0;       // the same for the generic-Kerr kernel
     uint64_t budget = 0;
     int flags = 0;
     char *arena_base = nullptr;
@@ -581,7 +597,8 @@ int32_t few_plan_create(const few_plan_desc *desc, few_plan *out) {
         p->device = desc->device;
         p->stream = (hipStream_t)desc->stream;
         p->fp32 = desc->precision == FEW_MIXED;
-        p->resident_wg = p->fp32 ? sum_resident_workgroups() : 0;
+        p->resident_wg = p->fp32 ? sum_resident_workgroups(2) : 0;
+        p->resident_wg3 = p->fp32 ? sum_resident_workgroups(3) : 0;
         p->max_knots = desc->max_knots ? desc->max_knots : kMaxKnots;
         p->max_modes = desc->max_modes ? desc->max_modes : 65536;
         p->max_inflight = desc->max_inflight ? desc->max_inflight : 2;
@@ -648,20 +665,21 @@ int32_t few_plan_destroy(few_plan p) {
     }
 }
 
-int32_t few_spline_fit(few_plan p, int32_t K, const double *t_knots, const double *phi_phi,
-                       const double *phi_r, int32_t M, const int32_t *lmn, const double *amp,
-                       few_spline *out) {
+namespace {
+int spline_fit_impl(few_plan p, int32_t K, const double *t_knots, const double *phi_phi,
+                    const double *phi_theta, const double *phi_r, int32_t M,
+                    const int32_t *modes, int width, const double *amp, few_spline *out) {
     if (!p) return fail(FEW_E_STATE, "null plan");
     if (!out) return fail(FEW_E_ARG, "null output handle");
     try {
-        int rc = validate_fit_args(K, t_knots, M, lmn, phi_phi, phi_r, amp, p->max_knots,
-                                   p->max_modes);
+        int rc = validate_fit_args(K, t_knots, M, modes, phi_phi, phi_r, amp, p->max_knots,
+                                   p->max_modes, width, phi_theta);
         if (rc) return rc;
         std::lock_guard<std::mutex> g(p->sync_mu);
         HIP_TRY(hipSetDevice(p->device));
         few_spline s = new (std::nothrow) few_spline_s;
         if (!s) return fail(FEW_E_NOMEM, "host allocation failed");
-        rc = make_host_req(K, t_knots, M, lmn, p->fp32, &s->h, &p->layouts);
+        rc = make_host_req(K, t_knots, M, modes, p->fp32, &s->h, &p->layouts, width);
         if (rc) {
             delete s;
             return rc;
@@ -680,7 +698,7 @@ int32_t few_spline_fit(few_plan p, int32_t K, const double *t_knots, const doubl
         char *base = p->arena.ptr(s->arena_off);
         rc = sync_upload(p, s->h, base);
         if (!rc) {
-            FitJob job = fit_job(s->h, one_block(s->h, base), phi_phi, phi_r, amp);
+            FitJob job = fit_job(s->h, one_block(s->h, base), phi_phi, phi_r, amp, phi_theta);
             rc = timed_launch(p, ST_FIT, p->stream, [&] { return launch_fit(job, p->stream); });
         }
         if (rc) {
@@ -694,6 +712,19 @@ int32_t few_spline_fit(few_plan p, int32_t K, const double *t_knots, const doubl
     } catch (...) {
         return fail(FEW_E_NOMEM, "exception in few_spline_fit");
     }
+}
+}  // namespace
+
+int32_t few_spline_fit(few_plan p, int32_t K, const double *t_knots, const double *phi_phi,
+                       const double *phi_r, int32_t M, const int32_t *lmn, const double *amp,
+                       few_spline *out) {
+    return spline_fit_impl(p, K, t_knots, phi_phi, nullptr, phi_r, M, lmn, 3, amp, out);
+}
+
+int32_t few_spline_fit_kerr(few_plan p, int32_t K, const double *t_knots,
+                            const double *phi_phi, const double *phi_theta, const double *phi_r,
+                            int32_t M, const int32_t *lmkn, const double *amp, few_spline *out) {
+    return spline_fit_impl(p, K, t_knots, phi_phi, phi_theta, phi_r, M, lmkn, 4, amp, out);
 }
 
 int32_t few_spline_free(few_spline s) {
@@ -720,7 +751,7 @@ int32_t few_spline_coefs(few_spline s, int32_t which, void *dst) {
                                hipMemcpyDeviceToDevice, p->stream));
     } else if (which == 1) {
         HIP_TRY(hipMemcpyAsync(dst, base + s->h.L.off_pcoef,
-                               sizeof(double) * 16 * (size_t)(s->h.K - 1),
+                               sizeof(double) * 8 * s->h.n_ph * (size_t)(s->h.K - 1),
                                hipMemcpyDeviceToDevice, p->stream));
     } else {
         return fail(FEW_E_ARG, "which must be 0 (amplitudes) or 1 (phases)");
@@ -738,7 +769,8 @@ int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double 
         std::lock_guard<std::mutex> g(p->sync_mu);
         HIP_TRY(hipSetDevice(p->device));
         char *base = p->arena.ptr(s->arena_off);
-        const Tiling tl = single_tiling(p->fp32, p->resident_wg);
+        const Tiling tl =
+            single_tiling(p->fp32, s->h.n_ph == 3 ? p->resident_wg3 : p->resident_wg);
         PrepJob pj = prep_job(s->h, one_block(s->h, base), theta, phi, scale, t_start, dt, n,
                               p->fp32, tl);
         rc = timed_launch(p, ST_PREP, p->stream,

@@ -11,6 +11,7 @@ namespace few {
 constexpr int kMaxKnots = 1024;       // phase-solve LDS: eight binary64 arrays of this length (64 KiB)
 constexpr int kMaxL = 30;             // Wigner-d sum stays well conditioned in binary64
 constexpr int kMaxAbsN = 1000;
+constexpr int kMaxAbsK = 30;          // polar index of generic-Kerr modes
 constexpr int kWave = 64;
 constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 #ifndef FEW_SEG_UNROLL
@@ -62,12 +63,16 @@ struct FitJob {
     const double *t;        // [K] knot times
     const double *phi_phi;  // [K]
     const double *phi_r;    // [K]
+    const double *phi_theta;  // [K] (generic Kerr) or null
     const double *amp;      // [K][M][2]
-    double *pcoef;          // [K-1][2][4][2] double-double phase cubics
+    double *pcoef;          // [K-1][n_ph][4][2] double-double phase cubics
     double *acoef;          // [K-1][M][4][2] amplitude cubics
     int K, M;
-    int amp_blocks;         // blocks covering the 2M amplitude series (after 2 phase blocks)
+    int n_ph;               // phases: Phi_phi, Phi_r (, Phi_theta)
+    int amp_blocks;         // blocks covering the 2M amplitude series (after n_ph phase blocks)
 };
+
+constexpr int kMaxPhases = 3;
 
 // Fold + interval bookkeeping for one request.
 struct PrepJob {
@@ -93,9 +98,9 @@ struct PrepJob {
 // Summation stage for one request.
 struct SumJob {
     const double *t;
-    const double *pcoef;
+    const double *pcoef;    // [K-1][n_ph][4][2]
     const void *table;
-    const int4 *segs;       // [n_segs]: (m, n_lo, length, first term)
+    const int4 *segs;       // [n_segs]: (m + 256 k, n_lo, length, first term)
     const int *chunks;      // [n_chunks + 1]: first segment of each LDS chunk
     const long long *starts;
     const int *tile_pref;
@@ -105,12 +110,14 @@ struct SumJob {
     long long short_len;    // samples at the end of each part cut into short tiles
     int parts;              // contiguous sample parts (one per XCD) or 1
     int K, n_terms, n_segs, n_chunks;
+    int n_ph;               // phases in pcoef (3: generic Kerr, Phi_theta last)
     int wave_base;          // first global tile slot of this job (batched launch)
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
-// Binary32 summation workgroups resident at once on the current device.
-int sum_resident_workgroups();
+// Binary32 summation workgroups resident at once on the current device, for
+// the two-phase (Schwarzschild) or three-phase (generic Kerr) kernel.
+int sum_resident_workgroups(int n_ph);
 hipError_t launch_fit(const FitJob &job, hipStream_t stream);
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream);
@@ -138,7 +145,7 @@ struct TermLayout {
 };
 
 // Build the folded term layout; returns 0 or a few_status error code.
-int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out);
+int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermLayout *out);
 void free_term_layout(TermLayout *t);
 
 // starts[i] for i in [0, K): see few_host_interval_starts.
@@ -177,7 +184,7 @@ struct ReqLayout {
     size_t dev_begin;       // first device-produced offset (== off_pcoef)
 };
 ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
-                         int n_chunks);
+                         int n_chunks, int n_ph);
 
 // Binary64 sample time exactly as written: t_start + j * dt, no contraction.
 double sample_time(double t_start, double dt, long long j);

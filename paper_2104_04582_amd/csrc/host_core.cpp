@@ -36,8 +36,10 @@ void interval_starts(int K, const double *t, double t_start, double dt, long lon
 }
 
 namespace {
+// One signed term contribution: (m, kp, n) of the signed mode, the listed mode
+// index and its (l, m), and whether it is the mirror of a listed m > 0 mode.
 struct Entry {
-    int m, n, k, l, mode_m, mirror;
+    int m, kp, n, k, l, mode_m, mirror;
 };
 }  // namespace
 
@@ -49,16 +51,17 @@ void free_term_layout(TermLayout *t) {
     *t = TermLayout{};
 }
 
-// Eq. (9) with k = 0: every listed mode (l, m >= 0, n) contributes A_lmn Y_lm to
-// the signed term (m, n); for m > 0 its mirror contributes
-// (-1)^l conj(A_lmn) Y_{l,-m} to the term (-m, -n).  For fixed viewing angles
-// the l-sum of Eq. (10) then folds into one complex cubic per signed (m, n).
-int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
+// Eq. (9): every listed mode (l, m >= 0, k, n) contributes A Y_lm to the
+// signed term (m, k, n); for m > 0 its mirror contributes
+// (-1)^{l+k} conj(A) Y_{l,-m} to the term (-m, -k, -n).  For fixed viewing
+// angles the l-sum then folds into one complex cubic per signed (m, k, n).
+// width 3: modes (l, m, n) with k = 0 (Schwarzschild); width 4: (l, m, k, n).
+int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermLayout *out) {
     *out = TermLayout{};
-    if (M < 1 || !lmn) return FEW_E_ARG;
-    // order by (m, n, k, mirror): entries are generated in (k, mirror) order,
-    // then a stable two-pass radix sort on the 18-bit key (m, n) keeps that
-    // order inside each (m, n)
+    if (M < 1 || !modes || (width != 3 && width != 4)) return FEW_E_ARG;
+    // order by (m, kp, n, listed index, mirror): entries are generated in
+    // (index, mirror) order, then a stable radix sort on the 23-bit key
+    // (m, kp, n) keeps that order inside each term
     // (scratch vectors are reused per thread: fresh large blocks would be
     // mapped and faulted in on every call)
     thread_local std::vector<Entry> gen, e;
@@ -66,46 +69,53 @@ int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
     thread_local std::vector<int> segs, term_ptr, src, chunks;
     gen.clear();
     key.clear();
+    auto pack = [](int m, int kp, int n) {
+        return (uint32_t)((m + kMaxL) << 17 | (kp + kMaxAbsK) << 11 | (n + kMaxAbsN));
+    };
     for (int k = 0; k < M; ++k) {
-        int l = lmn[3 * k], m = lmn[3 * k + 1], n = lmn[3 * k + 2];
-        if (l < 2 || l > kMaxL || m < 0 || m > l || n < -kMaxAbsN || n > kMaxAbsN)
+        const int32_t *md = modes + (size_t)width * k;
+        int l = md[0], m = md[1], kp = width == 4 ? md[2] : 0, n = md[width - 1];
+        if (l < 2 || l > kMaxL || m < 0 || m > l || n < -kMaxAbsN || n > kMaxAbsN ||
+            kp < -kMaxAbsK || kp > kMaxAbsK)
             return FEW_E_MODES;
-        gen.push_back({m, n, k, l, m, 0});
-        key.push_back((uint32_t)((m + kMaxL) << 12 | (n + kMaxAbsN)));
+        gen.push_back({m, kp, n, k, l, m, 0});
+        key.push_back(pack(m, kp, n));
         if (m > 0) {
-            gen.push_back({-m, -n, k, l, m, 1});
-            key.push_back((uint32_t)((-m + kMaxL) << 12 | (-n + kMaxAbsN)));
+            gen.push_back({-m, -kp, -n, k, l, m, 1});
+            key.push_back(pack(-m, -kp, -n));
         }
     }
     const size_t ne = gen.size();
     idx.resize(ne);
     tmp.resize(ne);
     for (size_t q = 0; q < ne; ++q) idx[q] = (uint32_t)q;
-    for (int pass = 0; pass < 2; ++pass) {
-        const int shift = 9 * pass;
-        uint32_t count[513] = {0};
-        for (size_t q = 0; q < ne; ++q) ++count[((key[idx[q]] >> shift) & 511) + 1];
-        for (int b = 0; b < 512; ++b) count[b + 1] += count[b];
-        for (size_t q = 0; q < ne; ++q) tmp[count[(key[idx[q]] >> shift) & 511]++] = idx[q];
+    for (int pass = 0; pass < 3; ++pass) {
+        const int shift = 8 * pass;
+        uint32_t count[257] = {0};
+        for (size_t q = 0; q < ne; ++q) ++count[((key[idx[q]] >> shift) & 255) + 1];
+        for (int b = 0; b < 256; ++b) count[b + 1] += count[b];
+        for (size_t q = 0; q < ne; ++q) tmp[count[(key[idx[q]] >> shift) & 255]++] = idx[q];
         idx.swap(tmp);
     }
     e.resize(ne);
     for (size_t q = 0; q < ne; ++q) e[q] = gen[idx[q]];
 
-    // segments over distinct (m, n): segs (m, n_lo, len, first), term_ptr
-    // (first contributor of each term), src (contributors)
+    // segments over distinct (m, kp, n) with contiguous n: segs
+    // (m + 256 kp, n_lo, len, first), term_ptr (first contributor of each
+    // term), src (contributors: listed index, l | m << 8 | mirror << 16 |
+    // (kp + 64) << 17)
     segs.clear();
     term_ptr.clear();
     src.clear();
     size_t p = 0;
     int term = 0;
     while (p < e.size()) {
-        int m = e[p].m;
+        int m = e[p].m, kp = e[p].kp;
         int n_lo = e[p].n, n_prev = e[p].n;
         int first = term;
-        // extend while the next distinct n in this m is within the allowed gap
+        // extend while the next distinct n of this (m, kp) is within the gap
         size_t q = p;
-        while (q < e.size() && e[q].m == m) {
+        while (q < e.size() && e[q].m == m && e[q].kp == kp) {
             int n = e[q].n;
             if (n > n_prev + 1 + max_gap && q != p) break;
             // no segment longer than one LDS chunk
@@ -117,14 +127,15 @@ int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
             }
             term_ptr.push_back((int)src.size() / 2);
             ++term;
-            while (q < e.size() && e[q].m == m && e[q].n == n) {
+            while (q < e.size() && e[q].m == m && e[q].kp == kp && e[q].n == n) {
                 src.push_back(e[q].k);
-                src.push_back(e[q].l | (e[q].mode_m << 8) | (e[q].mirror << 16));
+                src.push_back(e[q].l | (e[q].mode_m << 8) | (e[q].mirror << 16) |
+                              ((e[q].kp + 64) << 17));
                 ++q;
             }
             n_prev = n;
         }
-        segs.push_back(m);
+        segs.push_back(m + 256 * kp);
         segs.push_back(n_lo);
         segs.push_back(term - first);
         segs.push_back(first);
@@ -167,7 +178,7 @@ int build_term_layout(int M, const int32_t *lmn, int max_gap, TermLayout *out) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
-                         int n_chunks) {
+                         int n_chunks, int n_ph) {
     ReqLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -183,7 +194,7 @@ ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n
     L.off_chunks = take(sizeof(int) * (size_t)(n_chunks + 1));
     L.upload_end = L.off_chunks + sizeof(int) * (size_t)(n_chunks + 1);
     // device-produced arrays
-    L.off_pcoef = take(sizeof(double) * 16 * (size_t)(K - 1));
+    L.off_pcoef = take(sizeof(double) * 8 * n_ph * (size_t)(K - 1));
     L.dev_begin = L.off_pcoef;
     L.off_acoef = take(sizeof(double) * 8 * (size_t)(K - 1) * M);
     L.off_ybuf = take(sizeof(double) * 2 * (size_t)std::max(n_src, 1));
@@ -198,15 +209,15 @@ ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n
 
 using namespace few;
 
-extern "C" int32_t few_host_terms(int32_t M, const int32_t *lmn, int32_t max_gap,
-                                  int32_t cap_segs, int32_t *segs, int32_t *n_segs,
-                                  int32_t cap_terms, int32_t *term_ptr, int32_t *n_terms,
-                                  int32_t cap_src, int32_t *term_src, int32_t *n_src) {
-    if (!lmn || !segs || !n_segs || !term_ptr || !n_terms || !term_src || !n_src ||
+static int32_t host_terms(int32_t M, const int32_t *modes, int width, int32_t max_gap,
+                          int32_t cap_segs, int32_t *segs, int32_t *n_segs,
+                          int32_t cap_terms, int32_t *term_ptr, int32_t *n_terms,
+                          int32_t cap_src, int32_t *term_src, int32_t *n_src) {
+    if (!modes || !segs || !n_segs || !term_ptr || !n_terms || !term_src || !n_src ||
         max_gap < 0)
         return FEW_E_ARG;
     TermLayout L;
-    int rc = build_term_layout(M, lmn, max_gap, &L);
+    int rc = build_term_layout(M, modes, width, max_gap, &L);
     if (rc) return rc;
     *n_segs = L.n_segs;
     *n_terms = L.n_terms;
@@ -222,6 +233,22 @@ extern "C" int32_t few_host_terms(int32_t M, const int32_t *lmn, int32_t max_gap
     return FEW_OK;
 }
 
+extern "C" int32_t few_host_terms(int32_t M, const int32_t *lmn, int32_t max_gap,
+                                  int32_t cap_segs, int32_t *segs, int32_t *n_segs,
+                                  int32_t cap_terms, int32_t *term_ptr, int32_t *n_terms,
+                                  int32_t cap_src, int32_t *term_src, int32_t *n_src) {
+    return host_terms(M, lmn, 3, max_gap, cap_segs, segs, n_segs, cap_terms, term_ptr,
+                      n_terms, cap_src, term_src, n_src);
+}
+
+extern "C" int32_t few_host_terms_kerr(int32_t M, const int32_t *lmkn, int32_t max_gap,
+                                       int32_t cap_segs, int32_t *segs, int32_t *n_segs,
+                                       int32_t cap_terms, int32_t *term_ptr, int32_t *n_terms,
+                                       int32_t cap_src, int32_t *term_src, int32_t *n_src) {
+    return host_terms(M, lmkn, 4, max_gap, cap_segs, segs, n_segs, cap_terms, term_ptr,
+                      n_terms, cap_src, term_src, n_src);
+}
+
 extern "C" int32_t few_host_interval_starts(int32_t K, const double *t_knots, double t_start,
                                             double dt, int64_t n, int64_t *starts) {
     if (!t_knots || !starts || K < 4 || n < 1 || !(dt > 0.0)) return FEW_E_ARG;
@@ -233,6 +260,7 @@ extern "C" uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t
                                            int32_t n_terms) {
     if (K < 4 || M < 1 || n_terms < 1) return 0;
     // n_src <= 2M, n_segs <= n_terms
-    ReqLayout L = request_layout(precision == FEW_MIXED, K, M, n_terms, n_terms, 2 * M, n_terms);
+    ReqLayout L = request_layout(precision == FEW_MIXED, K, M, n_terms, n_terms, 2 * M, n_terms,
+                                 3);
     return (uint64_t)L.total;
 }

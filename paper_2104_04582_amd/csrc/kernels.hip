@@ -98,7 +98,7 @@ __device__ __forceinline__ double dev_sample_time(double t_start, double dt, lon
 // LDS (binary64 arrays of length K): h hi/lo, delta hi/lo, w, inverse pivot,
 // first solution s0, right-hand side / residual / correction.
 __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
-    const double *y = ph ? jb.phi_r : jb.phi_phi;
+    const double *y = ph == 0 ? jb.phi_phi : (ph == 1 ? jb.phi_r : jb.phi_theta);
     const double *t = jb.t;
     const int K = jb.K;
     const int tid = threadIdx.x, bs = blockDim.x;
@@ -192,7 +192,7 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
         const dd c = dd_div(dd_sub(dd_sub(dd_mul_d(d, 3.0), dd_mul_d(sa, 2.0)), sb), h);
         const dd e = dd_div(dd_sub(dd_add(sa, sb), dd_mul_d(d, 2.0)), dd_mul(h, h));
         const dd a = dd_reduce_2pi(dd_make(y[r]));
-        double *o = pc + ((size_t)r * 2 + ph) * 8;
+        double *o = pc + ((size_t)r * jb.n_ph + ph) * 8;
         o[0] = a.hi; o[1] = a.lo;
         o[2] = sa.hi; o[3] = sa.lo;
         o[4] = c.hi; o[5] = c.lo;
@@ -296,13 +296,14 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     }
 }
 
+// Workgroups 0 .. n_ph-1 fit the phases, the rest the amplitude series.
 __device__ __forceinline__ void fit_body(const FitJob &jb, double *lds) {
-    if (blockIdx.x < 2) {
+    if ((int)blockIdx.x < jb.n_ph) {
         fit_phase_dd(jb, blockIdx.x, lds);
         return;
     }
-    if ((int)blockIdx.x - 2 >= jb.amp_blocks) return;
-    fit_amplitudes(jb, blockIdx.x - 2, lds);
+    if ((int)blockIdx.x - jb.n_ph >= jb.amp_blocks) return;
+    fit_amplitudes(jb, blockIdx.x - jb.n_ph, lds);
 }
 
 __global__ __launch_bounds__(256) void fit_kernel(FitJob jb) {
@@ -396,17 +397,18 @@ __device__ void prep_intervals(const PrepJob &jb) {
 }
 
 // Harmonic weight of one contributor: -2Y_lm for a listed mode and
-// (-1)^l -2Y_{l,-m} for its mirror (Eq. (9) with k = 0).
+// (-1)^{l+k} -2Y_{l,-m} for its mirror (Eq. (9); k = 0 in Schwarzschild).
 __device__ void prep_harmonic(const PrepJob &jb, int e) {
     if (e >= jb.n_src) return;
     const int2 s = jb.term_src[e];
     const int l = s.y & 255, m = (s.y >> 8) & 255, mir = (s.y >> 16) & 1;
+    const int kp = ((s.y >> 17) & 127) - 64;
     double yr, yi;
     if (!mir) {
         few_swsh_m2(l, m, jb.theta, jb.phi, &yr, &yi);
     } else {
         few_swsh_m2(l, -m, jb.theta, jb.phi, &yr, &yi);
-        if (l & 1) {
+        if ((l + kp) & 1) {
             yr = -yr;
             yi = -yi;
         }
@@ -482,29 +484,21 @@ __global__ __launch_bounds__(256) void fold_batch_kernel(const PrepJob *jobs) {
 // ===========================================================================
 #pragma clang fp contract(off)
 
-// Reduced phases at one sample (both in [-pi, pi]).  pc: the interval's
-// [2][4][2] double-double phase cubic.
+// One reduced phase at one sample (in [-pi, pi]).  c: the interval's [4][2]
+// double-double cubic of that phase.
 template <bool DD>
-__device__ __forceinline__ void phase_eval(const FEW_AS4 double *pc, dd x, double *pf,
-                                           double *pr) {
-#pragma unroll
-    for (int ph = 0; ph < 2; ++ph) {
-        const FEW_AS4 double *c = pc + ph * 8;
-        double out;
-        if (DD) {
-            dd v = dd_make(c[6], c[7]);
-            v = dd_add(dd_mul(v, x), dd_make(c[4], c[5]));
-            v = dd_add(dd_mul(v, x), dd_make(c[2], c[3]));
-            v = dd_mul(v, x);
-            v = dd_add(v, dd_make(c[0], c[1]));
-            out = dd_reduce_2pi(v).hi;
-        } else {
-            const double xx = x.hi;
-            double v = fma(fma(fma(c[6], xx, c[4]), xx, c[2]), xx, c[0]);
-            out = d_reduce_2pi(v);
-        }
-        if (ph == 0) *pf = out; else *pr = out;
+__device__ __forceinline__ double phase_eval(const FEW_AS4 double *c, dd x) {
+    if (DD) {
+        dd v = dd_make(c[6], c[7]);
+        v = dd_add(dd_mul(v, x), dd_make(c[4], c[5]));
+        v = dd_add(dd_mul(v, x), dd_make(c[2], c[3]));
+        v = dd_mul(v, x);
+        v = dd_add(v, dd_make(c[0], c[1]));
+        return dd_reduce_2pi(v).hi;
     }
+    const double xx = x.hi;
+    const double v = fma(fma(fma(c[6], xx, c[4]), xx, c[2]), xx, c[0]);
+    return d_reduce_2pi(v);
 }
 
 // e^{-i a} for a reduced phase a in [-pi, pi] (binary64): the binary32 path
@@ -525,15 +519,20 @@ __device__ __forceinline__ void unit_phasor(double a, Real *re, Real *im) {
     }
 }
 
-// Per-lane state of SL samples of one tile.
-template <typename Real, int SL>
+// Per-lane state of SL samples of one tile.  NP = 3 (generic Kerr) adds the
+// polar phase and e^{-i Phi_theta}.
+template <typename Real, int SL, int NP>
 struct LaneState {
-    Real u[SL], fr[SL], fi[SL], er[SL], ei[SL];
-    double pf[SL], pr[SL];
+    static constexpr int ST = NP == 3 ? SL : 1;
+    Real u[SL], fr[SL], fi[SL], er[SL], ei[SL], tr[ST], ti[ST];
+    double pf[SL], pr[SL], pt[ST];
     long long jj[SL];
     Real hr[SL], hq[SL], cr[SL], cq[SL], zr[SL], zi[SL];
-    int pm, pn;
+    int pm, pk, pn;
 };
+
+// Segment record x = m + 256 k (k = 0 in Schwarzschild).
+__device__ __forceinline__ int seg_k(int x) { return (x + 128) >> 8; }
 
 // Knot interval of tile `local` (tp: tiles before each interval of one part).
 __device__ __forceinline__ int tile_interval(const FEW_AS4 int *tp, int K, int local) {
@@ -546,14 +545,14 @@ __device__ __forceinline__ int tile_interval(const FEW_AS4 int *tp, int K, int l
 }
 
 // Per-sample setup: samples j0 + s * 64 + lane (s < SL), valid below j1.
-template <typename Real, int SL, bool DD>
-__device__ __forceinline__ void lane_setup(LaneState<Real, SL> &L, const SumJob &jb, int iv,
+template <typename Real, int SL, bool DD, int NP>
+__device__ __forceinline__ void lane_setup(LaneState<Real, SL, NP> &L, const SumJob &jb, int iv,
                                            long long j0, long long j1) {
     const int lane = threadIdx.x & (kWave - 1);
     const FEW_AS4 double *tk = cptr(jb.t);
     const double ti = tk[iv];
     const double inv_h = 1.0 / (tk[iv + 1] - ti);
-    const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 16;
+    const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 8 * NP;   // Phi_phi, Phi_r (, Phi_theta)
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
         long long j = j0 + s * kWave + lane;
@@ -561,14 +560,20 @@ __device__ __forceinline__ void lane_setup(LaneState<Real, SL> &L, const SumJob 
         if (j >= j1) j = j1 - 1;
         const double tj = dev_sample_time(jb.t_start, jb.dt, j);
         const dd x = two_sum(tj, -ti);
-        phase_eval<DD>(pc, x, &L.pf[s], &L.pr[s]);
+        L.pf[s] = phase_eval<DD>(pc, x);
+        L.pr[s] = phase_eval<DD>(pc + 8, x);
         L.u[s] = (Real)(x.hi * inv_h);
         unit_phasor<Real>(L.pf[s], &L.er[s], &L.ei[s]);
         unit_phasor<Real>(L.pr[s], &L.fr[s], &L.fi[s]);
+        if constexpr (NP == 3) {
+            L.pt[s] = phase_eval<DD>(pc + 16, x);
+            unit_phasor<Real>(L.pt[s], &L.tr[s], &L.ti[s]);
+        }
         L.hr[s] = L.hq[s] = L.cr[s] = L.cq[s] = (Real)0;
         L.zr[s] = L.zi[s] = (Real)0;
     }
     L.pm = INT_MIN / 2;
+    L.pk = INT_MIN / 2;
     L.pn = INT_MIN / 2;
 }
 
@@ -588,9 +593,10 @@ __device__ __forceinline__ void load_term(const float *cp, float *c) {
     c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
 }
 
-// One segment: seed e^{-i(m Phi_phi + n_lo Phi_r)} (chained by e^{-i Phi_phi}
-// when m steps by one at the same n_lo), Horner over its terms in
-// f = e^{-i Phi_r} from the highest n down,
+// One segment: seed e^{-i(m Phi_phi + k Phi_theta + n_lo Phi_r)} (chained
+// from the previous segment's by e^{-i Phi_phi} when only m steps by one, or by
+// e^{-i Phi_theta} when only k does, at the same n_lo; else one sincos),
+// Horner over its terms in f = e^{-i Phi_r} from the highest n down,
 //   S <- S f + C_n(u),  C_n(u) = c0 + c1 u + c2 u^2 + c3 u^3,
 // then h += seed * S (Kahan-compensated when COMP).  `last` points at the 8
 // values (c0r, c0i, ..., c3i) of the segment's highest-n term; earlier terms
@@ -598,24 +604,38 @@ __device__ __forceinline__ void load_term(const float *cp, float *c) {
 // C_n(u) by Horner in u apart from the recurrence, leaving two dependent FMAs
 // per term on it; binary64 (coefficients in SGPRs, one scalar operand per
 // instruction) chains all five FMAs of each component into the recurrence.
-template <typename Real, int SL, bool COMP, typename Ptr>
-__device__ __forceinline__ void seg_step(LaneState<Real, SL> &L, const int4 S, Ptr last) {
-    if (S.x == L.pm + 1 && S.y == L.pn) {
+template <typename Real, int SL, bool COMP, int NP, typename Ptr>
+__device__ __forceinline__ void seg_step(LaneState<Real, SL, NP> &L, const int4 S, Ptr last) {
+    const int k = NP == 3 ? seg_k(S.x) : 0;
+    const int m = S.x - 256 * k;
+    const bool step_m = m == L.pm + 1 && k == L.pk && S.y == L.pn;
+    const bool step_k = NP == 3 && m == L.pm && k == L.pk + 1 && S.y == L.pn;
+    if (step_m || step_k) {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
-            const Real a = L.zr[s] * L.er[s] - L.zi[s] * L.ei[s];
-            const Real b = L.zr[s] * L.ei[s] + L.zi[s] * L.er[s];
+            Real gr, gi;
+            if constexpr (NP == 3) {
+                gr = step_k ? L.tr[s] : L.er[s];
+                gi = step_k ? L.ti[s] : L.ei[s];
+            } else {
+                gr = L.er[s];
+                gi = L.ei[s];
+            }
+            const Real a = L.zr[s] * gr - L.zi[s] * gi;
+            const Real b = L.zr[s] * gi + L.zi[s] * gr;
             L.zr[s] = a;
             L.zi[s] = b;
         }
     } else {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
-            const double a = d_reduce_2pi((double)S.x * L.pf[s] + (double)S.y * L.pr[s]);
-            unit_phasor<Real>(a, &L.zr[s], &L.zi[s]);
+            double ph = (double)m * L.pf[s] + (double)S.y * L.pr[s];
+            if constexpr (NP == 3) ph = ph + (double)k * L.pt[s];
+            unit_phasor<Real>(d_reduce_2pi(ph), &L.zr[s], &L.zi[s]);
         }
     }
-    L.pm = S.x;
+    L.pm = m;
+    L.pk = k;
     L.pn = S.y;
     Real sr[SL], si[SL];
 #pragma unroll
@@ -684,8 +704,8 @@ __device__ __forceinline__ void seg_step(LaneState<Real, SL> &L, const int4 S, P
     }
 }
 
-template <typename Real, int SL, bool COMP>
-__device__ __forceinline__ void lane_store(const LaneState<Real, SL> &L, const SumJob &jb,
+template <typename Real, int SL, bool COMP, int NP>
+__device__ __forceinline__ void lane_store(const LaneState<Real, SL, NP> &L, const SumJob &jb,
                                            long long j1) {
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
@@ -704,22 +724,22 @@ __device__ __forceinline__ void lane_store(const LaneState<Real, SL> &L, const S
 
 // Wave tile (binary64 path): 64 x SL consecutive samples [j0, j1) of interval
 // iv, coefficients read by scalar loads straight into SGPR operands.
-template <typename Real, int SL, bool COMP, bool DD>
+template <typename Real, int SL, bool COMP, bool DD, int NP>
 __device__ __forceinline__ void sum_wave_run(const SumJob &jb, int iv, long long j0,
                                              long long j1) {
-    LaneState<Real, SL> L;
-    lane_setup<Real, SL, DD>(L, jb, iv, j0, j1);
+    LaneState<Real, SL, NP> L;
+    lane_setup<Real, SL, DD, NP>(L, jb, iv, j0, j1);
     const FEW_AS4 Real *tab = cptr((const Real *)jb.table) + (size_t)iv * jb.n_terms * 8;
     for (int g = 0; g < jb.n_segs; ++g) {
         const int4 S = load_uniform(jb.segs + g);
-        seg_step<Real, SL, COMP>(L, S, tab + (size_t)(S.w + S.z - 1) * 8);
+        seg_step<Real, SL, COMP, NP>(L, S, tab + (size_t)(S.w + S.z - 1) * 8);
     }
-    lane_store<Real, SL, COMP>(L, jb, j1);
+    lane_store<Real, SL, COMP, NP>(L, jb, j1);
 }
 
 // Wave tile `local` of part `pt` of a request (binary64 launches use long
 // tiles only).
-template <typename Real, bool COMP, bool DD>
+template <typename Real, bool COMP, bool DD, int NP>
 __device__ __forceinline__ void sum_tile(const SumJob &jb, int pt, int local) {
     const FEW_AS4 int *tp = cptr(jb.tile_pref) + (size_t)pt * jb.K;
     if (local >= tp[jb.K - 1]) return;
@@ -728,7 +748,7 @@ __device__ __forceinline__ void sum_tile(const SumJob &jb, int pt, int local) {
     const PieceRange pr = piece_range(st[iv], st[iv + 1], jb.n, jb.parts, pt, 0);
     constexpr int LT = kWave * kSamplesPerLaneF64;
     const long long j0 = pr.lo + (long long)(local - tp[iv]) * LT;
-    sum_wave_run<Real, kSamplesPerLaneF64, COMP, DD>(jb, iv, j0, min(j0 + LT, pr.hi));
+    sum_wave_run<Real, kSamplesPerLaneF64, COMP, DD, NP>(jb, iv, j0, min(j0 + LT, pr.hi));
 }
 
 // Workgroup tile (binary32 path): 4 waves x 64 x SL consecutive samples
@@ -737,15 +757,15 @@ __device__ __forceinline__ void sum_tile(const SumJob &jb, int pt, int local) {
 // every wave reads each term with broadcast LDS loads into VGPRs: FMAs without
 // scalar operands issue at twice the rate on gfx950.  Every lane of the
 // workgroup reaches every barrier.
-template <typename Real, int SL, bool COMP, bool DD>
+template <typename Real, int SL, bool COMP, bool DD, int NP>
 __device__ __forceinline__ void sum_wg_run(const SumJob &jb, int iv, long long base,
                                            long long j1, Real *buf) {
     constexpr int WT = kWave * SL;                  // samples per wave
     const int wave = threadIdx.x / kWave;
     // a wave past the end of a partial tile only helps stage coefficients
     const bool busy = base + (long long)wave * WT < j1;
-    LaneState<Real, SL> L;
-    if (busy) lane_setup<Real, SL, DD>(L, jb, iv, base + (long long)wave * WT, j1);
+    LaneState<Real, SL, NP> L;
+    if (busy) lane_setup<Real, SL, DD, NP>(L, jb, iv, base + (long long)wave * WT, j1);
     const Real *tab = (const Real *)jb.table + (size_t)iv * jb.n_terms * 8;
     const FEW_AS4 int *ch = cptr(jb.chunks);
     for (int c = 0; c < jb.n_chunks; ++c) {
@@ -761,17 +781,17 @@ __device__ __forceinline__ void sum_wg_run(const SumJob &jb, int iv, long long b
         if (busy) {
             for (int g = g0; g < g1; ++g) {
                 const int4 S = load_uniform(jb.segs + g);
-                seg_step<Real, SL, COMP>(L, S, buf + (S.w - t0 + S.z - 1) * 8);
+                seg_step<Real, SL, COMP, NP>(L, S, buf + (S.w - t0 + S.z - 1) * 8);
             }
         }
     }
-    if (busy) lane_store<Real, SL, COMP>(L, jb, j1);
+    if (busy) lane_store<Real, SL, COMP, NP>(L, jb, j1);
 }
 
 // Tile `local` of part `pt` of a request: the part's samples in its interval,
 // [lo, hi), are covered by long tiles up to `split` and short tiles after it.
 // The branch is uniform per workgroup.
-template <typename Real, bool COMP, bool DD>
+template <typename Real, bool COMP, bool DD, int NP>
 __device__ __forceinline__ void sum_wg_tile(const SumJob &jb, int pt, int local, Real *buf) {
     const FEW_AS4 int *tp = cptr(jb.tile_pref) + (size_t)pt * jb.K;
     if (local >= tp[jb.K - 1]) return;
@@ -784,12 +804,12 @@ __device__ __forceinline__ void sum_wg_tile(const SumJob &jb, int pt, int local,
     const int r = local - tp[iv];
     if (r < n_long) {
         const long long base = pr.lo + (long long)r * LT;
-        sum_wg_run<Real, kSamplesPerLaneF32, COMP, DD>(jb, iv, base, min(base + LT, pr.split),
-                                                       buf);
+        sum_wg_run<Real, kSamplesPerLaneF32, COMP, DD, NP>(jb, iv, base,
+                                                           min(base + LT, pr.split), buf);
     } else {
         const long long base = pr.split + (long long)(r - n_long) * ST;
-        sum_wg_run<Real, kSamplesPerLaneShort, COMP, DD>(jb, iv, base, min(base + ST, pr.hi),
-                                                         buf);
+        sum_wg_run<Real, kSamplesPerLaneShort, COMP, DD, NP>(jb, iv, base,
+                                                             min(base + ST, pr.hi), buf);
     }
 }
 
@@ -821,21 +841,21 @@ __device__ __forceinline__ int find_job(const SumJob *jobs, int n_jobs, int w) {
 // One request: workgroup b runs on XCD b mod 8 (workgroups are dealt to the
 // XCDs in turn), so part b mod parts is that XCD's; its waves take the part's
 // tiles in dispatch order.  `slots`: wave tiles per part.
-template <typename Real, bool COMP, bool DD>
+template <typename Real, bool COMP, bool DD, int NP>
 __global__ __launch_bounds__(256) FEW_F64_ATTR void sum_kernel(SumJob jb, int slots) {
     const int b = blockIdx.x;
     const int pt = b % jb.parts;
     const int w = __builtin_amdgcn_readfirstlane(
         (int)((b / jb.parts) * (blockDim.x / kWave) + threadIdx.x / kWave));
     if (w >= slots) return;
-    sum_tile<Real, COMP, DD>(jb, pt, w);
+    sum_tile<Real, COMP, DD, NP>(jb, pt, w);
 }
 
 template <typename Real, bool COMP, bool DD>
 __device__ __forceinline__ void sum_slot(const SumJob *jobs, int n_jobs, int w) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, w));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_tile<Real, COMP, DD>(jb, 0, w - jb.wave_base);
+    sum_tile<Real, COMP, DD, 2>(jb, 0, w - jb.wave_base);
 }
 
 template <typename Real, bool COMP, bool DD>
@@ -866,20 +886,20 @@ __global__ __launch_bounds__(256) FEW_F64_ATTR void sum_persistent_kernel(const 
 // that part's tiles in dispatch order, so each XCD reads the coefficients of its
 // own intervals and ends on its short tiles while its last long tiles finish.
 // `slots`: tiles per part.
-template <typename Real, bool COMP, bool DD>
+template <typename Real, bool COMP, bool DD, int NP>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_kernel(SumJob jb, int slots) {
     extern __shared__ float4 sum_lds[];
     const int b = blockIdx.x;
     const int local = b / jb.parts;
     if (local >= slots) return;
-    sum_wg_tile<Real, COMP, DD>(jb, b % jb.parts, local, (Real *)sum_lds);
+    sum_wg_tile<Real, COMP, DD, NP>(jb, b % jb.parts, local, (Real *)sum_lds);
 }
 
 template <typename Real, bool COMP, bool DD>
 __device__ __forceinline__ void sum_wg_slot(const SumJob *jobs, int n_jobs, int b, Real *buf) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, b));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_wg_tile<Real, COMP, DD>(jb, 0, b - jb.wave_base, buf);
+    sum_wg_tile<Real, COMP, DD, 2>(jb, 0, b - jb.wave_base, buf);
 }
 
 template <typename Real, bool COMP, bool DD>
@@ -1089,14 +1109,14 @@ static inline size_t fit_lds_bytes(int K) {
 }
 
 hipError_t launch_fit(const FitJob &job, hipStream_t stream) {
-    dim3 grid(2 + job.amp_blocks);
+    dim3 grid(job.n_ph + job.amp_blocks);
     hipLaunchKernelGGL(fit_kernel, grid, dim3(256), fit_lds_bytes(job.K), stream, job);
     return hipGetLastError();
 }
 
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream) {
-    dim3 grid(2 + max_blocks, n_jobs);
+    dim3 grid(kMaxPhases + max_blocks, n_jobs);
     hipLaunchKernelGGL(fit_batch_kernel, grid, dim3(256), fit_lds_bytes(max_K), stream,
                        jobs_dev);
     return hipGetLastError();
@@ -1130,13 +1150,14 @@ hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_src
 
 static inline size_t sum_lds_bytes() { return sizeof(float) * 8 * (size_t)kChunkTerms; }
 
-int sum_resident_workgroups() {
+int sum_resident_workgroups(int n_ph) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, (const void *)sum_wg_kernel<float, true, false>, 256, sum_lds_bytes()) !=
+    const void *fn = n_ph == 3 ? (const void *)sum_wg_kernel<float, true, false, 3>
+                               : (const void *)sum_wg_kernel<float, true, false, 2>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, sum_lds_bytes()) !=
         hipSuccess)
         return 0;
     return cus * per_cu;
@@ -1144,14 +1165,25 @@ int sum_resident_workgroups() {
 
 hipError_t launch_sum(const SumJob &job, int slots, bool fp32, hipStream_t stream) {
     const long long parts = job.parts;
+    const bool kerr = job.n_ph == 3;
     if (fp32) {
-        hipLaunchKernelGGL((sum_wg_kernel<float, true, false>), dim3((unsigned)(parts * slots)),
-                           dim3(256), sum_lds_bytes(), stream, job, slots);
+        const dim3 grid((unsigned)(parts * slots));
+        if (kerr)
+            hipLaunchKernelGGL((sum_wg_kernel<float, true, false, 3>), grid, dim3(256),
+                               sum_lds_bytes(), stream, job, slots);
+        else
+            hipLaunchKernelGGL((sum_wg_kernel<float, true, false, 2>), grid, dim3(256),
+                               sum_lds_bytes(), stream, job, slots);
     } else {
         const int waves_per_block = 256 / kWave;
         const long long blocks = (slots + waves_per_block - 1) / waves_per_block;
-        hipLaunchKernelGGL((sum_kernel<double, false, true>), dim3((unsigned)(parts * blocks)),
-                           dim3(256), 0, stream, job, slots);
+        const dim3 grid((unsigned)(parts * blocks));
+        if (kerr)
+            hipLaunchKernelGGL((sum_kernel<double, false, true, 3>), grid, dim3(256), 0, stream,
+                               job, slots);
+        else
+            hipLaunchKernelGGL((sum_kernel<double, false, true, 2>), grid, dim3(256), 0, stream,
+                               job, slots);
     }
     return hipGetLastError();
 }

@@ -35,6 +35,7 @@ EXPORTED = [
     "few_spline_coefs", "few_mode_sum", "few_mode_select", "few_batch", "few_submit",
     "few_poll", "few_wait",
     "few_plan_timing", "few_last_error", "few_host_terms", "few_host_interval_starts",
+    "few_spline_fit_kerr", "few_host_terms_kerr",
     "few_host_request_bytes",
 ]
 
@@ -90,6 +91,7 @@ def load() -> ctypes.CDLL:
     lib.few_plan_create.argtypes = [P(PlanDesc), P(vp)]
     lib.few_plan_destroy.argtypes = [vp]
     lib.few_spline_fit.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, P(vp)]
+    lib.few_spline_fit_kerr.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, P(vp)]
     lib.few_spline_free.argtypes = [vp]
     lib.few_spline_coefs.argtypes = [vp, i32, vp]
     lib.few_mode_sum.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp]
@@ -103,6 +105,8 @@ def load() -> ctypes.CDLL:
     lib.few_last_error.restype = ctypes.c_char_p
     lib.few_host_terms.argtypes = [i32, vp, i32, i32, vp, P(i32), i32, vp, P(i32), i32, vp,
                                    P(i32)]
+    lib.few_host_terms_kerr.argtypes = [i32, vp, i32, i32, vp, P(i32), i32, vp, P(i32), i32,
+                                        vp, P(i32)]
     lib.few_host_interval_starts.argtypes = [i32, vp, dbl, dbl, i64, vp]
     lib.few_host_request_bytes.argtypes = [i32, i32, i32, i32]
     lib.few_host_request_bytes.restype = ctypes.c_uint64
@@ -146,14 +150,16 @@ def _dev_ptr(t, dtype=None, shape=None, name="tensor") -> int:
 class Spline:
     """A fitted spline resident in the plan arena (few_spline)."""
 
-    def __init__(self, plan: "Plan", handle: int, K: int, M: int, keep):
+    def __init__(self, plan: "Plan", handle: int, K: int, M: int, keep, n_phases: int = 2):
         self.plan, self.handle, self.K, self.M = plan, handle, K, M
+        self.n_phases = n_phases
         self._keep = keep          # inputs stay alive until the fit has run
 
     def coefs(self, which: int):
-        """Device copy of the coefficients (0: amplitudes [K-1,M,4,2]; 1: phases [K-1,2,4,2])."""
+        """Device copy of the coefficients (0: amplitudes [K-1,M,4,2]; 1: phases
+        [K-1,P,4,2] with P = 2, or 3 for generic-Kerr splines)."""
         import torch
-        shape = (self.K - 1, self.M, 4, 2) if which == 0 else (self.K - 1, 2, 4, 2)
+        shape = (self.K - 1, self.M, 4, 2) if which == 0 else (self.K - 1, self.n_phases, 4, 2)
         out = torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.plan.device}")
         _check(load().few_spline_coefs(self.handle, which, out.data_ptr()))
         return out
@@ -216,6 +222,21 @@ class Plan:
         _check(load().few_spline_fit(self.handle, K, t.ctypes.data, pp, pr, M, lm.ctypes.data,
                                      ap, ctypes.byref(h)))
         return Spline(self, h.value, K, M, (phi_phi, phi_r, amp))
+
+    def spline_fit_kerr(self, t_knots, phi_phi, phi_theta, phi_r, lmkn, amp) -> "Spline":
+        """few_spline_fit_kerr: modes lmkn [M, 4] = (l, m, k, n), three phases."""
+        import torch
+        t = _host_f64(t_knots)
+        lm = _host_i32(lmkn).reshape(-1, 4)
+        K, M = t.shape[0], lm.shape[0]
+        pp = _dev_ptr(phi_phi, torch.float64, (K,), "phi_phi")
+        pt = _dev_ptr(phi_theta, torch.float64, (K,), "phi_theta")
+        pr = _dev_ptr(phi_r, torch.float64, (K,), "phi_r")
+        ap = _dev_ptr(amp, torch.float64, (K, M, 2), "amp")
+        h = ctypes.c_void_p()
+        _check(load().few_spline_fit_kerr(self.handle, K, t.ctypes.data, pp, pt, pr, M,
+                                          lm.ctypes.data, ap, ctypes.byref(h)))
+        return Spline(self, h.value, K, M, (phi_phi, phi_theta, phi_r, amp), n_phases=3)
 
     def mode_sum(self, spline: Spline, theta: float, phi: float, dt: float, n_samples: int,
                  out=None, t_start: float = 0.0, scale: float = 1.0):
@@ -291,17 +312,22 @@ class Plan:
 
 
 def host_terms(lmn, max_gap: int = 4):
-    """Folded term layout (few_host_terms): (segs [S,4], term_ptr [T+1], term_src [E,2])."""
-    lm = _host_i32(lmn).reshape(-1, 3)
+    """Folded term layout (few_host_terms, or few_host_terms_kerr for modes
+    [M, 4] = (l, m, k, n)): (segs [S,4], term_ptr [T+1], term_src [E,2])."""
+    lm = _host_i32(lmn)
+    width = 4 if lm.ndim == 2 and lm.shape[1] == 4 else 3
+    lm = lm.reshape(-1, width)
     M = lm.shape[0]
-    cap = 4 * M + 64 + 2 * 2001 * 61
-    segs = np.zeros(4 * cap, dtype=np.int32)
-    tp = np.zeros(cap + 1, dtype=np.int32)
+    cap_segs = 2 * M + 64
+    cap_terms = 2 * M * (max_gap + 1) + 64
+    segs = np.zeros(4 * cap_segs, dtype=np.int32)
+    tp = np.zeros(cap_terms + 1, dtype=np.int32)
     src = np.zeros(2 * (2 * M + 1), dtype=np.int32)
     ns, nt, ne = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(load().few_host_terms(M, lm.ctypes.data, max_gap, cap, segs.ctypes.data,
-                                 ctypes.byref(ns), cap + 1, tp.ctypes.data, ctypes.byref(nt),
-                                 2 * M + 1, src.ctypes.data, ctypes.byref(ne)))
+    fn = load().few_host_terms_kerr if width == 4 else load().few_host_terms
+    _check(fn(M, lm.ctypes.data, max_gap, cap_segs, segs.ctypes.data, ctypes.byref(ns),
+              cap_terms + 1, tp.ctypes.data, ctypes.byref(nt), 2 * M + 1, src.ctypes.data,
+              ctypes.byref(ne)))
     return (segs[:4 * ns.value].reshape(-1, 4).copy(), tp[:nt.value + 1].copy(),
             src[:2 * ne.value].reshape(-1, 2).copy())
 

@@ -136,3 +136,72 @@ def test_request_bytes():
     b = native.host_request_bytes("mixed", 100, 3843, 1281)
     assert a > b > 99 * 3843 * 64
     assert native.host_request_bytes("fp64", 3, 10, 10) == 0
+
+
+def check_layout_kerr(lmkn, max_gap):
+    """Generic-Kerr layout: every listed (l, m, k, n) once as itself and, for
+    m > 0, once as its mirror (-m, -k, -n); segments of one signed (m, k) with
+    contiguous n, in (m, k, n) order."""
+    segs, tp, src = native.host_terms(lmkn, max_gap)
+    seen = {}
+    keys = []
+    for s_idx, (x, n_lo, ln, first) in enumerate(segs):
+        k = (int(x) + 128) >> 8
+        m = int(x) - 256 * k
+        keys.append((m, k, int(n_lo)))
+        if s_idx + 1 < len(segs):
+            assert segs[s_idx + 1][3] == first + ln
+        for q in range(ln):
+            for e in range(tp[first + q], tp[first + q + 1]):
+                idx, packed = src[e]
+                l, mm, mir = packed & 255, (packed >> 8) & 255, (packed >> 16) & 1
+                kp = ((packed >> 17) & 127) - 64
+                L, Mm, Kk, N = lmkn[idx]
+                assert (l, mm) == (L, Mm)
+                if mir:
+                    assert (m, k, n_lo + q, kp) == (-Mm, -Kk, -N, -Kk)
+                else:
+                    assert (m, k, n_lo + q, kp) == (Mm, Kk, N, Kk)
+                seen[(idx, mir)] = seen.get((idx, mir), 0) + 1
+    for idx, (L, Mm, Kk, N) in enumerate(lmkn):
+        assert seen.get((idx, 0)) == 1
+        assert seen.get((idx, 1), 0) == (1 if Mm > 0 else 0)
+    assert keys == sorted(keys)
+    return segs, tp, src
+
+
+def test_kerr_term_layout_full_mode_set():
+    lmkn = synth.mode_list_kerr(2, 10, 4, 30)
+    assert lmkn.shape[0] == 34587
+    segs, tp, src = check_layout_kerr(lmkn, 4)
+    assert segs.shape[0] == 21 * 9                   # signed (m, k)
+    assert tp.shape[0] - 1 == 21 * 9 * 61            # signed (m, k, n)
+    n_m0 = int(np.sum(lmkn[:, 1] == 0))
+    assert src.shape[0] == 34587 + (34587 - n_m0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_kerr_term_layout_random_subsets(seed):
+    rng = np.random.default_rng(100 + seed)
+    full = synth.mode_list_kerr(2, 6, 3, 8)
+    lmkn = full[rng.choice(full.shape[0], size=int(rng.integers(1, 80)), replace=True)]
+    for gap in (0, 3):
+        check_layout_kerr(lmkn, gap)
+
+
+def test_kerr_k_zero_layout_equals_schwarzschild():
+    """k = 0 everywhere: the same segments, terms and contributors as the
+    (l, m, n) layout (contributor words carry k + 64 = 64 in both)."""
+    lmn = synth.mode_list(2, 6, 7)
+    a = native.host_terms(lmn)
+    b = native.host_terms(np.insert(lmn, 2, 0, axis=1))
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_kerr_layout_rejects_bad_modes():
+    with pytest.raises(native.FewError) as e:
+        native.host_terms(np.array([[2, 1, 31, 0]]))
+    assert e.value.code == native.FEW_E_MODES
+    with pytest.raises(native.FewError):
+        native.host_terms(np.array([[2, 3, 0, 0]]))
