@@ -6,7 +6,8 @@ library never links or calls it, and it shares no code with the GPU path.
 """
 from .oracle import (OracleError, build, load, spline_coefs, swsh, phase,
                      mode_sum, mode_sum_waveform, ORACLE_SO)
-from .metrics import mismatch, max_rel_error
+from .metrics import mismatch, max_rel_error, inner_flat
 
 __all__ = ["OracleError", "build", "load", "spline_coefs", "swsh", "phase",
-           "mode_sum", "mode_sum_waveform", "mismatch", "max_rel_error", "ORACLE_SO"]
+           "mode_sum", "mode_sum_waveform", "mismatch", "max_rel_error", "inner_flat",
+           "ORACLE_SO"]

@@ -9,6 +9,11 @@ with no maximisation over time or phase shifts.
 
 Max relative error is max_j |a_j - b_j| / max_j |b_j| (a pointwise ratio is
 ill-posed at zeros of h).
+
+inner_flat is the noise-weighted inner product of Sec. VI with S_n = 1,
+4 Re int_0^inf conj(a~(f)) b~(f) df summed over both polarisations, which for
+sampled h = h_plus - i h_cross is exactly 2 dt Re sum_j conj(a_j) b_j
+(discrete Parseval, DC and Nyquist bins counted once).
 """
 from __future__ import annotations
 
@@ -32,3 +37,10 @@ def max_rel_error(a: np.ndarray, ref: np.ndarray) -> float:
     if scale == 0.0:
         return float(np.max(np.abs(a))) if a.size else 0.0
     return float(np.max(np.abs(a - ref)) / scale)
+
+
+def inner_flat(a: np.ndarray, b: np.ndarray, dt: float) -> float:
+    """<a|b> with a unit PSD: 2 dt Re sum_j conj(a_j) b_j (see module docstring)."""
+    a = np.asarray(a, dtype=np.complex128).ravel()
+    b = np.asarray(b, dtype=np.complex128).ravel()
+    return float(2.0 * dt * np.real(np.vdot(a, b)))
