@@ -116,6 +116,33 @@ def kerr_run(native, dev, steps: int = 5, warmup: int = 1):
     return res
 
 
+def inner_timing(native, w, dev, reps: int = 20):
+    """Fused <d|h>, <h|h> (few_inner_product) on the benchmark case: mean time
+    per call after one warm-up, per precision (the spline is fitted once)."""
+    import torch
+    res = {}
+    for prec in ("mixed", "fp64"):
+        cdt = torch.complex64 if prec == "mixed" else torch.complex128
+        pp, pr, amp = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                       for a in (w.phi_phi, w.phi_r, w.amp))
+        data = torch.ones(w.n_samples, dtype=cdt, device=dev)
+        with native.Plan(0, prec) as plan:
+            sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+            r = plan.inner_product(sp, w.theta, w.phi, w.dt, w.n_samples, data)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                plan.inner_product(sp, w.theta, w.phi, w.dt, w.n_samples, data, out2=r)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            res[prec] = {"ms": ms, "mode_samples_per_s": w.mode_samples / (ms * 1e-3),
+                         "hh": float(r[1].item())}
+    return res
+
+
 def select_timing(native, w, dev, eps: float = 1e-5, reps: int = 20):
     """Mode selector on the benchmark amplitudes: kept modes and mean time."""
     import torch
@@ -360,6 +387,9 @@ def main() -> int:
     sel = select_timing(native, w, dev)
     log(f"[bench] mode select: {json.dumps(sel)}")
 
+    inner = inner_timing(native, w, dev)
+    log(f"[bench] fused inner products: {json.dumps(inner)}")
+
     kerr = None
     if not args.no_kerr:
         log("[bench] generic-Kerr sum")
@@ -418,6 +448,7 @@ def main() -> int:
         "canonical_32flop_tflops": {p: res[p]["canonical_tflops"] for p in res},
         "mixed_vs_fp64": {"mismatch": mm, "max_rel_error": mx},
         "mode_select": sel,
+        "fused_inner": inner,
         "kerr": kerr,
         "batched": batch or None,
         "served": serve or None,

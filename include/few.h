@@ -190,6 +190,22 @@ int32_t few_mode_sum(few_plan plan, few_spline spline, double theta, double phi,
                      void *out);
 
 /*
+ * Fused inner products (Sec. VI): the same summation as few_mode_sum, but
+ * instead of writing h it forms, with a unit PSD (by Parseval the one-sided
+ * noise-weighted integral over both polarisations equals this time sum),
+ *   out2[0] = <d|h> = 2 dt sum_j Re(conj(d_j) h_j)
+ *   out2[1] = <h|h> = 2 dt sum_j |h_j|^2
+ * d: device [n_samples] complex data in the plan's output type (complex64 for
+ * FEW_MIXED, complex128 for FEW_FP64).  out2: device float64 [2].  Products
+ * and sums are binary64, added per tile and then in a fixed order, so results
+ * are reproducible.  h is never written; the plan keeps one partial-sum
+ * buffer (16 B per tile) in its arena.  Enqueued on the plan stream.
+ */
+int32_t few_inner_product(few_plan plan, few_spline spline, double theta, double phi,
+                          double scale, double t_start, double dt, int64_t n_samples,
+                          const void *data, double *out2);
+
+/*
  * Mode selector (Sec. III D): choose the modes that carry all but a fraction
  * eps of the power at some knot.  At every knot k the power of mode j is
  * |A_j(t_k)|^2 = re*re + im*im (binary64, no fused multiply-add); modes are

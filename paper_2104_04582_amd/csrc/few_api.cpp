@@ -450,6 +450,11 @@ struct few_plan_s {
     int max_knots = kMaxKnots, max_modes = 65536, max_inflight = 2;
     int resident_wg = 0;        // binary32 summation workgroups resident at once
     int resident_wg3 = 0;       // the same for the generic-Kerr kernel
+    // inner-product partial sums (grown on demand; the plan stream is drained
+    // before a smaller buffer is released)
+    double2 *inner_partial = nullptr;
+    size_t inner_off = SIZE_MAX;
+    long long inner_cap = 0;
     uint64_t budget = 0;
     int flags = 0;
     char *arena_base = nullptr;
@@ -759,12 +764,17 @@ int32_t few_spline_coefs(few_spline s, int32_t which, void *dst) {
     return FEW_OK;
 }
 
-int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double scale,
-                     double t_start, double dt, int64_t n, void *out) {
+namespace {
+// Shared by few_mode_sum (out != null) and few_inner_product (data, out2).
+int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, double t_start,
+             double dt, int64_t n, void *out, const void *data, double *out2) {
     if (!p) return fail(FEW_E_STATE, "null plan");
     if (!s || s->plan != p) return fail(FEW_E_STATE, "spline does not belong to this plan");
+    const bool inner = data != nullptr;
     try {
-        int rc = validate_sum_args(s->h.t.data(), s->h.K, theta, phi, scale, t_start, dt, n, out);
+        if (inner && !out2) return fail(FEW_E_ARG, "null result pointer");
+        int rc = validate_sum_args(s->h.t.data(), s->h.K, theta, phi, scale, t_start, dt, n,
+                                   inner ? data : out);
         if (rc) return rc;
         std::lock_guard<std::mutex> g(p->sync_mu);
         HIP_TRY(hipSetDevice(p->device));
@@ -781,12 +791,44 @@ int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double 
         long long slots = part_tile_bound(n, tl.parts, tl.short_len, s->h.K,
                                           tile_samples(p->fp32), pj.short_tile);
         if (slots * tl.parts > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
+        if (!inner)
+            return timed_launch(p, ST_SUM, p->stream, [&] {
+                return launch_sum(sj, (int)slots, p->fp32, p->stream);
+            });
+        const long long need = inner_slots(tl.parts, (int)slots, p->fp32);
+        if (need > p->inner_cap) {
+            const long long cap = need + need / 4;
+            const size_t off = p->arena.alloc(sizeof(double2) * (size_t)cap);
+            if (off == SIZE_MAX) return fail(FEW_E_NOMEM, "plan arena exhausted (partials)");
+            if (p->inner_off != SIZE_MAX) {
+                HIP_TRY(hipStreamSynchronize(p->stream));   // old buffer no longer in use
+                p->arena.release(p->inner_off);
+            }
+            p->inner_off = off;
+            p->inner_partial = (double2 *)p->arena.ptr(off);
+            p->inner_cap = cap;
+        }
+        sj.data = data;
+        sj.partial = p->inner_partial;
         return timed_launch(p, ST_SUM, p->stream, [&] {
-            return launch_sum(sj, (int)slots, p->fp32, p->stream);
+            return launch_sum_inner(sj, (int)slots, p->fp32, 2.0 * dt, out2, p->stream);
         });
     } catch (...) {
-        return fail(FEW_E_NOMEM, "exception in few_mode_sum");
+        return fail(FEW_E_NOMEM, "exception in the summation call");
     }
+}
+}  // namespace
+
+int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double scale,
+                     double t_start, double dt, int64_t n, void *out) {
+    return sum_impl(p, s, theta, phi, scale, t_start, dt, n, out, nullptr, nullptr);
+}
+
+int32_t few_inner_product(few_plan p, few_spline s, double theta, double phi, double scale,
+                          double t_start, double dt, int64_t n, const void *data,
+                          double *out2) {
+    if (!data) return fail(FEW_E_ARG, "null data pointer");
+    return sum_impl(p, s, theta, phi, scale, t_start, dt, n, nullptr, data, out2);
 }
 
 int32_t few_plan_timing(few_plan p, few_timing *out, int32_t reset) {

@@ -104,7 +104,9 @@ struct SumJob {
     const int *chunks;      // [n_chunks + 1]: first segment of each LDS chunk
     const long long *starts;
     const int *tile_pref;
-    void *out;
+    void *out;              // [n] complex output (store launches)
+    const void *data;       // [n] complex data d (inner-product launches)
+    double2 *partial;       // per tile slot: (sum Re(conj(d) h), sum |h|^2)
     double t_start, dt;
     long long n;
     long long short_len;    // samples at the end of each part cut into short tiles
@@ -124,7 +126,13 @@ hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, 
 hipError_t launch_prepare(const PrepJob &job, bool fp32, hipStream_t stream);
 hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_src_blocks,
                                 int max_fold_blocks, bool fp32, hipStream_t stream);
-hipError_t launch_sum(const SumJob &job, int wave_slots, bool fp32, hipStream_t stream);
+hipError_t launch_sum(const SumJob &job, int slots, bool fp32, hipStream_t stream);
+// Inner-product variant of launch_sum: instead of storing h, every tile slot
+// writes its partial sums to job.partial (inner_slots(...) entries), then one
+// workgroup adds them in a fixed order into out2 = 2 dt (<d|h> sum, <h|h> sum).
+hipError_t launch_sum_inner(const SumJob &job, int slots, bool fp32, double two_dt,
+                            double *out2, hipStream_t stream);
+long long inner_slots(int parts, int slots, bool fp32);
 hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_slots,
                             bool fp32, bool persistent, unsigned *counter_dev,
                             hipStream_t stream);

@@ -722,11 +722,43 @@ __device__ __forceinline__ void lane_store(const LaneState<Real, SL, NP> &L, con
     }
 }
 
+// Inner-product epilogue: this lane's sums of Re(conj(d_j) h_j) and |h_j|^2
+// over its valid samples, in binary64, with h_j exactly the value a store
+// launch would write.
+template <typename Real, int SL, bool COMP, int NP>
+__device__ __forceinline__ double2 lane_inner(const LaneState<Real, SL, NP> &L,
+                                              const SumJob &jb, long long j1) {
+    double dh = 0.0, hh = 0.0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        if (L.jj[s] < j1) {
+            const Real re = COMP ? L.hr[s] - L.cr[s] : L.hr[s];
+            const Real im = COMP ? L.hq[s] - L.cq[s] : L.hq[s];
+            const Real *d = (const Real *)jb.data + 2 * L.jj[s];
+            const double hr = re, hi = im, dr = d[0], di = d[1];
+            dh = dh + (dr * hr + di * hi);
+            hh = hh + (hr * hr + hi * hi);
+        }
+    }
+    return make_double2(dh, hh);
+}
+
+// Sum over the 64 lanes of a wave by a fixed butterfly (every lane ends with
+// the same bits: each step adds the same two values in either lane).
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        v.x = v.x + __shfl_xor(v.x, off);
+        v.y = v.y + __shfl_xor(v.y, off);
+    }
+    return v;
+}
+
 // Wave tile (binary64 path): 64 x SL consecutive samples [j0, j1) of interval
 // iv, coefficients read by scalar loads straight into SGPR operands.
-template <typename Real, int SL, bool COMP, bool DD, int NP>
-__device__ __forceinline__ void sum_wave_run(const SumJob &jb, int iv, long long j0,
-                                             long long j1) {
+template <typename Real, int SL, bool COMP, bool DD, int NP, bool INNER>
+__device__ __forceinline__ double2 sum_wave_run(const SumJob &jb, int iv, long long j0,
+                                                long long j1) {
     LaneState<Real, SL, NP> L;
     lane_setup<Real, SL, DD, NP>(L, jb, iv, j0, j1);
     const FEW_AS4 Real *tab = cptr((const Real *)jb.table) + (size_t)iv * jb.n_terms * 8;
@@ -734,21 +766,27 @@ __device__ __forceinline__ void sum_wave_run(const SumJob &jb, int iv, long long
         const int4 S = load_uniform(jb.segs + g);
         seg_step<Real, SL, COMP, NP>(L, S, tab + (size_t)(S.w + S.z - 1) * 8);
     }
-    lane_store<Real, SL, COMP, NP>(L, jb, j1);
+    if constexpr (INNER) {
+        return lane_inner<Real, SL, COMP, NP>(L, jb, j1);
+    } else {
+        lane_store<Real, SL, COMP, NP>(L, jb, j1);
+        return make_double2(0.0, 0.0);
+    }
 }
 
 // Wave tile `local` of part `pt` of a request (binary64 launches use long
 // tiles only).
-template <typename Real, bool COMP, bool DD, int NP>
-__device__ __forceinline__ void sum_tile(const SumJob &jb, int pt, int local) {
+template <typename Real, bool COMP, bool DD, int NP, bool INNER>
+__device__ __forceinline__ double2 sum_tile(const SumJob &jb, int pt, int local) {
     const FEW_AS4 int *tp = cptr(jb.tile_pref) + (size_t)pt * jb.K;
-    if (local >= tp[jb.K - 1]) return;
+    if (local >= tp[jb.K - 1]) return make_double2(0.0, 0.0);
     const int iv = tile_interval(tp, jb.K, local);
     const FEW_AS4 long long *st = cptr(jb.starts);
     const PieceRange pr = piece_range(st[iv], st[iv + 1], jb.n, jb.parts, pt, 0);
     constexpr int LT = kWave * kSamplesPerLaneF64;
     const long long j0 = pr.lo + (long long)(local - tp[iv]) * LT;
-    sum_wave_run<Real, kSamplesPerLaneF64, COMP, DD, NP>(jb, iv, j0, min(j0 + LT, pr.hi));
+    return sum_wave_run<Real, kSamplesPerLaneF64, COMP, DD, NP, INNER>(jb, iv, j0,
+                                                                       min(j0 + LT, pr.hi));
 }
 
 // Workgroup tile (binary32 path): 4 waves x 64 x SL consecutive samples
@@ -757,9 +795,9 @@ __device__ __forceinline__ void sum_tile(const SumJob &jb, int pt, int local) {
 // every wave reads each term with broadcast LDS loads into VGPRs: FMAs without
 // scalar operands issue at twice the rate on gfx950.  Every lane of the
 // workgroup reaches every barrier.
-template <typename Real, int SL, bool COMP, bool DD, int NP>
-__device__ __forceinline__ void sum_wg_run(const SumJob &jb, int iv, long long base,
-                                           long long j1, Real *buf) {
+template <typename Real, int SL, bool COMP, bool DD, int NP, bool INNER>
+__device__ __forceinline__ double2 sum_wg_run(const SumJob &jb, int iv, long long base,
+                                              long long j1, Real *buf) {
     constexpr int WT = kWave * SL;                  // samples per wave
     const int wave = threadIdx.x / kWave;
     // a wave past the end of a partial tile only helps stage coefficients
@@ -785,16 +823,21 @@ __device__ __forceinline__ void sum_wg_run(const SumJob &jb, int iv, long long b
             }
         }
     }
-    if (busy) lane_store<Real, SL, COMP, NP>(L, jb, j1);
+    if constexpr (INNER) {
+        if (busy) return lane_inner<Real, SL, COMP, NP>(L, jb, j1);
+    } else {
+        if (busy) lane_store<Real, SL, COMP, NP>(L, jb, j1);
+    }
+    return make_double2(0.0, 0.0);
 }
 
 // Tile `local` of part `pt` of a request: the part's samples in its interval,
 // [lo, hi), are covered by long tiles up to `split` and short tiles after it.
 // The branch is uniform per workgroup.
-template <typename Real, bool COMP, bool DD, int NP>
-__device__ __forceinline__ void sum_wg_tile(const SumJob &jb, int pt, int local, Real *buf) {
+template <typename Real, bool COMP, bool DD, int NP, bool INNER>
+__device__ __forceinline__ double2 sum_wg_tile(const SumJob &jb, int pt, int local, Real *buf) {
     const FEW_AS4 int *tp = cptr(jb.tile_pref) + (size_t)pt * jb.K;
-    if (local >= tp[jb.K - 1]) return;
+    if (local >= tp[jb.K - 1]) return make_double2(0.0, 0.0);
     const int iv = tile_interval(tp, jb.K, local);
     const FEW_AS4 long long *st = cptr(jb.starts);
     const PieceRange pr = piece_range(st[iv], st[iv + 1], jb.n, jb.parts, pt, jb.short_len);
@@ -804,12 +847,12 @@ __device__ __forceinline__ void sum_wg_tile(const SumJob &jb, int pt, int local,
     const int r = local - tp[iv];
     if (r < n_long) {
         const long long base = pr.lo + (long long)r * LT;
-        sum_wg_run<Real, kSamplesPerLaneF32, COMP, DD, NP>(jb, iv, base,
-                                                           min(base + LT, pr.split), buf);
+        return sum_wg_run<Real, kSamplesPerLaneF32, COMP, DD, NP, INNER>(
+            jb, iv, base, min(base + LT, pr.split), buf);
     } else {
         const long long base = pr.split + (long long)(r - n_long) * ST;
-        sum_wg_run<Real, kSamplesPerLaneShort, COMP, DD, NP>(jb, iv, base,
-                                                             min(base + ST, pr.hi), buf);
+        return sum_wg_run<Real, kSamplesPerLaneShort, COMP, DD, NP, INNER>(
+            jb, iv, base, min(base + ST, pr.hi), buf);
     }
 }
 
@@ -841,21 +884,28 @@ __device__ __forceinline__ int find_job(const SumJob *jobs, int n_jobs, int w) {
 // One request: workgroup b runs on XCD b mod 8 (workgroups are dealt to the
 // XCDs in turn), so part b mod parts is that XCD's; its waves take the part's
 // tiles in dispatch order.  `slots`: wave tiles per part.
-template <typename Real, bool COMP, bool DD, int NP>
+// INNER: every wave writes its tile's partial sums (zero without a tile) to
+// partial[b * 4 + wave].
+template <typename Real, bool COMP, bool DD, int NP, bool INNER>
 __global__ __launch_bounds__(256) FEW_F64_ATTR void sum_kernel(SumJob jb, int slots) {
     const int b = blockIdx.x;
     const int pt = b % jb.parts;
     const int w = __builtin_amdgcn_readfirstlane(
         (int)((b / jb.parts) * (blockDim.x / kWave) + threadIdx.x / kWave));
-    if (w >= slots) return;
-    sum_tile<Real, COMP, DD, NP>(jb, pt, w);
+    double2 v = make_double2(0.0, 0.0);
+    if (w < slots) v = sum_tile<Real, COMP, DD, NP, INNER>(jb, pt, w);
+    if constexpr (INNER) {
+        v = wave_sum(v);
+        if ((threadIdx.x & (kWave - 1)) == 0)
+            jb.partial[(size_t)b * (blockDim.x / kWave) + threadIdx.x / kWave] = v;
+    }
 }
 
 template <typename Real, bool COMP, bool DD>
 __device__ __forceinline__ void sum_slot(const SumJob *jobs, int n_jobs, int w) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, w));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_tile<Real, COMP, DD, 2>(jb, 0, w - jb.wave_base);
+    sum_tile<Real, COMP, DD, 2, false>(jb, 0, w - jb.wave_base);
 }
 
 template <typename Real, bool COMP, bool DD>
@@ -886,20 +936,37 @@ __global__ __launch_bounds__(256) FEW_F64_ATTR void sum_persistent_kernel(const 
 // that part's tiles in dispatch order, so each XCD reads the coefficients of its
 // own intervals and ends on its short tiles while its last long tiles finish.
 // `slots`: tiles per part.
-template <typename Real, bool COMP, bool DD, int NP>
+// INNER: every workgroup writes its tile's partial sums (zero without a tile)
+// to partial[b], adding its four waves in order.
+template <typename Real, bool COMP, bool DD, int NP, bool INNER>
 __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_kernel(SumJob jb, int slots) {
     extern __shared__ float4 sum_lds[];
     const int b = blockIdx.x;
-    const int local = b / jb.parts;
-    if (local >= slots) return;
-    sum_wg_tile<Real, COMP, DD, NP>(jb, b % jb.parts, local, (Real *)sum_lds);
+    const int local = b / jb.parts;     // < slots: the grid is parts x slots
+    double2 v = sum_wg_tile<Real, COMP, DD, NP, INNER>(jb, b % jb.parts, local,
+                                                       (Real *)sum_lds);
+    if constexpr (INNER) {
+        __shared__ double2 red[4];
+        v = wave_sum(v);
+        if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double2 t = red[0];
+            for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+                t.x = t.x + red[w].x;
+                t.y = t.y + red[w].y;
+            }
+            jb.partial[b] = t;
+        }
+    }
+    (void)slots;
 }
 
 template <typename Real, bool COMP, bool DD>
 __device__ __forceinline__ void sum_wg_slot(const SumJob *jobs, int n_jobs, int b, Real *buf) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, b));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_wg_tile<Real, COMP, DD, 2>(jb, 0, b - jb.wave_base, buf);
+    sum_wg_tile<Real, COMP, DD, 2, false>(jb, 0, b - jb.wave_base, buf);
 }
 
 template <typename Real, bool COMP, bool DD>
@@ -1155,8 +1222,8 @@ int sum_resident_workgroups(int n_ph) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    const void *fn = n_ph == 3 ? (const void *)sum_wg_kernel<float, true, false, 3>
-                               : (const void *)sum_wg_kernel<float, true, false, 2>;
+    const void *fn = n_ph == 3 ? (const void *)sum_wg_kernel<float, true, false, 3, false>
+                               : (const void *)sum_wg_kernel<float, true, false, 2, false>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, sum_lds_bytes()) !=
         hipSuccess)
         return 0;
@@ -1169,22 +1236,84 @@ hipError_t launch_sum(const SumJob &job, int slots, bool fp32, hipStream_t strea
     if (fp32) {
         const dim3 grid((unsigned)(parts * slots));
         if (kerr)
-            hipLaunchKernelGGL((sum_wg_kernel<float, true, false, 3>), grid, dim3(256),
+            hipLaunchKernelGGL((sum_wg_kernel<float, true, false, 3, false>), grid, dim3(256),
                                sum_lds_bytes(), stream, job, slots);
         else
-            hipLaunchKernelGGL((sum_wg_kernel<float, true, false, 2>), grid, dim3(256),
+            hipLaunchKernelGGL((sum_wg_kernel<float, true, false, 2, false>), grid, dim3(256),
                                sum_lds_bytes(), stream, job, slots);
     } else {
         const int waves_per_block = 256 / kWave;
         const long long blocks = (slots + waves_per_block - 1) / waves_per_block;
         const dim3 grid((unsigned)(parts * blocks));
         if (kerr)
-            hipLaunchKernelGGL((sum_kernel<double, false, true, 3>), grid, dim3(256), 0, stream,
-                               job, slots);
+            hipLaunchKernelGGL((sum_kernel<double, false, true, 3, false>), grid, dim3(256), 0,
+                               stream, job, slots);
         else
-            hipLaunchKernelGGL((sum_kernel<double, false, true, 2>), grid, dim3(256), 0, stream,
-                               job, slots);
+            hipLaunchKernelGGL((sum_kernel<double, false, true, 2, false>), grid, dim3(256), 0,
+                               stream, job, slots);
     }
+    return hipGetLastError();
+}
+
+// Adds count partials in a fixed order (strided per lane, then a tree in LDS)
+// and writes out2 = factor * (x sum, y sum).
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double2 *partial,
+                                                              long long count, double factor,
+                                                              double *out2) {
+    __shared__ double2 red[256];
+    double2 v = make_double2(0.0, 0.0);
+    for (long long i = threadIdx.x; i < count; i += blockDim.x) {
+        v.x = v.x + partial[i].x;
+        v.y = v.y + partial[i].y;
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            red[threadIdx.x].x = red[threadIdx.x].x + red[threadIdx.x + off].x;
+            red[threadIdx.x].y = red[threadIdx.x].y + red[threadIdx.x + off].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out2[0] = factor * red[0].x;
+        out2[1] = factor * red[0].y;
+    }
+}
+
+long long inner_slots(int parts, int slots, bool fp32) {
+    if (fp32) return (long long)parts * slots;
+    const int waves_per_block = 256 / kWave;
+    return (long long)parts * ((slots + waves_per_block - 1) / waves_per_block) * waves_per_block;
+}
+
+hipError_t launch_sum_inner(const SumJob &job, int slots, bool fp32, double two_dt,
+                            double *out2, hipStream_t stream) {
+    const long long parts = job.parts;
+    const bool kerr = job.n_ph == 3;
+    if (fp32) {
+        const dim3 grid((unsigned)(parts * slots));
+        if (kerr)
+            hipLaunchKernelGGL((sum_wg_kernel<float, true, false, 3, true>), grid, dim3(256),
+                               sum_lds_bytes(), stream, job, slots);
+        else
+            hipLaunchKernelGGL((sum_wg_kernel<float, true, false, 2, true>), grid, dim3(256),
+                               sum_lds_bytes(), stream, job, slots);
+    } else {
+        const int waves_per_block = 256 / kWave;
+        const long long blocks = (slots + waves_per_block - 1) / waves_per_block;
+        const dim3 grid((unsigned)(parts * blocks));
+        if (kerr)
+            hipLaunchKernelGGL((sum_kernel<double, false, true, 3, true>), grid, dim3(256), 0,
+                               stream, job, slots);
+        else
+            hipLaunchKernelGGL((sum_kernel<double, false, true, 2, true>), grid, dim3(256), 0,
+                               stream, job, slots);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, stream, job.partial,
+                       inner_slots(job.parts, slots, fp32), two_dt, out2);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ EXPORTED = [
     "few_spline_coefs", "few_mode_sum", "few_mode_select", "few_batch", "few_submit",
     "few_poll", "few_wait",
     "few_plan_timing", "few_last_error", "few_host_terms", "few_host_interval_starts",
-    "few_spline_fit_kerr", "few_host_terms_kerr",
+    "few_spline_fit_kerr", "few_host_terms_kerr", "few_inner_product",
     "few_host_request_bytes",
 ]
 
@@ -95,6 +95,7 @@ def load() -> ctypes.CDLL:
     lib.few_spline_free.argtypes = [vp]
     lib.few_spline_coefs.argtypes = [vp, i32, vp]
     lib.few_mode_sum.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp]
+    lib.few_inner_product.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp, vp]
     lib.few_batch.argtypes = [vp, i32, P(Request)]
     lib.few_mode_select.argtypes = [vp, i32, i32, vp, dbl, vp]
     lib.few_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
@@ -247,6 +248,20 @@ class Plan:
         _check(load().few_mode_sum(self.handle, spline.handle, float(theta), float(phi),
                                    float(scale), float(t_start), float(dt), int(n_samples), op))
         return out
+
+    def inner_product(self, spline: "Spline", theta: float, phi: float, dt: float,
+                      n_samples: int, data, out2=None, t_start: float = 0.0,
+                      scale: float = 1.0):
+        """few_inner_product: device float64 [2] = (<d|h>, <h|h>) with a unit PSD."""
+        import torch
+        dp = _dev_ptr(data, self.out_dtype, (n_samples,), "data")
+        if out2 is None:
+            out2 = torch.empty(2, dtype=torch.float64, device=f"cuda:{self.device}")
+        op = _dev_ptr(out2, torch.float64, (2,), "out2")
+        _check(load().few_inner_product(self.handle, spline.handle, float(theta), float(phi),
+                                        float(scale), float(t_start), float(dt),
+                                        int(n_samples), dp, op))
+        return out2
 
     def _request(self, t_knots, phi_phi, phi_r, lmn, amp, theta, phi, dt, n_samples, out,
                  t_start: float = 0.0, scale: float = 1.0):
