@@ -190,6 +190,24 @@ int32_t few_mode_sum(few_plan plan, few_spline spline, double theta, double phi,
                      void *out);
 
 /*
+ * Detector-frame waveform (Sec. II frame conventions): the sum of few_mode_sum
+ * viewed from sky position (theta_S, phi_S) for a spin direction
+ * (theta_K, phi_K), both in the solar-system-barycentre frame, written in the
+ * barycentre polarisation basis.  The source-frame viewing angles are
+ * theta = arccos(-R.S), phi = -pi/2 (R, S: unit vectors of the two
+ * directions); the pi/2 alignment of the polarisation bases flips the sign of
+ * h and the rotation through the polarisation angle psi (tan psi = [cos
+ * theta_S sin theta_K cos(phi_S - phi_K) - sin theta_S cos theta_K] /
+ * [sin theta_K sin(phi_S - phi_K)]) multiplies it by e^{-2 i psi}:
+ *   out[j] = -e^{-2 i psi} h(t_j; theta, phi)
+ * The constant factor is applied to the folded coefficients, so this costs the
+ * same as few_mode_sum.  R parallel to S leaves psi undefined (factor -1).
+ */
+int32_t few_mode_sum_ssb(few_plan plan, few_spline spline, double theta_S, double phi_S,
+                         double theta_K, double phi_K, double scale, double t_start,
+                         double dt, int64_t n_samples, void *out);
+
+/*
  * Fused inner products (Sec. VI): the same summation as few_mode_sum, but
  * instead of writing h it forms, with a unit PSD (by Parseval the one-sided
  * noise-weighted integral over both polarisations equals this time sum),
@@ -296,6 +314,12 @@ int32_t few_host_terms_kerr(int32_t M, const int32_t *lmkn, int32_t max_gap,
  */
 int32_t few_host_interval_starts(int32_t K, const double *t_knots, double t_start,
                                  double dt, int64_t n, int64_t *starts);
+
+/* Detector-frame quantities of few_mode_sum_ssb: out4 = (theta, phi, Re, Im)
+ * of the source viewing angles and the factor -e^{-2 i psi}.  FEW_E_ARG for
+ * non-finite angles. */
+int32_t few_host_frame(double theta_S, double phi_S, double theta_K, double phi_K,
+                       double *out4);
 
 /* Arena bytes a served request of this shape reserves (precision of the plan
  * descriptor `precision`), or 0 for invalid shapes. */

@@ -767,7 +767,8 @@ int32_t few_spline_coefs(few_spline s, int32_t which, void *dst) {
 namespace {
 // Shared by few_mode_sum (out != null) and few_inner_product (data, out2).
 int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, double t_start,
-             double dt, int64_t n, void *out, const void *data, double *out2) {
+             double dt, int64_t n, void *out, const void *data, double *out2,
+             double scale_im = 0.0) {
     if (!p) return fail(FEW_E_STATE, "null plan");
     if (!s || s->plan != p) return fail(FEW_E_STATE, "spline does not belong to this plan");
     const bool inner = data != nullptr;
@@ -783,6 +784,7 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
             single_tiling(p->fp32, s->h.n_ph == 3 ? p->resident_wg3 : p->resident_wg);
         PrepJob pj = prep_job(s->h, one_block(s->h, base), theta, phi, scale, t_start, dt, n,
                               p->fp32, tl);
+        pj.scale_im = scale_im;
         rc = timed_launch(p, ST_PREP, p->stream,
                           [&] { return launch_prepare(pj, p->fp32, p->stream); });
         if (rc) return rc;
@@ -822,6 +824,17 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
 int32_t few_mode_sum(few_plan p, few_spline s, double theta, double phi, double scale,
                      double t_start, double dt, int64_t n, void *out) {
     return sum_impl(p, s, theta, phi, scale, t_start, dt, n, out, nullptr, nullptr);
+}
+
+int32_t few_mode_sum_ssb(few_plan p, few_spline s, double theta_s, double phi_s,
+                         double theta_k, double phi_k, double scale, double t_start, double dt,
+                         int64_t n, void *out) {
+    double th, ph, rr, ri;
+    if (detector_frame(theta_s, phi_s, theta_k, phi_k, &th, &ph, &rr, &ri) != FEW_OK)
+        return fail(FEW_E_ARG, "non-finite sky or spin angle");
+    if (!std::isfinite(scale)) return fail(FEW_E_ARG, "non-finite scale");
+    return sum_impl(p, s, th, ph, scale * rr, t_start, dt, n, out, nullptr, nullptr,
+                    scale * ri);
 }
 
 int32_t few_inner_product(few_plan p, few_spline s, double theta, double phi, double scale,

@@ -85,6 +85,7 @@ struct PrepJob {
     long long *starts;      // [K]
     int *tile_pref;         // [parts][K]: tiles before each interval, per part
     double theta, phi, scale, t_start, dt;
+    double scale_im;        // imaginary part of a complex overall factor (0: real scale)
     long long n;
     long long short_len;    // samples at the end of each part cut into short tiles
     int parts;              // contiguous sample parts (one per XCD) or 1
@@ -155,6 +156,11 @@ struct TermLayout {
 // Build the folded term layout; returns 0 or a few_status error code.
 int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermLayout *out);
 void free_term_layout(TermLayout *t);
+
+// Detector frame (see few_host_frame): source viewing angles and the complex
+// factor -e^{-2 i psi}; returns 0 or FEW_E_ARG.
+int detector_frame(double theta_s, double phi_s, double theta_k, double phi_k,
+                   double *theta_src, double *phi_src, double *rot_re, double *rot_im);
 
 // starts[i] for i in [0, K): see few_host_interval_starts.
 void interval_starts(int K, const double *t, double t_start, double dt, long long n,

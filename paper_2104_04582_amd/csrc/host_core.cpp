@@ -175,6 +175,39 @@ int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermL
     return FEW_OK;
 }
 
+// Sec. II frame conventions.  With R (sky position) and S (spin direction) as
+// unit vectors in the barycentre frame, the source frame has z = S and x along
+// R x S, so the observer, at -R from the source, sits at polar angle
+// arccos(-R.S) and azimuth -pi/2.  The pi/2 turn of the polarisation basis is a
+// sign flip of h, and the barycentre frame follows by turning the basis through
+// psi, tan psi = [cos tS sin tK cos(pS - pK) - sin tS cos tK] /
+// [sin tK sin(pS - pK)], which multiplies h by e^{-2 i psi}.  e^{-2 i psi} is
+// formed from the numerator a and denominator b directly:
+// (b - i a)^2 / (a^2 + b^2); R parallel to S leaves psi undefined: factor 1.
+int detector_frame(double theta_s, double phi_s, double theta_k, double phi_k,
+                   double *theta_src, double *phi_src, double *rot_re, double *rot_im) {
+    if (!std::isfinite(theta_s) || !std::isfinite(phi_s) || !std::isfinite(theta_k) ||
+        !std::isfinite(phi_k))
+        return FEW_E_ARG;
+    const double st = std::sin(theta_s), ct = std::cos(theta_s);
+    const double sk = std::sin(theta_k), ck = std::cos(theta_k);
+    const double rs = st * sk * std::cos(phi_s - phi_k) + ct * ck;      // R . S
+    const double c = std::max(-1.0, std::min(1.0, -rs));
+    *theta_src = std::acos(c);
+    *phi_src = -M_PI / 2;
+    const double a = ct * sk * std::cos(phi_s - phi_k) - st * ck;
+    const double b = sk * std::sin(phi_s - phi_k);
+    const double q = a * a + b * b;
+    double er = 1.0, ei = 0.0;                                          // e^{-2 i psi}
+    if (q > 0.0) {
+        er = (b * b - a * a) / q;
+        ei = -2.0 * a * b / q;
+    }
+    *rot_re = -er;
+    *rot_im = -ei;
+    return FEW_OK;
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
@@ -247,6 +280,13 @@ extern "C" int32_t few_host_terms_kerr(int32_t M, const int32_t *lmkn, int32_t m
                                        int32_t cap_src, int32_t *term_src, int32_t *n_src) {
     return host_terms(M, lmkn, 4, max_gap, cap_segs, segs, n_segs, cap_terms, term_ptr,
                       n_terms, cap_src, term_src, n_src);
+}
+
+extern "C" int32_t few_host_frame(double theta_s, double phi_s, double theta_k, double phi_k,
+                                  double *out4) {
+    if (!out4) return FEW_E_ARG;
+    return detector_frame(theta_s, phi_s, theta_k, phi_k, &out4[0], &out4[1], &out4[2],
+                          &out4[3]);
 }
 
 extern "C" int32_t few_host_interval_starts(int32_t K, const double *t_knots, double t_start,

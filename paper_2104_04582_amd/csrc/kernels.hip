@@ -459,11 +459,23 @@ __device__ void fold_pair(const PrepJob &jb, long long p) {
     const double h = jb.t[i + 1] - jb.t[i];
     double f = jb.scale;
     Real *dst = (Real *)jb.table + ((size_t)i * jb.n_terms + term) * 8;
+    if (jb.scale_im == 0.0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        dst[2 * q] = (Real)(acc[2 * q] * f);
-        dst[2 * q + 1] = (Real)(acc[2 * q + 1] * f);
-        f *= h;
+        for (int q = 0; q < 4; ++q) {
+            dst[2 * q] = (Real)(acc[2 * q] * f);
+            dst[2 * q + 1] = (Real)(acc[2 * q + 1] * f);
+            f *= h;
+        }
+    } else {
+        // complex overall factor (scale, scale_im) (the detector-frame rotation)
+        double g = jb.scale_im;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            dst[2 * q] = (Real)(acc[2 * q] * f - acc[2 * q + 1] * g);
+            dst[2 * q + 1] = (Real)(acc[2 * q] * g + acc[2 * q + 1] * f);
+            f *= h;
+            g *= h;
+        }
     }
 }
 

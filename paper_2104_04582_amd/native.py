@@ -35,7 +35,8 @@ EXPORTED = [
     "few_spline_coefs", "few_mode_sum", "few_mode_select", "few_batch", "few_submit",
     "few_poll", "few_wait",
     "few_plan_timing", "few_last_error", "few_host_terms", "few_host_interval_starts",
-    "few_spline_fit_kerr", "few_host_terms_kerr", "few_inner_product",
+    "few_spline_fit_kerr", "few_host_terms_kerr", "few_inner_product", "few_mode_sum_ssb",
+    "few_host_frame",
     "few_host_request_bytes",
 ]
 
@@ -96,6 +97,8 @@ def load() -> ctypes.CDLL:
     lib.few_spline_coefs.argtypes = [vp, i32, vp]
     lib.few_mode_sum.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp]
     lib.few_inner_product.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp, vp]
+    lib.few_mode_sum_ssb.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, dbl, dbl, i64, vp]
+    lib.few_host_frame.argtypes = [dbl, dbl, dbl, dbl, vp]
     lib.few_batch.argtypes = [vp, i32, P(Request)]
     lib.few_mode_select.argtypes = [vp, i32, i32, vp, dbl, vp]
     lib.few_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
@@ -249,6 +252,20 @@ class Plan:
                                    float(scale), float(t_start), float(dt), int(n_samples), op))
         return out
 
+    def mode_sum_ssb(self, spline: "Spline", theta_s: float, phi_s: float, theta_k: float,
+                     phi_k: float, dt: float, n_samples: int, out=None, t_start: float = 0.0,
+                     scale: float = 1.0):
+        """few_mode_sum_ssb: the waveform in the barycentre frame for sky position
+        (theta_s, phi_s) and spin direction (theta_k, phi_k)."""
+        import torch
+        if out is None:
+            out = torch.empty(n_samples, dtype=self.out_dtype, device=f"cuda:{self.device}")
+        op = _dev_ptr(out, self.out_dtype, (n_samples,), "out")
+        _check(load().few_mode_sum_ssb(self.handle, spline.handle, float(theta_s), float(phi_s),
+                                       float(theta_k), float(phi_k), float(scale),
+                                       float(t_start), float(dt), int(n_samples), op))
+        return out
+
     def inner_product(self, spline: "Spline", theta: float, phi: float, dt: float,
                       n_samples: int, data, out2=None, t_start: float = 0.0,
                       scale: float = 1.0):
@@ -345,6 +362,14 @@ def host_terms(lmn, max_gap: int = 4):
               ctypes.byref(ne)))
     return (segs[:4 * ns.value].reshape(-1, 4).copy(), tp[:nt.value + 1].copy(),
             src[:2 * ne.value].reshape(-1, 2).copy())
+
+
+def host_frame(theta_s: float, phi_s: float, theta_k: float, phi_k: float):
+    """few_host_frame: (theta, phi, complex factor) of the detector-frame step."""
+    out = np.zeros(4, dtype=np.float64)
+    _check(load().few_host_frame(float(theta_s), float(phi_s), float(theta_k), float(phi_k),
+                                 out.ctypes.data))
+    return float(out[0]), float(out[1]), complex(out[2], out[3])
 
 
 def host_interval_starts(t_knots, t_start: float, dt: float, n: int) -> np.ndarray:

@@ -205,3 +205,24 @@ def test_kerr_layout_rejects_bad_modes():
     assert e.value.code == native.FEW_E_MODES
     with pytest.raises(native.FewError):
         native.host_terms(np.array([[2, 3, 0, 0]]))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_host_frame_matches_oracle(seed):
+    import math
+    from oracle.frame import frame_angles
+    rng = np.random.default_rng(seed)
+    ts, ps = math.acos(rng.uniform(-1, 1)), rng.uniform(0, 2 * math.pi)
+    tk, pk = math.acos(rng.uniform(-1, 1)), rng.uniform(0, 2 * math.pi)
+    th, ph, rot = native.host_frame(ts, ps, tk, pk)
+    t_ref, p_ref, psi = frame_angles(ts, ps, tk, pk)
+    assert abs(th - t_ref) < 1e-12 and ph == p_ref
+    assert abs(rot - (-np.exp(-2j * psi))) < 1e-12
+
+
+def test_host_frame_errors_and_degenerate():
+    with pytest.raises(native.FewError) as e:
+        native.host_frame(float("nan"), 0.0, 0.1, 0.2)
+    assert e.value.code == native.FEW_E_ARG
+    th, ph, rot = native.host_frame(0.4, 1.0, 0.4, 1.0)        # R = S
+    assert abs(th - np.pi) < 1e-7 and rot == -1.0
