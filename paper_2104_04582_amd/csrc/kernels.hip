@@ -1267,14 +1267,26 @@ hipError_t launch_sum(const SumJob &job, int slots, bool fp32, hipStream_t strea
     return hipGetLastError();
 }
 
-// Adds count partials in a fixed order (strided per lane, then a tree in LDS)
-// and writes out2 = factor * (x sum, y sum).
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const double2 *partial,
-                                                              long long count, double factor,
-                                                              double *out2) {
-    __shared__ double2 red[256];
+// Adds count partials in a fixed order (strided per lane, four loads in
+// flight, then a tree in LDS) and writes out2 = factor * (x sum, y sum).
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void reduce_partials_kernel(const double2 *partial,
+                                                                         long long count,
+                                                                         double factor,
+                                                                         double *out2) {
+    __shared__ double2 red[kReduceThreads];
     double2 v = make_double2(0.0, 0.0);
-    for (long long i = threadIdx.x; i < count; i += blockDim.x) {
+    const long long step = blockDim.x;
+    long long i = threadIdx.x;
+    for (; i + 3 * step < count; i += 4 * step) {
+        const double2 a = partial[i], b = partial[i + step], c = partial[i + 2 * step],
+                      d = partial[i + 3 * step];
+        v.x = v.x + a.x; v.y = v.y + a.y;
+        v.x = v.x + b.x; v.y = v.y + b.y;
+        v.x = v.x + c.x; v.y = v.y + c.y;
+        v.x = v.x + d.x; v.y = v.y + d.y;
+    }
+    for (; i < count; i += step) {
         v.x = v.x + partial[i].x;
         v.y = v.y + partial[i].y;
     }
@@ -1324,8 +1336,8 @@ hipError_t launch_sum_inner(const SumJob &job, int slots, bool fp32, double two_
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, stream, job.partial,
-                       inner_slots(job.parts, slots, fp32), two_dt, out2);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kReduceThreads), 0, stream,
+                       job.partial, inner_slots(job.parts, slots, fp32), two_dt, out2);
     return hipGetLastError();
 }
 
