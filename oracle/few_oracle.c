@@ -21,7 +21,8 @@
  * t_j = t_start + j dt, evaluated in IEEE binary64 exactly as written.
  *
  * Precision: x87 extended ("long double", 64-bit significand) throughout, with
- * the phase constant of each knot interval reduced modulo 2 pi in binary128.
+ * the phase constant of each knot interval reduced modulo 2 pi in binary128 and
+ * the alternating sum of each spin-weighted harmonic formed in binary128.
  * Adding a multiple of 2 pi to a phase leaves e^{-i(m Phi_phi + n Phi_r)}
  * unchanged for integer m, n, so the reduction is an identity, not an
  * approximation.  Binary64 here would put the oracle's own phase error
@@ -44,6 +45,7 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -209,44 +211,49 @@ int few_oracle_spline(int K, const double *t, int S, const double *y, double *ou
 /*                 e^{i m phi} cot^{2r+s-m}(theta/2)                        */
 /* The power of cot is k = 2r+s-m >= 0 and 2l - k >= 0 for every r in the    */
 /* summation range, so sin^{2l} cot^k = sin^{2l-k} cos^k is finite at        */
-/* theta = 0 and pi.                                                        */
+/* theta = 0 and pi.  The sum alternates and cancels by up to ~1e-9 of its   */
+/* largest term at l = 30, so it is formed in binary128 (113-bit            */
+/* significand) and only the result is rounded.                            */
 /* ------------------------------------------------------------------------ */
-static ld factl(int n) {
-    ld f = 1.0L;
-    for (int k = 2; k <= n; ++k) f *= (ld)k;
+typedef __float128 q128;
+
+static q128 factq(int n) {
+    q128 f = 1;
+    for (int k = 2; k <= n; ++k) f *= (q128)k;
     return f;
 }
 
-static ld binoml(int n, int k) {
-    if (k < 0 || k > n) return 0.0L;
-    return factl(n) / (factl(k) * factl(n - k));
+static q128 binomq(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    return factq(n) / (factq(k) * factq(n - k));
 }
 
-static ld ipowl(ld x, int k) {
-    ld r = 1.0L;
+static q128 ipowq(q128 x, int k) {
+    q128 r = 1;
     for (int i = 0; i < k; ++i) r *= x;
     return r;
 }
 
 static void swsh_ld(int s, int l, int m, ld theta, ld phi, ld *re, ld *im) {
     if (l < abs(s) || l < abs(m)) { *re = 0.0L; *im = 0.0L; return; }
-    const ld pi = 3.141592653589793238462643383279502884L;
-    ld pref = sqrtl(factl(l + m) * factl(l - m) * (ld)(2 * l + 1) /
-                    (4.0L * pi * factl(l + s) * factl(l - s)));
+    q128 pref = sqrtq(factq(l + m) * factq(l - m) * (q128)(2 * l + 1) /
+                      (4 * M_PIq * factq(l + s) * factq(l - s)));
     if (m & 1) pref = -pref;
-    ld sh = sinl(0.5L * theta), ch = cosl(0.5L * theta);
-    ld sum = 0.0L;
+    const q128 half = (q128)theta / 2;
+    const q128 sh = sinq(half), ch = cosq(half);
+    q128 sum = 0;
     for (int r = 0; r <= l - s; ++r) {
         int j = r + s - m;
         if (j < 0 || j > l + s) continue;
         int k = 2 * r + s - m;
-        ld term = binoml(l - s, r) * binoml(l + s, j) * ipowl(sh, 2 * l - k) * ipowl(ch, k);
+        q128 term = binomq(l - s, r) * binomq(l + s, j) * ipowq(sh, 2 * l - k) * ipowq(ch, k);
         if ((l - r - s) & 1) term = -term;
         sum += term;
     }
-    ld c = cosl((ld)m * phi), sn = sinl((ld)m * phi);
-    *re = pref * sum * c;
-    *im = pref * sum * sn;
+    const q128 a = pref * sum;
+    const q128 mphi = (q128)m * (q128)phi;
+    *re = (ld)(a * cosq(mphi));
+    *im = (ld)(a * sinq(mphi));
 }
 
 /* Exported for the harmonic pins. */

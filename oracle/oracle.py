@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (binary64 sample times, no FMA contraction)."""
     if force or not os.path.exists(ORACLE_SO):
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-               "-o", ORACLE_SO + ".tmp", SRC, "-lm"]
+               "-o", ORACLE_SO + ".tmp", SRC, "-lquadmath", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(ORACLE_SO + ".tmp", ORACLE_SO)
     return ORACLE_SO

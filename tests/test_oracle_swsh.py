@@ -105,3 +105,36 @@ def test_pole_selects_m_equal_minus_s(l):
             assert abs(abs(v) - math.sqrt((2 * l + 1) / (4 * math.pi))) < 1e-14
         else:
             assert abs(v) == 0.0
+
+
+def _mp_swsh(s, l, m, theta, phi, dps=60):
+    """sY_lm from Goldberg's sum evaluated with dps decimal digits."""
+    import mpmath as mp
+    with mp.workdps(dps):
+        t = mp.mpf(theta)
+        sh, ch = mp.sin(t / 2), mp.cos(t / 2)
+        pref = (-1) ** m * mp.sqrt(mp.factorial(l + m) * mp.factorial(l - m) * (2 * l + 1) /
+                                   (4 * mp.pi * mp.factorial(l + s) * mp.factorial(l - s)))
+        tot = mp.mpf(0)
+        for r in range(0, l - s + 1):
+            j = r + s - m
+            if j < 0 or j > l + s:
+                continue
+            k = 2 * r + s - m
+            tot += mp.binomial(l - s, r) * mp.binomial(l + s, j) * sh ** (2 * l - k) * ch ** k * \
+                (-1) ** (l - r - s)
+        v = pref * tot * mp.expj(m * mp.mpf(phi))
+        return complex(v)
+
+
+@pytest.mark.parametrize("l", [12, 20, 26, 30])
+def test_high_l_against_60_digit_sum(l):
+    """The accepted range goes to l = 30, where the alternating sum cancels
+    heavily: every -2Y_lm must still be accurate to 1e-14 of its magnitude
+    scale (the largest |Y| over m at that l and angle)."""
+    for theta in (0.3, 1.1, 2.4):
+        vals = {m: (oracle.swsh(-2, l, m, theta, 0.7), _mp_swsh(-2, l, m, theta, 0.7))
+                for m in range(-l, l + 1)}
+        scale = max(abs(r) for _, r in vals.values())
+        for m, (got, ref) in vals.items():
+            assert abs(got - ref) <= 1e-14 * scale, (l, m, theta, got, ref)
