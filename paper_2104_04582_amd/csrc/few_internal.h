@@ -81,7 +81,7 @@ struct PrepJob {
     const int *term_ptr;    // [n_terms + 1]
     const int2 *term_src;   // [n_src]: (mode, l | m << 8 | mirror << 16)
     double2 *ybuf;          // [n_src] harmonic weight of each contributor
-    void *table;            // [K-1][n_terms][8] binary32 or binary64
+    void *table;            // [K-1][n_terms][8] binary32 or binary64, terms in reverse order
     long long *starts;      // [K]
     int *tile_pref;         // [parts][K]: tiles before each interval, per part
     double theta, phi, scale, t_start, dt;

@@ -458,7 +458,9 @@ __device__ void fold_pair(const PrepJob &jb, long long p) {
     }
     const double h = jb.t[i + 1] - jb.t[i];
     double f = jb.scale;
-    Real *dst = (Real *)jb.table + ((size_t)i * jb.n_terms + term) * 8;
+    // terms are stored in reverse order (position n_terms - 1 - term), so the
+    // summation walks each segment from its highest n upwards in memory
+    Real *dst = (Real *)jb.table + ((size_t)i * jb.n_terms + (jb.n_terms - 1 - term)) * 8;
     if (jb.scale_im == 0.0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -611,9 +613,11 @@ __device__ __forceinline__ void load_term(const float *cp, float *c) {
 // Horner over its terms in f = e^{-i Phi_r} from the highest n down,
 //   S <- S f + C_n(u),  C_n(u) = c0 + c1 u + c2 u^2 + c3 u^3,
 // then h += seed * S (Kahan-compensated when COMP).  `last` points at the 8
-// values (c0r, c0i, ..., c3i) of the segment's highest-n term; earlier terms
-// precede it at a stride of 8.  Binary32 (coefficients in VGPRs) evaluates
-// C_n(u) by Horner in u apart from the recurrence, leaving two dependent FMAs
+// values (c0r, c0i, ..., c3i) of the segment's highest-n term; the lower-n
+// terms follow it at a stride of 8 (the table stores terms in reverse order,
+// so the walk runs upward in memory and the loads of two unrolled terms share
+// one base register with immediate offsets).  Binary32 (coefficients in VGPRs)
+// evaluates C_n(u) by Horner in u apart from the recurrence, leaving two dependent FMAs
 // per term on it; binary64 (coefficients in SGPRs, one scalar operand per
 // instruction) chains all five FMAs of each component into the recurrence.
 template <typename Real, int SL, bool COMP, int NP, typename Ptr>
@@ -652,20 +656,13 @@ __device__ __forceinline__ void seg_step(LaneState<Real, SL, NP> &L, const int4 
     Real sr[SL], si[SL];
 #pragma unroll
     for (int s = 0; s < SL; ++s) sr[s] = si[s] = (Real)0;
-    // the next term's coefficients are loaded while the current one is used
-    // (the last prefetch re-reads the first term, so it stays in bounds)
-    Ptr cp = last;
     const int len = S.z;
-    Real c[8];
-    load_term(cp, c);
 #pragma unroll FEW_SEG_UNROLL
     for (int q = 0; q < len; ++q) {
-        const Ptr np = (q + 1 < len) ? cp - 8 : cp;
-        Real cn[8];
-        load_term(np, cn);
+        Real c[8];
+        load_term(last + 8 * q, c);
         const Real c0r = c[0], c0i = c[1], c1r = c[2], c1i = c[3];
         const Real c2r = c[4], c2i = c[5], c3r = c[6], c3i = c[7];
-        cp = np;
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const Real u = L.u[s];
@@ -693,8 +690,6 @@ __device__ __forceinline__ void seg_step(LaneState<Real, SL, NP> &L, const int4 
             sr[s] = nr;
             si[s] = ni;
         }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) c[i] = cn[i];
     }
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
@@ -776,7 +771,7 @@ __device__ __forceinline__ double2 sum_wave_run(const SumJob &jb, int iv, long l
     const FEW_AS4 Real *tab = cptr((const Real *)jb.table) + (size_t)iv * jb.n_terms * 8;
     for (int g = 0; g < jb.n_segs; ++g) {
         const int4 S = load_uniform(jb.segs + g);
-        seg_step<Real, SL, COMP, NP>(L, S, tab + (size_t)(S.w + S.z - 1) * 8);
+        seg_step<Real, SL, COMP, NP>(L, S, tab + (size_t)(jb.n_terms - S.w - S.z) * 8);
     }
     if constexpr (INNER) {
         return lane_inner<Real, SL, COMP, NP>(L, jb, j1);
@@ -822,16 +817,17 @@ __device__ __forceinline__ double2 sum_wg_run(const SumJob &jb, int iv, long lon
         const int g0 = ch[c], g1 = ch[c + 1];
         const int t0 = load_uniform(jb.segs + g0).w;
         const int4 Sl = load_uniform(jb.segs + g1 - 1);
-        const int nv = (Sl.w + Sl.z - t0) * 8 * (int)sizeof(Real) / 16;
+        const int t1 = Sl.w + Sl.z;                 // terms [t0, t1), stored reversed
+        const int nv = (t1 - t0) * 8 * (int)sizeof(Real) / 16;
         __syncthreads();                            // previous chunk fully consumed
-        const float4 *src = (const float4 *)(tab + (size_t)t0 * 8);
+        const float4 *src = (const float4 *)(tab + (size_t)(jb.n_terms - t1) * 8);
         float4 *dst = (float4 *)buf;
         for (int v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
         __syncthreads();
         if (busy) {
             for (int g = g0; g < g1; ++g) {
                 const int4 S = load_uniform(jb.segs + g);
-                seg_step<Real, SL, COMP, NP>(L, S, buf + (S.w - t0 + S.z - 1) * 8);
+                seg_step<Real, SL, COMP, NP>(L, S, buf + (t1 - S.w - S.z) * 8);
             }
         }
     }
