@@ -607,6 +607,46 @@ __device__ __forceinline__ void load_term(const float *cp, float *c) {
     c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
 }
 
+// One Horner step over n for every sample of the lane: S <- S f + C_n(u),
+// with C_n's eight coefficients (c0r, c0i, ..., c3i) in c.  Binary32
+// (coefficients in VGPRs) evaluates C_n(u) by Horner in u apart from the
+// recurrence, leaving two dependent FMAs per term on it; binary64
+// (coefficients in SGPRs, one scalar operand per instruction) chains all five
+// FMAs of each component into the recurrence.
+template <typename Real, int SL, int NP>
+__device__ __forceinline__ void term_step(const LaneState<Real, SL, NP> &L, Real *sr, Real *si,
+                                          const Real *c) {
+    const Real c0r = c[0], c0i = c[1], c1r = c[2], c1i = c[3];
+    const Real c2r = c[4], c2i = c[5], c3r = c[6], c3i = c[7];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const Real u = L.u[s];
+        Real nr, ni;
+        if constexpr (sizeof(Real) == 4) {
+            // coefficients in VGPRs: cubic first, two FMAs on the recurrence
+            const Real pr = fmar(fmar(fmar(c3r, u, c2r), u, c1r), u, c0r);
+            const Real pi = fmar(fmar(fmar(c3i, u, c2i), u, c1i), u, c0i);
+            nr = fmar(sr[s], L.fr[s], fmar(-si[s], L.fi[s], pr));
+            ni = fmar(sr[s], L.fi[s], fmar(si[s], L.fr[s], pi));
+        } else {
+            // coefficients in SGPRs: one scalar operand per FMA
+            const Real u2 = u * u, u3 = u2 * u;
+            nr = fmar(sr[s], L.fr[s], c0r);
+            nr = fmar(-si[s], L.fi[s], nr);
+            nr = fmar(u, c1r, nr);
+            nr = fmar(u2, c2r, nr);
+            nr = fmar(u3, c3r, nr);
+            ni = fmar(sr[s], L.fi[s], c0i);
+            ni = fmar(si[s], L.fr[s], ni);
+            ni = fmar(u, c1i, ni);
+            ni = fmar(u2, c2i, ni);
+            ni = fmar(u3, c3i, ni);
+        }
+        sr[s] = nr;
+        si[s] = ni;
+    }
+}
+
 // One segment: seed e^{-i(m Phi_phi + k Phi_theta + n_lo Phi_r)} (chained
 // from the previous segment's by e^{-i Phi_phi} when only m steps by one, or by
 // e^{-i Phi_theta} when only k does, at the same n_lo; else one sincos),
@@ -616,10 +656,7 @@ __device__ __forceinline__ void load_term(const float *cp, float *c) {
 // values (c0r, c0i, ..., c3i) of the segment's highest-n term; the lower-n
 // terms follow it at a stride of 8 (the table stores terms in reverse order,
 // so the walk runs upward in memory and the loads of two unrolled terms share
-// one base register with immediate offsets).  Binary32 (coefficients in VGPRs)
-// evaluates C_n(u) by Horner in u apart from the recurrence, leaving two dependent FMAs
-// per term on it; binary64 (coefficients in SGPRs, one scalar operand per
-// instruction) chains all five FMAs of each component into the recurrence.
+// one base register with immediate offsets).
 template <typename Real, int SL, bool COMP, int NP, typename Ptr>
 __device__ __forceinline__ void seg_step(LaneState<Real, SL, NP> &L, const int4 S, Ptr last) {
     const int k = NP == 3 ? seg_k(S.x) : 0;
@@ -657,38 +694,34 @@ __device__ __forceinline__ void seg_step(LaneState<Real, SL, NP> &L, const int4 
 #pragma unroll
     for (int s = 0; s < SL; ++s) sr[s] = si[s] = (Real)0;
     const int len = S.z;
+    if constexpr (sizeof(Real) == 4) {
+        // LDS operands: each pair of unrolled terms is read by four 16-byte
+        // loads at immediate offsets from one base, waited on at once; the
+        // other waves of the SIMD cover the latency.
 #pragma unroll FEW_SEG_UNROLL
-    for (int q = 0; q < len; ++q) {
+        for (int q = 0; q < len; ++q) {
+            Real c[8];
+            load_term(last + 8 * q, c);
+            term_step<Real, SL, NP>(L, sr, si, c);
+        }
+    } else {
+        // scalar-load operands: the next term is loaded into a second register
+        // set while the current one is used, so each load has a term's FMAs
+        // to return in (scalar loads may return out of order, so every wait is
+        // for all of them); the last prefetch re-reads the last term, so it
+        // stays in bounds.
+        Ptr cp = last;
         Real c[8];
-        load_term(last + 8 * q, c);
-        const Real c0r = c[0], c0i = c[1], c1r = c[2], c1i = c[3];
-        const Real c2r = c[4], c2i = c[5], c3r = c[6], c3i = c[7];
+        load_term(cp, c);
+#pragma unroll FEW_SEG_UNROLL
+        for (int q = 0; q < len; ++q) {
+            const Ptr np = (q + 1 < len) ? cp + 8 : cp;
+            Real cn[8];
+            load_term(np, cn);
+            term_step<Real, SL, NP>(L, sr, si, c);
 #pragma unroll
-        for (int s = 0; s < SL; ++s) {
-            const Real u = L.u[s];
-            Real nr, ni;
-            if constexpr (sizeof(Real) == 4) {
-                // coefficients in VGPRs: cubic first, two FMAs on the recurrence
-                const Real pr = fmar(fmar(fmar(c3r, u, c2r), u, c1r), u, c0r);
-                const Real pi = fmar(fmar(fmar(c3i, u, c2i), u, c1i), u, c0i);
-                nr = fmar(sr[s], L.fr[s], fmar(-si[s], L.fi[s], pr));
-                ni = fmar(sr[s], L.fi[s], fmar(si[s], L.fr[s], pi));
-            } else {
-                // coefficients in SGPRs: one scalar operand per FMA
-                const Real u2 = u * u, u3 = u2 * u;
-                nr = fmar(sr[s], L.fr[s], c0r);
-                nr = fmar(-si[s], L.fi[s], nr);
-                nr = fmar(u, c1r, nr);
-                nr = fmar(u2, c2r, nr);
-                nr = fmar(u3, c3r, nr);
-                ni = fmar(sr[s], L.fi[s], c0i);
-                ni = fmar(si[s], L.fr[s], ni);
-                ni = fmar(u, c1i, ni);
-                ni = fmar(u2, c2i, ni);
-                ni = fmar(u3, c3i, ni);
-            }
-            sr[s] = nr;
-            si[s] = ni;
+            for (int i = 0; i < 8; ++i) c[i] = cn[i];
+            cp = np;
         }
     }
 #pragma unroll
