@@ -799,6 +799,7 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
 template <typename Real, int SL, bool COMP, bool DD, int NP, bool INNER>
 __device__ __forceinline__ double2 sum_wave_run(const SumJob &jb, int iv, long long j0,
                                                 long long j1) {
+    static_assert(sizeof(Real) == 8, "binary32 terms are read from LDS only");
     LaneState<Real, SL, NP> L;
     lane_setup<Real, SL, DD, NP>(L, jb, iv, j0, j1);
     const FEW_AS4 Real *tab = cptr((const Real *)jb.table) + (size_t)iv * jb.n_terms * 8;
@@ -838,6 +839,7 @@ __device__ __forceinline__ double2 sum_tile(const SumJob &jb, int pt, int local)
 template <typename Real, int SL, bool COMP, bool DD, int NP, bool INNER>
 __device__ __forceinline__ double2 sum_wg_run(const SumJob &jb, int iv, long long base,
                                               long long j1, Real *buf) {
+    static_assert(sizeof(Real) == 4, "binary64 terms are read by scalar loads");
     constexpr int WT = kWave * SL;                  // samples per wave
     const int wave = threadIdx.x / kWave;
     // a wave past the end of a partial tile only helps stage coefficients
