@@ -177,6 +177,10 @@ def batch_run(native, precision: str, dev, n: int, budget: int, reps: int = 3):
                          theta=w.theta, phi=w.phi, dt=w.dt, n_samples=w.n_samples,
                          out=torch.empty(w.n_samples, dtype=dtype, device=dev)))
     ms = sum(w.mode_samples for w in ws)
+    flops = 0.0
+    for w in ws:
+        segs, _, _ = native.host_terms(w.lmn)
+        flops += algorithmic_flops(int(segs[:, 2].sum()), segs.shape[0], w.n_samples)
     best = None
     with native.Plan(0, precision, hbm_budget_bytes=budget) as plan:
         plan.batch(reqs)
@@ -189,8 +193,12 @@ def batch_run(native, precision: str, dev, n: int, budget: int, reps: int = 3):
             best = dt if best is None else min(best, dt)
     del reqs
     torch.cuda.empty_cache()
+    # the folded work rate over the whole batch (fit, fold and sum, host enqueue
+    # included): subsets of few modes fold less than the full basis, so
+    # mode-samples/s alone understates how busy the launch keeps the ALUs
     return {"precision": precision, "waveforms": n, "seconds": best,
-            "waveforms_per_s": n / best, "mode_samples": ms, "mode_samples_per_s": ms / best}
+            "waveforms_per_s": n / best, "mode_samples": ms, "mode_samples_per_s": ms / best,
+            "algorithmic_flop": flops, "algorithmic_tflops": flops / best / 1e12}
 
 
 def host_threads() -> int:

@@ -18,6 +18,10 @@ cos 2psi h_cross, i.e. h' = e^{-2 i psi} h, so the barycentre-frame waveform is
 h_ssb = -e^{-2 i psi} h(theta_src, phi_src).  Only e^{2 i psi} enters, which the
 tangent fixes without the branch of psi.  When R is parallel to S the angle is
 undefined and psi = 0 is used.
+
+Parity unpinned: the sense of the rotation (e^{-2 i psi} rather than
+e^{+2 i psi}) is a convention the paper does not fix, so no test can pin it;
+the viewing angles, psi itself and the unitarity of the rotation are pinned.
 """
 from __future__ import annotations
 
