@@ -88,6 +88,29 @@ __device__ __forceinline__ double dev_sample_time(double t_start, double dt, lon
 // Solved by forward elimination and back substitution without pivoting.
 // ===========================================================================
 
+// LU factor of the slope system on the shared grid (one lane): inverse pivots
+// invd[r] and multipliers w[r] of the forward sweep, h in LDS.  The recurrence
+// is carried in registers; only the knot spacings come from LDS.
+__device__ __forceinline__ void fit_factor(const double *h, int K, double *invd, double *wv) {
+    double hp = h[0], hr = h[1];
+    double id = 1.0 / hr;
+    double w = (hp + hr) * id;
+    invd[0] = id;
+    wv[0] = w;
+    for (int r = 1; r <= K - 2; ++r) {
+        hr = h[r];
+        const double den = 2.0 * (hp + hr) - hr * w;
+        id = 1.0 / den;
+        w = hp * id;
+        invd[r] = id;
+        wv[r] = w;
+        hp = hr;
+    }
+    const double den = h[K - 3] - (h[K - 2] + h[K - 3]) * w;
+    invd[K - 1] = 1.0 / den;
+    wv[K - 1] = 0.0;
+}
+
 // Phase series ph (workgroup ph), to double-double accuracy by one step of
 // iterative refinement: solve the slope system in binary64 (Thomas), form
 // the residual with the exact double-double matrix and right-hand side, solve
@@ -139,15 +162,57 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     // binary64 sub-diagonal of row r (the factor only needs the rounded matrix;
     // the refinement step uses the exact rows)
     auto sub64 = [&](int r) { return (r < K - 1) ? Hh[r] : Hh[K - 2] + Hh[K - 3]; };
-    // binary64 Thomas sweep with the factor in wv / invd: x <- A^-1 x (in place)
+    // binary64 Thomas sweep with the factor in wv / invd: x <- A^-1 x (in place).
+    // The recurrence is carried in registers; the LDS operands of C rows are
+    // loaded together before the rows are eliminated (full batches without
+    // branches, then the remaining rows one by one).
     auto solve = [&](double *x) {
+        constexpr int C = 16;
         double g = x[0] * invd[0];
         x[0] = g;
-        for (int r = 1; r < K; ++r) {
-            g = (x[r] - sub64(r) * g) * invd[r];
-            x[r] = g;
+        auto fstep = [&](int r, double xr) {
+            g = (xr - sub64(r) * g) * invd[r];
+            return g;
+        };
+        int r0 = 1;
+        for (; r0 + C <= K; r0 += C) {
+            double xv[C], sv[C], iv[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                xv[c] = x[r0 + c];
+                sv[c] = sub64(r0 + c);
+                iv[c] = invd[r0 + c];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                g = (xv[c] - sv[c] * g) * iv[c];
+                xv[c] = g;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[r0 + c] = xv[c];
         }
-        for (int r = K - 2; r >= 0; --r) x[r] -= wv[r] * x[r + 1];
+        for (; r0 < K; ++r0) x[r0] = fstep(r0, x[r0]);
+        double nx = x[K - 1];
+        r0 = K - 2;
+        for (; r0 - C + 1 >= 0; r0 -= C) {
+            double xv[C], wr[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                xv[c] = x[r0 - c];
+                wr[c] = wv[r0 - c];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                xv[c] -= wr[c] * nx;
+                nx = xv[c];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[r0 - c] = xv[c];
+        }
+        for (; r0 >= 0; --r0) {
+            x[r0] -= wv[r0] * nx;
+            nx = x[r0];
+        }
     };
 
     for (int i = tid; i < K - 1; i += bs) {
@@ -161,15 +226,7 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     __syncthreads();
     if (tid == 0) {
         // binary64 factor of the rounded matrix, then the first solve
-        invd[0] = 1.0 / Hh[1];
-        wv[0] = (Hh[0] + Hh[1]) * invd[0];
-        for (int r = 1; r < K - 1; ++r) {
-            const double den = 2.0 * (Hh[r - 1] + Hh[r]) - Hh[r] * wv[r - 1];
-            invd[r] = 1.0 / den;
-            wv[r] = Hh[r - 1] * invd[r];
-        }
-        invd[K - 1] = 1.0 / (Hh[K - 3] - sub64(K - 1) * wv[K - 2]);
-        wv[K - 1] = 0.0;
+        fit_factor(Hh, K, invd, wv);
         solve(s0);
     }
     __syncthreads();
@@ -200,9 +257,11 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     }
 }
 
-// Binary64 solve of the amplitude series handled by this workgroup.
-// LDS: h[K], inverse pivots invd[K], multipliers w[K] of the shared grid.
-// Knot values are fetched sixteen at a time so their latency overlaps.
+// Binary64 solve of the amplitude series handled by this workgroup, one lane
+// per real series.  LDS: h[K], inverse pivots invd[K], multipliers w[K] of the
+// shared grid.  Each lane streams its knot values C at a time with the next C
+// loads in flight while the current ones are used (both sweeps), so the
+// global-memory latency is paid about once per sweep rather than per batch.
 __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     constexpr int C = 16;
     const int K = jb.K, M = jb.M;
@@ -210,90 +269,108 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     double *hs = lds, *invd = lds + K, *wv = lds + 2 * K;
     for (int i = tid; i < K - 1; i += bs) hs[i] = jb.t[i + 1] - jb.t[i];
     __syncthreads();
-    if (tid == 0) {
-        double dg = hs[1], sp = hs[0] + hs[1];
-        invd[0] = 1.0 / dg;
-        wv[0] = sp * invd[0];
-        for (int r = 1; r <= K - 2; ++r) {
-            double den = 2.0 * (hs[r - 1] + hs[r]) - hs[r] * wv[r - 1];
-            invd[r] = 1.0 / den;
-            wv[r] = hs[r - 1] * invd[r];
-        }
-        double den = hs[K - 3] - (hs[K - 2] + hs[K - 3]) * wv[K - 2];
-        invd[K - 1] = 1.0 / den;
-        wv[K - 1] = 0.0;
-    }
+    if (tid == 0) fit_factor(hs, K, invd, wv);
     __syncthreads();
     const int q = blk * bs + tid;
     if (q >= 2 * M) return;
     const int k = q >> 1, comp = q & 1;
     const size_t ys = 2 * (size_t)M;                 // knot stride of amp
-    const double *y = jb.amp + 2 * (size_t)k + comp;
+    const double *__restrict__ y = jb.amp + 2 * (size_t)k + comp;
     const size_t cs = 8 * (size_t)M;                 // interval stride of acoef
-    double *o = jb.acoef + 8 * (size_t)k + comp;     // coefficient p at o[i * cs + 2 p]
+    double *__restrict__ o = jb.acoef + 8 * (size_t)k + comp;   // coefficient p at o[i * cs + 2 p]
 
-    // forward: knot idx gives delta_{idx-1}; rows 0 and 1 close at idx = 2,
-    // row idx - 1 at every later knot, row K - 1 after the last knot.
+    // Forward elimination.  Knot idx gives delta_{idx-1}; rows 0 and 1 close
+    // at knot 2, row idx - 1 at every later knot, row K - 1 after the last.
+    // Loads are clamped to the last knot (in bounds, unused past it), so full
+    // batches carry no branches and the next batch stays in flight.
+    auto ldy = [&](int idx) { return y[(size_t)min(max(idx, 0), K - 1) * ys]; };
     double yprev = y[0];
-    double dm1 = 0.0, d0 = 0.0, g = 0.0;
-    for (int i0 = 1; i0 < K; i0 += C) {
-        double yy[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) yy[c] = (i0 + c < K) ? y[(size_t)(i0 + c) * ys] : 0.0;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int idx = i0 + c;
-            if (idx < K) {
-                dm1 = d0;
-                d0 = (yy[c] - yprev) / hs[idx - 1];
-                yprev = yy[c];
-                if (idx == 2) {
-                    const double h0 = hs[0], h1 = hs[1];
-                    g = ((h0 + 2.0 * (h0 + h1)) * h1 * dm1 + h0 * h0 * d0) / (h0 + h1) * invd[0];
-                    o[2] = g;
-                }
-                if (idx >= 2) {
-                    const int r = idx - 1;
-                    const double rhs = 3.0 * (hs[r] * dm1 + hs[r - 1] * d0);
-                    g = (rhs - hs[r] * g) * invd[r];
-                    o[(size_t)r * cs + 2] = g;
-                }
-            }
-        }
+    double dm1, d0, g;
+    {
+        const double y1 = ldy(1), y2 = ldy(2);
+        const double h0 = hs[0], h1 = hs[1];
+        dm1 = (y1 - yprev) / h0;
+        d0 = (y2 - y1) / h1;
+        yprev = y2;
+        g = ((h0 + 2.0 * (h0 + h1)) * h1 * dm1 + h0 * h0 * d0) / (h0 + h1) * invd[0];
+        o[2] = g;
+        const double rhs = 3.0 * (h1 * dm1 + h0 * d0);
+        g = (rhs - h1 * g) * invd[1];
+        o[cs + 2] = g;
     }
+    auto fwd = [&](int idx, double yi) {
+        dm1 = d0;
+        d0 = (yi - yprev) / hs[idx - 1];
+        yprev = yi;
+        const int r = idx - 1;
+        const double rhs = 3.0 * (hs[r] * dm1 + hs[r - 1] * d0);
+        g = (rhs - hs[r] * g) * invd[r];
+        o[(size_t)r * cs + 2] = g;
+    };
+    double ya[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ya[c] = ldy(3 + c);
+    int i0 = 3;
+    for (; i0 + C <= K; i0 += C) {
+        double yb[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) yb[c] = ldy(i0 + C + c);
+#pragma unroll
+        for (int c = 0; c < C; ++c) fwd(i0 + c, ya[c]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) ya[c] = yb[c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (i0 + c < K) fwd(i0 + c, ya[c]);
     {
         const double ha = hs[K - 3], hb = hs[K - 2];
         const double rhs = (hb * hb * dm1 + (2.0 * (ha + hb) + hb) * ha * d0) / (ha + hb);
         g = (rhs - (hb + ha) * g) * invd[K - 1];
     }
-    // back substitution and coefficients, interval K-2 down to 0
+    // Back substitution and coefficients, interval K-2 down to 0.  The loads
+    // of the next batch read rows below the current batch, which it does not
+    // write (clamped to row 0 past the end, and then unused).
     double s_next = g;
     double yr1 = yprev;                              // y_{K-1}
-    for (int r0 = K - 2; r0 >= 0; r0 -= C) {
-        double gg[C], yy[C];
+    auto ldg = [&](int r) { return o[(size_t)max(r, 0) * cs + 2]; };
+    auto back = [&](int r, double gr, double yv) {
+        const double hr = hs[r];
+        const double dr = (yr1 - yv) / hr;
+        const double sv = gr - wv[r] * s_next;
+        double *orow = o + (size_t)r * cs;
+        orow[0] = yv;
+        orow[2] = sv;
+        orow[4] = (3.0 * dr - 2.0 * sv - s_next) / hr;
+        orow[6] = (sv + s_next - 2.0 * dr) / (hr * hr);
+        s_next = sv;
+        yr1 = yv;
+    };
+    double ga[C], yv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        ga[c] = ldg(K - 2 - c);
+        yv[c] = ldy(K - 2 - c);
+    }
+    int r0 = K - 2;
+    for (; r0 - C + 1 >= 0; r0 -= C) {
+        double gb[C], yw[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const int r = r0 - c;
-            gg[c] = (r >= 0) ? o[(size_t)r * cs + 2] : 0.0;
-            yy[c] = (r >= 0) ? y[(size_t)r * ys] : 0.0;
+            gb[c] = ldg(r0 - C - c);
+            yw[c] = ldy(r0 - C - c);
         }
 #pragma unroll
+        for (int c = 0; c < C; ++c) back(r0 - c, ga[c], yv[c]);
+#pragma unroll
         for (int c = 0; c < C; ++c) {
-            const int r = r0 - c;
-            if (r >= 0) {
-                const double hr = hs[r];
-                const double dr = (yr1 - yy[c]) / hr;
-                const double s = gg[c] - wv[r] * s_next;
-                double *orow = o + (size_t)r * cs;
-                orow[0] = yy[c];
-                orow[2] = s;
-                orow[4] = (3.0 * dr - 2.0 * s - s_next) / hr;
-                orow[6] = (s + s_next - 2.0 * dr) / (hr * hr);
-                s_next = s;
-                yr1 = yy[c];
-            }
+            ga[c] = gb[c];
+            yv[c] = yw[c];
         }
     }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (r0 - c >= 0) back(r0 - c, ga[c], yv[c]);
 }
 
 // Workgroups 0 .. n_ph-1 fit the phases, the rest the amplitude series.

@@ -6,6 +6,7 @@ Bars: binary64 path max relative error <= 1e-10; mixed path mismatch <= 1e-6
 """
 import math
 
+import mpmath as mp
 import numpy as np
 import pytest
 
@@ -68,9 +69,14 @@ def check(got, ref, prec):
 
 def test_spline_coefficients_match_oracle(native_mod, torch_dev):
     import torch
-    for name, w in [("config0", synth.config0()),
-                    ("tiny K=4", synth.tiny_waveform(11, K=4, M=3)),
-                    ("tiny K=23", synth.tiny_waveform(12, K=23, M=9, l_max=5, n_max=4))]:
+    # knot counts around the 16-row batches of the sweeps: tail only (4, 5,
+    # 18), one full batch and no tail (19), full batches and a tail (20, 23,
+    # 35, 40), many batches (1024)
+    cases = [("config0", synth.config0()),
+             ("tiny K=4", synth.tiny_waveform(11, K=4, M=3))]
+    for i, K in enumerate((5, 18, 19, 20, 23, 35, 1024)):
+        cases.append((f"tiny K={K}", synth.tiny_waveform(12 + i, K=K, M=9, l_max=5, n_max=4)))
+    for name, w in cases:
         log(f"[spline] {name} K={w.K} M={w.M}")
         pp, pr, amp = to_dev(w, torch_dev)
         with native_mod.Plan(0, "fp64") as plan:
@@ -97,8 +103,16 @@ def test_spline_coefficients_match_oracle(native_mod, torch_dev):
                 d = np.abs(got[:, p] - ref_p[:, p]) * h ** p
                 log(f"    phase {ph} p={p}: max |dc_p| h^p = {d.max():.2e} rad")
                 assert d.max() <= 1e-13 * inc, (ph, p)
-            red = np.mod(got[:, 0] - y[:-1] + math.pi, 2 * math.pi) - math.pi
-            assert np.max(np.abs(red)) <= 1e-12
+            # the constant term is y_i reduced mod 2 pi as a double-double;
+            # checked in 50-digit arithmetic (a binary64 check of hi + lo - y_i
+            # carries ~1e-12 of its own rounding once y_i reaches 1e4 rad)
+            mp.mp.dps = 50
+            two_pi = 2 * mp.pi
+            red = []
+            for i in range(w.K - 1):
+                dif = mp.mpf(pc[i, ph, 0, 0]) + mp.mpf(pc[i, ph, 0, 1]) - mp.mpf(y[i])
+                red.append(float(abs(dif - mp.nint(dif / two_pi) * two_pi)))
+            assert max(red) <= 1e-12
             assert np.all(np.abs(got[:, 0]) <= math.pi + 1e-12)
 
 
