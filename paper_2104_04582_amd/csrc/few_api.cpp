@@ -392,8 +392,9 @@ PrepJob prep_job(const HostReq &r, ReqBase base, double theta, double phi, doubl
     j.short_tile = short_tile_samples(fp32);
     j.short_len = tl.short_len;
     j.parts = tl.parts;
-    j.src_blocks = (r.terms.n_src + 255) / 256;
-    j.fold_blocks = (int)(((long long)(r.K - 1) * r.terms.n_terms + 255) / 256);
+    // about one (interval, term) pair per lane of a 256-lane fold workgroup
+    j.fold_terms = std::max(1, std::min(64, 256 / (r.K - 1)));
+    j.fold_blocks = (r.terms.n_terms + j.fold_terms - 1) / j.fold_terms;
     return j;
 }
 
@@ -1065,7 +1066,7 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
     SumJob *sj = (SumJob *)(host + off_sum);
     const bool fp32 = p->fp32;
     const int tile = tile_samples(fp32);
-    int max_amp_blocks = 0, max_K = 4, max_src_blocks = 0, max_fold_blocks = 0;
+    int max_amp_blocks = 0, max_K = 4, max_fold_blocks = 0;
     long long waves = 0;
     for (int i = 0; i < n; ++i) {
         ServedReq *r = b->reqs[i];
@@ -1080,14 +1081,13 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         waves += tile_upper_bound(r->r.n_samples, r->h.K, tile);
         max_amp_blocks = std::max(max_amp_blocks, fj[i].amp_blocks);
         max_K = std::max(max_K, r->h.K);
-        max_src_blocks = std::max(max_src_blocks, pj[i].src_blocks);
         max_fold_blocks = std::max(max_fold_blocks, pj[i].fold_blocks);
     }
     if (waves > 0x3fffffff) return fail(FEW_E_ARG, "batch too large");
     HIP_TRY(hipMemcpyAsync(dev, host, upload_end, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_fit_batch((const FitJob *)(dev + off_fit), n, max_amp_blocks, max_K, s));
-    HIP_TRY(launch_prepare_batch((const PrepJob *)(dev + off_prep), n, max_src_blocks,
-                                 max_fold_blocks, fp32, s));
+    HIP_TRY(launch_prepare_batch((const PrepJob *)(dev + off_prep), n, max_fold_blocks, fp32,
+                                 s));
     HIP_TRY(launch_sum_batch((const SumJob *)(dev + off_sum), n, (int)waves, fp32, true,
                              counter, s));
     HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));

@@ -92,8 +92,8 @@ struct PrepJob {
     int K, M, n_terms, n_src;
     int tile;               // samples per tile
     int short_tile;         // samples per short tile
-    int src_blocks;         // workgroups of the harmonic pass
-    int fold_blocks;        // workgroups of the fold pass
+    int fold_terms;         // consecutive terms folded by one workgroup
+    int fold_blocks;        // term groups of the fold
 };
 
 // Summation stage for one request.
@@ -125,8 +125,8 @@ hipError_t launch_fit(const FitJob &job, hipStream_t stream);
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream);
 hipError_t launch_prepare(const PrepJob &job, bool fp32, hipStream_t stream);
-hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_src_blocks,
-                                int max_fold_blocks, bool fp32, hipStream_t stream);
+hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_fold_blocks,
+                                bool fp32, hipStream_t stream);
 hipError_t launch_sum(const SumJob &job, int slots, bool fp32, hipStream_t stream);
 // Inner-product variant of launch_sum: instead of storing h, every tile slot
 // writes its partial sums to job.partial (inner_slots(...) entries), then one

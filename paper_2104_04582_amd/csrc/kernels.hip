@@ -427,18 +427,27 @@ __device__ __forceinline__ PieceRange piece_range(long long a, long long e, long
     return r;
 }
 
+// ceil(a / b) for 0 <= a < 2^53 and b > 0, exactly: a binary64 estimate (off
+// by at most one) corrected with integer products, instead of the long
+// instruction sequence of a 64-bit integer division.
+__device__ __forceinline__ long long ceil_div_pos(long long a, int b) {
+    long long q = (long long)((double)a / (double)b);
+    if (q * b < a) ++q;
+    if (q > 0 && (q - 1) * b >= a) --q;
+    return q;
+}
+
 __device__ int piece_tiles(const PrepJob &jb, int p, int i) {
     const PieceRange r = piece_range(jb.starts[i], jb.starts[i + 1], jb.n, jb.parts, p,
                                      jb.short_len);
-    return (int)((r.split - r.lo + jb.tile - 1) / jb.tile +
-                 (r.hi - r.split + jb.short_tile - 1) / jb.short_tile);
+    return (int)(ceil_div_pos(r.split - r.lo, jb.tile) +
+                 ceil_div_pos(r.hi - r.split, jb.short_tile));
 }
 
 __device__ void prep_intervals(const PrepJob &jb) {
-    __shared__ int part[256];
-    const int tid = threadIdx.x, bs = blockDim.x;
+    const int tid = threadIdx.x;
     const int K = jb.K;
-    for (int i = tid; i < K; i += bs) {
+    for (int i = tid; i < K; i += blockDim.x) {
         long long s;
         if (i == 0) s = 0;
         else if (i == K - 1) s = jb.n;
@@ -446,30 +455,25 @@ __device__ void prep_intervals(const PrepJob &jb) {
         jb.starts[i] = s;
     }
     __syncthreads();
-    // per part: tiles per interval, exclusive prefix by runs of intervals
+    // per part (one wave each): tiles per interval and their exclusive prefix,
+    // 64 intervals at a time by a shuffle scan
     const int P = K - 1;
-    const int per = (P + bs - 1) / bs;
-    const int a = tid * per, b = min(a + per, P);
-    for (int pt = 0; pt < jb.parts; ++pt) {
+    const int lane = tid & (kWave - 1), waves = blockDim.x / kWave;
+    for (int pt = tid / kWave; pt < jb.parts; pt += waves) {
         int *tp = jb.tile_pref + (size_t)pt * K;
-        int local = 0;
-        for (int i = a; i < b; ++i) local += piece_tiles(jb, pt, i);
-        // inclusive block scan of the per-lane counts (Hillis-Steele in LDS)
-        __syncthreads();
-        part[tid] = local;
-        __syncthreads();
-        for (int off = 1; off < bs; off <<= 1) {
-            const int v = (tid >= off) ? part[tid - off] : 0;
-            __syncthreads();
-            part[tid] += v;
-            __syncthreads();
+        int run = 0;
+        for (int c0 = 0; c0 < P; c0 += kWave) {
+            const int i = c0 + lane;
+            const int cnt = (i < P) ? piece_tiles(jb, pt, i) : 0;
+            int incl = cnt;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int v = __shfl_up(incl, off);
+                if (lane >= off) incl += v;
+            }
+            if (i < P) tp[i] = run + incl - cnt;
+            run += __shfl(incl, kWave - 1);
         }
-        if (tid == bs - 1) tp[P] = part[tid];
-        int run = part[tid] - local;
-        for (int i = a; i < b; ++i) {
-            tp[i] = run;
-            run += piece_tiles(jb, pt, i);
-        }
+        if (lane == 0) tp[P] = run;
     }
 }
 
@@ -493,46 +497,45 @@ __device__ void prep_harmonic(const PrepJob &jb, int e) {
     jb.ybuf[e] = make_double2(yr, yi);
 }
 
-__device__ __forceinline__ void prep_body(const PrepJob &jb) {
-    if (blockIdx.x == 0) {
-        prep_intervals(jb);
-        return;
-    }
-    prep_harmonic(jb, (blockIdx.x - 1) * blockDim.x + threadIdx.x);
-}
-
-__global__ __launch_bounds__(256) void prepare_kernel(PrepJob jb) { prep_body(jb); }
-
-__global__ __launch_bounds__(256) void prepare_batch_kernel(const PrepJob *jobs) {
-    const PrepJob jb = jobs[blockIdx.y];
-    prep_body(jb);
-}
-
 // Fold the l-sum for one (interval, term) pair:
 //   C_term = scale * sum_e Y_e * (A_k or conj(A_k)),
-// rescaled to u = x / h_i (coefficient p times h_i^p).  Consecutive lanes take
-// consecutive terms of one interval, so table stores are contiguous.
+// rescaled to u = x / h_i (coefficient p times h_i^p).
 template <typename Real>
-__device__ void fold_pair(const PrepJob &jb, long long p) {
-    const long long P = (long long)(jb.K - 1) * jb.n_terms;
-    if (p >= P) return;
-    const int i = (int)(p / jb.n_terms), term = (int)(p % jb.n_terms);
+__device__ void fold_pair(const PrepJob &jb, int i, int term) {
     double acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-    const int ea = jb.term_ptr[term], eb = jb.term_ptr[term + 1];
-    for (int e = ea; e < eb; ++e) {
-        const double2 w = jb.ybuf[e];
-        const int2 src = jb.term_src[e];
+    auto add = [&](double2 w, int2 src, const double *a) {
         const double sgn = ((src.y >> 16) & 1) ? -1.0 : 1.0;
-        const double *a = jb.acoef + ((size_t)i * jb.M + src.x) * 8;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double ar = a[2 * q], ai = sgn * a[2 * q + 1];
             acc[2 * q] += w.x * ar - w.y * ai;
             acc[2 * q + 1] += w.x * ai + w.y * ar;
         }
+    };
+    const double *arow = jb.acoef + (size_t)i * jb.M * 8;
+    const int ea = jb.term_ptr[term], eb = jb.term_ptr[term + 1];
+    int e = ea;
+    // four contributors at a time: their weights, indices and coefficient rows
+    // are all loaded before any is added (in contributor order, as one by one)
+    for (; e + 4 <= eb; e += 4) {
+        double2 w[4];
+        int2 src[4];
+        double av[4][8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            w[j] = jb.ybuf[e + j];
+            src[j] = jb.term_src[e + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) av[j][c] = arow[(size_t)src[j].x * 8 + c];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) add(w[j], src[j], av[j]);
     }
+    for (; e < eb; ++e) add(jb.ybuf[e], jb.term_src[e], arow + (size_t)jb.term_src[e].x * 8);
     const double h = jb.t[i + 1] - jb.t[i];
     double f = jb.scale;
     // terms are stored in reverse order (position n_terms - 1 - term), so the
@@ -558,15 +561,41 @@ __device__ void fold_pair(const PrepJob &jb, long long p) {
     }
 }
 
+// Prepare and fold in one launch.  Workgroup 0 computes the interval starts
+// and the per-part tile prefixes; workgroup 1 + g folds the group of
+// fold_terms consecutive terms starting at g fold_terms over every interval
+// (fold_terms is chosen so that a group is about one (interval, term) pair per
+// lane).
+// The group first forms the harmonic weight of each of its contributors (each
+// contributor belongs to one term, so each weight is formed once, by the one
+// workgroup that reads it), then folds.  Consecutive lanes take consecutive
+// terms of one interval, so table stores are contiguous.
 template <typename Real>
-__global__ __launch_bounds__(256) void fold_kernel(PrepJob jb) {
-    fold_pair<Real>(jb, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+__device__ void prepare_body(const PrepJob &jb, int b) {
+    if (b == 0) {
+        prep_intervals(jb);
+        return;
+    }
+    const int t0 = (b - 1) * jb.fold_terms;
+    if (t0 >= jb.n_terms) return;                   // uniform per workgroup
+    const int nt = min(jb.fold_terms, jb.n_terms - t0);
+    const int e0 = jb.term_ptr[t0], e1 = jb.term_ptr[t0 + nt];
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) prep_harmonic(jb, e);
+    __syncthreads();                                // weights visible to the workgroup
+    const int pairs = (jb.K - 1) * nt;
+    for (int q = threadIdx.x; q < pairs; q += blockDim.x)
+        fold_pair<Real>(jb, q / nt, t0 + q % nt);
 }
 
 template <typename Real>
-__global__ __launch_bounds__(256) void fold_batch_kernel(const PrepJob *jobs) {
+__global__ __launch_bounds__(256) void prepare_kernel(PrepJob jb) {
+    prepare_body<Real>(jb, blockIdx.x);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void prepare_batch_kernel(const PrepJob *jobs) {
     const PrepJob jb = jobs[blockIdx.y];
-    fold_pair<Real>(jb, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+    prepare_body<Real>(jb, blockIdx.x);
 }
 
 // ===========================================================================
@@ -1310,28 +1339,21 @@ hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, 
 }
 
 hipError_t launch_prepare(const PrepJob &job, bool fp32, hipStream_t stream) {
-    hipLaunchKernelGGL(prepare_kernel, dim3(1 + job.src_blocks), dim3(256), 0, stream, job);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const dim3 grid(1 + job.fold_blocks);
     if (fp32)
-        hipLaunchKernelGGL(fold_kernel<float>, dim3(job.fold_blocks), dim3(256), 0, stream, job);
+        hipLaunchKernelGGL(prepare_kernel<float>, grid, dim3(256), 0, stream, job);
     else
-        hipLaunchKernelGGL(fold_kernel<double>, dim3(job.fold_blocks), dim3(256), 0, stream, job);
+        hipLaunchKernelGGL(prepare_kernel<double>, grid, dim3(256), 0, stream, job);
     return hipGetLastError();
 }
 
-hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_src_blocks,
-                                int max_fold_blocks, bool fp32, hipStream_t stream) {
-    hipLaunchKernelGGL(prepare_batch_kernel, dim3(1 + max_src_blocks, n_jobs), dim3(256), 0,
-                       stream, jobs_dev);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_prepare_batch(const PrepJob *jobs_dev, int n_jobs, int max_fold_blocks,
+                                bool fp32, hipStream_t stream) {
+    const dim3 grid(1 + max_fold_blocks, n_jobs);
     if (fp32)
-        hipLaunchKernelGGL(fold_batch_kernel<float>, dim3(max_fold_blocks, n_jobs), dim3(256), 0,
-                           stream, jobs_dev);
+        hipLaunchKernelGGL(prepare_batch_kernel<float>, grid, dim3(256), 0, stream, jobs_dev);
     else
-        hipLaunchKernelGGL(fold_batch_kernel<double>, dim3(max_fold_blocks, n_jobs), dim3(256),
-                           0, stream, jobs_dev);
+        hipLaunchKernelGGL(prepare_batch_kernel<double>, grid, dim3(256), 0, stream, jobs_dev);
     return hipGetLastError();
 }
 
