@@ -346,7 +346,7 @@ FitJob fit_job(const HostReq &r, ReqBase base, const double *pp, const double *p
     j.acoef = at_dev<double>(r, base, r.L.off_acoef);
     j.K = r.K;
     j.M = r.M;
-    j.amp_blocks = (2 * r.M + 255) / 256;
+    j.amp_blocks = (2 * r.M + kFitSeriesPerBlock - 1) / kFitSeriesPerBlock;
     return j;
 }
 

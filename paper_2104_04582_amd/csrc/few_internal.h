@@ -20,6 +20,10 @@ constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 #ifndef FEW_CHUNK_TERMS
 #define FEW_CHUNK_TERMS 1024
 #endif
+// Amplitude series per fit workgroup: one wave of the four does the sweeps,
+// so the series (and their scattered coefficient stores) spread over four
+// times as many compute units as with one series per lane of every wave.
+constexpr int kFitSeriesPerBlock = 64;
 constexpr int kChunkTerms = FEW_CHUNK_TERMS;   // terms staged in LDS at once (binary32: 32 B each)
 
 // Samples per lane in one wave tile of the summation kernel.

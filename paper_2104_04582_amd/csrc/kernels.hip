@@ -222,13 +222,13 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
         Dh[i] = d.hi; Dl[i] = d.lo;
     }
     __syncthreads();
-    for (int r = tid; r < K; r += bs) s0[r] = rhs(r).hi;
+    // binary64 factor of the rounded matrix (one lane of wave 0) while the
+    // other waves form the right-hand side, then the first solve
+    if (tid == 0) fit_factor(Hh, K, invd, wv);
+    if (tid >= kWave)
+        for (int r = tid - kWave; r < K; r += bs - kWave) s0[r] = rhs(r).hi;
     __syncthreads();
-    if (tid == 0) {
-        // binary64 factor of the rounded matrix, then the first solve
-        fit_factor(Hh, K, invd, wv);
-        solve(s0);
-    }
+    if (tid == 0) solve(s0);
     __syncthreads();
     // residual of the exact (double-double) system at s0
     for (int r = tid; r < K; r += bs) {
@@ -258,20 +258,27 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
 }
 
 // Binary64 solve of the amplitude series handled by this workgroup, one lane
-// per real series.  LDS: h[K], inverse pivots invd[K], multipliers w[K] of the
-// shared grid.  Each lane streams its knot values C at a time with the next C
+// per real series.  LDS: h[K], inverse pivots invd[K], multipliers w[K] and
+// 1 / h[K] of the shared grid (the sweeps multiply by 1 / h_i instead of
+// dividing: a division is a long dependent sequence on this hardware, and the
+// sweeps are latency bound).  Each lane streams its knot values C at a time with the next C
 // loads in flight while the current ones are used (both sweeps), so the
 // global-memory latency is paid about once per sweep rather than per batch.
 __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     constexpr int C = 16;
     const int K = jb.K, M = jb.M;
     const int tid = threadIdx.x, bs = blockDim.x;
-    double *hs = lds, *invd = lds + K, *wv = lds + 2 * K;
-    for (int i = tid; i < K - 1; i += bs) hs[i] = jb.t[i + 1] - jb.t[i];
+    double *hs = lds, *invd = lds + K, *wv = lds + 2 * K, *ih = lds + 3 * K;
+    for (int i = tid; i < K - 1; i += bs) {
+        const double h = jb.t[i + 1] - jb.t[i];
+        hs[i] = h;
+        ih[i] = 1.0 / h;
+    }
     __syncthreads();
     if (tid == 0) fit_factor(hs, K, invd, wv);
     __syncthreads();
-    const int q = blk * bs + tid;
+    if (tid >= kFitSeriesPerBlock) return;
+    const int q = blk * kFitSeriesPerBlock + tid;
     if (q >= 2 * M) return;
     const int k = q >> 1, comp = q & 1;
     const size_t ys = 2 * (size_t)M;                 // knot stride of amp
@@ -289,8 +296,8 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     {
         const double y1 = ldy(1), y2 = ldy(2);
         const double h0 = hs[0], h1 = hs[1];
-        dm1 = (y1 - yprev) / h0;
-        d0 = (y2 - y1) / h1;
+        dm1 = (y1 - yprev) * ih[0];
+        d0 = (y2 - y1) * ih[1];
         yprev = y2;
         g = ((h0 + 2.0 * (h0 + h1)) * h1 * dm1 + h0 * h0 * d0) / (h0 + h1) * invd[0];
         o[2] = g;
@@ -300,7 +307,7 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     }
     auto fwd = [&](int idx, double yi) {
         dm1 = d0;
-        d0 = (yi - yprev) / hs[idx - 1];
+        d0 = (yi - yprev) * ih[idx - 1];
         yprev = yi;
         const int r = idx - 1;
         const double rhs = 3.0 * (hs[r] * dm1 + hs[r - 1] * d0);
@@ -335,14 +342,14 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     double yr1 = yprev;                              // y_{K-1}
     auto ldg = [&](int r) { return o[(size_t)max(r, 0) * cs + 2]; };
     auto back = [&](int r, double gr, double yv) {
-        const double hr = hs[r];
-        const double dr = (yr1 - yv) / hr;
+        const double ir = ih[r];
+        const double dr = (yr1 - yv) * ir;
         const double sv = gr - wv[r] * s_next;
         double *orow = o + (size_t)r * cs;
         orow[0] = yv;
         orow[2] = sv;
-        orow[4] = (3.0 * dr - 2.0 * sv - s_next) / hr;
-        orow[6] = (sv + s_next - 2.0 * dr) / (hr * hr);
+        orow[4] = (3.0 * dr - 2.0 * sv - s_next) * ir;
+        orow[6] = (sv + s_next - 2.0 * dr) * (ir * ir);
         s_next = sv;
         yr1 = yv;
     };
@@ -1320,7 +1327,7 @@ __global__ void zero_u32_kernel(unsigned *p, int n) {
 static inline int round_up8(long long x) { return (int)((x + 7) / 8 * 8); }
 
 static inline size_t fit_lds_bytes(int K) {
-    // phase workgroups: 8 arrays of K; amplitude workgroups: 3 arrays of K
+    // phase workgroups: 8 arrays of K; amplitude workgroups: 4 arrays of K
     return sizeof(double) * 8 * (size_t)K;
 }
 
