@@ -8,7 +8,10 @@ HBM before timing starts.  The headline value is the mixed-precision path;
 the binary64 path is timed the same way and reported beside it.
 
 Also reported: the dominant kernel's roofline (the summation kernel, timed
-with HIP events recorded by the library on the stream it launches on), the
+with HIP events recorded by the library on the stream it launches on, around
+the summation launches of the timed steps only; the per-stage breakdown comes
+from a second, fully event-timed pass, since an event pair delays the launch
+after it by several microseconds), the
 served-stream latency (Poisson arrivals of uneven requests through
 few_submit/few_poll) and the CPU oracle timed on a bounded sample.
 
@@ -50,7 +53,11 @@ def algorithmic_flops(n_terms: int, n_segs: int, n: int) -> float:
     return float(n) * (20.0 * n_terms + 8.0 * n_segs)
 
 
-def time_path(native, plan, w, dev, steps: int, warmup: int):
+def time_path(native, plan, w, dev, steps: int, warmup: int, settle_s: float = 0.0):
+    """Mean wall time of `steps` fit + sum steps after at least `warmup` untimed
+    steps and at least `settle_s` seconds of them (the shader clock takes a few
+    milliseconds of load to settle), with the plan's kernel timings of the
+    timed steps."""
     import torch
     pp = torch.from_numpy(np.ascontiguousarray(w.phi_phi)).to(dev)
     pr = torch.from_numpy(np.ascontiguousarray(w.phi_r)).to(dev)
@@ -62,8 +69,13 @@ def time_path(native, plan, w, dev, steps: int, warmup: int):
         plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples, out=out)
         sp.free()
 
-    for _ in range(warmup):
+    t_w = time.perf_counter()
+    done = 0
+    while done < warmup or time.perf_counter() - t_w < settle_s:
         step()
+        done += 1
+        if done % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     plan.timing(reset=True)
     t0 = time.perf_counter()
@@ -367,16 +379,21 @@ def main() -> int:
     res = {}
     outs = {}
     for prec in ("mixed", "fp64"):
-        log(f"[bench] {prec}: warmup {args.warmup}, steps {args.steps}")
-        with native.Plan(0, prec, timing=True) as plan:
-            sec, tm, out = time_path(native, plan, w, dev, args.steps, args.warmup)
+        log(f"[bench] {prec}: warmup {args.warmup} (and >= 0.2 s), steps {args.steps}")
+        # Timed region: HIP events around the summation launches only (an event
+        # pair delays the launch after it; the other stages stay back to back).
+        with native.Plan(0, prec, timing="sum") as plan:
+            sec, tm, out = time_path(native, plan, w, dev, args.steps, args.warmup, 0.2)
             outs[prec] = out
+        # Stage breakdown: the same steps with events around every launch.
+        with native.Plan(0, prec, timing=True) as plan:
+            _, tms, _ = time_path(native, plan, w, dev, 5, 2)
         sum_ms = tm["sum_ms"] / max(tm["sum_launches"], 1)
         res[prec] = {
             "ms_per_step": sec * 1e3,
             "value": w.mode_samples / sec,
-            "spline_ms": tm["spline_ms"] / max(tm["spline_launches"], 1),
-            "prepare_ms": tm["prepare_ms"] / max(tm["prepare_launches"], 1),
+            "spline_ms": tms["spline_ms"] / max(tms["spline_launches"], 1),
+            "prepare_ms": tms["prepare_ms"] / max(tms["prepare_launches"], 1),
             "sum_ms": sum_ms,
             "sum_tflops": flops / (sum_ms * 1e-3) / 1e12,
             "canonical_tflops": canonical / (sum_ms * 1e-3) / 1e12,

@@ -79,7 +79,13 @@ typedef enum {
                        compensated binary32 accumulation; complex64 output */
 } few_precision;
 
-enum { FEW_FLAG_TIMING = 1 };   /* record HIP events around every kernel launch */
+enum {
+    FEW_FLAG_TIMING = 1,      /* record HIP events around every kernel launch */
+    FEW_FLAG_TIMING_SUM = 2   /* record them around summation launches only: each event pair
+                                 delays the launch after it by several microseconds, so this
+                                 keeps the other stages back to back while the dominant
+                                 kernel is timed */
+};
 
 typedef struct few_plan_s *few_plan;
 typedef struct few_spline_s *few_spline;

@@ -126,7 +126,7 @@ class PinnedPool {
             }
         void *p = nullptr;
         size_t sz = std::max<size_t>(bytes, 1 << 16);
-        if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipHostMalloc(&p, sz, hipHostMallocCoherent) != hipSuccess) return nullptr;
         bufs_.push_back({p, sz, true});
         return p;
     }
@@ -517,11 +517,12 @@ hipEvent_t pool_event(few_plan p) {
     return e;
 }
 
-// Run launch() between two timing events when FEW_FLAG_TIMING is set.
+// Run launch() between two timing events when FEW_FLAG_TIMING is set (or
+// FEW_FLAG_TIMING_SUM, for summation launches).
 template <typename F>
 int timed_launch(few_plan p, int stage, hipStream_t s, F launch) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (p->flags & FEW_FLAG_TIMING) {
+    if ((p->flags & FEW_FLAG_TIMING) || ((p->flags & FEW_FLAG_TIMING_SUM) && stage == ST_SUM)) {
         a = pool_event(p);
         b = pool_event(p);
         if (a && b) hipEventRecord(a, s);
@@ -533,6 +534,17 @@ int timed_launch(few_plan p, int stage, hipStream_t s, F launch) {
         p->timed.push_back({stage, {a, b}});
     }
     return FEW_OK;
+}
+
+// Copy `bytes` of pinned host memory (from hipHostMalloc, host-coherent) to
+// the device on stream s with the upload kernel: the GPU reads the host
+// buffer directly, so the copy is ordered on the compute queue like the
+// kernels that use it.
+hipError_t pinned_upload(void *dst, void *host, size_t bytes, hipStream_t s) {
+    void *src = nullptr;
+    hipError_t e = hipHostGetDevicePointer(&src, host, 0);
+    if (e != hipSuccess) return e;
+    return launch_upload(src, dst, bytes, s);
 }
 
 // Copy n bytes from host to device on the plan stream through a pinned slot.
@@ -547,11 +559,11 @@ int sync_upload(few_plan p, const HostReq &r, char *dst) {
         if (p->stage[s]) hipHostFree(p->stage[s]);
         p->stage[s] = nullptr;
         size_t sz = std::max<size_t>(r.upload_bytes, 1 << 20);
-        HIP_TRY(hipHostMalloc(&p->stage[s], sz, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc(&p->stage[s], sz, hipHostMallocCoherent));
         p->stage_size[s] = sz;
     }
     stage_upload(r, (char *)p->stage[s]);
-    HIP_TRY(hipMemcpyAsync(dst, p->stage[s], r.upload_bytes, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(pinned_upload(dst, p->stage[s], r.upload_bytes, p->stream));
     HIP_TRY(hipEventRecord(p->stage_ev[s], p->stream));
     p->stage_pending[s] = true;
     return FEW_OK;
@@ -1084,7 +1096,7 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         max_fold_blocks = std::max(max_fold_blocks, pj[i].fold_blocks);
     }
     if (waves > 0x3fffffff) return fail(FEW_E_ARG, "batch too large");
-    HIP_TRY(hipMemcpyAsync(dev, host, upload_end, hipMemcpyHostToDevice, s));
+    HIP_TRY(pinned_upload(dev, host, upload_end, s));
     HIP_TRY(launch_fit_batch((const FitJob *)(dev + off_fit), n, max_amp_blocks, max_K, s));
     HIP_TRY(launch_prepare_batch((const PrepJob *)(dev + off_prep), n, max_fold_blocks, fp32,
                                  s));

@@ -125,6 +125,7 @@ struct SumJob {
 // Binary32 summation workgroups resident at once on the current device, for
 // the two-phase (Schwarzschild) or three-phase (generic Kerr) kernel.
 int sum_resident_workgroups(int n_ph);
+hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t stream);
 hipError_t launch_fit(const FitJob &job, hipStream_t stream);
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream);

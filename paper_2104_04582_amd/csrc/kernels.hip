@@ -1326,6 +1326,29 @@ __global__ void zero_u32_kernel(unsigned *p, int n) {
 // ===========================================================================
 static inline int round_up8(long long x) { return (int)((x + 7) / 8 * 8); }
 
+// Upload of a request's host tables: `bytes` from pinned, host-coherent memory
+// (read by the GPU over the host link) into device memory, by a kernel on the
+// compute queue, so a small upload does not wait on a copy engine's signal.
+// 16-byte words, then the remaining bytes one per lane.
+__global__ __launch_bounds__(256) void upload_kernel(const unsigned char *src, unsigned char *dst,
+                                                     long long bytes) {
+    const long long n16 = bytes / 16;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = tid; i < n16; i += stride)
+        ((uint4 *)dst)[i] = ((const uint4 *)src)[i];
+    if (tid < bytes - n16 * 16) dst[n16 * 16 + tid] = src[n16 * 16 + tid];
+}
+
+hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t stream) {
+    if (bytes == 0) return hipSuccess;
+    const long long n16 = (long long)(bytes / 16);
+    const int blocks = (int)std::max<long long>(1, std::min<long long>((n16 + 255) / 256, 128));
+    hipLaunchKernelGGL(upload_kernel, dim3(blocks), dim3(256), 0, stream,
+                       (const unsigned char *)src, (unsigned char *)dst, (long long)bytes);
+    return hipGetLastError();
+}
+
 static inline size_t fit_lds_bytes(int K) {
     // phase workgroups: 8 arrays of K; amplitude workgroups: 4 arrays of K
     return sizeof(double) * 8 * (size_t)K;
