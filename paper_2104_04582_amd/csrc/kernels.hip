@@ -88,27 +88,57 @@ __device__ __forceinline__ double dev_sample_time(double t_start, double dt, lon
 // Solved by forward elimination and back substitution without pivoting.
 // ===========================================================================
 
-// LU factor of the slope system on the shared grid (one lane): inverse pivots
-// invd[r] and multipliers w[r] of the forward sweep, h in LDS.  The recurrence
-// is carried in registers; only the knot spacings come from LDS.
-__device__ __forceinline__ void fit_factor(const double *h, int K, double *invd, double *wv) {
-    double hp = h[0], hr = h[1];
-    double id = 1.0 / hr;
-    double w = (hp + hr) * id;
-    invd[0] = id;
-    wv[0] = w;
-    for (int r = 1; r <= K - 2; ++r) {
-        hr = h[r];
-        const double den = 2.0 * (hp + hr) - hr * w;
-        id = 1.0 / den;
-        w = hp * id;
-        invd[r] = id;
-        wv[r] = w;
+// LU factor of the slope system on the shared grid: inverse pivots invd[r] and
+// multipliers w[r] = c_r invd[r] of the forward sweep (c_r the super-diagonal),
+// with pivots den_r = a_r - b_r w_{r-1} (a_r diagonal, b_r sub-diagonal).
+// The pivot recurrence is a continued fraction; with w_r = p_r / q_r it is the
+// division-free pair
+//   q_r = a_r q_{r-1} - b_r p_{r-1},   p_r = c_r q_{r-1},   den_r = q_r / q_{r-1},
+// rescaled at every row by a power of two (exact, ratios unchanged) so it
+// cannot overflow.  One lane runs it (fit_factor_serial: a multiply, an FMA and
+// the rescale per row, knot spacings fetched 16 at a time), storing q_{r-1}
+// and q_r per row in invd / wv; then every lane forms the ratios
+// (fit_factor_finish).  A division per row on the serial chain was its
+// latency bound.
+__device__ __forceinline__ void fit_factor_serial(const double *h, int K, double *num,
+                                                  double *den) {
+    constexpr int C = 16;
+    double q = h[1], p = h[0] + h[1];               // row 0: diag h_1, super h_0 + h_1
+    num[0] = 1.0;
+    den[0] = q;
+    double hp = h[0];                               // h_{r-1}
+    auto row = [&](int r, double hr) {              // interior row r: b = h_r, a = 2(h_{r-1} + h_r), c = h_{r-1}
+        const double Q = (2.0 * (hp + hr)) * q - hr * p;
+        num[r] = q;
+        den[r] = Q;
+        int e;
+        const double m = frexp(Q, &e);
+        p = ldexp(hp * q, -e);
+        q = m;
         hp = hr;
+    };
+    int r0 = 1;
+    for (; r0 + C <= K - 1; r0 += C) {
+        double hv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) hv[c] = h[r0 + c];
+#pragma unroll
+        for (int c = 0; c < C; ++c) row(r0 + c, hv[c]);
     }
-    const double den = h[K - 3] - (h[K - 2] + h[K - 3]) * w;
-    invd[K - 1] = 1.0 / den;
-    wv[K - 1] = 0.0;
+    for (; r0 <= K - 2; ++r0) row(r0, h[r0]);
+    // row K-1: sub h_{K-2} + h_{K-3}, diag h_{K-3}
+    num[K - 1] = q;
+    den[K - 1] = h[K - 3] * q - (h[K - 2] + h[K - 3]) * p;
+}
+
+__device__ __forceinline__ void fit_factor_finish(const double *h, int K, double *invd,
+                                                  double *wv) {
+    for (int r = threadIdx.x; r < K; r += blockDim.x) {
+        const double id = invd[r] / wv[r];
+        const double c = r == 0 ? h[0] + h[1] : (r < K - 1 ? h[r - 1] : 0.0);
+        invd[r] = id;
+        wv[r] = c * id;
+    }
 }
 
 // Phase series ph (workgroup ph), to double-double accuracy by one step of
@@ -224,9 +254,11 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     __syncthreads();
     // binary64 factor of the rounded matrix (one lane of wave 0) while the
     // other waves form the right-hand side, then the first solve
-    if (tid == 0) fit_factor(Hh, K, invd, wv);
+    if (tid == 0) fit_factor_serial(Hh, K, invd, wv);
     if (tid >= kWave)
         for (int r = tid - kWave; r < K; r += bs - kWave) s0[r] = rhs(r).hi;
+    __syncthreads();
+    fit_factor_finish(Hh, K, invd, wv);
     __syncthreads();
     if (tid == 0) solve(s0);
     __syncthreads();
@@ -275,7 +307,9 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
         ih[i] = 1.0 / h;
     }
     __syncthreads();
-    if (tid == 0) fit_factor(hs, K, invd, wv);
+    if (tid == 0) fit_factor_serial(hs, K, invd, wv);
+    __syncthreads();
+    fit_factor_finish(hs, K, invd, wv);
     __syncthreads();
     if (tid >= kFitSeriesPerBlock) return;
     const int q = blk * kFitSeriesPerBlock + tid;
