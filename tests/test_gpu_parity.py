@@ -256,3 +256,29 @@ def test_error_codes(native_mod, torch_dev):
         torch.cuda.synchronize()
         ref = oracle.mode_sum_waveform(w)
         assert oracle.max_rel_error(out.cpu().numpy(), ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("mode", ["sum", True])
+def test_timing_flags(native_mod, torch_dev, mode):
+    """FEW_FLAG_TIMING_SUM records events around summation launches only;
+    FEW_FLAG_TIMING around every stage.  Timing leaves results unchanged."""
+    import torch
+    w = synth.config0()
+    log(f"[timing] mode={mode}")
+    pp, pr, amp = to_dev(w, torch_dev)
+    with native_mod.Plan(0, "mixed", timing=mode) as plan:
+        for _ in range(3):
+            sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+            out = plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples, t_start=w.t_start,
+                                scale=w.scale)
+            sp.free()
+        torch.cuda.synchronize()
+        t = plan.timing(reset=True)
+        again = plan.timing(reset=True)
+    assert t["sum_launches"] == 3 and t["sum_ms"] > 0
+    every = mode is True
+    assert t["spline_launches"] == (3 if every else 0)
+    assert t["prepare_launches"] == (3 if every else 0)
+    assert again["sum_launches"] == 0
+    ref = run_gpu(native_mod, w, "mixed", torch_dev)
+    assert np.array_equal(out.cpu().numpy().astype(np.complex128), ref)
