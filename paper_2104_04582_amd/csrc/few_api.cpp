@@ -279,6 +279,8 @@ class LayoutCache {
         b->n_terms = a.n_terms;
         b->n_src = a.n_src;
         b->n_chunks = a.n_chunks;
+        for (int q = 0; q < kTermGroups - 1; ++q) b->grp[q] = a.grp[q];
+        b->max_seg_terms = a.max_seg_terms;
         b->segs = (int *)std::malloc(sizeof(int) * 4 * (size_t)a.n_segs);
         b->term_ptr = (int *)std::malloc(sizeof(int) * (size_t)(a.n_terms + 1));
         b->term_src = (int *)std::malloc(sizeof(int) * 2 * (size_t)std::max(a.n_src, 1));
@@ -355,6 +357,7 @@ FitJob fit_job(const HostReq &r, ReqBase base, const double *pp, const double *p
 struct Tiling {
     int parts;
     long long short_len;
+    bool split = false;     // short tiles are term-split tiles (binary32)
 };
 
 // Single-request launch: one part per XCD; binary32 parts end in short tiles
@@ -389,7 +392,7 @@ PrepJob prep_job(const HostReq &r, ReqBase base, double theta, double phi, doubl
     j.n_terms = r.terms.n_terms;
     j.n_src = r.terms.n_src;
     j.tile = tile_samples(fp32);
-    j.short_tile = short_tile_samples(fp32);
+    j.short_tile = tl.split ? split_tile_samples() : short_tile_samples(fp32);
     j.short_len = tl.short_len;
     j.parts = tl.parts;
     // about one (interval, term) pair per lane of a 256-lane fold workgroup
@@ -420,6 +423,8 @@ SumJob sum_job(const HostReq &r, ReqBase base, double t_start, double dt, int64_
     j.short_len = tl.short_len;
     j.parts = tl.parts;
     j.wave_base = 0;
+    for (int q = 0; q < kTermGroups - 1; ++q) j.grp[q] = r.terms.grp[q];
+    j.split = tl.split ? 1 : 0;
     return j;
 }
 
@@ -793,8 +798,8 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
         std::lock_guard<std::mutex> g(p->sync_mu);
         HIP_TRY(hipSetDevice(p->device));
         char *base = p->arena.ptr(s->arena_off);
-        const Tiling tl =
-            single_tiling(p->fp32, s->h.n_ph == 3 ? p->resident_wg3 : p->resident_wg);
+        Tiling tl = single_tiling(p->fp32, s->h.n_ph == 3 ? p->resident_wg3 : p->resident_wg);
+        tl.split = p->fp32 && tl.short_len > 0 && s->h.terms.max_seg_terms <= kSplitTerms;
         PrepJob pj = prep_job(s->h, one_block(s->h, base), theta, phi, scale, t_start, dt, n,
                               p->fp32, tl);
         pj.scale_im = scale_im;

@@ -57,6 +57,20 @@ inline int short_tile_samples(bool fp32) {
     return fp32 ? 4 * kWave * kSamplesPerLaneShort : kWave * kSamplesPerLaneF64;
 }
 
+// Binary32 sums run over four term groups (consecutive segments with about a
+// quarter of the terms each): every sample's compensated sum restarts, and its
+// harmonic seed is recomputed, at each group's first segment, and the four
+// group values are added in group order.  A term-split tile uses that: its four
+// waves take the same 64 x kSamplesPerLaneF32 samples, one group each, staging
+// their group kSplitTerms terms at a time in their own quarter of the LDS
+// buffer.  Requests whose segments all fit a quarter cut their short tiles this
+// way (the end of a launch then drains in pieces a quarter as long); others
+// keep the 2-sample short tiles.  Either way a sample gets the same rounded
+// operations.
+constexpr int kTermGroups = 4;
+constexpr int kSplitTerms = FEW_CHUNK_TERMS / kTermGroups;
+inline int split_tile_samples() { return kWave * kSamplesPerLaneF32; }
+
 // ---------------------------------------------------------------------------
 // Device-side job descriptors.  Pointers are device addresses in the plan
 // arena (or caller memory for inputs/outputs).
@@ -119,6 +133,8 @@ struct SumJob {
     int K, n_terms, n_segs, n_chunks;
     int n_ph;               // phases in pcoef (3: generic Kerr, Phi_theta last)
     int wave_base;          // first global tile slot of this job (batched launch)
+    int grp[kTermGroups - 1];   // first segment of term groups 1..3 (binary32)
+    int split;              // short tiles are term-split tiles
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
@@ -156,6 +172,8 @@ struct TermLayout {
     int *term_ptr = nullptr;   // n_terms + 1
     int *term_src = nullptr;   // 2 * n_src
     int *chunks = nullptr;     // n_chunks + 1: first segment of each chunk of <= kChunkTerms terms
+    int grp[kTermGroups - 1] = {0, 0, 0};   // first segment of term groups 1..3
+    int max_seg_terms = 0;     // longest segment
 };
 
 // Build the folded term layout; returns 0 or a few_status error code.

@@ -156,6 +156,20 @@ int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermL
         run += len;
     }
     chunks.push_back(n_seg);
+    // term groups: group q starts at the segment boundary nearest to q / 4 of
+    // the terms (boundaries non-decreasing; a group may be empty)
+    {
+        int g = 0, start = 0;
+        for (int q = 1; q < kTermGroups; ++q) {
+            const double target = (double)term * q / kTermGroups;
+            while (g < n_seg && start + segs[4 * g + 2] <= target) start += segs[4 * g++ + 2];
+            if (g < n_seg && target - start > start + segs[4 * g + 2] - target)
+                start += segs[4 * g++ + 2];
+            out->grp[q - 1] = g;
+        }
+        out->max_seg_terms = 0;
+        for (int k = 0; k < n_seg; ++k) out->max_seg_terms = std::max(out->max_seg_terms, segs[4 * k + 2]);
+    }
     out->n_chunks = (int)chunks.size() - 1;
     out->n_segs = (int)segs.size() / 4;
     out->n_terms = term;

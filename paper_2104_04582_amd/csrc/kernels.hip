@@ -27,13 +27,12 @@ namespace few {
 
 #define FEW_AS4 __attribute__((address_space(4)))
 
-// Optional minimum waves per SIMD (register cap) for the binary32 and the
-// binary64 summation kernels.
-#ifdef FEW_SUM_WAVES
-#define FEW_SUM_ATTR __attribute__((amdgpu_waves_per_eu(FEW_SUM_WAVES)))
-#else
-#define FEW_SUM_ATTR
+// Minimum waves per SIMD (register cap) of the single-request binary32
+// summation kernel (4: at most 128 registers), and of the binary64 kernels.
+#ifndef FEW_SUM_WAVES
+#define FEW_SUM_WAVES 4
 #endif
+#define FEW_SUM_ATTR __attribute__((amdgpu_waves_per_eu(FEW_SUM_WAVES)))
 // Binary64: the five-FMA chains per component need more waves in flight than
 // the register count alone allows (4 per SIMD); 5 costs one spill outside the
 // term loop.
@@ -689,6 +688,7 @@ struct LaneState {
     double pf[SL], pr[SL], pt[ST];
     long long jj[SL];
     Real hr[SL], hq[SL], cr[SL], cq[SL], zr[SL], zi[SL];
+    Real gr[SL], gi[SL];    // binary32: sum of the closed term groups
     int pm, pk, pn;
 };
 
@@ -732,6 +732,7 @@ __device__ __forceinline__ void lane_setup(LaneState<Real, SL, NP> &L, const Sum
         }
         L.hr[s] = L.hq[s] = L.cr[s] = L.cq[s] = (Real)0;
         L.zr[s] = L.zi[s] = (Real)0;
+        L.gr[s] = L.gi[s] = (Real)0;
     }
     L.pm = INT_MIN / 2;
     L.pk = INT_MIN / 2;
@@ -891,6 +892,44 @@ __device__ __forceinline__ void seg_step(LaneState<Real, SL, NP> &L, const int4 
     }
 }
 
+// Value of the current (compensated) sum of sample s.
+template <typename Real, int SL, bool COMP, int NP>
+__device__ __forceinline__ void acc_value(const LaneState<Real, SL, NP> &L, int s, Real *re,
+                                          Real *im) {
+    *re = COMP ? L.hr[s] - L.cr[s] : L.hr[s];
+    *im = COMP ? L.hq[s] - L.cq[s] : L.hq[s];
+}
+
+// Close a term group (binary32): add its value to the group total, restart
+// the compensated sum, and make the next segment seed by sincos.
+template <typename Real, int SL, bool COMP, int NP>
+__device__ __forceinline__ void group_close(LaneState<Real, SL, NP> &L) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        Real vr, vi;
+        acc_value<Real, SL, COMP, NP>(L, s, &vr, &vi);
+        L.gr[s] = L.gr[s] + vr;
+        L.gi[s] = L.gi[s] + vi;
+        L.hr[s] = L.hq[s] = L.cr[s] = L.cq[s] = (Real)0;
+    }
+    L.pm = INT_MIN / 2;
+    L.pk = INT_MIN / 2;
+    L.pn = INT_MIN / 2;
+}
+
+// Final value of sample s: the group total (binary32, after the last group is
+// closed) or the running sum (binary64).
+template <typename Real, int SL, bool COMP, int NP>
+__device__ __forceinline__ void lane_value(const LaneState<Real, SL, NP> &L, int s, Real *re,
+                                           Real *im) {
+    if constexpr (sizeof(Real) == 4) {
+        *re = L.gr[s];
+        *im = L.gi[s];
+    } else {
+        acc_value<Real, SL, COMP, NP>(L, s, re, im);
+    }
+}
+
 template <typename Real, int SL, bool COMP, int NP>
 __device__ __forceinline__ void lane_store(const LaneState<Real, SL, NP> &L, const SumJob &jb,
                                            long long j1) {
@@ -898,13 +937,7 @@ __device__ __forceinline__ void lane_store(const LaneState<Real, SL, NP> &L, con
     for (int s = 0; s < SL; ++s) {
         if (L.jj[s] < j1) {
             Real *o = (Real *)jb.out + 2 * L.jj[s];
-            if (COMP) {
-                o[0] = L.hr[s] - L.cr[s];
-                o[1] = L.hq[s] - L.cq[s];
-            } else {
-                o[0] = L.hr[s];
-                o[1] = L.hq[s];
-            }
+            lane_value<Real, SL, COMP, NP>(L, s, &o[0], &o[1]);
         }
     }
 }
@@ -919,8 +952,8 @@ __device__ __forceinline__ double2 lane_inner(const LaneState<Real, SL, NP> &L,
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
         if (L.jj[s] < j1) {
-            const Real re = COMP ? L.hr[s] - L.cr[s] : L.hr[s];
-            const Real im = COMP ? L.hq[s] - L.cq[s] : L.hq[s];
+            Real re, im;
+            lane_value<Real, SL, COMP, NP>(L, s, &re, &im);
             const Real *d = (const Real *)jb.data + 2 * L.jj[s];
             const double hr = re, hi = im, dr = d[0], di = d[1];
             dh = dh + (dr * hr + di * hi);
@@ -1008,23 +1041,103 @@ __device__ __forceinline__ double2 sum_wg_run(const SumJob &jb, int iv, long lon
         __syncthreads();
         if (busy) {
             for (int g = g0; g < g1; ++g) {
+#pragma unroll
+                for (int q = 0; q < kTermGroups - 1; ++q)
+                    if (g == jb.grp[q]) group_close<Real, SL, COMP, NP>(L);
                 const int4 S = load_uniform(jb.segs + g);
                 seg_step<Real, SL, COMP, NP>(L, S, buf + (t1 - S.w - S.z) * 8);
             }
         }
     }
+    if (!busy) return make_double2(0.0, 0.0);
+    // close the last group, then any empty groups after it (each adds zero,
+    // as in a term-split tile)
+    group_close<Real, SL, COMP, NP>(L);
+#pragma unroll
+    for (int q = 0; q < kTermGroups - 1; ++q)
+        if (jb.grp[q] == jb.n_segs) group_close<Real, SL, COMP, NP>(L);
     if constexpr (INNER) {
-        if (busy) return lane_inner<Real, SL, COMP, NP>(L, jb, j1);
+        return lane_inner<Real, SL, COMP, NP>(L, jb, j1);
     } else {
-        if (busy) lane_store<Real, SL, COMP, NP>(L, jb, j1);
+        lane_store<Real, SL, COMP, NP>(L, jb, j1);
+        return make_double2(0.0, 0.0);
     }
-    return make_double2(0.0, 0.0);
+}
+
+// Term-split tile (binary32): 64 x SL samples [base, j1) of interval iv, taken
+// by all four waves; wave w sums term group w (segments [grp[w-1], grp[w])),
+// staging it kSplitTerms terms (whole segments) at a time in its own quarter
+// of the LDS buffer, so the waves need no barrier until they combine.  Each
+// wave leaves its group value in its quarter; wave 0 adds the four in group
+// order, starting from zero, exactly as a long tile closes its groups.  Needs
+// every segment to fit a quarter (checked on the host).
+template <typename Real, int SL, bool COMP, bool DD, int NP, bool INNER>
+__device__ __forceinline__ double2 sum_wg_split(const SumJob &jb, int iv, long long base,
+                                                long long j1, Real *buf) {
+    static_assert(sizeof(Real) == 4, "term-split tiles are binary32 tiles");
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    LaneState<Real, SL, NP> L;
+    lane_setup<Real, SL, DD, NP>(L, jb, iv, base, j1);
+    const int gb = wave == 0 ? 0 : jb.grp[wave - 1];
+    const int ge = wave == kTermGroups - 1 ? jb.n_segs : jb.grp[wave];
+    Real *wb = buf + (size_t)wave * kSplitTerms * 8;
+    const Real *tab = (const Real *)jb.table + (size_t)iv * jb.n_terms * 8;
+    for (int g = gb; g < ge;) {
+        // whole segments [g, h) with at most kSplitTerms terms
+        const int t0 = load_uniform(jb.segs + g).w;
+        int h = g, t1 = t0;
+        while (h < ge) {
+            const int4 S = load_uniform(jb.segs + h);
+            if (S.w + S.z - t0 > kSplitTerms) break;
+            t1 = S.w + S.z;
+            ++h;
+        }
+        // terms [t0, t1) are stored reversed: one contiguous run
+        const int nv = (t1 - t0) * 8 * (int)sizeof(Real) / 16;
+        const float4 *src = (const float4 *)(tab + (size_t)(jb.n_terms - t1) * 8);
+        float4 *dst = (float4 *)wb;
+        for (int v = lane; v < nv; v += kWave) dst[v] = src[v];
+        __builtin_amdgcn_wave_barrier();
+        for (; g < h; ++g) {
+            const int4 S = load_uniform(jb.segs + g);
+            seg_step<Real, SL, COMP, NP>(L, S, wb + (t1 - S.w - S.z) * 8);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // this wave's group value, next to its staging area
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        Real vr, vi;
+        acc_value<Real, SL, COMP, NP>(L, s, &vr, &vi);
+        wb[(s * kWave + lane) * 2] = vr;
+        wb[(s * kWave + lane) * 2 + 1] = vi;
+    }
+    __syncthreads();
+    if (wave != 0) return make_double2(0.0, 0.0);
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        Real gr = (Real)0, gi = (Real)0;
+#pragma unroll
+        for (int w = 0; w < kTermGroups; ++w) {
+            const Real *v = buf + (size_t)w * kSplitTerms * 8 + (s * kWave + lane) * 2;
+            gr = gr + v[0];
+            gi = gi + v[1];
+        }
+        L.gr[s] = gr;
+        L.gi[s] = gi;
+    }
+    if constexpr (INNER) {
+        return lane_inner<Real, SL, COMP, NP>(L, jb, j1);
+    } else {
+        lane_store<Real, SL, COMP, NP>(L, jb, j1);
+        return make_double2(0.0, 0.0);
+    }
 }
 
 // Tile `local` of part `pt` of a request: the part's samples in its interval,
 // [lo, hi), are covered by long tiles up to `split` and short tiles after it.
 // The branch is uniform per workgroup.
-template <typename Real, bool COMP, bool DD, int NP, bool INNER>
+template <typename Real, bool COMP, bool DD, int NP, bool INNER, bool SPLIT>
 __device__ __forceinline__ double2 sum_wg_tile(const SumJob &jb, int pt, int local, Real *buf) {
     const FEW_AS4 int *tp = cptr(jb.tile_pref) + (size_t)pt * jb.K;
     if (local >= tp[jb.K - 1]) return make_double2(0.0, 0.0);
@@ -1033,12 +1146,17 @@ __device__ __forceinline__ double2 sum_wg_tile(const SumJob &jb, int pt, int loc
     const PieceRange pr = piece_range(st[iv], st[iv + 1], jb.n, jb.parts, pt, jb.short_len);
     constexpr int LT = 4 * kWave * kSamplesPerLaneF32;
     constexpr int ST = 4 * kWave * kSamplesPerLaneShort;
+    constexpr int XT = kWave * kSamplesPerLaneF32;   // term-split tile
     const int n_long = (int)((pr.split - pr.lo + LT - 1) / LT);
     const int r = local - tp[iv];
     if (r < n_long) {
         const long long base = pr.lo + (long long)r * LT;
         return sum_wg_run<Real, kSamplesPerLaneF32, COMP, DD, NP, INNER>(
             jb, iv, base, min(base + LT, pr.split), buf);
+    } else if (SPLIT && jb.split) {
+        const long long base = pr.split + (long long)(r - n_long) * XT;
+        return sum_wg_split<Real, kSamplesPerLaneF32, COMP, DD, NP, INNER>(
+            jb, iv, base, min(base + XT, pr.hi), buf);
     } else {
         const long long base = pr.split + (long long)(r - n_long) * ST;
         return sum_wg_run<Real, kSamplesPerLaneShort, COMP, DD, NP, INNER>(
@@ -1133,7 +1251,7 @@ __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_kernel(SumJob jb, int
     extern __shared__ float4 sum_lds[];
     const int b = blockIdx.x;
     const int local = b / jb.parts;     // < slots: the grid is parts x slots
-    double2 v = sum_wg_tile<Real, COMP, DD, NP, INNER>(jb, b % jb.parts, local,
+    double2 v = sum_wg_tile<Real, COMP, DD, NP, INNER, true>(jb, b % jb.parts, local,
                                                        (Real *)sum_lds);
     if constexpr (INNER) {
         __shared__ double2 red[4];
@@ -1156,11 +1274,11 @@ template <typename Real, bool COMP, bool DD>
 __device__ __forceinline__ void sum_wg_slot(const SumJob *jobs, int n_jobs, int b, Real *buf) {
     const int jx = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, b));
     const SumJob jb = load_uniform(jobs + jx);
-    sum_wg_tile<Real, COMP, DD, 2, false>(jb, 0, b - jb.wave_base, buf);
+    sum_wg_tile<Real, COMP, DD, 2, false, false>(jb, 0, b - jb.wave_base, buf);
 }
 
 template <typename Real, bool COMP, bool DD>
-__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_batch_kernel(const SumJob *jobs, int n_jobs,
+__global__ __launch_bounds__(256) void sum_wg_batch_kernel(const SumJob *jobs, int n_jobs,
                                                            int slots) {
     extern __shared__ float4 sum_lds[];
     const int b = xcd_block_id();
@@ -1171,7 +1289,7 @@ __global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_batch_kernel(const Su
 // Persistent variant: workgroups pull tile slots from one atomic counter
 // (lane 0 draws, the slot is broadcast through LDS) until all are handed out.
 template <typename Real, bool COMP, bool DD>
-__global__ __launch_bounds__(256) FEW_SUM_ATTR void sum_wg_persistent_kernel(const SumJob *jobs,
+__global__ __launch_bounds__(256) void sum_wg_persistent_kernel(const SumJob *jobs,
                                                                 int n_jobs, int slots,
                                                                 unsigned *counter) {
     extern __shared__ float4 sum_lds[];
