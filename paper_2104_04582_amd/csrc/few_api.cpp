@@ -799,7 +799,8 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
         HIP_TRY(hipSetDevice(p->device));
         char *base = p->arena.ptr(s->arena_off);
         Tiling tl = single_tiling(p->fp32, s->h.n_ph == 3 ? p->resident_wg3 : p->resident_wg);
-        tl.split = p->fp32 && tl.short_len > 0 && s->h.terms.max_seg_terms <= kSplitTerms;
+        tl.split = p->fp32 && tl.short_len > 0 && s->h.terms.n_terms >= kGroupMinTerms &&
+                   s->h.terms.max_seg_terms <= kSplitTerms;
         PrepJob pj = prep_job(s->h, one_block(s->h, base), theta, phi, scale, t_start, dt, n,
                               p->fp32, tl);
         pj.scale_im = scale_im;

@@ -69,6 +69,10 @@ inline int short_tile_samples(bool fp32) {
 // operations.
 constexpr int kTermGroups = 4;
 constexpr int kSplitTerms = FEW_CHUNK_TERMS / kTermGroups;
+// Requests with fewer folded terms form one group (reseeding at group starts
+// costs a few sincos per sample and tile, which short sums do not repay) and
+// keep the 2-sample short tiles.
+constexpr int kGroupMinTerms = 1024;
 inline int split_tile_samples() { return kWave * kSamplesPerLaneF32; }
 
 // ---------------------------------------------------------------------------

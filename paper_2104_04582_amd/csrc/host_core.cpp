@@ -157,10 +157,15 @@ int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermL
     }
     chunks.push_back(n_seg);
     // term groups: group q starts at the segment boundary nearest to q / 4 of
-    // the terms (boundaries non-decreasing; a group may be empty)
+    // the terms (boundaries non-decreasing; a group may be empty); one group
+    // below kGroupMinTerms terms
     {
         int g = 0, start = 0;
         for (int q = 1; q < kTermGroups; ++q) {
+            if (term < kGroupMinTerms) {
+                out->grp[q - 1] = n_seg;
+                continue;
+            }
             const double target = (double)term * q / kTermGroups;
             while (g < n_seg && start + segs[4 * g + 2] <= target) start += segs[4 * g++ + 2];
             if (g < n_seg && target - start > start + segs[4 * g + 2] - target)

@@ -282,3 +282,17 @@ def test_timing_flags(native_mod, torch_dev, mode):
     assert again["sum_launches"] == 0
     ref = run_gpu(native_mod, w, "mixed", torch_dev)
     assert np.array_equal(out.cpu().numpy().astype(np.complex128), ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_term_split_tiles_full_output(native_mod, torch_dev, prec):
+    """The 3843-mode list (1281 folded terms: four term groups) on 20,000
+    samples spread over the whole year: every sample of a single-request
+    mixed launch falls in the term-split tiles at the end of its part.  Full
+    output against the oracle."""
+    w = synth.config1()
+    w.dt = w.T / 20_000
+    w.n_samples = 20_000
+    log(f"[split] {prec} M={w.M} N={w.n_samples} dt={w.dt:.1f}")
+    ref = oracle.mode_sum_waveform(w)
+    check(run_gpu(native_mod, w, prec, torch_dev), ref, prec)
