@@ -1084,6 +1084,32 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
     SumJob *sj = (SumJob *)(host + off_sum);
     const bool fp32 = p->fp32;
     const int tile = tile_samples(fp32);
+    if (n == 1) {
+        // A batch of one request runs the single-request launches (sample
+        // parts per XCD and short tiles at the end of each part), which drain
+        // a long request better than the persistent batch grid; a sample gets
+        // the same rounded operations either way.
+        ServedReq *r = b->reqs[0];
+        const ReqBase rb{dev + up_off[0], dev + dev_off[0]};
+        stage_upload(r->h, host + up_off[0]);
+        Tiling tl = single_tiling(fp32, r->h.n_ph == 3 ? p->resident_wg3 : p->resident_wg);
+        tl.split = fp32 && tl.short_len > 0 && r->h.terms.n_terms >= kGroupMinTerms &&
+                   r->h.terms.max_seg_terms <= kSplitTerms;
+        const FitJob f = fit_job(r->h, rb, r->r.phi_phi, r->r.phi_r, r->r.amp);
+        const PrepJob q = prep_job(r->h, rb, r->r.theta, r->r.phi, r->r.scale, r->r.t_start,
+                                   r->r.dt, r->r.n_samples, fp32, tl);
+        const SumJob u = sum_job(r->h, rb, r->r.t_start, r->r.dt, r->r.n_samples, r->r.out, tl);
+        const long long slots = part_tile_bound(r->r.n_samples, tl.parts, tl.short_len, r->h.K,
+                                                tile, q.short_tile);
+        if (slots * tl.parts > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
+        HIP_TRY(pinned_upload(dev, host, upload_end, s));
+        HIP_TRY(launch_fit(f, s));
+        HIP_TRY(launch_prepare(q, fp32, s));
+        HIP_TRY(launch_sum(u, (int)slots, fp32, s));
+        HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(b->done, s));
+        return FEW_OK;
+    }
     int max_amp_blocks = 0, max_K = 4, max_fold_blocks = 0;
     long long waves = 0;
     for (int i = 0; i < n; ++i) {

@@ -1,22 +1,31 @@
 // gfx950 kernels of libfew: the interpolated harmonic-mode summation of
 // arXiv:2104.04582, Sec. III C (spline stage, then summation stage) for the
-// Schwarzschild sum of Eq. (10) with the mirror modes of Eq. (9).
+// Schwarzschild sum of Eq. (10) with the mirror modes of Eq. (9), and the
+// generic-Kerr sum of Sec. VII (a third phase).
 //
+//  upload_kernel   copies a request's host tables (knots, term layout) from
+//                  pinned host memory, ordered on the compute queue.
 //  fit_kernel      not-a-knot cubic splines of every series on the shared knot
 //                  grid.  Amplitude series: binary64, one lane per real series,
 //                  the grid's tridiagonal factor computed once per workgroup
-//                  in LDS.  Phase series: double-double, one lane each.
+//                  in LDS.  Phase series: double-double (one refinement step).
 //  prepare_kernel  per-request constants: first sample of every knot interval
-//                  and the wave-tile prefix; -2Y_lm and the fold of the l-sum
-//                  into one complex cubic per signed (m, n) term.
-//  sum_kernel      one wave = one tile of consecutive samples inside one knot
-//                  interval.  Per sample: phases in binary64 (double-double on
-//                  the FP64 path) reduced mod 2 pi, one sincos each; then for
-//                  every segment of terms a Horner recurrence in
-//                  e^{-i Phi_r} over n, seeded by e^{-i(m Phi_phi + n_lo Phi_r)}
-//                  (chained by e^{-i Phi_phi} across consecutive m).  Term
-//                  coefficients are wave-uniform and are read through the
-//                  scalar cache straight into SGPR operands of the FMAs.
+//                  and the tile prefixes; -2Y_lm and the fold of the l-sum
+//                  into one complex cubic per signed (m, [k,] n) term.
+//  sum_wg_kernel   binary32: one workgroup of 4 waves = one tile of
+//                  consecutive samples inside one knot interval; the term
+//                  coefficients are staged in LDS and broadcast to VGPR
+//                  operands.  Per sample: phases in binary64 reduced mod 2 pi,
+//                  one sincos each; then for every segment of terms a Horner
+//                  recurrence in e^{-i Phi_r} over n, seeded by
+//                  e^{-i(m Phi_phi + n_lo Phi_r)} (chained across consecutive
+//                  m or k), Kahan-compensated within four term groups whose
+//                  values are added in order; the end of a launch uses
+//                  term-split tiles (the four waves take one group each).
+//  sum_kernel      binary64: one wave = one tile; phases in double-double;
+//                  coefficients read by scalar loads into SGPR operands.
+//  select_kernel   the mode selector of Sec. III D (per-knot sort and
+//                  cumulative power threshold).
 #include "dd.h"
 #include "few_internal.h"
 #include "swsh.h"
