@@ -36,8 +36,9 @@ namespace few {
 
 #define FEW_AS4 __attribute__((address_space(4)))
 
-// Minimum waves per SIMD (register cap) of the single-request binary32
-// summation kernel (4: at most 128 registers), and of the binary64 kernels.
+// Minimum waves per SIMD (a register cap) of the single-request binary32
+// summation kernel: 4, i.e. at most 128 registers, which keeps the three-phase
+// (generic-Kerr) instantiation at four workgroups per CU as well.
 #ifndef FEW_SUM_WAVES
 #define FEW_SUM_WAVES 4
 #endif
