@@ -284,6 +284,23 @@ def cpu_baseline(w, target_s: float = 12.0):
                       f"all {w.M} modes, x87 extended precision, {dt:.1f} s wall"}
 
 
+def cpu_small(threads: int):
+    """The oracle on the whole one-day, 132-mode case (8640 samples), on one
+    host core and on `threads` cores: a reported context figure beside the
+    bounded baseline above."""
+    import oracle
+    from paper_2104_04582_amd import synth
+    w = synth.config0()
+    res = {"workload": f"{w.M} modes x {w.n_samples} samples (1 day at dt = 10 s), whole "
+                       "waveform, x87 extended precision", "unit": "mode-samples/s"}
+    for key, n in (("one_core", 1), ("all_cores", threads)):
+        t0 = time.perf_counter()
+        oracle.mode_sum_waveform(w, n_threads=n)
+        res[key] = w.mode_samples / (time.perf_counter() - t0)
+    res["cores"] = threads
+    return res
+
+
 def served(native, precision: str, seconds: float, dev, budget: int):
     """Replay a Poisson trace (20 req/s, 10% full 4-yr requests) through
     few_submit/few_poll; latency = arrival -> completion seen by the host."""
@@ -436,10 +453,13 @@ def main() -> int:
             log(f"[bench] served {prec}: {json.dumps(serve[prec])}")
 
     cpu = None
+    cpu_1day = None
     if not args.no_cpu:
         log("[bench] cpu oracle baseline")
         cpu = cpu_baseline(w)
         log(f"[bench] cpu: {json.dumps(cpu)}")
+        cpu_1day = cpu_small(cpu["cores"])
+        log(f"[bench] cpu, one-day case: {json.dumps(cpu_1day)}")
 
     m = res["mixed"]
     ach = m["sum_tflops"]
@@ -478,6 +498,7 @@ def main() -> int:
         "batched": batch or None,
         "served": serve or None,
         "cpu_baseline": cpu,
+        "cpu_oracle_1day": cpu_1day,
     }
     print(json.dumps(line), flush=True)
     return 0
