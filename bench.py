@@ -84,7 +84,22 @@ def time_path(native, plan, w, dev, steps: int, warmup: int, settle_s: float = 0
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tm = plan.timing(reset=True)
-    return elapsed / steps, tm, out
+    return elapsed / steps, tm, out, step
+
+
+def step_spread(step, steps: int):
+    """Median and min of single steps: a separate pass of `steps` steps, each
+    between two events on the plan's stream (torch's current stream)."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return {"median_ms": float(np.median(ms)), "min_ms": float(ms.min()),
+            "max_ms": float(ms.max()), "steps": steps}
 
 
 def kerr_run(native, dev, steps: int = 5, warmup: int = 1):
@@ -228,11 +243,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sum_kernel_traffic.txt")
 
 
 def sources_digest() -> str:
-    """sha256 over the native sources (file names and contents, sorted)."""
+    """sha256 over the kernel sources: kernels.hip and the headers it includes
+    (file names and contents, sorted).  The host runtime (*.cpp) does not
+    change what a kernel reads or writes."""
     import hashlib
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".cpp", ".h")):
+        if name.endswith((".hip", ".h")):
             h.update(name.encode())
             h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()
@@ -257,10 +274,42 @@ def measured_traffic():
         return None
 
 
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def accuracy(got: np.ndarray, ref: np.ndarray) -> dict:
+    """Max relative error (max |got - ref| / max |ref|) and mismatch (unit
+    PSD, both polarisations) of a GPU output against the oracle."""
+    import oracle
+    g = got.astype(np.complex128)
+    return {"max_rel_error": float(oracle.max_rel_error(g, ref)),
+            "mismatch": float(oracle.mismatch(g, ref)), "samples": int(ref.size)}
+
+
+def spread_indices(native, w, n_random: int = 3000, seed: int = 1) -> np.ndarray:
+    """Both ends, both sides of every interior knot and n_random random
+    samples over the whole waveform."""
+    rng = np.random.default_rng(seed)
+    idx = set(rng.choice(w.n_samples, n_random, replace=False).tolist())
+    idx.update([0, 1, w.n_samples - 2, w.n_samples - 1])
+    for s in native.host_interval_starts(w.t_knots, w.t_start, w.dt, w.n_samples)[1:-1]:
+        idx.update([int(s) - 1, int(s), int(s) + 1])
+    return np.array(sorted(i for i in idx if 0 <= i < w.n_samples), dtype=np.int64)
+
+
 def cpu_baseline(w, target_s: float = 12.0):
     """The oracle as it stands on the host cores, on a contiguous sample slice
     sized (from two short probes, which separate the fixed spline setup from
-    the per-sample cost) to take about target_s seconds."""
+    the per-sample cost) to take about target_s seconds.  Also returns the
+    oracle's output on that slice (the bench compares the GPU outputs with
+    it)."""
     import oracle
     threads = host_threads()
 
@@ -276,12 +325,49 @@ def cpu_baseline(w, target_s: float = 12.0):
     n_s = int(min(w.n_samples, max(b, (target_s - setup) / per)))
     idx = np.arange(n_s, dtype=np.int64)
     t0 = time.perf_counter()
-    oracle.mode_sum_waveform(w, idx=idx, n_threads=threads)
+    ref = oracle.mode_sum_waveform(w, idx=idx, n_threads=threads)
     dt = time.perf_counter() - t0
     return {"value": w.M * n_s / dt, "unit": "mode-samples/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": host_cpu_model(),
             "sample": f"first {n_s} of {w.n_samples} samples of the 3843-mode 1-yr case, "
-                      f"all {w.M} modes, x87 extended precision, {dt:.1f} s wall"}
+                      f"all {w.M} modes, x87 extended precision, {dt:.1f} s wall"}, ref
+
+
+def cpu_one_core_slice(w, frac: float = 0.01):
+    """The oracle on one host core over a contiguous slice of `frac` of the
+    one-year case's samples; the whole-waveform time is extrapolated from it
+    (the work is linear in the sample count)."""
+    import oracle
+    n_s = max(1, int(w.n_samples * frac))
+    t0 = time.perf_counter()
+    oracle.mode_sum_waveform(w, idx=np.arange(n_s, dtype=np.int64), n_threads=1)
+    dt = time.perf_counter() - t0
+    return {"value": w.M * n_s / dt, "unit": "mode-samples/s", "cores": 1,
+            "sample": f"first {n_s} samples ({frac:.0%}) of the 3843-mode 1-yr case",
+            "slice_s": dt, "whole_waveform_s_extrapolated": dt / frac,
+            "extrapolation": f"x{1 / frac:.0f} (work is linear in samples)"}
+
+
+def cpu_served_requests(threads: int, n_req: int = 8, max_samples: int = 20000):
+    """The oracle on the first n_req requests of the served trace (uneven and
+    full requests), first max_samples samples of each, on `threads` cores."""
+    import oracle
+    from paper_2104_04582_amd import synth
+    trace = synth.served_trace(rate=20.0, duration=60.0, p_full=0.1, seed=4)[:n_req]
+    work = 0
+    sec = 0.0
+    kinds = []
+    for a in trace:
+        w = synth.served_request(a)
+        n_s = min(w.n_samples, max_samples)
+        t0 = time.perf_counter()
+        oracle.mode_sum_waveform(w, idx=np.arange(n_s, dtype=np.int64), n_threads=threads)
+        sec += time.perf_counter() - t0
+        work += w.M * n_s
+        kinds.append(f"{a.kind}:{w.M}")
+    return {"value": work / sec, "unit": "mode-samples/s", "cores": threads,
+            "sample": f"first {n_req} served requests ({', '.join(kinds)} modes), first "
+                      f"{max_samples} samples of each", "seconds": sec}
 
 
 def cpu_small(threads: int):
@@ -301,7 +387,8 @@ def cpu_small(threads: int):
     return res
 
 
-def served(native, precision: str, seconds: float, dev, budget: int):
+def served(native, precision: str, seconds: float, dev, budget: int,
+           check_oracle: bool = True):
     """Replay a Poisson trace (20 req/s, 10% full 4-yr requests) through
     few_submit/few_poll; latency = arrival -> completion seen by the host."""
     import torch
@@ -319,6 +406,7 @@ def served(native, precision: str, seconds: float, dev, budget: int):
     lat = []
     kinds = []
     mode_samples = 0
+    first_full = None   # (waveform, output) of the first full request served
     with native.Plan(0, precision, hbm_budget_bytes=budget, max_inflight=4) as plan:
         pending = {}
         t_start = time.perf_counter()
@@ -339,6 +427,8 @@ def served(native, precision: str, seconds: float, dev, budget: int):
                 lat.append(t_done - a.t_arrival)
                 kinds.append(a.kind)
                 mode_samples += w.mode_samples
+                if a.kind == "full" and first_full is None:
+                    first_full = (w, out)
             if not done:
                 time.sleep(0.0002)
         wall = time.perf_counter() - t_start
@@ -348,7 +438,17 @@ def served(native, precision: str, seconds: float, dev, budget: int):
     def pct(x, q):
         return float(np.percentile(x, q)) if x.size else None
 
+    vs_oracle = None
+    if first_full is not None and check_oracle:
+        import oracle
+        w, out = first_full
+        idx = spread_indices(native, w)
+        ref = oracle.mode_sum_waveform(w, idx=idx, n_threads=host_threads())
+        got = out[torch.from_numpy(idx).to(dev)].cpu().numpy()
+        vs_oracle = dict(accuracy(got, ref), request=f"first full request ({w.M} modes, "
+                         f"{w.n_samples} samples, 4 yr), ends, knots and random samples")
     return {"precision": precision, "requests": int(lat.size), "trace_s": seconds,
+            "vs_oracle": vs_oracle,
             "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
             "p50_full_ms": pct(lat[kinds == "full"], 50),
             "p99_full_ms": pct(lat[kinds == "full"], 99),
@@ -362,7 +462,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--serve-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kerr", action="store_true", help="skip the generic-Kerr line")
     ap.add_argument("--batch", type=int, default=128, help="uneven instances in one launch")
@@ -400,11 +500,12 @@ def main() -> int:
         # Timed region: HIP events around the summation launches only (an event
         # pair delays the launch after it; the other stages stay back to back).
         with native.Plan(0, prec, timing="sum") as plan:
-            sec, tm, out = time_path(native, plan, w, dev, args.steps, args.warmup, 0.2)
+            sec, tm, out, step = time_path(native, plan, w, dev, args.steps, args.warmup, 0.2)
+            spread = step_spread(step, args.steps)
             outs[prec] = out
         # Stage breakdown: the same steps with events around every launch.
         with native.Plan(0, prec, timing=True) as plan:
-            _, tms, _ = time_path(native, plan, w, dev, 5, 2)
+            _, tms, _, _ = time_path(native, plan, w, dev, 5, 2)
         sum_ms = tm["sum_ms"] / max(tm["sum_launches"], 1)
         res[prec] = {
             "ms_per_step": sec * 1e3,
@@ -414,6 +515,7 @@ def main() -> int:
             "sum_ms": sum_ms,
             "sum_tflops": flops / (sum_ms * 1e-3) / 1e12,
             "canonical_tflops": canonical / (sum_ms * 1e-3) / 1e12,
+            "step_spread": spread,
         }
         log(f"[bench] {prec}: {json.dumps(res[prec])}")
     a = outs["fp64"]
@@ -422,6 +524,7 @@ def main() -> int:
     den = math.sqrt(torch.real(torch.vdot(a, a)).item() * torch.real(torch.vdot(b, b)).item())
     mm = 1.0 - num / den
     mx = (torch.max(torch.abs(a - b)) / torch.max(torch.abs(a))).item()
+    host_out = {p: outs[p].cpu().numpy() for p in outs}
     del outs, a, b
     torch.cuda.empty_cache()
 
@@ -453,13 +556,30 @@ def main() -> int:
             log(f"[bench] served {prec}: {json.dumps(serve[prec])}")
 
     cpu = None
-    cpu_1day = None
+    cpu_1day = cpu_1core = cpu_served = None
+    vs_oracle = None
     if not args.no_cpu:
+        import oracle
         log("[bench] cpu oracle baseline")
-        cpu = cpu_baseline(w)
+        cpu, ref_slice = cpu_baseline(w)
         log(f"[bench] cpu: {json.dumps(cpu)}")
+        # accuracy of both GPU outputs against the oracle: on the baseline's
+        # contiguous slice and on samples spread over the whole year
+        idx = spread_indices(native, w)
+        ref_spread = oracle.mode_sum_waveform(w, idx=idx, n_threads=cpu["cores"])
+        n_s = ref_slice.size
+        vs_oracle = {p: {"slice": accuracy(host_out[p][:n_s], ref_slice),
+                         "spread": accuracy(host_out[p][idx], ref_spread)}
+                     for p in host_out}
+        vs_oracle["samples"] = {"slice": f"first {n_s} samples",
+                                "spread": "both ends, both sides of every knot, 3000 random"}
+        log(f"[bench] vs oracle: {json.dumps(vs_oracle)}")
         cpu_1day = cpu_small(cpu["cores"])
         log(f"[bench] cpu, one-day case: {json.dumps(cpu_1day)}")
+        cpu_1core = cpu_one_core_slice(w)
+        log(f"[bench] cpu, one core, 1% slice: {json.dumps(cpu_1core)}")
+        cpu_served = cpu_served_requests(cpu["cores"])
+        log(f"[bench] cpu, served requests: {json.dumps(cpu_served)}")
 
     m = res["mixed"]
     ach = m["sum_tflops"]
@@ -471,6 +591,9 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": m["ms_per_step"],
+        "step_ms": {"mean": m["ms_per_step"], "median": m["step_spread"]["median_ms"],
+                    "min": m["step_spread"]["min_ms"],
+                    "note": "median and min from a second pass with an event between steps"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -487,10 +610,13 @@ def main() -> int:
                      "flop_per_launch": flops, "launch_ms": m["sum_ms"]},
         "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
                  "sum_ms": res["fp64"]["sum_ms"], "sum_tflops": res["fp64"]["sum_tflops"],
+                 "step_ms": {"median": res["fp64"]["step_spread"]["median_ms"],
+                             "min": res["fp64"]["step_spread"]["min_ms"]},
                  "frac_fp64_peak": res["fp64"]["sum_tflops"] / PEAK_FP64_VALU},
         "stages_ms": {p: {k: res[p][k] for k in ("spline_ms", "prepare_ms", "sum_ms")}
                       for p in res},
         "canonical_32flop_tflops": {p: res[p]["canonical_tflops"] for p in res},
+        "vs_oracle": vs_oracle,
         "mixed_vs_fp64": {"mismatch": mm, "max_rel_error": mx},
         "mode_select": sel,
         "fused_inner": inner,
@@ -499,6 +625,8 @@ def main() -> int:
         "served": serve or None,
         "cpu_baseline": cpu,
         "cpu_oracle_1day": cpu_1day,
+        "cpu_oracle_1core": cpu_1core,
+        "cpu_oracle_served": cpu_served,
     }
     print(json.dumps(line), flush=True)
     return 0

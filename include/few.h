@@ -168,7 +168,11 @@ int32_t few_spline_fit_kerr(few_plan plan, int32_t K, const double *t_knots,
                             const double *phi_r, int32_t M, const int32_t *lmkn,
                             const double *amp, few_spline *out);
 
-/* Release a spline's arena memory (stream-ordered: safe while work using it is queued). */
+/* Release a spline's arena memory.  Safe while work using the spline is still
+ * queued on the plan stream: the block returns to the arena only once the work
+ * enqueued there before this call has completed (an event recorded now), so
+ * neither synchronous calls nor served batches on the library's own streams
+ * receive it earlier. */
 int32_t few_spline_free(few_spline spline);
 
 /*
@@ -260,9 +264,17 @@ int32_t few_batch(few_plan plan, int32_t n, const few_request *reqs);
  * Served path: queue one request (spline fit + summation) for continuous
  * batching.  A host scheduler thread admits queued requests in arrival order
  * while their arena footprint fits the plan budget, packs the admitted ones
- * into one batched launch on one of max_inflight streams, and retires them
- * when that launch completes.  Each result is bitwise identical to the same
- * request run alone.  Returns FEW_E_TOO_LARGE if the request can never fit.
+ * into one batched launch on one of max_inflight library-owned streams, and
+ * retires them when that launch completes.  Each result is bitwise identical
+ * to the same request run alone.
+ * Ordering: few_submit records an event on the plan stream and the request's
+ * launch waits for it, so work the caller enqueued on the plan stream before
+ * the call (writing phi_phi, phi_r, amp; last reads of out) completes first.
+ * Work on other streams must be ordered before the call by the caller.
+ * Errors: FEW_E_TOO_LARGE at submit if the request can never fit the budget;
+ * few_poll returns FEW_E_NOMEM if, with none of the plan's served work in
+ * flight, the arena still cannot hold the request because synchronous-path
+ * splines or buffers occupy it.
  */
 int32_t few_submit(few_plan plan, const few_request *req, uint64_t *ticket);
 

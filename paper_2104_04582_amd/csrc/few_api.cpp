@@ -104,6 +104,15 @@ class Arena {
         }
         free_[off] = sz;
     }
+    // whether alloc(bytes) would succeed now
+    bool alloc_probe(size_t bytes) {
+        std::lock_guard<std::mutex> g(mu_);
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (bytes == 0) bytes = 256;
+        for (auto &kv : free_)
+            if (kv.second >= bytes) return true;
+        return false;
+    }
     char *ptr(size_t off) const { return base_ + off; }
     size_t size() const { return size_; }
 
@@ -439,6 +448,10 @@ struct ServedReq {
     HostReq h;
     int status = FEW_PENDING;
     size_t footprint = 0;
+    // recorded on the plan stream at submit: the batch stream waits for it, so
+    // work the caller enqueued there before few_submit (producing the inputs,
+    // last using the output buffer) is complete before the request runs
+    hipEvent_t ready = nullptr;
 };
 
 struct Batch {
@@ -492,15 +505,21 @@ struct few_plan_s {
     bool stop = false, worker_started = false;
     uint64_t next_ticket = 1;
     unsigned *counters = nullptr;   // one persistent-kernel counter per stream slot
-    // few_batch on the plan stream: its own counter, and arena blocks / pinned
-    // buffers released once the recorded event has completed
+    // few_batch on the plan stream: its own counter
     unsigned *sync_counter = nullptr;
+    // Arena blocks (and pinned buffers) released once the event recorded after
+    // the last work that uses them has completed: few_spline_free, few_batch
+    // blocks and grown inner-product buffers.  The served scheduler carves the
+    // same arena for batches on other streams, so a block is never handed out
+    // again while queued plan-stream work still reads it.
     struct Deferred {
         size_t arena_off;
         void *pinned;
         hipEvent_t ev;
     };
+    std::mutex def_mu;                  // deferred and sync_events
     std::vector<Deferred> deferred;
+    std::vector<hipEvent_t> sync_events;   // pool of timing-disabled events
 };
 
 struct few_spline_s {
@@ -578,8 +597,47 @@ void scheduler_main(few_plan p);
 int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter);
 size_t batch_bytes(const std::vector<ServedReq *> &reqs);
 
-// Release few_batch resources whose work has completed (all of them if wait).
-void reap_deferred(few_plan p, bool wait) {
+// A timing-disabled event from the plan's pool (or a new one).
+hipEvent_t sync_event(few_plan p) {
+    {
+        std::lock_guard<std::mutex> g(p->def_mu);
+        if (!p->sync_events.empty()) {
+            hipEvent_t e = p->sync_events.back();
+            p->sync_events.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+void put_sync_event(few_plan p, hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> g(p->def_mu);
+    p->sync_events.push_back(e);
+}
+
+// Release arena block `off` (and pinned buffer `pinned`, if any) once the work
+// enqueued so far on stream s has completed.  Without an event (creation or
+// record failed) the stream is drained and the block released at once.
+void defer_release(few_plan p, size_t off, void *pinned, hipStream_t s) {
+    hipEvent_t e = sync_event(p);
+    if (e && hipEventRecord(e, s) == hipSuccess) {
+        std::lock_guard<std::mutex> g(p->def_mu);
+        p->deferred.push_back({off, pinned, e});
+        return;
+    }
+    if (e) put_sync_event(p, e);
+    hipStreamSynchronize(s);
+    if (off != SIZE_MAX) p->arena.release(off);
+    if (pinned) p->pinned.put(pinned);
+}
+
+// Release deferred blocks whose work has completed (all of them if wait).
+// Returns the number still outstanding.
+size_t reap_deferred(few_plan p, bool wait) {
+    std::lock_guard<std::mutex> g(p->def_mu);
     for (size_t i = 0; i < p->deferred.size();) {
         auto &d = p->deferred[i];
         if (wait) hipEventSynchronize(d.ev);
@@ -587,11 +645,24 @@ void reap_deferred(few_plan p, bool wait) {
             ++i;
             continue;
         }
-        p->arena.release(d.arena_off);
-        p->pinned.put(d.pinned);
-        hipEventDestroy(d.ev);
+        if (d.arena_off != SIZE_MAX) p->arena.release(d.arena_off);
+        if (d.pinned) p->pinned.put(d.pinned);
+        p->sync_events.push_back(d.ev);
         p->deferred.erase(p->deferred.begin() + i);
     }
+    return p->deferred.size();
+}
+
+// Arena allocation for work on the plan stream: retries after releasing the
+// deferred blocks whose work has completed, then after waiting for all.
+size_t alloc_sync(few_plan p, size_t bytes) {
+    size_t off = p->arena.alloc(bytes);
+    if (off != SIZE_MAX) return off;
+    if (reap_deferred(p, false) == 0) return p->arena.alloc(bytes);
+    off = p->arena.alloc(bytes);
+    if (off != SIZE_MAX) return off;
+    reap_deferred(p, true);
+    return p->arena.alloc(bytes);
 }
 
 }  // namespace
@@ -636,6 +707,19 @@ int32_t few_plan_create(const few_plan_desc *desc, few_plan *out) {
         }
         p->arena_base = (char *)base;
         p->arena.init(p->arena_base, p->budget);
+        // persistent-kernel counters (one 256-byte block per served stream
+        // slot, then the few_batch one) at the bottom of the arena, so these
+        // long-lived blocks never split the space requests allocate from
+        {
+            const size_t off = p->arena.alloc(256 * (size_t)(p->max_inflight + 1));
+            if (off == SIZE_MAX) {
+                hipFree(base);
+                delete p;
+                return fail(FEW_E_TOO_LARGE, "plan budget below the counter blocks");
+            }
+            p->counters = (unsigned *)p->arena.ptr(off);
+            p->sync_counter = p->counters + 64 * p->max_inflight;
+        }
         for (int s = 0; s < 2; ++s) {
             if (hipEventCreateWithFlags(&p->stage_ev[s], hipEventDisableTiming) != hipSuccess) {
                 hipFree(base);
@@ -664,11 +748,18 @@ int32_t few_plan_destroy(few_plan p) {
             hipStreamSynchronize(s);
             hipStreamDestroy(s);
         }
-        for (auto &kv : p->tickets) delete kv.second;
+        for (auto &kv : p->tickets) {
+            if (kv.second->ready) hipEventDestroy(kv.second->ready);
+            delete kv.second;
+        }
         for (ServedReq *r : p->pending)
-            if (!p->tickets.count(r->ticket)) delete r;
+            if (!p->tickets.count(r->ticket)) {
+                if (r->ready) hipEventDestroy(r->ready);
+                delete r;
+            }
         hipStreamSynchronize(p->stream);
         reap_deferred(p, true);
+        for (hipEvent_t e : p->sync_events) hipEventDestroy(e);
         for (few_spline s : p->splines) delete s;
         for (auto &t : p->timed) {
             hipEventDestroy(t.second.first);
@@ -712,7 +803,7 @@ int spline_fit_impl(few_plan p, int32_t K, const double *t_knots, const double *
             return fail(FEW_E_TOO_LARGE, "spline needs %zu bytes, plan budget %llu",
                         s->h.L.total, (unsigned long long)p->budget);
         }
-        s->arena_off = p->arena.alloc(s->h.L.total);
+        s->arena_off = alloc_sync(p, s->h.L.total);
         if (s->arena_off == SIZE_MAX) {
             delete s;
             return fail(FEW_E_NOMEM, "plan arena exhausted");
@@ -725,7 +816,7 @@ int spline_fit_impl(few_plan p, int32_t K, const double *t_knots, const double *
             rc = timed_launch(p, ST_FIT, p->stream, [&] { return launch_fit(job, p->stream); });
         }
         if (rc) {
-            p->arena.release(s->arena_off);
+            defer_release(p, s->arena_off, nullptr, p->stream);
             delete s;
             return rc;
         }
@@ -755,8 +846,10 @@ int32_t few_spline_free(few_spline s) {
     few_plan p = s->plan;
     std::lock_guard<std::mutex> g(p->sync_mu);
     if (!p->splines.count(s)) return fail(FEW_E_STATE, "spline not owned by its plan");
-    // stream-ordered reuse: later work on the plan stream runs after queued work
-    p->arena.release(s->arena_off);
+    // the block returns to the arena once the work queued on the plan stream so
+    // far (which may still read it) has completed
+    HIP_TRY(hipSetDevice(p->device));
+    defer_release(p, s->arena_off, nullptr, p->stream);
     p->splines.erase(s);
     delete s;
     return FEW_OK;
@@ -819,12 +912,9 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
         const long long need = inner_slots(tl.parts, (int)slots, p->fp32);
         if (need > p->inner_cap) {
             const long long cap = need + need / 4;
-            const size_t off = p->arena.alloc(sizeof(double2) * (size_t)cap);
+            const size_t off = alloc_sync(p, sizeof(double2) * (size_t)cap);
             if (off == SIZE_MAX) return fail(FEW_E_NOMEM, "plan arena exhausted (partials)");
-            if (p->inner_off != SIZE_MAX) {
-                HIP_TRY(hipStreamSynchronize(p->stream));   // old buffer no longer in use
-                p->arena.release(p->inner_off);
-            }
+            if (p->inner_off != SIZE_MAX) defer_release(p, p->inner_off, nullptr, p->stream);
             p->inner_off = off;
             p->inner_partial = (double2 *)p->arena.ptr(off);
             p->inner_cap = cap;
@@ -925,20 +1015,35 @@ int32_t few_submit(few_plan p, const few_request *req, uint64_t *ticket) {
             return fail(FEW_E_TOO_LARGE, "request needs %zu bytes, plan budget %llu", need,
                         (unsigned long long)p->budget);
         }
-        std::unique_lock<std::mutex> g(p->mu);
-        if (p->stop) {
+        auto reject = [&](int code, const char *what, hipError_t e) {
+            if (r->ready) put_sync_event(p, r->ready);
             delete r;
-            return fail(FEW_E_STATE, "plan is being destroyed");
-        }
+            return fail(code, "%s%s%s", what, e != hipSuccess ? ": " : "",
+                        e != hipSuccess ? hipGetErrorString(e) : "");
+        };
+        hipError_t he = hipSetDevice(p->device);
+        if (he != hipSuccess) return reject(FEW_E_HIP, "hipSetDevice", he);
+        // the request's batch waits for what the caller has enqueued on the plan
+        // stream so far (its inputs may still be in production there)
+        r->ready = sync_event(p);
+        if (!r->ready) return reject(FEW_E_HIP, "event creation failed", hipSuccess);
+        he = hipEventRecord(r->ready, p->stream);
+        if (he != hipSuccess) return reject(FEW_E_HIP, "hipEventRecord", he);
+        std::unique_lock<std::mutex> g(p->mu);
+        if (p->stop) return reject(FEW_E_STATE, "plan is being destroyed", hipSuccess);
         if (!p->worker_started) {
-            HIP_TRY(hipSetDevice(p->device));
-            p->bstreams.resize(p->max_inflight);
-            p->slot_busy.assign(p->max_inflight, false);
-            for (int s = 0; s < p->max_inflight; ++s)
-                HIP_TRY(hipStreamCreateWithFlags(&p->bstreams[s], hipStreamNonBlocking));
-            size_t off = p->arena.alloc(256 * (size_t)p->max_inflight);
-            if (off == SIZE_MAX) return fail(FEW_E_NOMEM, "arena exhausted (counters)");
-            p->counters = (unsigned *)p->arena.ptr(off);
+            if (p->bstreams.empty()) {
+                p->bstreams.assign(p->max_inflight, nullptr);
+                for (int s = 0; s < p->max_inflight; ++s) {
+                    he = hipStreamCreateWithFlags(&p->bstreams[s], hipStreamNonBlocking);
+                    if (he != hipSuccess) {
+                        for (int q = 0; q < s; ++q) hipStreamDestroy(p->bstreams[q]);
+                        p->bstreams.clear();
+                        return reject(FEW_E_HIP, "hipStreamCreateWithFlags", he);
+                    }
+                }
+                p->slot_busy.assign(p->max_inflight, false);
+            }
             p->worker = std::thread(scheduler_main, p);
             p->worker_started = true;
         }
@@ -963,6 +1068,9 @@ int32_t few_poll(few_plan p, uint64_t ticket) {
     if (st == FEW_PENDING) return FEW_PENDING;
     delete it->second;
     p->tickets.erase(it);
+    if (st == FEW_E_NOMEM)
+        return fail(st, "request not admitted: with nothing in flight the plan arena cannot "
+                        "hold it (memory is held by synchronous-path splines or buffers)");
     if (st != FEW_OK) return fail(st, "request failed on the device path");
     return FEW_OK;
 }
@@ -1019,21 +1127,12 @@ int32_t few_batch(few_plan p, int32_t n, const few_request *reqs) {
         std::lock_guard<std::mutex> g(p->sync_mu);
         HIP_TRY(hipSetDevice(p->device));
         reap_deferred(p, false);
-        if (!p->sync_counter) {
-            size_t off = p->arena.alloc(256);
-            if (off == SIZE_MAX) return fail(FEW_E_NOMEM, "arena exhausted (counter)");
-            p->sync_counter = (unsigned *)p->arena.ptr(off);
-        }
         const size_t bytes = batch_bytes(list);
         if (bytes > p->budget) return fail(FEW_E_TOO_LARGE, "batch needs %zu bytes", bytes);
         Batch b;
         b.slot = -1;
         b.reqs = list;
-        b.arena_off = p->arena.alloc(bytes);
-        if (b.arena_off == SIZE_MAX) {
-            reap_deferred(p, true);
-            b.arena_off = p->arena.alloc(bytes);
-        }
+        b.arena_off = alloc_sync(p, bytes);
         if (b.arena_off == SIZE_MAX) return fail(FEW_E_NOMEM, "plan arena exhausted");
         int rc = launch_batch(p, &b, p->stream, p->sync_counter);
         if (rc != FEW_OK) {
@@ -1043,7 +1142,10 @@ int32_t few_batch(few_plan p, int32_t n, const few_request *reqs) {
             if (b.pinned) p->pinned.put(b.pinned);
             return rc;
         }
-        p->deferred.push_back({b.arena_off, b.pinned, b.done});
+        {
+            std::lock_guard<std::mutex> dg(p->def_mu);
+            p->deferred.push_back({b.arena_off, b.pinned, b.done});
+        }
         return FEW_OK;
     } catch (...) {
         return fail(FEW_E_NOMEM, "exception in few_batch");
@@ -1057,6 +1159,9 @@ namespace {
 // Build and launch one batch on stream slot `slot`.  Called without p->mu held.
 int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
     const int n = (int)b->reqs.size();
+    // served requests: order after the caller's work on the plan stream
+    for (ServedReq *r : b->reqs)
+        if (r->ready) HIP_TRY(hipStreamWaitEvent(s, r->ready, 0));
     // arena block: [FitJob[n] | PrepJob[n] | SumJob[n] | upload region of every
     // request | device-produced region of every request]; one copy stages the
     // job arrays and all upload regions
@@ -1166,7 +1271,11 @@ void scheduler_main(few_plan p) {
                 continue;
             }
             int st = (q == hipSuccess) ? FEW_OK : FEW_E_HIP;
-            for (ServedReq *r : b->reqs) r->status = st;
+            for (ServedReq *r : b->reqs) {
+                r->status = st;
+                put_sync_event(p, r->ready);
+                r->ready = nullptr;
+            }
             p->arena.release(b->arena_off);
             p->pinned.put(b->pinned);
             hipEventDestroy(b->done);
@@ -1193,10 +1302,29 @@ void scheduler_main(few_plan p) {
                     break;
                 }
             }
+            // blocks freed by completed plan-stream work (freed splines,
+            // few_batch blocks) return to the arena first
+            reap_deferred(p, false);
             while (!take.empty()) {
                 off = p->arena.alloc(batch_bytes(take));
                 if (off != SIZE_MAX) break;
                 take.pop_back();
+            }
+            if (off == SIZE_MAX && p->inflight.empty()) {
+                // Nothing of this plan runs that could free memory: if no
+                // deferred release is outstanding either, the head request
+                // cannot be admitted until the caller frees memory held by
+                // the synchronous path, so fail it rather than wait forever.
+                if (reap_deferred(p, false) == 0 &&
+                    p->arena.alloc_probe(batch_bytes({p->pending.front()})) == false) {
+                    ServedReq *r = p->pending.front();
+                    p->pending.pop_front();
+                    r->status = FEW_E_NOMEM;
+                    put_sync_event(p, r->ready);
+                    r->ready = nullptr;
+                    p->cv_done.notify_all();
+                    continue;
+                }
             }
             if (off != SIZE_MAX && !take.empty()) {
                 for (size_t i = 0; i < take.size(); ++i) p->pending.pop_front();
@@ -1215,7 +1343,11 @@ void scheduler_main(few_plan p) {
                     } else {
                         hipStreamSynchronize(p->bstreams[slot]);
                     }
-                    for (ServedReq *r : b->reqs) r->status = rc;
+                    for (ServedReq *r : b->reqs) {
+                        r->status = rc;
+                        put_sync_event(p, r->ready);
+                        r->ready = nullptr;
+                    }
                     p->arena.release(b->arena_off);
                     if (b->pinned) p->pinned.put(b->pinned);
                     p->slot_busy[slot] = false;

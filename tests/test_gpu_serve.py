@@ -171,3 +171,108 @@ def test_poll_unknown_ticket(env):
         with pytest.raises(native.FewError) as e:
             plan.poll(12345)
         assert e.value.code == native.FEW_E_STATE
+
+
+def test_freed_spline_block_not_reused_while_queued_sums_read_it(env):
+    """few_spline_free with summations of that spline still queued on the plan
+    stream, then served requests that allocate from the same arena and run on
+    the library's own streams: the freed block is handed out again only after
+    the queued sums have run, so their output equals a solo run bit for bit."""
+    native, torch, dev = env
+    w = synth.config1()
+    w.n_samples = 1_000_000
+    ref = solo(native, torch, dev, w, "mixed")
+    small = instances(6, max_samples=300_000)
+    small_refs = [solo(native, torch, dev, s, "mixed") for s in small]
+    pp, pr, amp = dev_inputs(torch, w, dev)
+    ins = [dev_inputs(torch, s, dev) for s in small]
+    outs = [torch.empty(s.n_samples, dtype=torch.complex64, device=dev) for s in small]
+    sums = [torch.empty(w.n_samples, dtype=torch.complex64, device=dev) for _ in range(4)]
+    log("[serve] free with queued sums, then served requests")
+    with native.Plan(0, "mixed", max_inflight=2) as plan:
+        sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+        for o in sums:
+            plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples, out=o)
+        sp.free()
+        tickets = [submit(plan, s, ins[i], outs[i]) for i, s in enumerate(small)]
+        for tk in tickets:
+            plan.wait(tk)
+        torch.cuda.synchronize()
+    for o in sums:
+        assert np.array_equal(o.cpu().numpy(), ref)
+    for i in range(len(small)):
+        assert np.array_equal(outs[i].cpu().numpy(), small_refs[i]), i
+
+
+def test_served_inputs_produced_asynchronously_on_the_plan_stream(env):
+    """Inputs written by work still queued on the plan's stream when
+    few_submit is called (no host synchronisation): the served batch waits for
+    that work, so it reads the final inputs, not the NaNs written before."""
+    native, torch, dev = env
+    ws = instances(3, max_samples=300_000)
+    refs = [solo(native, torch, dev, w, "mixed") for w in ws]
+    src = [dev_inputs(torch, w, dev) for w in ws]
+    torch.cuda.synchronize()
+    with native.Plan(0, "mixed", max_inflight=2) as plan:
+        stream = torch.cuda.current_stream(dev)
+        assert plan.stream == stream.cuda_stream
+        ins = [tuple(torch.full_like(a, float("nan")) for a in s) for s in src]
+        outs = [torch.full((w.n_samples,), float("nan"), dtype=torch.complex64, device=dev)
+                for w in ws]
+        # tens of milliseconds of queued work before the inputs are written
+        x = torch.randn(4096, 4096, device=dev)
+        for _ in range(16):
+            x = torch.tanh(x @ x * 1e-3)
+        for s, d in zip(src, ins):
+            for a, b in zip(s, d):
+                b.copy_(a)
+        log("[serve] submitting with the input copies still queued")
+        tickets = [submit(plan, w, ins[i], outs[i]) for i, w in enumerate(ws)]
+        for tk in tickets:
+            plan.wait(tk)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(x).all())
+    for i in range(len(ws)):
+        assert np.array_equal(outs[i].cpu().numpy(), refs[i]), i
+
+
+def test_admission_fails_when_synchronous_memory_blocks_it(env):
+    """With nothing in flight and the arena held by a synchronous-path spline,
+    a served request that cannot fit fails with FEW_E_NOMEM instead of waiting
+    forever; after the spline is freed the same request is served."""
+    native, torch, dev = env
+    full = synth.config1()
+    full.n_samples = 200_000
+    ref = solo(native, torch, dev, full, "mixed")
+    need = native.host_request_bytes("mixed", full.K, full.M, 1281)
+    pp, pr, amp = dev_inputs(torch, full, dev)
+    out = torch.empty(full.n_samples, dtype=torch.complex64, device=dev)
+    log(f"[serve] arena blocked by a synchronous spline ({need / 1e6:.1f} MB each)")
+    with native.Plan(0, "mixed", hbm_budget_bytes=int(need * 1.5)) as plan:
+        sp = plan.spline_fit(full.t_knots, pp, pr, full.lmn, amp)
+        tk = submit(plan, full, (pp, pr, amp), out)
+        with pytest.raises(native.FewError) as e:
+            plan.wait(tk)
+        assert e.value.code == native.FEW_E_NOMEM
+        sp.free()
+        torch.cuda.synchronize()
+        plan.wait(submit(plan, full, (pp, pr, amp), out))
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
+def test_plan_destroy_with_queued_submissions(env):
+    """few_plan_destroy while requests are still queued drains them: every
+    output is complete and equal to its solo run."""
+    native, torch, dev = env
+    ws = instances(6, max_samples=400_000)
+    refs = [solo(native, torch, dev, w, "mixed") for w in ws]
+    ins = [dev_inputs(torch, w, dev) for w in ws]
+    outs = [torch.empty(w.n_samples, dtype=torch.complex64, device=dev) for w in ws]
+    log("[serve] destroy with queued submissions")
+    plan = native.Plan(0, "mixed", max_inflight=1)
+    for i, w in enumerate(ws):
+        submit(plan, w, ins[i], outs[i])
+    plan.close()
+    torch.cuda.synchronize()
+    for i in range(len(ws)):
+        assert np.array_equal(outs[i].cpu().numpy(), refs[i]), i
