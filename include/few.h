@@ -234,6 +234,28 @@ int32_t few_inner_product(few_plan plan, few_spline spline, double theta, double
                           const void *data, double *out2);
 
 /*
+ * Allocation-free variant of few_inner_product, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and kernels (the
+ * results equal few_inner_product's bit for bit), but the per-tile partial
+ * sums go to a static device array of 131072 entries (2 MiB, one per GPU,
+ * held until the process ends) instead of a buffer grown in the plan arena,
+ * and no events are recorded (timing flags are ignored).  The call makes no
+ * hipMalloc, hipFree or other allocating call; the array's device address is
+ * looked up once per device by few_plan_create.  Every tile slot the launch
+ * uses is written before it is read, so nothing needs clearing between calls.
+ *   Limit: the launch's tile slots must fit the array (about 16 million
+ *   samples in binary64, 130 million in binary32, at 100 knots); larger
+ *   calls return FEW_E_TOO_LARGE before anything is enqueued.
+ *   Concurrency: every call on one GPU shares that GPU's array, so calls that
+ *   overlap on the device (other plans, streams or threads) race; serialise
+ *   them, for example by issuing them on one stream.
+ */
+int32_t few_inner_product_noalloc(few_plan plan, few_spline spline, double theta, double phi,
+                                  double scale, double t_start, double dt, int64_t n_samples,
+                                  const void *data, double *out2);
+
+/*
  * Mode selector (Sec. III D): choose the modes that carry all but a fraction
  * eps of the power at some knot.  At every knot k the power of mode j is
  * |A_j(t_k)|^2 = re*re + im*im (binary64, no fused multiply-add); modes are

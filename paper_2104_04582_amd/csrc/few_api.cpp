@@ -472,6 +472,7 @@ struct few_plan_s {
     // inner-product partial sums (grown on demand; the plan stream is drained
     // before a smaller buffer is released)
     double2 *inner_partial = nullptr;
+    double2 *scratch = nullptr;   // device address of the static partial-sum array (no-alloc path)
     size_t inner_off = SIZE_MAX;
     long long inner_cap = 0;
     uint64_t budget = 0;
@@ -707,6 +708,15 @@ int32_t few_plan_create(const few_plan_desc *desc, few_plan *out) {
         }
         p->arena_base = (char *)base;
         p->arena.init(p->arena_base, p->budget);
+        // device address of this GPU's static partial-sum array, looked up now
+        // with the plan's device current
+        e = noalloc_scratch(p->device, &p->scratch);
+        if (e != hipSuccess) {
+            hipFree(base);
+            delete p;
+            return fail(FEW_E_HIP, "hipGetSymbolAddress(scratch) failed: %s",
+                        hipGetErrorString(e));
+        }
         // persistent-kernel counters (one 256-byte block per served stream
         // slot, then the few_batch one) at the bottom of the arena, so these
         // long-lived blocks never split the space requests allocate from
@@ -879,7 +889,7 @@ namespace {
 // Shared by few_mode_sum (out != null) and few_inner_product (data, out2).
 int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, double t_start,
              double dt, int64_t n, void *out, const void *data, double *out2,
-             double scale_im = 0.0) {
+             double scale_im = 0.0, bool noalloc = false) {
     if (!p) return fail(FEW_E_STATE, "null plan");
     if (!s || s->plan != p) return fail(FEW_E_STATE, "spline does not belong to this plan");
     const bool inner = data != nullptr;
@@ -897,20 +907,28 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
         PrepJob pj = prep_job(s->h, one_block(s->h, base), theta, phi, scale, t_start, dt, n,
                               p->fp32, tl);
         pj.scale_im = scale_im;
-        rc = timed_launch(p, ST_PREP, p->stream,
-                          [&] { return launch_prepare(pj, p->fp32, p->stream); });
-        if (rc) return rc;
         SumJob sj = sum_job(s->h, one_block(s->h, base), t_start, dt, n, out, tl);
-        // tiles per part; the grid holds parts x slots tiles
+        // tiles per part; the grid holds parts x slots tiles.  Every size check
+        // comes before the first launch.
         long long slots = part_tile_bound(n, tl.parts, tl.short_len, s->h.K,
                                           tile_samples(p->fp32), pj.short_tile);
         if (slots * tl.parts > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
-        if (!inner)
-            return timed_launch(p, ST_SUM, p->stream, [&] {
-                return launch_sum(sj, (int)slots, p->fp32, p->stream);
-            });
-        const long long need = inner_slots(tl.parts, (int)slots, p->fp32);
-        if (need > p->inner_cap) {
+        const long long need = inner ? inner_slots(tl.parts, (int)slots, p->fp32) : 0;
+        if (noalloc) {
+            // partials in the static per-GPU array: no arena growth, no events
+            if (need > kNoAllocSlots)
+                return fail(FEW_E_TOO_LARGE,
+                            "%lld partial-sum slots exceed the no-alloc limit of %lld "
+                            "(about 16 million samples in binary64, 130 million in binary32, "
+                            "at 100 knots)",
+                            need, (long long)kNoAllocSlots);
+            sj.data = data;
+            sj.partial = p->scratch;
+            HIP_TRY(launch_prepare(pj, p->fp32, p->stream));
+            HIP_TRY(launch_sum_inner(sj, (int)slots, p->fp32, 2.0 * dt, out2, p->stream));
+            return FEW_OK;
+        }
+        if (inner && need > p->inner_cap) {
             const long long cap = need + need / 4;
             const size_t off = alloc_sync(p, sizeof(double2) * (size_t)cap);
             if (off == SIZE_MAX) return fail(FEW_E_NOMEM, "plan arena exhausted (partials)");
@@ -919,6 +937,13 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
             p->inner_partial = (double2 *)p->arena.ptr(off);
             p->inner_cap = cap;
         }
+        rc = timed_launch(p, ST_PREP, p->stream,
+                          [&] { return launch_prepare(pj, p->fp32, p->stream); });
+        if (rc) return rc;
+        if (!inner)
+            return timed_launch(p, ST_SUM, p->stream, [&] {
+                return launch_sum(sj, (int)slots, p->fp32, p->stream);
+            });
         sj.data = data;
         sj.partial = p->inner_partial;
         return timed_launch(p, ST_SUM, p->stream, [&] {
@@ -951,6 +976,13 @@ int32_t few_inner_product(few_plan p, few_spline s, double theta, double phi, do
                           double *out2) {
     if (!data) return fail(FEW_E_ARG, "null data pointer");
     return sum_impl(p, s, theta, phi, scale, t_start, dt, n, nullptr, data, out2);
+}
+
+int32_t few_inner_product_noalloc(few_plan p, few_spline s, double theta, double phi,
+                                  double scale, double t_start, double dt, int64_t n,
+                                  const void *data, double *out2) {
+    if (!data) return fail(FEW_E_ARG, "null data pointer");
+    return sum_impl(p, s, theta, phi, scale, t_start, dt, n, nullptr, data, out2, 0.0, true);
 }
 
 int32_t few_plan_timing(few_plan p, few_timing *out, int32_t reset) {

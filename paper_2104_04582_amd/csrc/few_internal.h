@@ -159,6 +159,13 @@ hipError_t launch_sum(const SumJob &job, int slots, bool fp32, hipStream_t strea
 hipError_t launch_sum_inner(const SumJob &job, int slots, bool fp32, double two_dt,
                             double *out2, hipStream_t stream);
 long long inner_slots(int parts, int slots, bool fp32);
+// Allocation-free inner product: partial sums go to a static device array of
+// kNoAllocSlots entries (2 MiB, one copy per GPU).  noalloc_scratch() returns
+// its device address on `device`, which must be the current device; it looks
+// the address up (hipGetSymbolAddress) on the first call per device.
+constexpr long long kNoAllocSlots = 131072;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, double2 **out);
 hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_slots,
                             bool fp32, bool persistent, unsigned *counter_dev,
                             hipStream_t stream);

@@ -31,6 +31,7 @@
 #include "swsh.h"
 
 #include <climits>
+#include <mutex>
 
 namespace few {
 
@@ -1625,6 +1626,32 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_partials_kernel(const d
         out2[0] = factor * red[0].x;
         out2[1] = factor * red[0].y;
     }
+}
+
+// Partial sums of the allocation-free inner product: a file-scope device
+// array, one copy per GPU, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in); it uses the device address hipGetSymbolAddress returns, looked up
+// once per device by noalloc_scratch().
+static __device__ __align__(256) double2 scratch[kNoAllocSlots];
+
+hipError_t noalloc_scratch(int device, double2 **out) {
+    static std::mutex mu;
+    static double2 *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // caller makes `device` current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (double2 *)p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 long long inner_slots(int parts, int slots, bool fp32) {

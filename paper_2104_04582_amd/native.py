@@ -38,7 +38,7 @@ EXPORTED = [
     "few_plan_timing", "few_last_error", "few_host_terms", "few_host_interval_starts",
     "few_spline_fit_kerr", "few_host_terms_kerr", "few_inner_product", "few_mode_sum_ssb",
     "few_host_frame",
-    "few_host_request_bytes",
+    "few_host_request_bytes", "few_inner_product_noalloc",
 ]
 
 
@@ -98,6 +98,7 @@ def load() -> ctypes.CDLL:
     lib.few_spline_coefs.argtypes = [vp, i32, vp]
     lib.few_mode_sum.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp]
     lib.few_inner_product.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp, vp]
+    lib.few_inner_product_noalloc.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, i64, vp, vp]
     lib.few_mode_sum_ssb.argtypes = [vp, vp, dbl, dbl, dbl, dbl, dbl, dbl, dbl, i64, vp]
     lib.few_host_frame.argtypes = [dbl, dbl, dbl, dbl, vp]
     lib.few_batch.argtypes = [vp, i32, P(Request)]
