@@ -81,10 +81,14 @@ typedef enum {
 
 enum {
     FEW_FLAG_TIMING = 1,      /* record HIP events around every kernel launch */
-    FEW_FLAG_TIMING_SUM = 2   /* record them around summation launches only: each event pair
+    FEW_FLAG_TIMING_SUM = 2,  /* record them around summation launches only: each event pair
                                  delays the launch after it by several microseconds, so this
                                  keeps the other stages back to back while the dominant
                                  kernel is timed */
+    FEW_FLAG_VECTOR_ONLY = 4  /* FEW_MIXED: never use the matrix-core summation (fp16 hi/lo
+                                 operands on the MFMA units, fp32 accumulation); every sum
+                                 runs on the vector units in binary32 with Kahan-compensated
+                                 accumulation */
 };
 
 typedef struct few_plan_s *few_plan;

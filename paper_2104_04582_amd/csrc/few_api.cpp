@@ -171,6 +171,7 @@ struct HostReq {
     TermLayout terms;
     ReqLayout L{};
     size_t upload_bytes = 0;   // [0, upload_bytes) of the layout comes from the host
+    bool mfma = false;         // binary32 sums of this request run on the matrix-core path
     ~HostReq() { free_term_layout(&terms); }
 };
 
@@ -222,6 +223,7 @@ void stage_upload(const HostReq &r, char *dst) {
     std::memcpy(dst + r.L.off_term_ptr, r.terms.term_ptr, sizeof(int) * (r.terms.n_terms + 1));
     std::memcpy(dst + r.L.off_term_src, r.terms.term_src, sizeof(int) * 2 * r.terms.n_src);
     std::memcpy(dst + r.L.off_chunks, r.terms.chunks, sizeof(int) * (r.terms.n_chunks + 1));
+    std::memcpy(dst + r.L.off_mrows, r.terms.mrows, sizeof(int) * 2 * (r.terms.n_mrows + 1));
 }
 
 // Recently used term layouts, keyed by the full mode list (an MCMC client
@@ -290,14 +292,20 @@ class LayoutCache {
         b->n_chunks = a.n_chunks;
         for (int q = 0; q < kTermGroups - 1; ++q) b->grp[q] = a.grp[q];
         b->max_seg_terms = a.max_seg_terms;
+        b->n_mrows = a.n_mrows;
+        b->n_min = a.n_min;
+        b->n_max = a.n_max;
+        b->mfma = a.mfma;
+        b->mrows = (int *)std::malloc(sizeof(int) * 2 * (size_t)(a.n_mrows + 1));
         b->segs = (int *)std::malloc(sizeof(int) * 4 * (size_t)a.n_segs);
         b->term_ptr = (int *)std::malloc(sizeof(int) * (size_t)(a.n_terms + 1));
         b->term_src = (int *)std::malloc(sizeof(int) * 2 * (size_t)std::max(a.n_src, 1));
         b->chunks = (int *)std::malloc(sizeof(int) * (size_t)(a.n_chunks + 1));
-        if (!b->segs || !b->term_ptr || !b->term_src || !b->chunks) {
+        if (!b->segs || !b->term_ptr || !b->term_src || !b->chunks || !b->mrows) {
             free_term_layout(b);
             return FEW_E_NOMEM;
         }
+        std::memcpy(b->mrows, a.mrows, sizeof(int) * 2 * (size_t)(a.n_mrows + 1));
         std::memcpy(b->chunks, a.chunks, sizeof(int) * (size_t)(a.n_chunks + 1));
         std::memcpy(b->segs, a.segs, sizeof(int) * 4 * (size_t)a.n_segs);
         std::memcpy(b->term_ptr, a.term_ptr, sizeof(int) * (size_t)(a.n_terms + 1));
@@ -309,7 +317,7 @@ class LayoutCache {
 };
 
 int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, HostReq *r,
-                  LayoutCache *cache, int width = 3) {
+                  LayoutCache *cache, int width = 3, bool allow_mfma = true) {
     r->K = K;
     r->M = M;
     r->width = width;
@@ -317,8 +325,9 @@ int make_host_req(int K, const double *t, int M, const int32_t *lmn, bool fp32, 
     r->t.assign(t, t + K);
     int rc = cache->get(M, lmn, width, &r->terms);
     if (rc) return fail(rc, "mode list rejected while building the term layout");
+    r->mfma = fp32 && allow_mfma && r->terms.mfma && width == 3;
     r->L = request_layout(fp32, K, M, r->terms.n_segs, r->terms.n_terms, r->terms.n_src,
-                          r->terms.n_chunks, r->n_ph);
+                          r->terms.n_chunks, r->n_ph, r->mfma, r->terms.n_mrows);
     r->upload_bytes = r->L.upload_end;
     return FEW_OK;
 }
@@ -407,6 +416,13 @@ PrepJob prep_job(const HostReq &r, ReqBase base, double theta, double phi, doubl
     // about one (interval, term) pair per lane of a 256-lane fold workgroup
     j.fold_terms = std::max(1, std::min(64, 256 / (r.K - 1)));
     j.fold_blocks = (r.terms.n_terms + j.fold_terms - 1) / j.fold_terms;
+    j.segs = at_up<const int4>(r, base, r.L.off_segs);
+    j.mrows = at_up<const int2>(r, base, r.L.off_mrows);
+    j.mtab = r.mfma ? at_dev<char>(r, base, r.L.off_mtab) : nullptr;
+    j.mscale = r.mfma ? at_dev<float>(r, base, r.L.off_mscale) : nullptr;
+    j.n_mrows = r.terms.n_mrows;
+    j.n_min = r.terms.n_min;
+    j.n_segs = r.terms.n_segs;
     return j;
 }
 
@@ -434,6 +450,12 @@ SumJob sum_job(const HostReq &r, ReqBase base, double t_start, double dt, int64_
     j.wave_base = 0;
     for (int q = 0; q < kTermGroups - 1; ++q) j.grp[q] = r.terms.grp[q];
     j.split = tl.split ? 1 : 0;
+    j.mtab = r.mfma ? at_dev<const char>(r, base, r.L.off_mtab) : nullptr;
+    j.mscale = r.mfma ? at_dev<const float>(r, base, r.L.off_mscale) : nullptr;
+    j.mrows = at_up<const int2>(r, base, r.L.off_mrows);
+    j.n_mrows = r.terms.n_mrows;
+    j.n_min = r.terms.n_min;
+    j.sample_base = 0;
     return j;
 }
 
@@ -469,6 +491,8 @@ struct few_plan_s {
     int max_knots = kMaxKnots, max_modes = 65536, max_inflight = 2;
     int resident_wg = 0;        // binary32 summation workgroups resident at once
     int resident_wg3 = 0;       // the same for the generic-Kerr kernel
+    int mf_wg = 0;              // matrix-core summation workgroups (one per compute unit)
+    bool allow_mfma = true;     // binary32 requests may take the matrix-core path
     // inner-product partial sums (grown on demand; the plan stream is drained
     // before a smaller buffer is released)
     double2 *inner_partial = nullptr;
@@ -694,6 +718,8 @@ int32_t few_plan_create(const few_plan_desc *desc, few_plan *out) {
         p->fp32 = desc->precision == FEW_MIXED;
         p->resident_wg = p->fp32 ? sum_resident_workgroups(2) : 0;
         p->resident_wg3 = p->fp32 ? sum_resident_workgroups(3) : 0;
+        p->mf_wg = p->fp32 ? mfma_workgroups() : 0;
+        p->allow_mfma = p->fp32 && p->mf_wg > 0 && !(desc->flags & FEW_FLAG_VECTOR_ONLY);
         p->max_knots = desc->max_knots ? desc->max_knots : kMaxKnots;
         p->max_modes = desc->max_modes ? desc->max_modes : 65536;
         p->max_inflight = desc->max_inflight ? desc->max_inflight : 2;
@@ -803,7 +829,8 @@ int spline_fit_impl(few_plan p, int32_t K, const double *t_knots, const double *
         HIP_TRY(hipSetDevice(p->device));
         few_spline s = new (std::nothrow) few_spline_s;
         if (!s) return fail(FEW_E_NOMEM, "host allocation failed");
-        rc = make_host_req(K, t_knots, M, modes, p->fp32, &s->h, &p->layouts, width);
+        rc = make_host_req(K, t_knots, M, modes, p->fp32, &s->h, &p->layouts, width,
+                           p->allow_mfma);
         if (rc) {
             delete s;
             return rc;
@@ -913,7 +940,22 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
         long long slots = part_tile_bound(n, tl.parts, tl.short_len, s->h.K,
                                           tile_samples(p->fp32), pj.short_tile);
         if (slots * tl.parts > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
-        const long long need = inner ? inner_slots(tl.parts, (int)slots, p->fp32) : 0;
+        const bool mf = s->h.mfma;
+        const long long need =
+            !inner ? 0 : mf ? (long long)p->mf_wg : inner_slots(tl.parts, (int)slots, p->fp32);
+        // matrix-core requests fold in binary64, then pack the fp16 operand table
+        auto prep = [&]() -> hipError_t {
+            hipError_t e = launch_prepare(pj, p->fp32 && !mf, p->stream);
+            if (e == hipSuccess && mf) e = launch_pack(pj, p->stream);
+            return e;
+        };
+        auto sum = [&]() -> hipError_t {
+            if (mf)
+                return inner ? launch_sum_mfma_inner(sj, p->mf_wg, 2.0 * dt, out2, p->stream)
+                             : launch_sum_mfma(sj, p->mf_wg, p->stream);
+            return inner ? launch_sum_inner(sj, (int)slots, p->fp32, 2.0 * dt, out2, p->stream)
+                         : launch_sum(sj, (int)slots, p->fp32, p->stream);
+        };
         if (noalloc) {
             // partials in the static per-GPU array: no arena growth, no events
             if (need > kNoAllocSlots)
@@ -924,8 +966,8 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
                             need, (long long)kNoAllocSlots);
             sj.data = data;
             sj.partial = p->scratch;
-            HIP_TRY(launch_prepare(pj, p->fp32, p->stream));
-            HIP_TRY(launch_sum_inner(sj, (int)slots, p->fp32, 2.0 * dt, out2, p->stream));
+            HIP_TRY(prep());
+            HIP_TRY(sum());
             return FEW_OK;
         }
         if (inner && need > p->inner_cap) {
@@ -937,18 +979,13 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
             p->inner_partial = (double2 *)p->arena.ptr(off);
             p->inner_cap = cap;
         }
-        rc = timed_launch(p, ST_PREP, p->stream,
-                          [&] { return launch_prepare(pj, p->fp32, p->stream); });
+        if (inner) {
+            sj.data = data;
+            sj.partial = p->inner_partial;
+        }
+        rc = timed_launch(p, ST_PREP, p->stream, prep);
         if (rc) return rc;
-        if (!inner)
-            return timed_launch(p, ST_SUM, p->stream, [&] {
-                return launch_sum(sj, (int)slots, p->fp32, p->stream);
-            });
-        sj.data = data;
-        sj.partial = p->inner_partial;
-        return timed_launch(p, ST_SUM, p->stream, [&] {
-            return launch_sum_inner(sj, (int)slots, p->fp32, 2.0 * dt, out2, p->stream);
-        });
+        return timed_launch(p, ST_SUM, p->stream, sum);
     } catch (...) {
         return fail(FEW_E_NOMEM, "exception in the summation call");
     }
@@ -1032,7 +1069,7 @@ int32_t few_submit(few_plan p, const few_request *req, uint64_t *ticket) {
         if (!r) return fail(FEW_E_NOMEM, "host allocation failed");
         r->r = *req;
         rc = make_host_req(req->n_knots, req->t_knots, req->n_modes, req->lmn, p->fp32, &r->h,
-                           &p->layouts);
+                           &p->layouts, 3, p->allow_mfma);
         if (rc) {
             delete r;
             return rc;
@@ -1151,7 +1188,7 @@ int32_t few_batch(few_plan p, int32_t n, const few_request *reqs) {
             ServedReq *r = own.back().get();
             r->r = *q;
             rc = make_host_req(q->n_knots, q->t_knots, q->n_modes, q->lmn, p->fp32, &r->h,
-                               &p->layouts);
+                               &p->layouts, 3, p->allow_mfma);
             if (rc) return rc;
             r->r.t_knots = r->h.t.data();
             list.push_back(r);
@@ -1241,36 +1278,62 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         if (slots * tl.parts > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
         HIP_TRY(pinned_upload(dev, host, upload_end, s));
         HIP_TRY(launch_fit(f, s));
-        HIP_TRY(launch_prepare(q, fp32, s));
-        HIP_TRY(launch_sum(u, (int)slots, fp32, s));
+        if (r->h.mfma) {
+            HIP_TRY(launch_prepare(q, false, s));
+            HIP_TRY(launch_pack(q, s));
+            HIP_TRY(launch_sum_mfma(u, p->mf_wg, s));
+        } else {
+            HIP_TRY(launch_prepare(q, fp32, s));
+            HIP_TRY(launch_sum(u, (int)slots, fp32, s));
+        }
         HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
         HIP_TRY(hipEventRecord(b->done, s));
         return FEW_OK;
     }
-    int max_amp_blocks = 0, max_K = 4, max_fold_blocks = 0;
-    long long waves = 0;
+    // vector-path jobs first in the prepare and sum job arrays, then the
+    // matrix-core ones (each set has its own launches)
+    int nv = 0;
+    for (ServedReq *r : b->reqs) nv += r->h.mfma ? 0 : 1;
+    int max_amp_blocks = 0, max_K = 4, max_fold_blocks = 0, max_fold_mf = 0, max_K_mf = 4;
+    long long waves = 0, mf_total = 0;
+    int kv = 0, km = nv;
     for (int i = 0; i < n; ++i) {
         ServedReq *r = b->reqs[i];
         const ReqBase rb{dev + up_off[i], dev + dev_off[i]};
         stage_upload(r->h, host + up_off[i]);
         fj[i] = fit_job(r->h, rb, r->r.phi_phi, r->r.phi_r, r->r.amp);
-        pj[i] = prep_job(r->h, rb, r->r.theta, r->r.phi, r->r.scale, r->r.t_start, r->r.dt,
+        const int k = r->h.mfma ? km++ : kv++;
+        pj[k] = prep_job(r->h, rb, r->r.theta, r->r.phi, r->r.scale, r->r.t_start, r->r.dt,
                          r->r.n_samples, fp32, Tiling{1, 0});
-        sj[i] = sum_job(r->h, rb, r->r.t_start, r->r.dt, r->r.n_samples, r->r.out,
+        sj[k] = sum_job(r->h, rb, r->r.t_start, r->r.dt, r->r.n_samples, r->r.out,
                         Tiling{1, 0});
-        sj[i].wave_base = (int)waves;
-        waves += tile_upper_bound(r->r.n_samples, r->h.K, tile);
+        if (r->h.mfma) {
+            sj[k].sample_base = mf_total;
+            mf_total += r->r.n_samples;
+            max_fold_mf = std::max(max_fold_mf, pj[k].fold_blocks);
+            max_K_mf = std::max(max_K_mf, r->h.K);
+        } else {
+            sj[k].wave_base = (int)waves;
+            waves += tile_upper_bound(r->r.n_samples, r->h.K, tile);
+            max_fold_blocks = std::max(max_fold_blocks, pj[k].fold_blocks);
+        }
         max_amp_blocks = std::max(max_amp_blocks, fj[i].amp_blocks);
         max_K = std::max(max_K, r->h.K);
-        max_fold_blocks = std::max(max_fold_blocks, pj[i].fold_blocks);
     }
     if (waves > 0x3fffffff) return fail(FEW_E_ARG, "batch too large");
+    const PrepJob *pd = (const PrepJob *)(dev + off_prep);
+    const SumJob *sd = (const SumJob *)(dev + off_sum);
     HIP_TRY(pinned_upload(dev, host, upload_end, s));
     HIP_TRY(launch_fit_batch((const FitJob *)(dev + off_fit), n, max_amp_blocks, max_K, s));
-    HIP_TRY(launch_prepare_batch((const PrepJob *)(dev + off_prep), n, max_fold_blocks, fp32,
-                                 s));
-    HIP_TRY(launch_sum_batch((const SumJob *)(dev + off_sum), n, (int)waves, fp32, true,
-                             counter, s));
+    if (nv > 0) {
+        HIP_TRY(launch_prepare_batch(pd, nv, max_fold_blocks, fp32, s));
+        HIP_TRY(launch_sum_batch(sd, nv, (int)waves, fp32, true, counter, s));
+    }
+    if (nv < n) {
+        HIP_TRY(launch_prepare_batch(pd + nv, n - nv, max_fold_mf, false, s));
+        HIP_TRY(launch_pack_batch(pd + nv, n - nv, max_K_mf, s));
+        HIP_TRY(launch_sum_mfma_batch(sd + nv, n - nv, mf_total, p->mf_wg, s));
+    }
     HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(b->done, s));
     return FEW_OK;

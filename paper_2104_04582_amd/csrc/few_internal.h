@@ -75,6 +75,29 @@ constexpr int kSplitTerms = FEW_CHUNK_TERMS / kTermGroups;
 constexpr int kGroupMinTerms = 1024;
 inline int split_tile_samples() { return kWave * kSamplesPerLaneF32; }
 
+// Matrix-core summation (binary32 output).  Per knot interval the folded sum
+// is a contraction: with rows = the distinct signed m values (a complex row
+// each, as a real re/im pair) and columns (q, p), q = n - n_min,
+//   h = sum_m e^{-i(m Phi_phi + n_min Phi_r)} sum_{q,p} C^p_{m,q} u^p f^q,
+// f = e^{-i Phi_r}: the product of the coefficient matrix [rows x (q, p,
+// re/im)] with the matrix of u^p f^q over the samples, run on
+// v_mfma_f32_16x16x32_f16 with both operands split into fp16 hi + lo parts
+// (hi*hi + hi*lo + lo*hi, about 22 significant bits) and fp32 accumulation.
+// Fixed shape: kMfMT tiles of 16 matrix rows (8 signed m each), kMfT steps of
+// 32 columns (4 values of q; q < 4 kMfT), kMfNT tiles of 16 samples per wave,
+// kMfWaves waves per workgroup.  A request takes this path when its term
+// layout fits the shape and is long enough to repay it.
+constexpr int kMfMT = 3;
+constexpr int kMfT = 16;
+constexpr int kMfNT = 4;
+constexpr int kMfWaves = 8;
+constexpr int kMfRows = 8 * kMfMT;          // signed m values per request
+constexpr int kMfQ = 4 * kMfT;              // n_max - n_min + 1 <= kMfQ
+constexpr int kMfRound = kMfWaves * kMfNT * 16;   // samples per workgroup round
+// fp16 values of one interval: [mt][t][hi, lo][lane 64][8]
+constexpr size_t kMfIntervalHalves = (size_t)kMfMT * kMfT * 2 * 64 * 8;
+constexpr int kMfMinTerms = 480;            // below this the vector kernel is cheaper
+
 // ---------------------------------------------------------------------------
 // Device-side job descriptors.  Pointers are device addresses in the plan
 // arena (or caller memory for inputs/outputs).
@@ -116,6 +139,13 @@ struct PrepJob {
     int short_tile;         // samples per short tile
     int fold_terms;         // consecutive terms folded by one workgroup
     int fold_blocks;        // term groups of the fold
+    // matrix-core path: the fold writes binary64 into `table`, then the pack
+    // step writes the fp16 operand table and the per-(interval, row) scales
+    const int4 *segs;       // [n_segs]
+    const int2 *mrows;      // [n_mrows + 1]: (m, first segment) per row, sentinel (0, n_segs)
+    void *mtab;             // [K-1][kMfIntervalHalves] fp16
+    float *mscale;          // [K-1][kMfRows]: 2^E with row values scaled by 2^-E
+    int n_mrows, n_min, n_segs;
 };
 
 // Summation stage for one request.
@@ -139,6 +169,12 @@ struct SumJob {
     int wave_base;          // first global tile slot of this job (batched launch)
     int grp[kTermGroups - 1];   // first segment of term groups 1..3 (binary32)
     int split;              // short tiles are term-split tiles
+    // matrix-core path
+    const void *mtab;       // [K-1][kMfIntervalHalves] fp16 operand table
+    const float *mscale;    // [K-1][kMfRows]
+    const int2 *mrows;      // [n_mrows + 1]
+    int n_mrows, n_min;
+    long long sample_base;  // first sample of this job in a batched launch's range
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
@@ -170,6 +206,19 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_s
                             bool fp32, bool persistent, unsigned *counter_dev,
                             hipStream_t stream);
 hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t stream);
+// Matrix-core path: pack the binary64 fold into the fp16 operand table (one
+// request, or n_jobs of them with max_K knots at most), and the summation
+// (every workgroup takes an equal contiguous share of the samples; n_wg
+// workgroups; with INNER each writes its partial sums to job.partial[b] and
+// one more launch adds them into out2 = two_dt * sums).
+hipError_t launch_pack(const PrepJob &job, hipStream_t stream);
+hipError_t launch_pack_batch(const PrepJob *jobs_dev, int n_jobs, int max_K, hipStream_t stream);
+int mfma_workgroups();
+hipError_t launch_sum_mfma(const SumJob &job, int n_wg, hipStream_t stream);
+hipError_t launch_sum_mfma_inner(const SumJob &job, int n_wg, double two_dt, double *out2,
+                                 hipStream_t stream);
+hipError_t launch_sum_mfma_batch(const SumJob *jobs_dev, int n_jobs, long long total,
+                                 int n_wg, hipStream_t stream);
 hipError_t launch_select(const double *amp, int K, int M, double eps, int *keep,
                          hipStream_t stream);
 constexpr int kMaxSelectModes = 4096;   // LDS: (binary64 key + int index) per padded mode
@@ -185,6 +234,10 @@ struct TermLayout {
     int *chunks = nullptr;     // n_chunks + 1: first segment of each chunk of <= kChunkTerms terms
     int grp[kTermGroups - 1] = {0, 0, 0};   // first segment of term groups 1..3
     int max_seg_terms = 0;     // longest segment
+    // matrix-core path: distinct signed m values (rows) and the n range
+    int n_mrows = 0, n_min = 0, n_max = 0;
+    int *mrows = nullptr;      // 2 * (n_mrows + 1): (m, first segment), sentinel (0, n_segs)
+    bool mfma = false;         // layout fits the matrix-core shape (Schwarzschild terms)
 };
 
 // Build the folded term layout; returns 0 or a few_status error code.
@@ -227,12 +280,16 @@ inline long long part_tile_bound(long long n, int parts, long long short_len, in
 
 // Arena layout of one request's resident state.
 struct ReqLayout {
-    size_t off_t, off_segs, off_term_ptr, off_term_src, off_chunks, upload_end;   // host-staged
-    size_t off_pcoef, off_acoef, off_ybuf, off_table, off_starts, off_tile_pref, total;
+    size_t off_t, off_segs, off_term_ptr, off_term_src, off_chunks, off_mrows,
+        upload_end;   // host-staged
+    size_t off_pcoef, off_acoef, off_ybuf, off_table, off_starts, off_tile_pref, off_mtab,
+        off_mscale, total;
     size_t dev_begin;       // first device-produced offset (== off_pcoef)
 };
+// mfma: binary32 request on the matrix-core path (binary64 fold table, fp16
+// operand table and row scales; n_mrows rows)
 ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
-                         int n_chunks, int n_ph);
+                         int n_chunks, int n_ph, bool mfma = false, int n_mrows = 0);
 
 // Binary64 sample time exactly as written: t_start + j * dt, no contraction.
 double sample_time(double t_start, double dt, long long j);

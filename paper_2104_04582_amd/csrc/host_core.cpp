@@ -2,6 +2,7 @@
 // each knot interval, and the arena layout of one request.  No device work;
 // the exported few_host_* helpers are usable on machines without a GPU.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -48,6 +49,7 @@ void free_term_layout(TermLayout *t) {
     std::free(t->term_ptr);
     std::free(t->term_src);
     std::free(t->chunks);
+    std::free(t->mrows);
     *t = TermLayout{};
 }
 
@@ -175,6 +177,34 @@ int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermL
         out->max_seg_terms = 0;
         for (int k = 0; k < n_seg; ++k) out->max_seg_terms = std::max(out->max_seg_terms, segs[4 * k + 2]);
     }
+    // matrix-core rows: the distinct signed m values (segments are in m order)
+    // and the n range over all segments
+    {
+        std::vector<int> mr;
+        int n_min = INT32_MAX, n_max = INT32_MIN;
+        for (int g = 0; g < n_seg; ++g) {
+            const int m = segs[4 * g];
+            if (g == 0 || m != segs[4 * (g - 1)]) {
+                mr.push_back(m);
+                mr.push_back(g);
+            }
+            n_min = std::min(n_min, segs[4 * g + 1]);
+            n_max = std::max(n_max, segs[4 * g + 1] + segs[4 * g + 2] - 1);
+        }
+        mr.push_back(0);
+        mr.push_back(n_seg);
+        out->n_mrows = (int)mr.size() / 2 - 1;
+        out->n_min = n_min;
+        out->n_max = n_max;
+        out->mfma = width == 3 && n_max - n_min + 1 <= kMfQ && out->n_mrows <= kMfRows &&
+                    term >= kMfMinTerms;
+        out->mrows = (int *)std::malloc(sizeof(int) * mr.size());
+        if (!out->mrows) {
+            free_term_layout(out);
+            return FEW_E_NOMEM;
+        }
+        std::memcpy(out->mrows, mr.data(), sizeof(int) * mr.size());
+    }
     out->n_chunks = (int)chunks.size() - 1;
     out->n_segs = (int)segs.size() / 4;
     out->n_terms = term;
@@ -230,7 +260,7 @@ int detector_frame(double theta_s, double phi_s, double theta_k, double phi_k,
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n_src,
-                         int n_chunks, int n_ph) {
+                         int n_chunks, int n_ph, bool mfma, int n_mrows) {
     ReqLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -244,15 +274,21 @@ ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n
     L.off_term_ptr = take(sizeof(int) * (size_t)(n_terms + 1));
     L.off_term_src = take(sizeof(int) * 2 * (size_t)std::max(n_src, 1));
     L.off_chunks = take(sizeof(int) * (size_t)(n_chunks + 1));
-    L.upload_end = L.off_chunks + sizeof(int) * (size_t)(n_chunks + 1);
+    L.off_mrows = take(sizeof(int) * 2 * (size_t)(n_mrows + 1));
+    L.upload_end = L.off_mrows + sizeof(int) * 2 * (size_t)(n_mrows + 1);
     // device-produced arrays
     L.off_pcoef = take(sizeof(double) * 8 * n_ph * (size_t)(K - 1));
     L.dev_begin = L.off_pcoef;
     L.off_acoef = take(sizeof(double) * 8 * (size_t)(K - 1) * M);
     L.off_ybuf = take(sizeof(double) * 2 * (size_t)std::max(n_src, 1));
-    L.off_table = take((fp32 ? 4 : 8) * 8 * (size_t)(K - 1) * n_terms);
+    // binary64 fold table for the binary64 and matrix-core paths (the
+    // matrix-core request's binary32 calls that use the vector kernel, the
+    // fused inner product included, fold into the same region as binary32)
+    L.off_table = take((fp32 && !mfma ? 4 : 8) * 8 * (size_t)(K - 1) * n_terms);
     L.off_starts = take(sizeof(long long) * K);
     L.off_tile_pref = take(sizeof(int) * kParts * (size_t)K);
+    L.off_mtab = take(mfma ? sizeof(uint16_t) * kMfIntervalHalves * (size_t)(K - 1) : 0);
+    L.off_mscale = take(mfma ? sizeof(float) * kMfRows * (size_t)(K - 1) : 0);
     L.total = o;
     return L;
 }
@@ -319,7 +355,9 @@ extern "C" uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t
                                            int32_t n_terms) {
     if (K < 4 || M < 1 || n_terms < 1) return 0;
     // n_src <= 2M, n_segs <= n_terms
+    // binary32 requests long enough for the matrix-core path are sized for it
+    const bool mf = precision == FEW_MIXED && n_terms >= kMfMinTerms;
     ReqLayout L = request_layout(precision == FEW_MIXED, K, M, n_terms, n_terms, 2 * M, n_terms,
-                                 3);
+                                 3, mf, mf ? kMfRows : 0);
     return (uint64_t)L.total;
 }

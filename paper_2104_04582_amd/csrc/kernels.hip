@@ -1315,6 +1315,361 @@ __global__ __launch_bounds__(256) void sum_wg_persistent_kernel(const SumJob *jo
     }
 }
 
+// ===========================================================================
+// Matrix-core summation (binary32 output).  See the shape constants in
+// few_internal.h: per knot interval and power p of u, the product of the
+// coefficient matrix (rows: the real and imaginary part of each signed m;
+// columns: (q, re/im), q = n - n_min) with the matrix of harmonics
+// (Re f^q, Im f^q) over the samples, f = e^{-i Phi_r}, on fp16 hi/lo operands
+// with fp32 accumulation; the sum over p is a Horner recurrence in u on the
+// accumulators, and the rows are combined with e^{-i(m Phi_phi + n_min Phi_r)}.
+// ===========================================================================
+typedef _Float16 mf_half8 __attribute__((ext_vector_type(8)));
+typedef float mf_float4 __attribute__((ext_vector_type(4)));
+
+// Pack interval iv, row tile mt (rows 8 mt .. 8 mt + 7) of the binary64 fold
+// into the fp16 operand table.  Row r (signed m value m_r) is the pair of
+// matrix rows 2r (real part) and 2r + 1 (imaginary part).  Column
+// (q, p, c) multiplies u^p Re f^q (c = 0) or u^p Im f^q (c = 1); with
+// C = C^p_{m_r, n_min + q} (zero where the layout has no term), row 2r holds
+// (Re C, -Im C) and row 2r + 1 holds (Im C, Re C) there, so the row pair
+// times the column pair is the complex product C u^p f^q.  Each row is
+// scaled by 2^-E, E the exponent of its largest |value| on the interval (so
+// scaled values stay below 1), and split into hi = fp16(v) and
+// lo = fp16(v - hi), both from binary64.  Table layout, per interval:
+// [mt][t][hi, lo][lane 64][8 values], lane l's operand fragment of
+// v_mfma_f32_16x16x32_f16 for step t: matrix row l % 16 of the tile, columns
+// q = 4 t + l / 16 and (p, c) = (i / 2, i % 2) for value i.
+__device__ void pack_body(const PrepJob &jb, int iv, int mt) {
+    __shared__ double rsc[8];
+    const int tid = threadIdx.x;
+    const double *tab = (const double *)jb.table + (size_t)iv * jb.n_terms * 8;
+    {
+        const int k = tid >> 5, sub = tid & 31;     // 8 rows x 32 lanes
+        const int r = 8 * mt + k;
+        double mx = 0.0;
+        if (k < 8 && r < jb.n_mrows) {
+            const int g0 = jb.mrows[r].y, g1 = jb.mrows[r + 1].y;
+            for (int g = g0; g < g1; ++g) {
+                const int4 S = jb.segs[g];
+                for (int q = sub; q < S.z; q += 32) {
+                    const double *c = tab + (size_t)(jb.n_terms - 1 - (S.w + q)) * 8;
+                    for (int i = 0; i < 8; ++i) mx = fmax(mx, fabs(c[i]));
+                }
+            }
+        }
+        for (int off = 16; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 32));
+        if (k < 8 && sub == 0) {
+            int e = 0;
+            double sc = 0.0;
+            float ms = 0.0f;
+            if (mx > 0.0) {
+                frexp(mx, &e);
+                sc = ldexp(1.0, -e);
+                ms = (float)ldexp(1.0, e);
+            }
+            rsc[k] = sc;
+            jb.mscale[(size_t)iv * kMfRows + r] = ms;
+        }
+    }
+    __syncthreads();
+    _Float16 *dst = (_Float16 *)jb.mtab + (size_t)iv * kMfIntervalHalves;
+    for (int it = tid; it < kMfT * 64; it += blockDim.x) {
+        const int ln = it & 63, t = it >> 6;
+        const int kk = (ln & 15) >> 1, comp = ln & 1, g = ln >> 4;
+        const int rr = 8 * mt + kk;
+        const int q = 4 * t + g;
+        const double sc = rsc[kk];
+        double c8[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) c8[i] = 0.0;
+        if (rr < jb.n_mrows) {
+            const int n = jb.n_min + q;
+            const int g0 = jb.mrows[rr].y, g1 = jb.mrows[rr + 1].y;
+            for (int sg = g0; sg < g1; ++sg) {
+                const int4 S = jb.segs[sg];
+                if (n >= S.y && n < S.y + S.z) {
+                    const double *cp = tab + (size_t)(jb.n_terms - 1 - (S.w + n - S.y)) * 8;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) c8[i] = cp[i];
+                }
+            }
+        }
+        mf_half8 hi, lo;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const double cr = c8[2 * p], ci = c8[2 * p + 1];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double v = c == 0 ? (comp == 0 ? cr : ci) : (comp == 0 ? -ci : cr);
+                v = v * sc;
+                const _Float16 h = (_Float16)v;
+                hi[2 * p + c] = h;
+                lo[2 * p + c] = (_Float16)(v - (double)h);
+            }
+        }
+        const size_t at = (((size_t)mt * kMfT + t) * 2) * 512 + (size_t)ln * 8;
+        *(mf_half8 *)(dst + at) = hi;
+        *(mf_half8 *)(dst + at + 512) = lo;
+    }
+}
+
+__global__ __launch_bounds__(256) void pack_kernel(PrepJob jb) {
+    pack_body(jb, blockIdx.x / kMfMT, blockIdx.x % kMfMT);
+}
+
+__global__ __launch_bounds__(256) void pack_batch_kernel(const PrepJob *jobs) {
+    const PrepJob jb = jobs[blockIdx.y];
+    const int iv = blockIdx.x / kMfMT;
+    if (iv >= jb.K - 1) return;                     // uniform per workgroup
+    pack_body(jb, iv, blockIdx.x % kMfMT);
+}
+
+__device__ __forceinline__ void cmulf(float ar, float ai, float br, float bi, float *cr,
+                                      float *ci) {
+    *cr = ar * br - ai * bi;
+    *ci = ar * bi + ai * br;
+}
+
+// fp16 hi/lo split of 8 binary32 values.
+__device__ __forceinline__ void split8(const float *v, mf_half8 &hi, mf_half8 &lo) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const _Float16 h = (_Float16)v[i];
+        hi[i] = h;
+        lo[i] = (_Float16)(v[i] - (float)h);
+    }
+}
+
+// One round of a workgroup: wave w takes samples base + (w kMfNT + nt) 16 +
+// (lane % 16), nt < kMfNT, of interval iv (valid below e).  The four lane
+// groups of a 16-sample tile hold the operand columns of q = 4 t + g of the
+// same samples (g = lane / 16), each lane stepping its power f^q by f^4.
+// Returns this lane's binary64 inner-product sums (INNER) or stores h.
+template <bool INNER>
+__device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long base,
+                                            long long e, const float4 *lds, const float *msc,
+                                            const int *mm) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int g = lane >> 4, col = lane & 15;
+    const FEW_AS4 double *tk = cptr(jb.t);
+    const double ti = tk[iv];
+    const double inv_h = 1.0 / (tk[iv + 1] - ti);
+    const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 16;
+    float u1[kMfNT], u2[kMfNT], u3[kMfNT], cr[kMfNT], ci[kMfNT], sr[kMfNT], si[kMfNT];
+#pragma unroll
+    for (int nt = 0; nt < kMfNT; ++nt) {
+        long long j = base + (long long)(w * kMfNT + nt) * 16 + col;
+        if (j >= e) j = e - 1;
+        const double tj = dev_sample_time(jb.t_start, jb.dt, j);
+        const dd x = two_sum(tj, -ti);
+        const double pr = phase_eval<false>(pc + 8, x);
+        const float u = (float)(x.hi * inv_h);
+        u1[nt] = u;
+        u2[nt] = u * u;
+        u3[nt] = u2[nt] * u;
+        float fr, fi, f2r, f2i, f3r, f3i;
+        unit_phasor<float>(pr, &fr, &fi);
+        cmulf(fr, fi, fr, fi, &f2r, &f2i);
+        cmulf(f2r, f2i, fr, fi, &f3r, &f3i);
+        cmulf(f2r, f2i, f2r, f2i, &sr[nt], &si[nt]);       // f^4
+        cr[nt] = g == 0 ? 1.0f : g == 1 ? fr : g == 2 ? f2r : f3r;
+        ci[nt] = g == 0 ? 0.0f : g == 1 ? fi : g == 2 ? f2i : f3i;
+    }
+    mf_float4 acc[kMfMT][kMfNT];
+#pragma unroll
+    for (int mt = 0; mt < kMfMT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < kMfNT; ++nt) acc[mt][nt] = mf_float4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < kMfT; ++t) {
+        mf_half8 bh[kMfNT], bl[kMfNT];
+#pragma unroll
+        for (int nt = 0; nt < kMfNT; ++nt) {
+            float v[8];
+            v[0] = cr[nt];
+            v[1] = ci[nt];
+            v[2] = u1[nt] * cr[nt];
+            v[3] = u1[nt] * ci[nt];
+            v[4] = u2[nt] * cr[nt];
+            v[5] = u2[nt] * ci[nt];
+            v[6] = u3[nt] * cr[nt];
+            v[7] = u3[nt] * ci[nt];
+            split8(v, bh[nt], bl[nt]);
+            float nr, ni;
+            cmulf(cr[nt], ci[nt], sr[nt], si[nt], &nr, &ni);
+            cr[nt] = nr;
+            ci[nt] = ni;
+        }
+#pragma unroll
+        for (int mt = 0; mt < kMfMT; ++mt) {
+            const float4 *fa = lds + (((mt * kMfT + t) * 2) * 64 + lane);
+            const float4 a0 = fa[0], a1 = fa[64];
+            const mf_half8 ah = __builtin_bit_cast(mf_half8, a0);
+            const mf_half8 al = __builtin_bit_cast(mf_half8, a1);
+#pragma unroll
+            for (int nt = 0; nt < kMfNT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[nt], acc[mt][nt],
+                                                                     0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < kMfNT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[nt], acc[mt][nt],
+                                                                     0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < kMfNT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[nt], acc[mt][nt],
+                                                                     0, 0, 0);
+        }
+    }
+    // rows -> h: this lane holds rows 8 mt + 2 g and + 1 of its sample
+    double dh = 0.0, hh = 0.0;
+#pragma unroll
+    for (int nt = 0; nt < kMfNT; ++nt) {
+        const long long jr = base + (long long)(w * kMfNT + nt) * 16 + col;
+        const long long j = jr < e ? jr : e - 1;
+        const double tj = dev_sample_time(jb.t_start, jb.dt, j);
+        const dd x = two_sum(tj, -ti);
+        const double pf = phase_eval<false>(pc, x);
+        const double pr = phase_eval<false>(pc + 8, x);
+        float er, ei;
+        unit_phasor<float>(pf, &er, &ei);
+        float hr = 0.0f, hq = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < kMfMT; ++mt) {
+            const int r0 = 8 * mt + 2 * g;
+            const int m0 = mm[r0], m1 = mm[r0 + 1];
+            float zr, zi;
+            unit_phasor<float>(d_reduce_2pi((double)m0 * pf + (double)jb.n_min * pr), &zr, &zi);
+            const float s0 = msc[r0], s1 = msc[r0 + 1];
+            const float a0 = acc[mt][nt][0] * s0, b0 = acc[mt][nt][1] * s0;
+            hr = hr + (zr * a0 - zi * b0);
+            hq = hq + (zr * b0 + zi * a0);
+            float yr, yi;
+            if (m1 == m0 + 1)
+                cmulf(zr, zi, er, ei, &yr, &yi);
+            else
+                unit_phasor<float>(d_reduce_2pi((double)m1 * pf + (double)jb.n_min * pr), &yr,
+                                   &yi);
+            const float a1 = acc[mt][nt][2] * s1, b1 = acc[mt][nt][3] * s1;
+            hr = hr + (yr * a1 - yi * b1);
+            hq = hq + (yr * b1 + yi * a1);
+        }
+        // the four lane groups hold the other rows of the same sample
+        hr = hr + __shfl_xor(hr, 16);
+        hq = hq + __shfl_xor(hq, 16);
+        hr = hr + __shfl_xor(hr, 32);
+        hq = hq + __shfl_xor(hq, 32);
+        if (g == 0 && jr < e) {
+            if constexpr (INNER) {
+                const float *d = (const float *)jb.data + 2 * jr;
+                const double xr = hr, xi = hq, dr = d[0], di = d[1];
+                dh = dh + (dr * xr + di * xi);
+                hh = hh + (xr * xr + xi * xi);
+            } else {
+                float2 *o = (float2 *)jb.out + jr;
+                *o = make_float2(hr, hq);
+            }
+        }
+    }
+    return make_double2(dh, hh);
+}
+
+// Samples [lo, hi) of one job (matrix-core path), interval by interval; each
+// interval's operand table and row scales are staged in LDS first.  Every
+// lane of the workgroup runs the same loop (lo, hi uniform).
+template <bool INNER>
+__device__ double2 mf_range(const SumJob &jb, long long lo, long long hi, float4 *lds,
+                            float *msc, int *mm) {
+    double2 acc = make_double2(0.0, 0.0);
+    if (lo >= hi) return acc;
+    __syncthreads();                                // rows of a previous job no longer read
+    if ((int)threadIdx.x < kMfRows) {
+        const int r = threadIdx.x;
+        const FEW_AS4 int2 *mr = cptr(jb.mrows);
+        mm[r] = r < jb.n_mrows ? mr[r].x : mr[jb.n_mrows - 1].x + (r - jb.n_mrows + 1);
+    }
+    const FEW_AS4 long long *st = cptr(jb.starts);
+    int iv = 0, top = jb.K - 2;
+    while (iv < top) {
+        const int mid = (iv + top + 1) >> 1;
+        if (st[mid] <= lo) iv = mid; else top = mid - 1;
+    }
+    for (; iv <= jb.K - 2 && lo < hi; ++iv) {
+        const long long e = min(hi, (long long)st[iv + 1]);
+        if (e <= lo) continue;
+        __syncthreads();                            // previous interval no longer read
+        const float4 *src = (const float4 *)((const _Float16 *)jb.mtab +
+                                             (size_t)iv * kMfIntervalHalves);
+        constexpr int n4 = (int)(kMfIntervalHalves * sizeof(_Float16) / 16);
+        for (int v = threadIdx.x; v < n4; v += blockDim.x) lds[v] = src[v];
+        if ((int)threadIdx.x < kMfRows)
+            msc[threadIdx.x] = jb.mscale[(size_t)iv * kMfRows + threadIdx.x];
+        __syncthreads();
+        for (long long base = lo; base < e; base += kMfRound) {
+            const double2 v = mf_round<INNER>(jb, iv, base, e, lds, msc, mm);
+            acc.x = acc.x + v.x;
+            acc.y = acc.y + v.y;
+        }
+        lo = e;
+    }
+    return acc;
+}
+
+// Share r of G of [0, total): workgroup b runs on XCD b mod 8 and takes share
+// (b mod 8) G/8 + b/8, so each XCD works through one contiguous eighth.
+__device__ __forceinline__ void mf_share(long long total, long long *lo, long long *hi) {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int r = (G % 8 == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
+    *lo = total * r / G;
+    *hi = total * (r + 1) / G;
+}
+
+template <bool INNER>
+__global__ __launch_bounds__(512) void sum_mfma_kernel(SumJob jb) {
+    extern __shared__ float4 mf_lds[];
+    __shared__ float msc[kMfRows];
+    __shared__ int mm[kMfRows];
+    long long lo, hi;
+    mf_share(jb.n, &lo, &hi);
+    double2 v = mf_range<INNER>(jb, lo, hi, mf_lds, msc, mm);
+    if constexpr (INNER) {
+        __shared__ double2 red[kMfWaves];
+        v = wave_sum(v);
+        if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double2 t = red[0];
+            for (int w = 1; w < kMfWaves; ++w) {
+                t.x = t.x + red[w].x;
+                t.y = t.y + red[w].y;
+            }
+            jb.partial[blockIdx.x] = t;
+        }
+    }
+}
+
+// Batched launch: the jobs' samples laid end to end (job j from sample_base_j),
+// split into equal shares.
+__global__ __launch_bounds__(512) void sum_mfma_batch_kernel(const SumJob *jobs, int n_jobs,
+                                                             long long total) {
+    extern __shared__ float4 mf_lds[];
+    __shared__ float msc[kMfRows];
+    __shared__ int mm[kMfRows];
+    long long lo, hi;
+    mf_share(total, &lo, &hi);
+    int j = 0, top = n_jobs - 1;
+    while (j < top) {
+        const int mid = (j + top + 1) >> 1;
+        if (*cptr(&jobs[mid].sample_base) <= lo) j = mid; else top = mid - 1;
+    }
+    for (; j < n_jobs; ++j) {
+        const long long b0 = *cptr(&jobs[j].sample_base);
+        if (b0 >= hi) break;
+        const SumJob jb = load_uniform(jobs + j);
+        const long long a = max(lo, b0) - b0, e = min(hi, b0 + jb.n) - b0;
+        if (a < e) mf_range<false>(jb, a, e, mf_lds, msc, mm);
+    }
+}
+
 #pragma clang fp contract(on)
 
 // ===========================================================================
@@ -1687,6 +2042,61 @@ hipError_t launch_sum_inner(const SumJob &job, int slots, bool fp32, double two_
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kReduceThreads), 0, stream,
                        job.partial, inner_slots(job.parts, slots, fp32), two_dt, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const PrepJob &job, hipStream_t stream) {
+    hipLaunchKernelGGL(pack_kernel, dim3((job.K - 1) * kMfMT), dim3(256), 0, stream, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_batch(const PrepJob *jobs_dev, int n_jobs, int max_K, hipStream_t stream) {
+    hipLaunchKernelGGL(pack_batch_kernel, dim3((max_K - 1) * kMfMT, n_jobs), dim3(256), 0,
+                       stream, jobs_dev);
+    return hipGetLastError();
+}
+
+static constexpr size_t mf_lds_bytes() { return kMfIntervalHalves * sizeof(_Float16); }
+
+// One workgroup per compute unit (the operand table takes most of the LDS).
+int mfma_workgroups() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        hipFuncSetAttribute((const void *)sum_mfma_kernel<false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)mf_lds_bytes());
+        hipFuncSetAttribute((const void *)sum_mfma_kernel<true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)mf_lds_bytes());
+        hipFuncSetAttribute((const void *)sum_mfma_batch_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)mf_lds_bytes());
+    });
+    return cus;
+}
+
+hipError_t launch_sum_mfma(const SumJob &job, int n_wg, hipStream_t stream) {
+    hipLaunchKernelGGL(sum_mfma_kernel<false>, dim3(n_wg), dim3(64 * kMfWaves), mf_lds_bytes(),
+                       stream, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_mfma_inner(const SumJob &job, int n_wg, double two_dt, double *out2,
+                                 hipStream_t stream) {
+    hipLaunchKernelGGL(sum_mfma_kernel<true>, dim3(n_wg), dim3(64 * kMfWaves), mf_lds_bytes(),
+                       stream, job);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kReduceThreads), 0, stream,
+                       job.partial, (long long)n_wg, two_dt, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_mfma_batch(const SumJob *jobs_dev, int n_jobs, long long total, int n_wg,
+                                 hipStream_t stream) {
+    hipLaunchKernelGGL(sum_mfma_batch_kernel, dim3(n_wg), dim3(64 * kMfWaves), mf_lds_bytes(),
+                       stream, jobs_dev, n_jobs, total);
     return hipGetLastError();
 }
 

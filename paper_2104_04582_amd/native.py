@@ -30,6 +30,7 @@ FEW_FP64 = 0
 FEW_MIXED = 1
 FEW_FLAG_TIMING = 1
 FEW_FLAG_TIMING_SUM = 2
+FEW_FLAG_VECTOR_ONLY = 4
 
 EXPORTED = [
     "few_plan_create", "few_plan_destroy", "few_spline_fit", "few_spline_free",
@@ -180,11 +181,13 @@ class Plan:
     """few_plan: device arena, precision, stream and the request server.
 
     timing: False, True (HIP events around every launch, FEW_FLAG_TIMING) or
-    "sum" (around summation launches only, FEW_FLAG_TIMING_SUM)."""
+    "sum" (around summation launches only, FEW_FLAG_TIMING_SUM).
+    vector_only: mixed precision without the matrix-core summation
+    (FEW_FLAG_VECTOR_ONLY)."""
 
     def __init__(self, device: int = 0, precision: str = "fp64", stream: Optional[int] = None,
                  hbm_budget_bytes: int = 0, max_inflight: int = 0, timing=False,
-                 max_knots: int = 0, max_modes: int = 0):
+                 max_knots: int = 0, max_modes: int = 0, vector_only: bool = False):
         import torch
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
@@ -198,7 +201,8 @@ class Plan:
                      max_knots=max_knots, max_modes=max_modes, max_inflight=max_inflight,
                      hbm_budget_bytes=hbm_budget_bytes,
                      flags=(FEW_FLAG_TIMING_SUM if timing == "sum"
-                            else FEW_FLAG_TIMING if timing else 0))
+                            else FEW_FLAG_TIMING if timing else 0)
+                     | (FEW_FLAG_VECTOR_ONLY if vector_only else 0))
         h = ctypes.c_void_p()
         _check(load().few_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self.handle = h.value

@@ -1,0 +1,172 @@
+"""GPU parity of the matrix-core summation (mixed precision).
+
+Binary32 requests whose folded layout fits the matrix-core shape (at most 24
+signed m values, an n range of at most 64, at least 480 folded terms) are
+summed on the MFMA units with fp16 hi/lo operands and fp32 accumulation.
+Every case here takes that path (checked through the term layout) and is
+compared with the oracle (mismatch <= 1e-6, max relative error <= 1e-5) and
+with the vector-only path of the same plan type (FEW_FLAG_VECTOR_ONLY).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_04582_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+MISMATCH = 1e-6
+MAXREL = 1e-5
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2104_04582_amd import native
+    native.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return native, torch, torch.device("cuda:0")
+
+
+def takes_mfma_path(native, lmn):
+    segs, tp, _ = native.host_terms(lmn)
+    ms = sorted(set(int(m) for m in segs[:, 0]))
+    n_lo = int(segs[:, 1].min())
+    n_hi = int((segs[:, 1] + segs[:, 2] - 1).max())
+    return len(ms) <= 24 and n_hi - n_lo + 1 <= 64 and tp.shape[0] - 1 >= 480
+
+
+def run(native, torch, dev, w, vector_only=False):
+    pp, pr, amp = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                   for a in (w.phi_phi, w.phi_r, w.amp))
+    with native.Plan(0, "mixed", vector_only=vector_only) as plan:
+        sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+        out = plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples, t_start=w.t_start,
+                            scale=w.scale)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.complex128)
+
+
+def check(got, ref, what):
+    err = oracle.max_rel_error(got, ref)
+    mm = oracle.mismatch(got, ref)
+    log(f"    {what}: max_rel_err={err:.3e} mismatch={mm:.3e}")
+    assert np.all(np.isfinite(got))
+    assert mm <= MISMATCH
+    assert err <= MAXREL
+
+
+def full_modes_short(seed, n_samples, K=40, T=86400.0):
+    """The 3843-mode list on a short waveform (so the oracle checks every
+    sample)."""
+    rng = np.random.default_rng(seed)
+    w = synth.draw_waveform(rng, synth.mode_list(2, 10, 30), T, K, 10.0)
+    w.n_samples = min(w.n_samples, n_samples)
+    return w
+
+
+def drop_m(w, ms):
+    keep = ~np.isin(w.lmn[:, 1], ms)
+    w.lmn = w.lmn[keep].copy()
+    w.amp = w.amp[:, keep, :].copy()
+    return w
+
+
+def narrow_n(w, lo, hi, holes=()):
+    n = w.lmn[:, 2]
+    keep = (n >= lo) & (n <= hi) & ~np.isin(n, holes)
+    w.lmn = w.lmn[keep].copy()
+    w.amp = w.amp[:, keep, :].copy()
+    return w
+
+
+CASES = [
+    ("1 sample", lambda: full_modes_short(40, 1)),
+    ("3 samples", lambda: full_modes_short(41, 3)),
+    ("ragged 1000", lambda: full_modes_short(42, 1000)),
+    ("one day", lambda: full_modes_short(43, 8640)),
+    ("m 3 and 7 missing", lambda: drop_m(full_modes_short(44, 5000), [3, 7])),
+    ("n -20..25 with holes", lambda: narrow_n(full_modes_short(45, 5000), -20, 25,
+                                              holes=(-3, 4, 5, 6, 7, 8, 9, 17))),
+    ("scale and offset start", lambda: full_modes_short(46, 4000)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_mfma_whole_output_against_oracle(env, case):
+    native, torch, dev = env
+    name, make = case
+    w = make()
+    if name == "scale and offset start":
+        w.scale = 2.5e-3
+        w.t_start = 0.37 * (w.t_knots[1] - w.t_knots[0])
+        w.n_samples = int((w.t_knots[-1] - w.t_start) / w.dt) - 1
+    assert takes_mfma_path(native, w.lmn), name
+    log(f"[mfma] {name}: K={w.K} M={w.M} N={w.n_samples}")
+    ref = oracle.mode_sum_waveform(w)
+    got = run(native, torch, dev, w)
+    check(got, ref, name + " (matrix core)")
+    vec = run(native, torch, dev, w, vector_only=True)
+    check(vec, ref, name + " (vector)")
+    mm = oracle.mismatch(got, vec)
+    log(f"    matrix core vs vector: mismatch={mm:.3e}")
+    assert mm <= MISMATCH
+
+
+def test_mfma_one_year_whole_output_against_vector_and_oracle(env):
+    """The one-year benchmark case: every sample against the vector path, and
+    sampled outputs against the oracle."""
+    native, torch, dev = env
+    w = synth.config1()
+    assert takes_mfma_path(native, w.lmn)
+    got = run(native, torch, dev, w)
+    vec = run(native, torch, dev, w, vector_only=True)
+    mm = oracle.mismatch(got, vec)
+    err = oracle.max_rel_error(got, vec)
+    log(f"[mfma] one year: vs vector mismatch={mm:.3e} max_rel={err:.3e}")
+    assert mm <= MISMATCH and err <= MAXREL
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.choice(w.n_samples, 2000, replace=False),
+                                    [0, w.n_samples - 1]])).astype(np.int64)
+    ref = oracle.mode_sum_waveform(w, idx=idx)
+    check(got[idx], ref, "one year (matrix core, sampled)")
+
+
+def test_mfma_repeat_is_bitwise_deterministic(env):
+    native, torch, dev = env
+    w = full_modes_short(47, 8640)
+    a = run(native, torch, dev, w)
+    b = run(native, torch, dev, w)
+    assert np.array_equal(a, b)
+
+
+def test_mfma_inner_product_matches_its_waveform(env):
+    """few_inner_product on a matrix-core request forms the same h as
+    few_mode_sum (binary64 reductions of the stored waveform agree to 1e-12)."""
+    native, torch, dev = env
+    w = synth.config1()
+    w.n_samples = 500_000
+    g = torch.Generator(device="cpu").manual_seed(3)
+    dat = torch.complex(torch.randn(w.n_samples, generator=g, dtype=torch.float64),
+                        torch.randn(w.n_samples, generator=g, dtype=torch.float64))
+    dat = dat.to(torch.complex64).to(dev)
+    pp, pr, amp = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                   for a in (w.phi_phi, w.phi_r, w.amp))
+    with native.Plan(0, "mixed") as plan:
+        sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+        h = plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples)
+        got = plan.inner_product(sp, w.theta, w.phi, w.dt, w.n_samples, dat).cpu().numpy()
+        torch.cuda.synchronize()
+    h64 = h.to(torch.complex128)
+    d64 = dat.to(torch.complex128)
+    ref_dh = 2 * w.dt * torch.real(torch.vdot(d64, h64)).item()
+    ref_hh = 2 * w.dt * torch.real(torch.vdot(h64, h64)).item()
+    norm = 2 * w.dt * torch.linalg.norm(d64).item() * torch.linalg.norm(h64).item()
+    log(f"[mfma] inner: dh err {abs(got[0] - ref_dh) / norm:.2e}, "
+        f"hh err {abs(got[1] - ref_hh) / ref_hh:.2e}")
+    assert abs(got[0] - ref_dh) <= 1e-12 * norm
+    assert abs(got[1] - ref_hh) <= 1e-12 * ref_hh
