@@ -77,25 +77,35 @@ inline int split_tile_samples() { return kWave * kSamplesPerLaneF32; }
 
 // Matrix-core summation (binary32 output).  Per knot interval the folded sum
 // is a contraction: with rows = the distinct signed m values (a complex row
-// each, as a real re/im pair) and columns (q, p), q = n - n_min,
-//   h = sum_m e^{-i(m Phi_phi + n_min Phi_r)} sum_{q,p} C^p_{m,q} u^p f^q,
-// f = e^{-i Phi_r}: the product of the coefficient matrix [rows x (q, p,
-// re/im)] with the matrix of u^p f^q over the samples, run on
-// v_mfma_f32_16x16x32_f16 with both operands split into fp16 hi + lo parts
-// (hi*hi + hi*lo + lo*hi, about 22 significant bits) and fp32 accumulation.
-// Fixed shape: kMfMT tiles of 16 matrix rows (8 signed m each), kMfT steps of
-// 32 columns (4 values of q; q < 4 kMfT), kMfNT tiles of 16 samples per wave,
-// kMfWaves waves per workgroup.  A request takes this path when its term
-// layout fits the shape and is long enough to repay it.
+// each, as a real re/im pair) and columns n,
+//   h = sum_m e^{-i m Phi_phi} sum_p u^p sum_n C^p_{m,n} f^n,
+// f = e^{-i Phi_r}.  For each p the sum over n is the product of the
+// coefficient matrix [rows x (n, re/im)] with the matrix of powers f^n over
+// the samples, run on v_mfma_f32_16x16x32_f16 with both operands split into
+// fp16 hi + lo parts (hi*hi + hi*lo + lo*hi, about 22 significant bits) and
+// fp32 accumulation; the sum over p is a Horner recurrence in u on the
+// accumulators.  Only the powers f^a, a = |n| >= 0, are formed: a column of
+// n < 0 multiplies conj(f^|n|), and the conjugation lives in the coefficient
+// matrix, so the columns of n and -n share one operand fragment.  Fixed
+// shape: kMfMT tiles of 16 matrix rows (8 signed m each), two signs x kMfT
+// steps of 32 columns (16 values of |n| each; |n| < 16 kMfT), kMfNT tiles of
+// 16 samples per wave, kMfWaves waves per workgroup.  A request takes this
+// path when its term layout fits the shape and is long enough to repay it.
+#ifndef FEW_MF_NT
+#define FEW_MF_NT 3
+#endif
+#ifndef FEW_MF_WAVES
+#define FEW_MF_WAVES 12
+#endif
 constexpr int kMfMT = 3;
-constexpr int kMfT = 16;
-constexpr int kMfNT = 4;
-constexpr int kMfWaves = 8;
+constexpr int kMfT = 2;
+constexpr int kMfNT = FEW_MF_NT;
+constexpr int kMfWaves = FEW_MF_WAVES;
 constexpr int kMfRows = 8 * kMfMT;          // signed m values per request
-constexpr int kMfQ = 4 * kMfT;              // n_max - n_min + 1 <= kMfQ
+constexpr int kMfA = 16 * kMfT;             // |n| < kMfA
 constexpr int kMfRound = kMfWaves * kMfNT * 16;   // samples per workgroup round
-// fp16 values of one interval: [mt][t][hi, lo][lane 64][8]
-constexpr size_t kMfIntervalHalves = (size_t)kMfMT * kMfT * 2 * 64 * 8;
+// fp16 values of one interval: [p 4][mt][sign 2][t][hi, lo][lane 64][8]
+constexpr size_t kMfIntervalHalves = (size_t)4 * kMfMT * 2 * kMfT * 2 * 64 * 8;
 constexpr int kMfMinTerms = 480;            // below this the vector kernel is cheaper
 
 // ---------------------------------------------------------------------------
@@ -175,6 +185,7 @@ struct SumJob {
     const int2 *mrows;      // [n_mrows + 1]
     int n_mrows, n_min;
     long long sample_base;  // first sample of this job in a batched launch's range
+    float unit;             // 1.0 (an operand the compiler cannot fold away)
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.

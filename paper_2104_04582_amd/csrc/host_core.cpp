@@ -196,7 +196,7 @@ int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermL
         out->n_mrows = (int)mr.size() / 2 - 1;
         out->n_min = n_min;
         out->n_max = n_max;
-        out->mfma = width == 3 && n_max - n_min + 1 <= kMfQ && out->n_mrows <= kMfRows &&
+        out->mfma = width == 3 && n_min > -kMfA && n_max < kMfA && out->n_mrows <= kMfRows &&
                     term >= kMfMinTerms;
         out->mrows = (int *)std::malloc(sizeof(int) * mr.size());
         if (!out->mrows) {

@@ -1319,27 +1319,29 @@ __global__ __launch_bounds__(256) void sum_wg_persistent_kernel(const SumJob *jo
 // Matrix-core summation (binary32 output).  See the shape constants in
 // few_internal.h: per knot interval and power p of u, the product of the
 // coefficient matrix (rows: the real and imaginary part of each signed m;
-// columns: (q, re/im), q = n - n_min) with the matrix of harmonics
-// (Re f^q, Im f^q) over the samples, f = e^{-i Phi_r}, on fp16 hi/lo operands
-// with fp32 accumulation; the sum over p is a Horner recurrence in u on the
-// accumulators, and the rows are combined with e^{-i(m Phi_phi + n_min Phi_r)}.
+// columns: (n, re/im)) with the matrix of harmonics (Re f^|n|, Im f^|n|) over
+// the samples, f = e^{-i Phi_r}, on fp16 hi/lo operands with fp32
+// accumulation; the sum over p is a Horner recurrence in u on the
+// accumulators, and the rows are combined with e^{-i m Phi_phi}.
 // ===========================================================================
 typedef _Float16 mf_half8 __attribute__((ext_vector_type(8)));
 typedef float mf_float4 __attribute__((ext_vector_type(4)));
 
 // Pack interval iv, row tile mt (rows 8 mt .. 8 mt + 7) of the binary64 fold
 // into the fp16 operand table.  Row r (signed m value m_r) is the pair of
-// matrix rows 2r (real part) and 2r + 1 (imaginary part).  Column
-// (q, p, c) multiplies u^p Re f^q (c = 0) or u^p Im f^q (c = 1); with
-// C = C^p_{m_r, n_min + q} (zero where the layout has no term), row 2r holds
-// (Re C, -Im C) and row 2r + 1 holds (Im C, Re C) there, so the row pair
-// times the column pair is the complex product C u^p f^q.  Each row is
-// scaled by 2^-E, E the exponent of its largest |value| on the interval (so
-// scaled values stay below 1), and split into hi = fp16(v) and
-// lo = fp16(v - hi), both from binary64.  Table layout, per interval:
-// [mt][t][hi, lo][lane 64][8 values], lane l's operand fragment of
-// v_mfma_f32_16x16x32_f16 for step t: matrix row l % 16 of the tile, columns
-// q = 4 t + l / 16 and (p, c) = (i / 2, i % 2) for value i.
+// matrix rows 2r (real part) and 2r + 1 (imaginary part).  For power p,
+// column (n, c) multiplies Re w (c = 0) or Im w (c = 1), w = f^|n|.  With
+// C = C^p_{m_r, n} (zero where the layout has no term): for n >= 0, C w is
+// (Re C Re w - Im C Im w) + i (Im C Re w + Re C Im w), so row 2r holds
+// (Re C, -Im C) and row 2r + 1 holds (Im C, Re C); for n < 0, C conj(w) is
+// (Re C Re w + Im C Im w) + i (Im C Re w - Re C Im w): (Re C, Im C) and
+// (Im C, -Re C).  Each row is scaled by 2^-E, E the exponent of its largest
+// |value| on the interval (so scaled values stay below 1), and split into
+// hi = fp16(v) and lo = fp16(v - hi), both from binary64.  Table layout, per
+// interval: [p][mt][sign][t][hi, lo][lane 64][8 values], lane l's operand
+// fragment of v_mfma_f32_16x16x32_f16: matrix row l % 16 of the tile, columns
+// |n| = 16 t + 4 (l / 16) + i / 2 and c = i % 2 for value i (sign 0: n = |n|,
+// sign 1: n = -|n|, whose n = 0 column is zero).
 __device__ void pack_body(const PrepJob &jb, int iv, int mt) {
     __shared__ double rsc[8];
     const int tid = threadIdx.x;
@@ -1374,41 +1376,45 @@ __device__ void pack_body(const PrepJob &jb, int iv, int mt) {
     }
     __syncthreads();
     _Float16 *dst = (_Float16 *)jb.mtab + (size_t)iv * kMfIntervalHalves;
-    for (int it = tid; it < kMfT * 64; it += blockDim.x) {
-        const int ln = it & 63, t = it >> 6;
+    for (int it = tid; it < 4 * 2 * kMfT * 64; it += blockDim.x) {
+        const int ln = it & 63, t = (it >> 6) % kMfT, sg = ((it >> 6) / kMfT) & 1;
+        const int p = (it >> 6) / (2 * kMfT);
         const int kk = (ln & 15) >> 1, comp = ln & 1, g = ln >> 4;
         const int rr = 8 * mt + kk;
-        const int q = 4 * t + g;
         const double sc = rsc[kk];
-        double c8[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) c8[i] = 0.0;
-        if (rr < jb.n_mrows) {
-            const int n = jb.n_min + q;
-            const int g0 = jb.mrows[rr].y, g1 = jb.mrows[rr + 1].y;
-            for (int sg = g0; sg < g1; ++sg) {
-                const int4 S = jb.segs[sg];
-                if (n >= S.y && n < S.y + S.z) {
-                    const double *cp = tab + (size_t)(jb.n_terms - 1 - (S.w + n - S.y)) * 8;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) c8[i] = cp[i];
-                }
-            }
-        }
         mf_half8 hi, lo;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const double cr = c8[2 * p], ci = c8[2 * p + 1];
+        for (int j = 0; j < 4; ++j) {
+            const int a = 16 * t + 4 * g + j;
+            const int n = sg == 0 ? a : -a;
+            double cr = 0.0, ci = 0.0;
+            if (rr < jb.n_mrows && (sg == 0 || a > 0)) {
+                const int g0 = jb.mrows[rr].y, g1 = jb.mrows[rr + 1].y;
+                for (int q = g0; q < g1; ++q) {
+                    const int4 S = jb.segs[q];
+                    if (n >= S.y && n < S.y + S.z) {
+                        const double *cp =
+                            tab + (size_t)(jb.n_terms - 1 - (S.w + n - S.y)) * 8;
+                        cr = cp[2 * p];
+                        ci = cp[2 * p + 1];
+                    }
+                }
+            }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                double v = c == 0 ? (comp == 0 ? cr : ci) : (comp == 0 ? -ci : cr);
+                double v;
+                if (sg == 0)
+                    v = c == 0 ? (comp == 0 ? cr : ci) : (comp == 0 ? -ci : cr);
+                else
+                    v = c == 0 ? (comp == 0 ? cr : ci) : (comp == 0 ? ci : -cr);
                 v = v * sc;
                 const _Float16 h = (_Float16)v;
-                hi[2 * p + c] = h;
-                lo[2 * p + c] = (_Float16)(v - (double)h);
+                hi[2 * j + c] = h;
+                lo[2 * j + c] = (_Float16)(v - (double)h);
             }
         }
-        const size_t at = (((size_t)mt * kMfT + t) * 2) * 512 + (size_t)ln * 8;
+        const size_t at =
+            (((((size_t)p * kMfMT + mt) * 2 + sg) * kMfT + t) * 2) * 512 + (size_t)ln * 8;
         *(mf_half8 *)(dst + at) = hi;
         *(mf_half8 *)(dst + at + 512) = lo;
     }
@@ -1425,139 +1431,233 @@ __global__ __launch_bounds__(256) void pack_batch_kernel(const PrepJob *jobs) {
     pack_body(jb, iv, blockIdx.x % kMfMT);
 }
 
+// Complex product with one rounding per component (fused multiply-add).
 __device__ __forceinline__ void cmulf(float ar, float ai, float br, float bi, float *cr,
                                       float *ci) {
-    *cr = ar * br - ai * bi;
-    *ci = ar * bi + ai * br;
+    *cr = __builtin_fmaf(ar, br, -(ai * bi));
+    *ci = __builtin_fmaf(ar, bi, ai * br);
 }
 
-// fp16 hi/lo split of 8 binary32 values.
-__device__ __forceinline__ void split8(const float *v, mf_half8 &hi, mf_half8 &lo) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const _Float16 h = (_Float16)v[i];
-        hi[i] = h;
-        lo[i] = (_Float16)(v[i] - (float)h);
-    }
+// fp16 hi/lo parts of a binary32 value: hi = fp16(a), lo = fp16(a - hi)
+// (the difference is exact in binary32), about 22 significant bits together.
+// `one` is 1.0 from the job descriptor: written as a * one - hi the
+// difference maps onto one mixed-precision multiply-add reading hi as fp16.
+__device__ __forceinline__ void split1(float a, float one, _Float16 &hi, _Float16 &lo) {
+    const _Float16 h = (_Float16)a;
+    hi = h;
+    lo = (_Float16)__builtin_fmaf(a, one, -(float)h);
 }
 
-// One round of a workgroup: wave w takes samples base + (w kMfNT + nt) 16 +
-// (lane % 16), nt < kMfNT, of interval iv (valid below e).  The four lane
-// groups of a 16-sample tile hold the operand columns of q = 4 t + g of the
-// same samples (g = lane / 16), each lane stepping its power f^q by f^4.
-// Returns this lane's binary64 inner-product sums (INNER) or stores h.
+// Lane value of lane `src` (a row of 16 lanes broadcast to all four rows).
+__device__ __forceinline__ float lane_get(float v, int src) { return __shfl(v, src); }
+
+// One round of a workgroup: wave w takes the kMfNT * 16 samples
+// base + w kMfNT 16 + s, s = 16 nt + c (tiles nt of 16, valid below e).  The
+// lanes first form the per-sample values of sample s = lane + 64 k (phases,
+// harmonics and their powers); in tile nt the four lane groups g = l / 16 of
+// column c read them from the lane that formed them.  Group g holds the
+// operand columns |n| = 16 t + 4 g + j, j < 4, of step t: f^{16 t + 4 g} times
+// f^j (the same fragment serves n and -n).  The accumulators run a Horner
+// recurrence in u over p = 3 .. 0.  Returns this lane's binary64
+// inner-product sums (INNER) or stores h.
 template <bool INNER>
 __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long base,
                                             long long e, const float4 *lds, const float *msc,
-                                            const int *mm) {
+                                            const int *mm, bool consec) {
+    constexpr int SPW = kMfNT * 16;                 // samples per wave
+    constexpr int OWN = (SPW + kWave - 1) / kWave;  // samples formed per lane
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int g = lane >> 4, col = lane & 15;
     const FEW_AS4 double *tk = cptr(jb.t);
     const double ti = tk[iv];
     const double inv_h = 1.0 / (tk[iv + 1] - ti);
     const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 16;
-    float u1[kMfNT], u2[kMfNT], u3[kMfNT], cr[kMfNT], ci[kMfNT], sr[kMfNT], si[kMfNT];
+    const long long wbase = base + (long long)w * SPW;
+    // this lane's samples
+    double pf[OWN], pr[OWN];
+    float u[OWN], er[OWN], ei[OWN], fr[OWN], fi[OWN], f4r[OWN], f4i[OWN], f8r[OWN], f8i[OWN];
+    float f12r[OWN], f12i[OWN], f16r[OWN], f16i[OWN];
 #pragma unroll
-    for (int nt = 0; nt < kMfNT; ++nt) {
-        long long j = base + (long long)(w * kMfNT + nt) * 16 + col;
+    for (int k = 0; k < OWN; ++k) {
+        long long j = wbase + lane + (long long)kWave * k;
         if (j >= e) j = e - 1;
         const double tj = dev_sample_time(jb.t_start, jb.dt, j);
         const dd x = two_sum(tj, -ti);
-        const double pr = phase_eval<false>(pc + 8, x);
-        const float u = (float)(x.hi * inv_h);
-        u1[nt] = u;
-        u2[nt] = u * u;
-        u3[nt] = u2[nt] * u;
-        float fr, fi, f2r, f2i, f3r, f3i;
-        unit_phasor<float>(pr, &fr, &fi);
-        cmulf(fr, fi, fr, fi, &f2r, &f2i);
-        cmulf(f2r, f2i, fr, fi, &f3r, &f3i);
-        cmulf(f2r, f2i, f2r, f2i, &sr[nt], &si[nt]);       // f^4
-        cr[nt] = g == 0 ? 1.0f : g == 1 ? fr : g == 2 ? f2r : f3r;
-        ci[nt] = g == 0 ? 0.0f : g == 1 ? fi : g == 2 ? f2i : f3i;
+        pf[k] = phase_eval<false>(pc, x);
+        pr[k] = phase_eval<false>(pc + 8, x);
+        u[k] = (float)(x.hi * inv_h);
+        unit_phasor<float>(pf[k], &er[k], &ei[k]);
+        unit_phasor<float>(pr[k], &fr[k], &fi[k]);
+        float f2r, f2i;
+        cmulf(fr[k], fi[k], fr[k], fi[k], &f2r, &f2i);
+        cmulf(f2r, f2i, f2r, f2i, &f4r[k], &f4i[k]);
+        cmulf(f4r[k], f4i[k], f4r[k], f4i[k], &f8r[k], &f8i[k]);
+        cmulf(f8r[k], f8i[k], f4r[k], f4i[k], &f12r[k], &f12i[k]);
+        cmulf(f8r[k], f8i[k], f8r[k], f8i[k], &f16r[k], &f16i[k]);
+    }
+    // operands: powers of f for every tile and step
+    mf_half8 bh[kMfNT][kMfT], bl[kMfNT][kMfT];
+    float uu[kMfNT];
+#pragma unroll
+    for (int nt = 0; nt < kMfNT; ++nt) {
+        const int src = (16 * nt + col) % kWave, k = (16 * nt) / kWave;
+        uu[nt] = lane_get(u[k], src);
+        const float ar = lane_get(fr[k], src), ai = lane_get(fi[k], src);
+        const float b4r = lane_get(f4r[k], src), b4i = lane_get(f4i[k], src);
+        const float b8r = lane_get(f8r[k], src), b8i = lane_get(f8i[k], src);
+        const float b12r = lane_get(f12r[k], src), b12i = lane_get(f12i[k], src);
+        const float sr = lane_get(f16r[k], src), si = lane_get(f16i[k], src);
+        float cr = g == 0 ? 1.0f : g == 1 ? b4r : g == 2 ? b8r : b12r;
+        float ci = g == 0 ? 0.0f : g == 1 ? b4i : g == 2 ? b8i : b12i;
+#pragma unroll
+        for (int t = 0; t < kMfT; ++t) {
+            float v[8];
+            v[0] = cr;
+            v[1] = ci;
+            cmulf(v[0], v[1], ar, ai, &v[2], &v[3]);
+            cmulf(v[2], v[3], ar, ai, &v[4], &v[5]);
+            cmulf(v[4], v[5], ar, ai, &v[6], &v[7]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                _Float16 h, l;
+                split1(v[i], jb.unit, h, l);
+                bh[nt][t][i] = h;
+                bl[nt][t][i] = l;
+            }
+            if (t + 1 < kMfT) {
+                float nr, ni;
+                cmulf(cr, ci, sr, si, &nr, &ni);
+                cr = nr;
+                ci = ni;
+            }
+        }
     }
     mf_float4 acc[kMfMT][kMfNT];
 #pragma unroll
     for (int mt = 0; mt < kMfMT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < kMfNT; ++nt) acc[mt][nt] = mf_float4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t = 0; t < kMfT; ++t) {
-        mf_half8 bh[kMfNT], bl[kMfNT];
+#pragma unroll 1
+    for (int p = 3; p >= 0; --p) {
+        if (p < 3) {
 #pragma unroll
-        for (int nt = 0; nt < kMfNT; ++nt) {
-            float v[8];
-            v[0] = cr[nt];
-            v[1] = ci[nt];
-            v[2] = u1[nt] * cr[nt];
-            v[3] = u1[nt] * ci[nt];
-            v[4] = u2[nt] * cr[nt];
-            v[5] = u2[nt] * ci[nt];
-            v[6] = u3[nt] * cr[nt];
-            v[7] = u3[nt] * ci[nt];
-            split8(v, bh[nt], bl[nt]);
-            float nr, ni;
-            cmulf(cr[nt], ci[nt], sr[nt], si[nt], &nr, &ni);
-            cr[nt] = nr;
-            ci[nt] = ni;
+            for (int mt = 0; mt < kMfMT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < kMfNT; ++nt) acc[mt][nt] = acc[mt][nt] * uu[nt];
         }
+        // operand fragments of power p, (mt, sign, t) in order, each read one
+        // fragment ahead of its products
+        const float4 *fp = lds + (size_t)p * kMfMT * 2 * kMfT * 2 * 64 + lane;
+        constexpr int NF = kMfMT * 2 * kMfT;
+        float4 ch = fp[0], cl = fp[64];
 #pragma unroll
-        for (int mt = 0; mt < kMfMT; ++mt) {
-            const float4 *fa = lds + (((mt * kMfT + t) * 2) * 64 + lane);
-            const float4 a0 = fa[0], a1 = fa[64];
-            const mf_half8 ah = __builtin_bit_cast(mf_half8, a0);
-            const mf_half8 al = __builtin_bit_cast(mf_half8, a1);
+        for (int k = 0; k < NF; ++k) {
+            const int t = k % kMfT, mt = k / (2 * kMfT);
+            float4 nh = ch, nl = cl;
+            if (k + 1 < NF) {
+                nh = fp[((k + 1) * 2) * 64];
+                nl = fp[((k + 1) * 2 + 1) * 64];
+            }
+            // keep the next fragment's reads ahead of this fragment's products
+            __builtin_amdgcn_sched_barrier(0);
+            const mf_half8 ah = __builtin_bit_cast(mf_half8, ch);
+            const mf_half8 al = __builtin_bit_cast(mf_half8, cl);
 #pragma unroll
             for (int nt = 0; nt < kMfNT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[nt], acc[mt][nt],
-                                                                     0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[nt][t],
+                                                                     acc[mt][nt], 0, 0, 0);
 #pragma unroll
             for (int nt = 0; nt < kMfNT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[nt], acc[mt][nt],
-                                                                     0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[nt][t],
+                                                                     acc[mt][nt], 0, 0, 0);
 #pragma unroll
             for (int nt = 0; nt < kMfNT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[nt], acc[mt][nt],
-                                                                     0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[nt][t],
+                                                                     acc[mt][nt], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            ch = nh;
+            cl = nl;
         }
     }
-    // rows -> h: this lane holds rows 8 mt + 2 g and + 1 of its sample
+    // Rows -> h.  Row r's harmonic is z_r = e^{-i m_r Phi_phi}.
+    // With consecutive m values (m_r = m_0 + r) it is z_0 E^r, E = e^{-i Phi_phi}:
+    // the sample's lane forms z_0 and E^2, E^4, E^6, E^8, and group g starts
+    // from z_0 E^{2g}.  Otherwise every row takes its own sincos.
+    float z0r[OWN], z0i[OWN], e2r[OWN], e2i[OWN], e4r[OWN], e4i[OWN], e6r[OWN], e6i[OWN];
+    float e8r[OWN], e8i[OWN];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        z0r[k] = z0i[k] = e2r[k] = e2i[k] = e4r[k] = e4i[k] = 0.0f;
+        e6r[k] = e6i[k] = e8r[k] = e8i[k] = 0.0f;
+        if (consec) {
+            unit_phasor<float>(d_reduce_2pi((double)mm[0] * pf[k]), &z0r[k], &z0i[k]);
+            cmulf(er[k], ei[k], er[k], ei[k], &e2r[k], &e2i[k]);
+            cmulf(e2r[k], e2i[k], e2r[k], e2i[k], &e4r[k], &e4i[k]);
+            cmulf(e4r[k], e4i[k], e2r[k], e2i[k], &e6r[k], &e6i[k]);
+            cmulf(e4r[k], e4i[k], e4r[k], e4i[k], &e8r[k], &e8i[k]);
+        }
+    }
     double dh = 0.0, hh = 0.0;
 #pragma unroll
     for (int nt = 0; nt < kMfNT; ++nt) {
-        const long long jr = base + (long long)(w * kMfNT + nt) * 16 + col;
-        const long long j = jr < e ? jr : e - 1;
-        const double tj = dev_sample_time(jb.t_start, jb.dt, j);
-        const dd x = two_sum(tj, -ti);
-        const double pf = phase_eval<false>(pc, x);
-        const double pr = phase_eval<false>(pc + 8, x);
-        float er, ei;
-        unit_phasor<float>(pf, &er, &ei);
+        const int src = (16 * nt + col) % kWave, k = (16 * nt) / kWave;
+        const float Er = lane_get(er[k], src), Ei = lane_get(ei[k], src);
         float hr = 0.0f, hq = 0.0f;
-#pragma unroll
-        for (int mt = 0; mt < kMfMT; ++mt) {
+        // h += (z 2^E) (a + i b) for the lane's two rows of tile mt
+        auto add_rows = [&](int mt, float zr, float zi, float yr, float yi) {
             const int r0 = 8 * mt + 2 * g;
-            const int m0 = mm[r0], m1 = mm[r0 + 1];
-            float zr, zi;
-            unit_phasor<float>(d_reduce_2pi((double)m0 * pf + (double)jb.n_min * pr), &zr, &zi);
             const float s0 = msc[r0], s1 = msc[r0 + 1];
-            const float a0 = acc[mt][nt][0] * s0, b0 = acc[mt][nt][1] * s0;
-            hr = hr + (zr * a0 - zi * b0);
-            hq = hq + (zr * b0 + zi * a0);
-            float yr, yi;
-            if (m1 == m0 + 1)
-                cmulf(zr, zi, er, ei, &yr, &yi);
-            else
-                unit_phasor<float>(d_reduce_2pi((double)m1 * pf + (double)jb.n_min * pr), &yr,
-                                   &yi);
-            const float a1 = acc[mt][nt][2] * s1, b1 = acc[mt][nt][3] * s1;
-            hr = hr + (yr * a1 - yi * b1);
-            hq = hq + (yr * b1 + yi * a1);
+            const float zsr = zr * s0, zsi = zi * s0, ysr = yr * s1, ysi = yi * s1;
+            const float a0 = acc[mt][nt][0], b0 = acc[mt][nt][1];
+            const float a1 = acc[mt][nt][2], b1 = acc[mt][nt][3];
+            hr = __builtin_fmaf(zsr, a0, __builtin_fmaf(-zsi, b0, hr));
+            hq = __builtin_fmaf(zsr, b0, __builtin_fmaf(zsi, a0, hq));
+            hr = __builtin_fmaf(ysr, a1, __builtin_fmaf(-ysi, b1, hr));
+            hq = __builtin_fmaf(ysr, b1, __builtin_fmaf(ysi, a1, hq));
+        };
+        if (consec) {
+            const float q0r = lane_get(z0r[k], src), q0i = lane_get(z0i[k], src);
+            const float q2r = lane_get(e2r[k], src), q2i = lane_get(e2i[k], src);
+            const float q4r = lane_get(e4r[k], src), q4i = lane_get(e4i[k], src);
+            const float q6r = lane_get(e6r[k], src), q6i = lane_get(e6i[k], src);
+            const float q8r = lane_get(e8r[k], src), q8i = lane_get(e8i[k], src);
+            const float gr = g == 0 ? 1.0f : g == 1 ? q2r : g == 2 ? q4r : q6r;
+            const float gi = g == 0 ? 0.0f : g == 1 ? q2i : g == 2 ? q4i : q6i;
+            float zr, zi;
+            cmulf(q0r, q0i, gr, gi, &zr, &zi);          // z_{2g}
+#pragma unroll
+            for (int mt = 0; mt < kMfMT; ++mt) {
+                float yr, yi;
+                cmulf(zr, zi, Er, Ei, &yr, &yi);        // z_{8 mt + 2g + 1}
+                add_rows(mt, zr, zi, yr, yi);
+                if (mt + 1 < kMfMT) {
+                    float nr, ni;
+                    cmulf(zr, zi, q8r, q8i, &nr, &ni);  // z_{8 (mt + 1) + 2g}
+                    zr = nr;
+                    zi = ni;
+                }
+            }
+        } else {
+            const double spf = __shfl(pf[k], src);
+#pragma unroll
+            for (int mt = 0; mt < kMfMT; ++mt) {
+                const int r0 = 8 * mt + 2 * g;
+                const int m0 = mm[r0], m1 = mm[r0 + 1];
+                float zr, zi, yr, yi;
+                unit_phasor<float>(d_reduce_2pi((double)m0 * spf), &zr, &zi);
+                if (m1 == m0 + 1)
+                    cmulf(zr, zi, Er, Ei, &yr, &yi);
+                else
+                    unit_phasor<float>(d_reduce_2pi((double)m1 * spf), &yr, &yi);
+                add_rows(mt, zr, zi, yr, yi);
+            }
         }
         // the four lane groups hold the other rows of the same sample
         hr = hr + __shfl_xor(hr, 16);
         hq = hq + __shfl_xor(hq, 16);
         hr = hr + __shfl_xor(hr, 32);
         hq = hq + __shfl_xor(hq, 32);
+        const long long jr = wbase + 16 * nt + col;
         if (g == 0 && jr < e) {
             if constexpr (INNER) {
                 const float *d = (const float *)jb.data + 2 * jr;
@@ -1587,6 +1687,12 @@ __device__ double2 mf_range(const SumJob &jb, long long lo, long long hi, float4
         const FEW_AS4 int2 *mr = cptr(jb.mrows);
         mm[r] = r < jb.n_mrows ? mr[r].x : mr[jb.n_mrows - 1].x + (r - jb.n_mrows + 1);
     }
+    // consecutive signed m values (padding rows continue the run)
+    bool consec = true;
+    {
+        const FEW_AS4 int2 *mr = cptr(jb.mrows);
+        for (int r = 1; r < jb.n_mrows; ++r) consec = consec && mr[r].x == mr[r - 1].x + 1;
+    }
     const FEW_AS4 long long *st = cptr(jb.starts);
     int iv = 0, top = jb.K - 2;
     while (iv < top) {
@@ -1605,7 +1711,7 @@ __device__ double2 mf_range(const SumJob &jb, long long lo, long long hi, float4
             msc[threadIdx.x] = jb.mscale[(size_t)iv * kMfRows + threadIdx.x];
         __syncthreads();
         for (long long base = lo; base < e; base += kMfRound) {
-            const double2 v = mf_round<INNER>(jb, iv, base, e, lds, msc, mm);
+            const double2 v = mf_round<INNER>(jb, iv, base, e, lds, msc, mm, consec);
             acc.x = acc.x + v.x;
             acc.y = acc.y + v.y;
         }
@@ -1624,7 +1730,7 @@ __device__ __forceinline__ void mf_share(long long total, long long *lo, long lo
 }
 
 template <bool INNER>
-__global__ __launch_bounds__(512) void sum_mfma_kernel(SumJob jb) {
+__global__ __launch_bounds__(64 * kMfWaves) void sum_mfma_kernel(SumJob jb) {
     extern __shared__ float4 mf_lds[];
     __shared__ float msc[kMfRows];
     __shared__ int mm[kMfRows];
@@ -1649,7 +1755,7 @@ __global__ __launch_bounds__(512) void sum_mfma_kernel(SumJob jb) {
 
 // Batched launch: the jobs' samples laid end to end (job j from sample_base_j),
 // split into equal shares.
-__global__ __launch_bounds__(512) void sum_mfma_batch_kernel(const SumJob *jobs, int n_jobs,
+__global__ __launch_bounds__(64 * kMfWaves) void sum_mfma_batch_kernel(const SumJob *jobs, int n_jobs,
                                                              long long total) {
     extern __shared__ float4 mf_lds[];
     __shared__ float msc[kMfRows];
