@@ -35,6 +35,7 @@ if ROOT not in sys.path:
 # Published MI355X peaks used for the roofline (TFLOP/s, TB/s).
 PEAK_FP32_VALU = 157.3
 PEAK_FP64_VALU = 78.6
+PEAK_FP16_MFMA = 2500.0   # dense
 PEAK_HBM_TBS = 8.0
 
 
@@ -51,6 +52,44 @@ def algorithmic_flops(n_terms: int, n_segs: int, n: int) -> float:
     (6 flop) and the accumulation (2 flop): 8 flop.
     """
     return float(n) * (20.0 * n_terms + 8.0 * n_segs)
+
+
+def mfma_algorithmic_flops(n_terms: int, n_rows: int, n: int) -> float:
+    """Flops of the matrix-core contraction per launch, counted once: per
+    folded (m, n) term, power p of u and sample one complex multiply-add of the
+    coefficient with u^p f^n (4 x 8 flop), and per signed m row and sample the
+    complex multiply-add with e^{-i m Phi_phi} (8 flop).  The hi/lo split
+    executes each product three times on the matrix cores; that is not
+    counted here."""
+    return float(n) * (32.0 * n_terms + 8.0 * n_rows)
+
+
+def path_flops(native, lmn, n: int, precision: str) -> float:
+    """Algorithmic flops of the summation path a request takes."""
+    segs, tp, _ = native.host_terms(lmn)
+    n_terms = tp.shape[0] - 1
+    if precision == "mixed" and native.host_mfma_path(lmn):
+        return mfma_algorithmic_flops(n_terms, len(set(int(x) for x in segs[:, 0])), n)
+    return algorithmic_flops(n_terms, segs.shape[0], n)
+
+
+def mfma_instructions(native, w, n_wg: int) -> int:
+    """MFMA instructions of one matrix-core launch of request w: every
+    workgroup takes an equal contiguous share of the samples and runs whole
+    rounds (waves x tiles x 16 samples) inside each knot interval."""
+    sh = native.host_mfma_shape()
+    per_round = sh["waves"] * sh["tiles_per_wave"] * 16
+    starts = [int(x) for x in native.host_interval_starts(w.t_knots, w.t_start, w.dt,
+                                                          w.n_samples)]
+    n = w.n_samples
+    rounds = 0
+    for r in range(n_wg):
+        lo, hi = n * r // n_wg, n * (r + 1) // n_wg
+        for i in range(len(starts) - 1):
+            a, e = max(lo, starts[i]), min(hi, starts[i + 1])
+            if e > a:
+                rounds += (e - a + per_round - 1) // per_round
+    return rounds * sh["waves"] * sh["tiles_per_wave"] * sh["mfma_per_tile"]
 
 
 def time_path(native, plan, w, dev, steps: int, warmup: int, settle_s: float = 0.0):
@@ -204,10 +243,7 @@ def batch_run(native, precision: str, dev, n: int, budget: int, reps: int = 3):
                          theta=w.theta, phi=w.phi, dt=w.dt, n_samples=w.n_samples,
                          out=torch.empty(w.n_samples, dtype=dtype, device=dev)))
     ms = sum(w.mode_samples for w in ws)
-    flops = 0.0
-    for w in ws:
-        segs, _, _ = native.host_terms(w.lmn)
-        flops += algorithmic_flops(int(segs[:, 2].sum()), segs.shape[0], w.n_samples)
+    flops = sum(path_flops(native, w.lmn, w.n_samples, precision) for w in ws)
     best = None
     with native.Plan(0, precision, hbm_budget_bytes=budget) as plan:
         plan.batch(reqs)
@@ -489,24 +525,37 @@ def main() -> int:
     w = synth.config1()
     segs, tp, _ = native.host_terms(w.lmn)
     n_terms, n_segs = tp.shape[0] - 1, segs.shape[0]
-    flops = algorithmic_flops(n_terms, n_segs, w.n_samples)
+    n_rows = len(set(int(x) for x in segs[:, 0]))
+    mfma = native.host_mfma_path(w.lmn)
+    flops_vec = algorithmic_flops(n_terms, n_segs, w.n_samples)
+    flops_mf = mfma_algorithmic_flops(n_terms, n_rows, w.n_samples)
     canonical = 32.0 * w.M * w.n_samples
-    log(f"[bench] workload K={w.K} M={w.M} N={w.n_samples} terms={n_terms} segs={n_segs}")
+    n_wg = torch.cuda.get_device_properties(0).multi_processor_count
+    mf_instr = mfma_instructions(native, w, n_wg) if mfma else 0
+    log(f"[bench] workload K={w.K} M={w.M} N={w.n_samples} terms={n_terms} segs={n_segs} "
+        f"matrix-core path={mfma} ({mf_instr} MFMA instructions per launch on {n_wg} CUs)")
 
     res = {}
     outs = {}
-    for prec in ("mixed", "fp64"):
+    # "mixed" is the headline (matrix-core summation for this mode list);
+    # "mixed_vector" the same precision on the vector units only
+    for prec in ("mixed", "fp64", "mixed_vector"):
+        pp = "mixed" if prec == "mixed_vector" else prec
+        vec = prec == "mixed_vector"
         log(f"[bench] {prec}: warmup {args.warmup} (and >= 0.2 s), steps {args.steps}")
         # Timed region: HIP events around the summation launches only (an event
         # pair delays the launch after it; the other stages stay back to back).
-        with native.Plan(0, prec, timing="sum") as plan:
+        with native.Plan(0, pp, timing="sum", vector_only=vec) as plan:
             sec, tm, out, step = time_path(native, plan, w, dev, args.steps, args.warmup, 0.2)
             spread = step_spread(step, args.steps)
-            outs[prec] = out
+            if not vec:
+                outs[prec] = out
+            del out
         # Stage breakdown: the same steps with events around every launch.
-        with native.Plan(0, prec, timing=True) as plan:
+        with native.Plan(0, pp, timing=True, vector_only=vec) as plan:
             _, tms, _, _ = time_path(native, plan, w, dev, 5, 2)
         sum_ms = tm["sum_ms"] / max(tm["sum_launches"], 1)
+        flops = flops_mf if (prec == "mixed" and mfma) else flops_vec
         res[prec] = {
             "ms_per_step": sec * 1e3,
             "value": w.mode_samples / sec,
@@ -597,17 +646,40 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16/f32" if mfma else "f32",
         "data": "synthetic",
         "config": {"workload": "interpolated mode sum, 3843 modes (l 2..10, m 0..l, n -30..30), "
                                "100 knots, 1 yr at dt 10 s (3,155,760 samples), mixed precision",
                    "modes": w.M, "knots": w.K, "samples": w.n_samples,
-                   "folded_terms": n_terms, "segments": n_segs},
-        "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VALU,
-                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU,
-                     "traffic": measured_traffic(),
-                     "kernel": "sum_wg_kernel<float>",
-                     "flop_per_launch": flops, "launch_ms": m["sum_ms"]},
+                   "folded_terms": n_terms, "segments": n_segs,
+                   "summation": "matrix cores: fp16 hi/lo operands, fp32 accumulation" if mfma
+                   else "vector units: binary32, Kahan-compensated"},
+        "roofline": ({"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_MFMA,
+                      "unit": "TFLOP/s", "frac": ach / PEAK_FP16_MFMA,
+                      "traffic": measured_traffic(),
+                      "kernel": "sum_mfma_kernel<false>",
+                      "flop_per_launch": flops_mf,
+                      "flop_count": "folded contraction counted once: 32 flop per folded "
+                                    "term and sample + 8 per signed-m row and sample",
+                      "launch_ms": m["sum_ms"],
+                      "executed_mfma_instructions": mf_instr,
+                      "executed_mfma_tflops": mf_instr * 16384.0 / (m["sum_ms"] * 1e-3) / 1e12,
+                      "executed_mfma_frac": mf_instr * 16384.0 / (m["sum_ms"] * 1e-3) / 1e12
+                      / PEAK_FP16_MFMA,
+                      "canonical_32flop_frac": m["canonical_tflops"] / PEAK_FP16_MFMA}
+                     if mfma else
+                     {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VALU,
+                      "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU,
+                      "traffic": measured_traffic(),
+                      "kernel": "sum_wg_kernel<float>",
+                      "flop_per_launch": flops_vec, "launch_ms": m["sum_ms"]}),
+        "mixed_vector": {"value": res["mixed_vector"]["value"],
+                         "ms_per_step": res["mixed_vector"]["ms_per_step"],
+                         "sum_ms": res["mixed_vector"]["sum_ms"],
+                         "sum_tflops": res["mixed_vector"]["sum_tflops"],
+                         "frac_fp32_peak": res["mixed_vector"]["sum_tflops"] / PEAK_FP32_VALU,
+                         "note": "the same precision with FEW_FLAG_VECTOR_ONLY: binary32 "
+                                 "vector-unit summation with Kahan-compensated accumulation"},
         "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
                  "sum_ms": res["fp64"]["sum_ms"], "sum_tflops": res["fp64"]["sum_tflops"],
                  "step_ms": {"median": res["fp64"]["step_spread"]["median_ms"],

@@ -370,6 +370,22 @@ int32_t few_host_frame(double theta_S, double phi_S, double theta_K, double phi_
 uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t M,
                                 int32_t n_terms);
 
+/*
+ * Matrix-core summation of FEW_MIXED plans (a contraction of the folded
+ * coefficients of Eq. (10) with powers of e^{-i Phi_r}, Sec. III C, on fp16
+ * hi/lo operands with fp32 accumulation).  few_host_mfma_path returns 1 if a
+ * binary32 request with this (l, m, n) mode list is summed on the matrix
+ * cores (unless the plan sets FEW_FLAG_VECTOR_ONLY), 0 if on the vector
+ * units, or a negative few_status for an invalid list.  few_host_mfma_shape
+ * writes the launch shape: out8 = (waves per workgroup, 16-sample tiles per
+ * wave, 16-row tiles, 32-column steps per sign of n, MFMA instructions per
+ * tile and round, largest |n| + 1, largest number of signed m values,
+ * smallest number of folded terms).  Each workgroup takes an equal contiguous
+ * share of the samples, one per compute unit.
+ */
+int32_t few_host_mfma_path(int32_t M, const int32_t *lmn);
+void few_host_mfma_shape(int32_t *out8);
+
 #ifdef __cplusplus
 }
 #endif

@@ -361,3 +361,24 @@ extern "C" uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t
                                  3, mf, mf ? kMfRows : 0);
     return (uint64_t)L.total;
 }
+
+extern "C" int32_t few_host_mfma_path(int32_t M, const int32_t *lmn) {
+    TermLayout L;
+    const int rc = build_term_layout(M, lmn, 3, kMaxGap, &L);
+    if (rc) return rc;
+    const int ok = L.mfma ? 1 : 0;
+    free_term_layout(&L);
+    return ok;
+}
+
+extern "C" void few_host_mfma_shape(int32_t *out8) {
+    if (!out8) return;
+    out8[0] = kMfWaves;
+    out8[1] = kMfNT;
+    out8[2] = kMfMT;
+    out8[3] = kMfT;
+    out8[4] = 4 * kMfMT * 2 * kMfT * 3;
+    out8[5] = kMfA;
+    out8[6] = kMfRows;
+    out8[7] = kMfMinTerms;
+}

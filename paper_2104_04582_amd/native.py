@@ -39,7 +39,8 @@ EXPORTED = [
     "few_plan_timing", "few_last_error", "few_host_terms", "few_host_interval_starts",
     "few_spline_fit_kerr", "few_host_terms_kerr", "few_inner_product", "few_mode_sum_ssb",
     "few_host_frame",
-    "few_host_request_bytes", "few_inner_product_noalloc",
+    "few_host_request_bytes", "few_inner_product_noalloc", "few_host_mfma_path",
+    "few_host_mfma_shape",
 ]
 
 
@@ -116,6 +117,8 @@ def load() -> ctypes.CDLL:
                                         vp, P(i32)]
     lib.few_host_interval_starts.argtypes = [i32, vp, dbl, dbl, i64, vp]
     lib.few_host_request_bytes.argtypes = [i32, i32, i32, i32]
+    lib.few_host_mfma_path.argtypes = [i32, vp]
+    lib.few_host_mfma_shape.argtypes = [vp]
     lib.few_host_request_bytes.restype = ctypes.c_uint64
     for name in EXPORTED:
         f = getattr(lib, name)
@@ -123,6 +126,7 @@ def load() -> ctypes.CDLL:
             f.restype = ctypes.c_int32
     lib.few_last_error.restype = ctypes.c_char_p
     lib.few_host_request_bytes.restype = ctypes.c_uint64
+    lib.few_host_mfma_shape.restype = None
     _lib = lib
     return lib
 
@@ -393,3 +397,19 @@ def host_interval_starts(t_knots, t_start: float, dt: float, n: int) -> np.ndarr
 def host_request_bytes(precision: str, K: int, M: int, n_terms: int) -> int:
     return int(load().few_host_request_bytes(FEW_MIXED if precision == "mixed" else FEW_FP64,
                                              K, M, n_terms))
+
+
+def host_mfma_path(lmn) -> bool:
+    """few_host_mfma_path: whether a binary32 request with this (l, m, n) list
+    is summed on the matrix cores."""
+    lm = _host_i32(lmn).reshape(-1, 3)
+    return bool(_check(load().few_host_mfma_path(lm.shape[0], lm.ctypes.data)))
+
+
+def host_mfma_shape() -> dict:
+    """few_host_mfma_shape: launch shape of the matrix-core summation."""
+    out = np.zeros(8, dtype=np.int32)
+    load().few_host_mfma_shape(out.ctypes.data)
+    keys = ("waves", "tiles_per_wave", "row_tiles", "column_steps", "mfma_per_tile",
+            "abs_n_limit", "max_rows", "min_terms")
+    return dict(zip(keys, (int(v) for v in out)))

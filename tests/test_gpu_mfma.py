@@ -1,8 +1,8 @@
 """GPU parity of the matrix-core summation (mixed precision).
 
 Binary32 requests whose folded layout fits the matrix-core shape (at most 24
-signed m values, an n range of at most 64, at least 480 folded terms) are
-summed on the MFMA units with fp16 hi/lo operands and fp32 accumulation.
+signed m values, |n| <= 31, at least 480 folded terms) are summed on the
+MFMA units with fp16 hi/lo operands and fp32 accumulation.
 Every case here takes that path (checked through the term layout) and is
 compared with the oracle (mismatch <= 1e-6, max relative error <= 1e-5) and
 with the vector-only path of the same plan type (FEW_FLAG_VECTOR_ONLY).
@@ -33,11 +33,7 @@ def env():
 
 
 def takes_mfma_path(native, lmn):
-    segs, tp, _ = native.host_terms(lmn)
-    ms = sorted(set(int(m) for m in segs[:, 0]))
-    n_lo = int(segs[:, 1].min())
-    n_hi = int((segs[:, 1] + segs[:, 2] - 1).max())
-    return len(ms) <= 24 and n_hi - n_lo + 1 <= 64 and tp.shape[0] - 1 >= 480
+    return native.host_mfma_path(lmn)
 
 
 def run(native, torch, dev, w, vector_only=False):

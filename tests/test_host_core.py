@@ -233,3 +233,21 @@ def test_host_frame_errors_and_degenerate():
     assert e.value.code == native.FEW_E_ARG
     th, ph, rot = native.host_frame(0.4, 1.0, 0.4, 1.0)        # R = S
     assert abs(th - np.pi) < 1e-7 and rot == -1.0
+
+
+def test_mfma_path_and_shape():
+    """Which binary32 requests take the matrix-core summation: at most 24
+    signed m values, |n| < 32 and at least 480 folded terms (Schwarzschild
+    lists only)."""
+    shape = native.host_mfma_shape()
+    assert shape["max_rows"] == 24 and shape["abs_n_limit"] == 32
+    assert shape["min_terms"] == 480
+    assert shape["mfma_per_tile"] == 4 * shape["row_tiles"] * 2 * shape["column_steps"] * 3
+    full = synth.mode_list(2, 10, 30)                 # 21 signed m, |n| <= 30, 1281 terms
+    assert native.host_mfma_path(full)
+    assert not native.host_mfma_path(synth.mode_list(2, 4, 5))        # 99 terms
+    assert native.host_mfma_path(synth.mode_list(2, 10, 31))          # |n| = 31
+    assert not native.host_mfma_path(synth.mode_list(2, 10, 32))      # |n| = 32
+    assert not native.host_mfma_path(synth.mode_list(2, 12, 20))      # 25 signed m
+    with pytest.raises(native.FewError):
+        native.host_mfma_path(np.array([[1, 0, 0]], dtype=np.int32))
