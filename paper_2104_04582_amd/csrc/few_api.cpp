@@ -295,6 +295,7 @@ class LayoutCache {
         b->n_mrows = a.n_mrows;
         b->n_min = a.n_min;
         b->n_max = a.n_max;
+        b->l_max = a.l_max;
         b->mfma = a.mfma;
         b->mrows = (int *)std::malloc(sizeof(int) * 2 * (size_t)(a.n_mrows + 1));
         b->segs = (int *)std::malloc(sizeof(int) * 4 * (size_t)a.n_segs);
@@ -423,6 +424,7 @@ PrepJob prep_job(const HostReq &r, ReqBase base, double theta, double phi, doubl
     j.n_mrows = r.terms.n_mrows;
     j.n_min = r.terms.n_min;
     j.n_segs = r.terms.n_segs;
+    j.l_max = r.terms.l_max;
     return j;
 }
 
@@ -944,11 +946,9 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
         const bool mf = s->h.mfma;
         const long long need =
             !inner ? 0 : mf ? (long long)p->mf_wg : inner_slots(tl.parts, (int)slots, p->fp32);
-        // matrix-core requests fold in binary64, then pack the fp16 operand table
+        // matrix-core requests fold straight into the fp16 operand table
         auto prep = [&]() -> hipError_t {
-            hipError_t e = launch_prepare(pj, p->fp32 && !mf, p->stream);
-            if (e == hipSuccess && mf) e = launch_pack(pj, p->stream);
-            return e;
+            return mf ? launch_fold_pack(pj, p->stream) : launch_prepare(pj, p->fp32, p->stream);
         };
         auto sum = [&]() -> hipError_t {
             if (mf)
@@ -1280,8 +1280,7 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         HIP_TRY(pinned_upload(dev, host, upload_end, s));
         HIP_TRY(launch_fit(f, s));
         if (r->h.mfma) {
-            HIP_TRY(launch_prepare(q, false, s));
-            HIP_TRY(launch_pack(q, s));
+            HIP_TRY(launch_fold_pack(q, s));
             HIP_TRY(launch_sum_mfma(u, p->mf_wg, s));
         } else {
             HIP_TRY(launch_prepare(q, fp32, s));
@@ -1295,7 +1294,7 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
     // matrix-core ones (each set has its own launches)
     int nv = 0;
     for (ServedReq *r : b->reqs) nv += r->h.mfma ? 0 : 1;
-    int max_amp_blocks = 0, max_K = 4, max_fold_blocks = 0, max_fold_mf = 0, max_K_mf = 4;
+    int max_amp_blocks = 0, max_K = 4, max_fold_blocks = 0, max_K_mf = 4;
     long long waves = 0, mf_total = 0;
     int kv = 0, km = nv;
     for (int i = 0; i < n; ++i) {
@@ -1311,7 +1310,6 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         if (r->h.mfma) {
             sj[k].sample_base = mf_total;
             mf_total += r->r.n_samples;
-            max_fold_mf = std::max(max_fold_mf, pj[k].fold_blocks);
             max_K_mf = std::max(max_K_mf, r->h.K);
         } else {
             sj[k].wave_base = (int)waves;
@@ -1331,8 +1329,7 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         HIP_TRY(launch_sum_batch(sd, nv, (int)waves, fp32, true, counter, s));
     }
     if (nv < n) {
-        HIP_TRY(launch_prepare_batch(pd + nv, n - nv, max_fold_mf, false, s));
-        HIP_TRY(launch_pack_batch(pd + nv, n - nv, max_K_mf, s));
+        HIP_TRY(launch_fold_pack_batch(pd + nv, n - nv, max_K_mf, s));
         HIP_TRY(launch_sum_mfma_batch(sd + nv, n - nv, mf_total, p->mf_wg, s));
     }
     HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));

@@ -24,6 +24,9 @@ constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 // so the series (and their scattered coefficient stores) spread over four
 // times as many compute units as with one series per lane of every wave.
 constexpr int kFitSeriesPerBlock = 64;
+// Grids of at most this many knots stage each workgroup's knot values and
+// forward-sweep results in LDS (2 x 64 x K binary64, 128 KiB at the limit).
+constexpr int kFitStageKnots = 128;
 constexpr int kChunkTerms = FEW_CHUNK_TERMS;   // terms staged in LDS at once (binary32: 32 B each)
 
 // Samples per lane in one wave tile of the summation kernel.
@@ -149,13 +152,14 @@ struct PrepJob {
     int short_tile;         // samples per short tile
     int fold_terms;         // consecutive terms folded by one workgroup
     int fold_blocks;        // term groups of the fold
-    // matrix-core path: the fold writes binary64 into `table`, then the pack
-    // step writes the fp16 operand table and the per-(interval, row) scales
+    // matrix-core path: the fold writes the fp16 operand table and the
+    // per-(interval, row) scales
     const int4 *segs;       // [n_segs]
     const int2 *mrows;      // [n_mrows + 1]: (m, first segment) per row, sentinel (0, n_segs)
     void *mtab;             // [K-1][kMfIntervalHalves] fp16
     float *mscale;          // [K-1][kMfRows]: 2^E with row values scaled by 2^-E
     int n_mrows, n_min, n_segs;
+    int l_max;              // largest listed l
 };
 
 // Summation stage for one request.
@@ -217,13 +221,14 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_wave_s
                             bool fp32, bool persistent, unsigned *counter_dev,
                             hipStream_t stream);
 hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t stream);
-// Matrix-core path: pack the binary64 fold into the fp16 operand table (one
-// request, or n_jobs of them with max_K knots at most), and the summation
-// (every workgroup takes an equal contiguous share of the samples; n_wg
-// workgroups; with INNER each writes its partial sums to job.partial[b] and
-// one more launch adds them into out2 = two_dt * sums).
-hipError_t launch_pack(const PrepJob &job, hipStream_t stream);
-hipError_t launch_pack_batch(const PrepJob *jobs_dev, int n_jobs, int max_K, hipStream_t stream);
+// Matrix-core path: the prepare step (interval starts, fold and the fp16
+// operand table, one request or n_jobs of them with max_K knots at most), and
+// the summation (every workgroup takes an equal contiguous share of the
+// samples; n_wg workgroups; with INNER each writes its partial sums to
+// job.partial[b] and one more launch adds them into out2 = two_dt * sums).
+hipError_t launch_fold_pack(const PrepJob &job, hipStream_t stream);
+hipError_t launch_fold_pack_batch(const PrepJob *jobs_dev, int n_jobs, int max_K,
+                                  hipStream_t stream);
 int mfma_workgroups();
 hipError_t launch_sum_mfma(const SumJob &job, int n_wg, hipStream_t stream);
 hipError_t launch_sum_mfma_inner(const SumJob &job, int n_wg, double two_dt, double *out2,
@@ -246,7 +251,7 @@ struct TermLayout {
     int grp[kTermGroups - 1] = {0, 0, 0};   // first segment of term groups 1..3
     int max_seg_terms = 0;     // longest segment
     // matrix-core path: distinct signed m values (rows) and the n range
-    int n_mrows = 0, n_min = 0, n_max = 0;
+    int n_mrows = 0, n_min = 0, n_max = 0, l_max = 0;
     int *mrows = nullptr;      // 2 * (n_mrows + 1): (m, first segment), sentinel (0, n_segs)
     bool mfma = false;         // layout fits the matrix-core shape (Schwarzschild terms)
 };

@@ -194,6 +194,9 @@ int build_term_layout(int M, const int32_t *modes, int width, int max_gap, TermL
         mr.push_back(0);
         mr.push_back(n_seg);
         out->n_mrows = (int)mr.size() / 2 - 1;
+        int lm = 0;
+        for (int k = 0; k < M; ++k) lm = std::max(lm, (int)modes[(size_t)width * k]);
+        out->l_max = lm;
         out->n_min = n_min;
         out->n_max = n_max;
         out->mfma = width == 3 && n_min > -kMfA && n_max < kMfA && out->n_mrows <= kMfRows &&
@@ -281,10 +284,9 @@ ReqLayout request_layout(bool fp32, int K, int M, int n_segs, int n_terms, int n
     L.dev_begin = L.off_pcoef;
     L.off_acoef = take(sizeof(double) * 8 * (size_t)(K - 1) * M);
     L.off_ybuf = take(sizeof(double) * 2 * (size_t)std::max(n_src, 1));
-    // binary64 fold table for the binary64 and matrix-core paths (the
-    // matrix-core request's binary32 calls that use the vector kernel, the
-    // fused inner product included, fold into the same region as binary32)
-    L.off_table = take((fp32 && !mfma ? 4 : 8) * 8 * (size_t)(K - 1) * n_terms);
+    // fold table of the vector kernels (matrix-core requests fold straight
+    // into the fp16 operand table)
+    L.off_table = take(mfma ? 0 : (fp32 ? 4 : 8) * 8 * (size_t)(K - 1) * n_terms);
     L.off_starts = take(sizeof(long long) * K);
     L.off_tile_pref = take(sizeof(int) * kParts * (size_t)K);
     L.off_mtab = take(mfma ? sizeof(uint16_t) * kMfIntervalHalves * (size_t)(K - 1) : 0);

@@ -141,13 +141,19 @@ __device__ __forceinline__ void fit_factor_serial(const double *h, int K, double
     den[K - 1] = h[K - 3] * q - (h[K - 2] + h[K - 3]) * p;
 }
 
+// Ratios of the factor: inverse pivots invd[r], back-sweep multipliers
+// wv[r] = c_r invd[r] and forward-sweep multipliers bv[r] = b_r invd[r] (b_r
+// the sub-diagonal), so each forward step is one fused multiply-add on the
+// serial chain: g_r = rhs_r invd_r - bv_r g_{r-1}.
 __device__ __forceinline__ void fit_factor_finish(const double *h, int K, double *invd,
-                                                  double *wv) {
+                                                  double *wv, double *bv) {
     for (int r = threadIdx.x; r < K; r += blockDim.x) {
         const double id = invd[r] / wv[r];
         const double c = r == 0 ? h[0] + h[1] : (r < K - 1 ? h[r - 1] : 0.0);
+        const double b = r == 0 ? 0.0 : (r < K - 1 ? h[r] : h[K - 2] + h[K - 3]);
         invd[r] = id;
         wv[r] = c * id;
+        bv[r] = b * id;
     }
 }
 
@@ -167,6 +173,7 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     const int tid = threadIdx.x, bs = blockDim.x;
     double *Hh = lds, *Hl = lds + K, *Dh = lds + 2 * K, *Dl = lds + 3 * K;
     double *wv = lds + 4 * K, *invd = lds + 5 * K, *s0 = lds + 6 * K, *rr = lds + 7 * K;
+    double *bv = lds + 8 * K;
     auto H = [&](int i) { return dd_make(Hh[i], Hl[i]); };
     auto D = [&](int i) { return dd_make(Dh[i], Dl[i]); };
     // row r of the slope system: sub, diag, super (double-double)
@@ -199,39 +206,38 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
                              dd_mul(dd_mul(dd_add(dd_mul_d(sum, 2.0), hb), ha), D(K - 2))),
                       sum);
     };
-    // binary64 sub-diagonal of row r (the factor only needs the rounded matrix;
-    // the refinement step uses the exact rows)
-    auto sub64 = [&](int r) { return (r < K - 1) ? Hh[r] : Hh[K - 2] + Hh[K - 3]; };
-    // binary64 Thomas sweep with the factor in wv / invd: x <- A^-1 x (in place).
-    // The recurrence is carried in registers; the LDS operands of C rows are
-    // loaded together before the rows are eliminated (full batches without
-    // branches, then the remaining rows one by one).
+    // binary64 Thomas sweep with the factor in invd / wv / bv (of the rounded
+    // matrix; the refinement step uses the exact rows): x <- A^-1 x in place.
+    // The recurrence is carried in registers: the LDS operands of C rows are
+    // loaded together, the rows eliminated (one fused multiply-add each on
+    // the serial chain), and the C results stored after the batch.
     auto solve = [&](double *x) {
         constexpr int C = 16;
         double g = x[0] * invd[0];
         x[0] = g;
-        auto fstep = [&](int r, double xr) {
-            g = (xr - sub64(r) * g) * invd[r];
-            return g;
-        };
         int r0 = 1;
         for (; r0 + C <= K; r0 += C) {
-            double xv[C], sv[C], iv[C];
+            double xv[C], bb[C], iv[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 xv[c] = x[r0 + c];
-                sv[c] = sub64(r0 + c);
+                bb[c] = bv[r0 + c];
                 iv[c] = invd[r0 + c];
             }
 #pragma unroll
+            for (int c = 0; c < C; ++c) xv[c] = xv[c] * iv[c];
+#pragma unroll
             for (int c = 0; c < C; ++c) {
-                g = (xv[c] - sv[c] * g) * iv[c];
+                g = fma(-bb[c], g, xv[c]);
                 xv[c] = g;
             }
 #pragma unroll
             for (int c = 0; c < C; ++c) x[r0 + c] = xv[c];
         }
-        for (; r0 < K; ++r0) x[r0] = fstep(r0, x[r0]);
+        for (; r0 < K; ++r0) {
+            g = fma(-bv[r0], g, x[r0] * invd[r0]);
+            x[r0] = g;
+        }
         double nx = x[K - 1];
         r0 = K - 2;
         for (; r0 - C + 1 >= 0; r0 -= C) {
@@ -243,14 +249,14 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
             }
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                xv[c] -= wr[c] * nx;
+                xv[c] = fma(-wr[c], nx, xv[c]);
                 nx = xv[c];
             }
 #pragma unroll
             for (int c = 0; c < C; ++c) x[r0 - c] = xv[c];
         }
         for (; r0 >= 0; --r0) {
-            x[r0] -= wv[r0] * nx;
+            x[r0] = fma(-wv[r0], nx, x[r0]);
             nx = x[r0];
         }
     };
@@ -268,7 +274,7 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     if (tid >= kWave)
         for (int r = tid - kWave; r < K; r += bs - kWave) s0[r] = rhs(r).hi;
     __syncthreads();
-    fit_factor_finish(Hh, K, invd, wv);
+    fit_factor_finish(Hh, K, invd, wv, bv);
     __syncthreads();
     if (tid == 0) solve(s0);
     __syncthreads();
@@ -300,42 +306,83 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
 }
 
 // Binary64 solve of the amplitude series handled by this workgroup, one lane
-// per real series.  LDS: h[K], inverse pivots invd[K], multipliers w[K] and
-// 1 / h[K] of the shared grid (the sweeps multiply by 1 / h_i instead of
-// dividing: a division is a long dependent sequence on this hardware, and the
-// sweeps are latency bound).  Each lane streams its knot values C at a time with the next C
-// loads in flight while the current ones are used (both sweeps), so the
-// global-memory latency is paid about once per sweep rather than per batch.
+// of wave 0 per real series.  LDS: h[K], inverse pivots invd[K], multipliers
+// wv[K] and bv[K] and 1 / h[K] of the shared grid (the sweeps multiply by
+// 1 / h_i instead of dividing: a division is a long dependent sequence on this
+// hardware, and the sweeps are latency bound).  Wave 0 forms the grid and one
+// of its lanes the factor while the other waves fetch knot values.
+// STAGED (K <= kFitStageKnots): those waves copy the workgroup's knot values,
+// [K][64] binary64, into LDS with many loads in flight, and the forward sweep
+// keeps its results in a second [K][64] LDS array, so neither sweep waits on
+// global memory.  Otherwise each lane streams its knot values from global
+// memory and the forward results go through the coefficient array.
+// Both sweeps work in batches of C rows: every operand of the batch is read
+// first, the serial chain (one fused multiply-add per row) runs in registers,
+// and the batch's results are stored after it.
+template <bool STAGED>
 __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     constexpr int C = 16;
     const int K = jb.K, M = jb.M;
     const int tid = threadIdx.x, bs = blockDim.x;
-    double *hs = lds, *invd = lds + K, *wv = lds + 2 * K, *ih = lds + 3 * K;
-    for (int i = tid; i < K - 1; i += bs) {
-        const double h = jb.t[i + 1] - jb.t[i];
-        hs[i] = h;
-        ih[i] = 1.0 / h;
+    double *hs = lds, *invd = lds + K, *wv = lds + 2 * K, *ih = lds + 3 * K, *bv = lds + 4 * K;
+    double *ys = lds + 5 * K;                        // STAGED: [K][64] knot values
+    double *gs = ys + (size_t)K * kFitSeriesPerBlock; // STAGED: [K][64] forward results
+    const int q0 = blk * kFitSeriesPerBlock;
+    const size_t ys_stride = 2 * (size_t)M;          // knot stride of amp
+    if (tid < kWave) {
+        for (int i = tid; i < K - 1; i += kWave) {
+            const double h = jb.t[i + 1] - jb.t[i];
+            hs[i] = h;
+            ih[i] = 1.0 / h;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (tid == 0) fit_factor_serial(hs, K, invd, wv);
+    } else if (STAGED) {
+        constexpr int B = 16;                        // loads in flight per lane
+        const int ns = min(kFitSeriesPerBlock, 2 * M - q0);
+        const int total = K * kFitSeriesPerBlock, nb = bs - kWave;
+        for (int x0 = tid - kWave; x0 < total; x0 += nb * B) {
+            double v[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                const int x = x0 + j * nb;
+                const int i = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
+                v[j] = (x < total && sj < ns) ? jb.amp[(size_t)i * ys_stride + q0 + sj] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                if (x0 + j * nb < total) ys[x0 + j * nb] = v[j];
+        }
     }
     __syncthreads();
-    if (tid == 0) fit_factor_serial(hs, K, invd, wv);
-    __syncthreads();
-    fit_factor_finish(hs, K, invd, wv);
+    fit_factor_finish(hs, K, invd, wv, bv);
     __syncthreads();
     if (tid >= kFitSeriesPerBlock) return;
-    const int q = blk * kFitSeriesPerBlock + tid;
+    const int q = q0 + tid;
     if (q >= 2 * M) return;
     const int k = q >> 1, comp = q & 1;
-    const size_t ys = 2 * (size_t)M;                 // knot stride of amp
     const double *__restrict__ y = jb.amp + 2 * (size_t)k + comp;
     const size_t cs = 8 * (size_t)M;                 // interval stride of acoef
     double *__restrict__ o = jb.acoef + 8 * (size_t)k + comp;   // coefficient p at o[i * cs + 2 p]
+    // knot value idx (clamped to the grid: in bounds, unused past it)
+    auto ldy = [&](int idx) {
+        const int i = min(max(idx, 0), K - 1);
+        return STAGED ? ys[i * kFitSeriesPerBlock + tid] : y[(size_t)i * ys_stride];
+    };
+    auto stg = [&](int r, double gv) {
+        if (STAGED)
+            gs[r * kFitSeriesPerBlock + tid] = gv;
+        else
+            o[(size_t)r * cs + 2] = gv;
+    };
+    auto ldg = [&](int r) {
+        const int i = max(r, 0);
+        return STAGED ? gs[i * kFitSeriesPerBlock + tid] : o[(size_t)i * cs + 2];
+    };
 
     // Forward elimination.  Knot idx gives delta_{idx-1}; rows 0 and 1 close
     // at knot 2, row idx - 1 at every later knot, row K - 1 after the last.
-    // Loads are clamped to the last knot (in bounds, unused past it), so full
-    // batches carry no branches and the next batch stays in flight.
-    auto ldy = [&](int idx) { return y[(size_t)min(max(idx, 0), K - 1) * ys]; };
-    double yprev = y[0];
+    double yprev = ldy(0);
     double dm1, d0, g;
     {
         const double y1 = ldy(1), y2 = ldy(2);
@@ -344,19 +391,46 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
         d0 = (y2 - y1) * ih[1];
         yprev = y2;
         g = ((h0 + 2.0 * (h0 + h1)) * h1 * dm1 + h0 * h0 * d0) / (h0 + h1) * invd[0];
-        o[2] = g;
+        stg(0, g);
         const double rhs = 3.0 * (h1 * dm1 + h0 * d0);
-        g = (rhs - h1 * g) * invd[1];
-        o[cs + 2] = g;
+        g = fma(-bv[1], g, rhs * invd[1]);
+        stg(1, g);
     }
+    // one row: r = idx - 1 closes at knot idx
     auto fwd = [&](int idx, double yi) {
-        dm1 = d0;
-        d0 = (yi - yprev) * ih[idx - 1];
-        yprev = yi;
         const int r = idx - 1;
-        const double rhs = 3.0 * (hs[r] * dm1 + hs[r - 1] * d0);
-        g = (rhs - hs[r] * g) * invd[r];
-        o[(size_t)r * cs + 2] = g;
+        dm1 = d0;
+        d0 = (yi - yprev) * ih[r];
+        yprev = yi;
+        g = fma(-bv[r], g, (3.0 * (hs[r] * dm1 + hs[r - 1] * d0)) * invd[r]);
+        stg(r, g);
+    };
+    // C rows: operands first, then the chain, then the stores
+    auto fwd_batch = [&](int i0, const double *ya) {
+        double hr[C], hm[C], iv[C], bb[C], rv[C];
+        const int rb = i0 - 1;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            hr[c] = hs[rb + c];
+            hm[c] = hs[rb + c - 1];
+            rv[c] = ih[rb + c];
+            iv[c] = invd[rb + c];
+            bb[c] = bv[rb + c];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            dm1 = d0;
+            d0 = (ya[c] - yprev) * rv[c];
+            yprev = ya[c];
+            rv[c] = (3.0 * (hr[c] * dm1 + hm[c] * d0)) * iv[c];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            g = fma(-bb[c], g, rv[c]);
+            rv[c] = g;
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) stg(rb + c, rv[c]);
     };
     double ya[C];
 #pragma unroll
@@ -366,53 +440,70 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
         double yb[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) yb[c] = ldy(i0 + C + c);
-#pragma unroll
-        for (int c = 0; c < C; ++c) fwd(i0 + c, ya[c]);
+        fwd_batch(i0, ya);
 #pragma unroll
         for (int c = 0; c < C; ++c) ya[c] = yb[c];
     }
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-        if (i0 + c < K) fwd(i0 + c, ya[c]);
+    for (int c = 0; i0 + c < K; ++c) fwd(i0 + c, ya[c]);
     {
         const double ha = hs[K - 3], hb = hs[K - 2];
         const double rhs = (hb * hb * dm1 + (2.0 * (ha + hb) + hb) * ha * d0) / (ha + hb);
-        g = (rhs - (hb + ha) * g) * invd[K - 1];
+        g = fma(-bv[K - 1], g, rhs * invd[K - 1]);
     }
-    // Back substitution and coefficients, interval K-2 down to 0.  The loads
-    // of the next batch read rows below the current batch, which it does not
-    // write (clamped to row 0 past the end, and then unused).
+    // Back substitution and coefficients, interval K-2 down to 0, in batches
+    // of C rows r0, r0 - 1, ...: operands first (the batch's forward results
+    // and knot values, and the next batch's in flight), then the chain.
     double s_next = g;
     double yr1 = yprev;                              // y_{K-1}
-    auto ldg = [&](int r) { return o[(size_t)max(r, 0) * cs + 2]; };
-    auto back = [&](int r, double gr, double yv) {
-        const double ir = ih[r];
-        const double dr = (yr1 - yv) * ir;
-        const double sv = gr - wv[r] * s_next;
-        double *orow = o + (size_t)r * cs;
-        orow[0] = yv;
-        orow[2] = sv;
-        orow[4] = (3.0 * dr - 2.0 * sv - s_next) * ir;
-        orow[6] = (sv + s_next - 2.0 * dr) * (ir * ir);
-        s_next = sv;
-        yr1 = yv;
-    };
     double ga[C], yv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         ga[c] = ldg(K - 2 - c);
         yv[c] = ldy(K - 2 - c);
     }
+    auto back = [&](int r, double gr, double yv0) {
+        const double ir = ih[r];
+        const double dr = (yr1 - yv0) * ir;
+        const double sv = fma(-wv[r], s_next, gr);
+        double *orow = o + (size_t)r * cs;
+        orow[0] = yv0;
+        orow[2] = sv;
+        orow[4] = (3.0 * dr - 2.0 * sv - s_next) * ir;
+        orow[6] = (sv + s_next - 2.0 * dr) * (ir * ir);
+        s_next = sv;
+        yr1 = yv0;
+    };
     int r0 = K - 2;
     for (; r0 - C + 1 >= 0; r0 -= C) {
-        double gb[C], yw[C];
+        double gb[C], yw[C], irv[C], wrv[C], sv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             gb[c] = ldg(r0 - C - c);
             yw[c] = ldy(r0 - C - c);
+            irv[c] = ih[r0 - c];
+            wrv[c] = wv[r0 - c];
+        }
+        double sn = s_next;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            sn = fma(-wrv[c], sn, ga[c]);
+            sv[c] = sn;
         }
 #pragma unroll
-        for (int c = 0; c < C; ++c) back(r0 - c, ga[c], yv[c]);
+        for (int c = 0; c < C; ++c) {
+            const int r = r0 - c;
+            const double sh = c == 0 ? s_next : sv[c - 1];    // slope at knot r + 1
+            const double yh = c == 0 ? yr1 : yv[c - 1];       // value at knot r + 1
+            const double ir = irv[c];
+            const double dr = (yh - yv[c]) * ir;
+            double *orow = o + (size_t)r * cs;
+            orow[0] = yv[c];
+            orow[2] = sv[c];
+            orow[4] = (3.0 * dr - 2.0 * sv[c] - sh) * ir;
+            orow[6] = (sv[c] + sh - 2.0 * dr) * (ir * ir);
+        }
+        s_next = sn;
+        yr1 = yv[C - 1];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             ga[c] = gb[c];
@@ -431,7 +522,10 @@ __device__ __forceinline__ void fit_body(const FitJob &jb, double *lds) {
         return;
     }
     if ((int)blockIdx.x - jb.n_ph >= jb.amp_blocks) return;
-    fit_amplitudes(jb, blockIdx.x - jb.n_ph, lds);
+    if (jb.K <= kFitStageKnots)
+        fit_amplitudes<true>(jb, blockIdx.x - jb.n_ph, lds);
+    else
+        fit_amplitudes<false>(jb, blockIdx.x - jb.n_ph, lds);
 }
 
 __global__ __launch_bounds__(256) void fit_kernel(FitJob jb) {
@@ -1327,39 +1421,122 @@ __global__ __launch_bounds__(256) void sum_wg_persistent_kernel(const SumJob *jo
 typedef _Float16 mf_half8 __attribute__((ext_vector_type(8)));
 typedef float mf_float4 __attribute__((ext_vector_type(4)));
 
-// Pack interval iv, row tile mt (rows 8 mt .. 8 mt + 7) of the binary64 fold
-// into the fp16 operand table.  Row r (signed m value m_r) is the pair of
-// matrix rows 2r (real part) and 2r + 1 (imaginary part).  For power p,
-// column (n, c) multiplies Re w (c = 0) or Im w (c = 1), w = f^|n|.  With
-// C = C^p_{m_r, n} (zero where the layout has no term): for n >= 0, C w is
-// (Re C Re w - Im C Im w) + i (Im C Re w + Re C Im w), so row 2r holds
-// (Re C, -Im C) and row 2r + 1 holds (Im C, Re C); for n < 0, C conj(w) is
-// (Re C Re w + Im C Im w) + i (Im C Re w - Re C Im w): (Re C, Im C) and
-// (Im C, -Re C).  Each row is scaled by 2^-E, E the exponent of its largest
-// |value| on the interval (so scaled values stay below 1), and split into
-// hi = fp16(v) and lo = fp16(v - hi), both from binary64.  Table layout, per
-// interval: [p][mt][sign][t][hi, lo][lane 64][8 values], lane l's operand
-// fragment of v_mfma_f32_16x16x32_f16: matrix row l % 16 of the tile, columns
+// Fold and pack for the matrix-core path: workgroup 0 computes the interval
+// starts and tile prefixes; workgroup 1 + iv kMfMT + mt folds interval iv of
+// row tile mt (rows 8 mt .. 8 mt + 7, the signed m values m_r) and writes its
+// fp16 operand table.
+//
+// Fold (Eqs. (9)-(10) for fixed viewing angles, Sec. IV): every term (m_r, n)
+// is C = scale sum_contributors w A, with w = -2Y_{l, m_r} for a listed mode
+// and (-1)^l -2Y_{l, m_r} for the mirror of a listed mode (m_r = -m, the
+// amplitude conjugated), and coefficient p rescaled to u = x / h_i by h_i^p.
+// The weights depend on (l, m_r) only, so the workgroup forms them once per
+// row and l.  The folded values stay in LDS.
+//
+// Pack.  Row r is the pair of matrix rows 2r (real part) and 2r + 1
+// (imaginary part).  For power p, column (n, c) multiplies Re w (c = 0) or
+// Im w (c = 1), w = f^|n|.  For n >= 0, C w is (Re C Re w - Im C Im w) +
+// i (Im C Re w + Re C Im w), so row 2r holds (Re C, -Im C) and row 2r + 1
+// holds (Im C, Re C); for n < 0, C conj(w) is (Re C Re w + Im C Im w) +
+// i (Im C Re w - Re C Im w): (Re C, Im C) and (Im C, -Re C).  Each row is
+// scaled by 2^-E, E the exponent of its largest |value| on the interval (so
+// scaled values stay below 1), and split into hi = fp16(v) and
+// lo = fp16(v - hi), both from binary64.  Table layout, per interval:
+// [p][mt][sign][t][hi, lo][lane 64][8 values], lane l's operand fragment of
+// v_mfma_f32_16x16x32_f16: matrix row l % 16 of the tile, columns
 // |n| = 16 t + 4 (l / 16) + i / 2 and c = i % 2 for value i (sign 0: n = |n|,
 // sign 1: n = -|n|, whose n = 0 column is zero).
-__device__ void pack_body(const PrepJob &jb, int iv, int mt) {
+__device__ void fold_pack_body(const PrepJob &jb, int b) {
+    if (b == 0) {
+        prep_intervals(jb);
+        return;
+    }
+    const int iv = (b - 1) / kMfMT, mt = (b - 1) % kMfMT;
+    if (iv >= jb.K - 1) return;                     // uniform per workgroup (batched grid)
+    constexpr int NL = kMaxL + 1, NN = 2 * kMfA;    // l = 0..30; n + kMfA - 1 in [0, NN - 1)
+    __shared__ double2 yw[8][NL];
+    __shared__ double cf[8][NN][8];
     __shared__ double rsc[8];
+    __shared__ int rowm[9];
     const int tid = threadIdx.x;
-    const double *tab = (const double *)jb.table + (size_t)iv * jb.n_terms * 8;
+    const int r0 = 8 * mt;
+    if (tid < 9) {
+        const int r = r0 + tid;
+        rowm[tid] = r <= jb.n_mrows ? jb.mrows[r].y : jb.mrows[jb.n_mrows].y;   // first segment
+    }
+    for (int x = tid; x < 8 * NL; x += blockDim.x) {
+        const int k = x / NL, l = x % NL, r = r0 + k;
+        double yr = 0.0, yi = 0.0;
+        if (r < jb.n_mrows) {
+            const int m = jb.mrows[r].x;
+            if (l >= 2 && l >= abs(m) && l <= jb.l_max)
+                few_swsh_m2(l, m, jb.theta, jb.phi, &yr, &yi);
+        }
+        yw[k][l] = make_double2(yr, yi);
+    }
+    for (int x = tid; x < 8 * NN * 8; x += blockDim.x) (&cf[0][0][0])[x] = 0.0;
+    __syncthreads();
+    // terms of rows r0 .. r0 + 7 are one contiguous run [t0, t1)
+    const int g0 = rowm[0], g1 = rowm[8];
+    const int t0 = g0 < jb.n_segs ? jb.segs[g0].w : jb.n_terms;
+    const int t1 = g1 < jb.n_segs ? jb.segs[g1].w : jb.n_terms;
+    const double h = jb.t[iv + 1] - jb.t[iv];
+    const double *arow = jb.acoef + (size_t)iv * jb.M * 8;
+    for (int tt = t0 + tid; tt < t1; tt += blockDim.x) {
+        int g = g0;
+        while (g + 1 < g1 && jb.segs[g + 1].w <= tt) ++g;
+        const int4 S = jb.segs[g];
+        int k = 0;
+        while (k + 1 < 8 && rowm[k + 1] <= g) ++k;
+        const int n = S.y + (tt - S.w);
+        double acc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+        auto add = [&](int2 src, const double *a) {
+            const int l = src.y & 255, mir = (src.y >> 16) & 1;
+            double2 w = yw[k][l];
+            if (mir && (l & 1)) w = make_double2(-w.x, -w.y);
+            const double sgn = mir ? -1.0 : 1.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double ar = a[2 * q], ai = sgn * a[2 * q + 1];
+                acc[2 * q] += w.x * ar - w.y * ai;
+                acc[2 * q + 1] += w.x * ai + w.y * ar;
+            }
+        };
+        // four contributors at a time: indices, then their coefficient rows,
+        // all loaded before any is added (in contributor order)
+        const int ea = jb.term_ptr[tt], eb = jb.term_ptr[tt + 1];
+        int e = ea;
+        for (; e + 4 <= eb; e += 4) {
+            int2 src[4];
+            double av[4][8];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) src[j] = jb.term_src[e + j];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) av[j][c] = arow[(size_t)src[j].x * 8 + c];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) add(src[j], av[j]);
+        }
+        for (; e < eb; ++e) add(jb.term_src[e], arow + (size_t)jb.term_src[e].x * 8);
+        double f = jb.scale, fi = jb.scale_im;
+        double *dst = cf[k][n + kMfA - 1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            dst[2 * q] = acc[2 * q] * f - acc[2 * q + 1] * fi;
+            dst[2 * q + 1] = acc[2 * q] * fi + acc[2 * q + 1] * f;
+            f *= h;
+            fi *= h;
+        }
+    }
+    __syncthreads();
     {
         const int k = tid >> 5, sub = tid & 31;     // 8 rows x 32 lanes
-        const int r = 8 * mt + k;
         double mx = 0.0;
-        if (k < 8 && r < jb.n_mrows) {
-            const int g0 = jb.mrows[r].y, g1 = jb.mrows[r + 1].y;
-            for (int g = g0; g < g1; ++g) {
-                const int4 S = jb.segs[g];
-                for (int q = sub; q < S.z; q += 32) {
-                    const double *c = tab + (size_t)(jb.n_terms - 1 - (S.w + q)) * 8;
-                    for (int i = 0; i < 8; ++i) mx = fmax(mx, fabs(c[i]));
-                }
-            }
-        }
+        if (k < 8)
+            for (int x = sub; x < NN * 8; x += 32) mx = fmax(mx, fabs((&cf[k][0][0])[x]));
         for (int off = 16; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 32));
         if (k < 8 && sub == 0) {
             int e = 0;
@@ -1371,7 +1548,7 @@ __device__ void pack_body(const PrepJob &jb, int iv, int mt) {
                 ms = (float)ldexp(1.0, e);
             }
             rsc[k] = sc;
-            jb.mscale[(size_t)iv * kMfRows + r] = ms;
+            jb.mscale[(size_t)iv * kMfRows + r0 + k] = ms;
         }
     }
     __syncthreads();
@@ -1380,7 +1557,6 @@ __device__ void pack_body(const PrepJob &jb, int iv, int mt) {
         const int ln = it & 63, t = (it >> 6) % kMfT, sg = ((it >> 6) / kMfT) & 1;
         const int p = (it >> 6) / (2 * kMfT);
         const int kk = (ln & 15) >> 1, comp = ln & 1, g = ln >> 4;
-        const int rr = 8 * mt + kk;
         const double sc = rsc[kk];
         mf_half8 hi, lo;
 #pragma unroll
@@ -1388,17 +1564,9 @@ __device__ void pack_body(const PrepJob &jb, int iv, int mt) {
             const int a = 16 * t + 4 * g + j;
             const int n = sg == 0 ? a : -a;
             double cr = 0.0, ci = 0.0;
-            if (rr < jb.n_mrows && (sg == 0 || a > 0)) {
-                const int g0 = jb.mrows[rr].y, g1 = jb.mrows[rr + 1].y;
-                for (int q = g0; q < g1; ++q) {
-                    const int4 S = jb.segs[q];
-                    if (n >= S.y && n < S.y + S.z) {
-                        const double *cp =
-                            tab + (size_t)(jb.n_terms - 1 - (S.w + n - S.y)) * 8;
-                        cr = cp[2 * p];
-                        ci = cp[2 * p + 1];
-                    }
-                }
+            if (sg == 0 || a > 0) {
+                cr = cf[kk][n + kMfA - 1][2 * p];
+                ci = cf[kk][n + kMfA - 1][2 * p + 1];
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -1408,9 +1576,11 @@ __device__ void pack_body(const PrepJob &jb, int iv, int mt) {
                 else
                     v = c == 0 ? (comp == 0 ? cr : ci) : (comp == 0 ? ci : -cr);
                 v = v * sc;
-                const _Float16 h = (_Float16)v;
-                hi[2 * j + c] = h;
-                lo[2 * j + c] = (_Float16)(v - (double)h);
+                // through binary32 (one instruction each way; the pair still
+                // carries about 22 bits: lo takes the exact binary64 residual)
+                const _Float16 hv = (_Float16)(float)v;
+                hi[2 * j + c] = hv;
+                lo[2 * j + c] = (_Float16)(float)(v - (double)hv);
             }
         }
         const size_t at =
@@ -1420,15 +1590,17 @@ __device__ void pack_body(const PrepJob &jb, int iv, int mt) {
     }
 }
 
-__global__ __launch_bounds__(256) void pack_kernel(PrepJob jb) {
-    pack_body(jb, blockIdx.x / kMfMT, blockIdx.x % kMfMT);
+// 512 lanes: about one folded term per lane (the fold's dependent loads
+// dominate), two operand items per lane in the pack.
+constexpr int kFoldPackThreads = 512;
+
+__global__ __launch_bounds__(kFoldPackThreads) void fold_pack_kernel(PrepJob jb) {
+    fold_pack_body(jb, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void pack_batch_kernel(const PrepJob *jobs) {
+__global__ __launch_bounds__(kFoldPackThreads) void fold_pack_batch_kernel(const PrepJob *jobs) {
     const PrepJob jb = jobs[blockIdx.y];
-    const int iv = blockIdx.x / kMfMT;
-    if (iv >= jb.K - 1) return;                     // uniform per workgroup
-    pack_body(jb, iv, blockIdx.x % kMfMT);
+    fold_pack_body(jb, blockIdx.x);
 }
 
 // Complex product with one rounding per component (fused multiply-add).
@@ -1974,11 +2146,26 @@ hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t s
 }
 
 static inline size_t fit_lds_bytes(int K) {
-    // phase workgroups: 8 arrays of K; amplitude workgroups: 4 arrays of K
-    return sizeof(double) * 8 * (size_t)K;
+    // phase workgroups: 9 arrays of K; amplitude workgroups: 5 arrays of K,
+    // plus (K <= kFitStageKnots) the staged knot values and forward results
+    size_t n = 9 * (size_t)K;
+    if (K <= kFitStageKnots) n = std::max(n, (5 + 2 * (size_t)kFitSeriesPerBlock) * K);
+    return sizeof(double) * n;
+}
+
+static void fit_lds_attributes() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const int bytes = (int)fit_lds_bytes(kFitStageKnots);
+        hipFuncSetAttribute((const void *)fit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+        hipFuncSetAttribute((const void *)fit_batch_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    });
 }
 
 hipError_t launch_fit(const FitJob &job, hipStream_t stream) {
+    fit_lds_attributes();
     dim3 grid(job.n_ph + job.amp_blocks);
     hipLaunchKernelGGL(fit_kernel, grid, dim3(256), fit_lds_bytes(job.K), stream, job);
     return hipGetLastError();
@@ -1986,8 +2173,12 @@ hipError_t launch_fit(const FitJob &job, hipStream_t stream) {
 
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream) {
+    fit_lds_attributes();
     dim3 grid(kMaxPhases + max_blocks, n_jobs);
-    hipLaunchKernelGGL(fit_batch_kernel, grid, dim3(256), fit_lds_bytes(max_K), stream,
+    // jobs of up to kFitStageKnots knots stage in LDS whatever max_K is
+    const size_t bytes =
+        std::max(fit_lds_bytes(max_K), fit_lds_bytes(std::min(max_K, kFitStageKnots)));
+    hipLaunchKernelGGL(fit_batch_kernel, grid, dim3(256), bytes, stream,
                        jobs_dev);
     return hipGetLastError();
 }
@@ -2151,14 +2342,16 @@ hipError_t launch_sum_inner(const SumJob &job, int slots, bool fp32, double two_
     return hipGetLastError();
 }
 
-hipError_t launch_pack(const PrepJob &job, hipStream_t stream) {
-    hipLaunchKernelGGL(pack_kernel, dim3((job.K - 1) * kMfMT), dim3(256), 0, stream, job);
+hipError_t launch_fold_pack(const PrepJob &job, hipStream_t stream) {
+    hipLaunchKernelGGL(fold_pack_kernel, dim3(1 + (job.K - 1) * kMfMT), dim3(kFoldPackThreads), 0,
+                       stream, job);
     return hipGetLastError();
 }
 
-hipError_t launch_pack_batch(const PrepJob *jobs_dev, int n_jobs, int max_K, hipStream_t stream) {
-    hipLaunchKernelGGL(pack_batch_kernel, dim3((max_K - 1) * kMfMT, n_jobs), dim3(256), 0,
-                       stream, jobs_dev);
+hipError_t launch_fold_pack_batch(const PrepJob *jobs_dev, int n_jobs, int max_K,
+                                  hipStream_t stream) {
+    hipLaunchKernelGGL(fold_pack_batch_kernel, dim3(1 + (max_K - 1) * kMfMT, n_jobs),
+                       dim3(kFoldPackThreads), 0, stream, jobs_dev);
     return hipGetLastError();
 }
 
