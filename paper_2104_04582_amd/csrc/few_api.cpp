@@ -902,9 +902,8 @@ int32_t few_spline_coefs(few_spline s, int32_t which, void *dst) {
     HIP_TRY(hipSetDevice(p->device));
     char *base = p->arena.ptr(s->arena_off);
     if (which == 0) {
-        HIP_TRY(hipMemcpyAsync(dst, base + s->h.L.off_acoef,
-                               sizeof(double) * 8 * (size_t)(s->h.K - 1) * s->h.M,
-                               hipMemcpyDeviceToDevice, p->stream));
+        HIP_TRY(launch_acoef_export((const double *)(base + s->h.L.off_acoef), (double *)dst,
+                                    s->h.K, s->h.M, p->stream));
     } else if (which == 1) {
         HIP_TRY(hipMemcpyAsync(dst, base + s->h.L.off_pcoef,
                                sizeof(double) * 8 * s->h.n_ph * (size_t)(s->h.K - 1),

@@ -124,7 +124,7 @@ struct FitJob {
     const double *phi_theta;  // [K] (generic Kerr) or null
     const double *amp;      // [K][M][2]
     double *pcoef;          // [K-1][n_ph][4][2] double-double phase cubics
-    double *acoef;          // [K-1][M][4][2] amplitude cubics
+    double *acoef;          // [K-1][4][2M] amplitude cubics: coefficient p of series q = 2k + re/im
     int K, M;
     int n_ph;               // phases: Phi_phi, Phi_r (, Phi_theta)
     int amp_blocks;         // blocks covering the 2M amplitude series (after n_ph phase blocks)
@@ -197,6 +197,9 @@ struct SumJob {
 // the two-phase (Schwarzschild) or three-phase (generic Kerr) kernel.
 int sum_resident_workgroups(int n_ph);
 hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t stream);
+// acoef [K-1][4][2M] -> dst [K-1][M][4][2] (the few_spline_coefs layout)
+hipError_t launch_acoef_export(const double *src, double *dst, int K, int M,
+                               hipStream_t stream);
 hipError_t launch_fit(const FitJob &job, hipStream_t stream);
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream);

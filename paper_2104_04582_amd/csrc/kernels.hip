@@ -305,65 +305,23 @@ __device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
     }
 }
 
-// Binary64 solve of the amplitude series handled by this workgroup, one lane
-// of wave 0 per real series.  LDS: h[K], inverse pivots invd[K], multipliers
-// wv[K] and bv[K] and 1 / h[K] of the shared grid (the sweeps multiply by
-// 1 / h_i instead of dividing: a division is a long dependent sequence on this
-// hardware, and the sweeps are latency bound).  Wave 0 forms the grid and one
-// of its lanes the factor while the other waves fetch knot values.
-// STAGED (K <= kFitStageKnots): those waves copy the workgroup's knot values,
-// [K][64] binary64, into LDS with many loads in flight, and the forward sweep
-// keeps its results in a second [K][64] LDS array, so neither sweep waits on
-// global memory.  Otherwise each lane streams its knot values from global
-// memory and the forward results go through the coefficient array.
-// Both sweeps work in batches of C rows: every operand of the batch is read
-// first, the serial chain (one fused multiply-add per row) runs in registers,
-// and the batch's results are stored after it.
+// The two sweeps of one real amplitude series q (lane tid of wave 0).
+// STAGED: knot values from ys, forward results kept in gs and replaced by the
+// slopes in the back sweep (the workgroup forms the coefficients afterwards).
+// Otherwise knot values come from global memory, the forward results go
+// through the coefficient array, and each row's coefficients are stored as
+// its slope is found.
 template <bool STAGED>
-__device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
+__device__ __forceinline__ void fit_sweeps(const FitJob &jb, int tid, int q, int K, int M,
+                                           const double *hs, const double *invd,
+                                           const double *wv, const double *ih,
+                                           const double *bv, const double *ys, double *gs) {
     constexpr int C = 16;
-    const int K = jb.K, M = jb.M;
-    const int tid = threadIdx.x, bs = blockDim.x;
-    double *hs = lds, *invd = lds + K, *wv = lds + 2 * K, *ih = lds + 3 * K, *bv = lds + 4 * K;
-    double *ys = lds + 5 * K;                        // STAGED: [K][64] knot values
-    double *gs = ys + (size_t)K * kFitSeriesPerBlock; // STAGED: [K][64] forward results
-    const int q0 = blk * kFitSeriesPerBlock;
-    const size_t ys_stride = 2 * (size_t)M;          // knot stride of amp
-    if (tid < kWave) {
-        for (int i = tid; i < K - 1; i += kWave) {
-            const double h = jb.t[i + 1] - jb.t[i];
-            hs[i] = h;
-            ih[i] = 1.0 / h;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (tid == 0) fit_factor_serial(hs, K, invd, wv);
-    } else if (STAGED) {
-        constexpr int B = 16;                        // loads in flight per lane
-        const int ns = min(kFitSeriesPerBlock, 2 * M - q0);
-        const int total = K * kFitSeriesPerBlock, nb = bs - kWave;
-        for (int x0 = tid - kWave; x0 < total; x0 += nb * B) {
-            double v[B];
-#pragma unroll
-            for (int j = 0; j < B; ++j) {
-                const int x = x0 + j * nb;
-                const int i = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
-                v[j] = (x < total && sj < ns) ? jb.amp[(size_t)i * ys_stride + q0 + sj] : 0.0;
-            }
-#pragma unroll
-            for (int j = 0; j < B; ++j)
-                if (x0 + j * nb < total) ys[x0 + j * nb] = v[j];
-        }
-    }
-    __syncthreads();
-    fit_factor_finish(hs, K, invd, wv, bv);
-    __syncthreads();
-    if (tid >= kFitSeriesPerBlock) return;
-    const int q = q0 + tid;
-    if (q >= 2 * M) return;
+    const size_t ys_stride = 2 * (size_t)M;
+    const size_t ps = 2 * (size_t)M, cs = 4 * ps;
     const int k = q >> 1, comp = q & 1;
     const double *__restrict__ y = jb.amp + 2 * (size_t)k + comp;
-    const size_t cs = 8 * (size_t)M;                 // interval stride of acoef
-    double *__restrict__ o = jb.acoef + 8 * (size_t)k + comp;   // coefficient p at o[i * cs + 2 p]
+    double *__restrict__ o = jb.acoef + q;
     // knot value idx (clamped to the grid: in bounds, unused past it)
     auto ldy = [&](int idx) {
         const int i = min(max(idx, 0), K - 1);
@@ -373,11 +331,11 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
         if (STAGED)
             gs[r * kFitSeriesPerBlock + tid] = gv;
         else
-            o[(size_t)r * cs + 2] = gv;
+            o[(size_t)r * cs + ps] = gv;
     };
     auto ldg = [&](int r) {
         const int i = max(r, 0);
-        return STAGED ? gs[i * kFitSeriesPerBlock + tid] : o[(size_t)i * cs + 2];
+        return STAGED ? gs[i * kFitSeriesPerBlock + tid] : o[(size_t)i * cs + ps];
     };
 
     // Forward elimination.  Knot idx gives delta_{idx-1}; rows 0 and 1 close
@@ -450,6 +408,32 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
         const double rhs = (hb * hb * dm1 + (2.0 * (ha + hb) + hb) * ha * d0) / (ha + hb);
         g = fma(-bv[K - 1], g, rhs * invd[K - 1]);
     }
+    if (STAGED) {
+        // back substitution: slopes only, s_r = g_r - wv_r s_{r+1}, into gs
+        double sn = g;
+        gs[(K - 1) * kFitSeriesPerBlock + tid] = sn;
+        int r0 = K - 2;
+        for (; r0 - C + 1 >= 0; r0 -= C) {
+            double gv[C], wr[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                gv[c] = gs[(r0 - c) * kFitSeriesPerBlock + tid];
+                wr[c] = wv[r0 - c];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                sn = fma(-wr[c], sn, gv[c]);
+                gv[c] = sn;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) gs[(r0 - c) * kFitSeriesPerBlock + tid] = gv[c];
+        }
+        for (; r0 >= 0; --r0) {
+            sn = fma(-wv[r0], sn, gs[r0 * kFitSeriesPerBlock + tid]);
+            gs[r0 * kFitSeriesPerBlock + tid] = sn;
+        }
+        return;
+    }
     // Back substitution and coefficients, interval K-2 down to 0, in batches
     // of C rows r0, r0 - 1, ...: operands first (the batch's forward results
     // and knot values, and the next batch's in flight), then the chain.
@@ -467,9 +451,9 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
         const double sv = fma(-wv[r], s_next, gr);
         double *orow = o + (size_t)r * cs;
         orow[0] = yv0;
-        orow[2] = sv;
-        orow[4] = (3.0 * dr - 2.0 * sv - s_next) * ir;
-        orow[6] = (sv + s_next - 2.0 * dr) * (ir * ir);
+        orow[ps] = sv;
+        orow[2 * ps] = (3.0 * dr - 2.0 * sv - s_next) * ir;
+        orow[3 * ps] = (sv + s_next - 2.0 * dr) * (ir * ir);
         s_next = sv;
         yr1 = yv0;
     };
@@ -498,9 +482,9 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
             const double dr = (yh - yv[c]) * ir;
             double *orow = o + (size_t)r * cs;
             orow[0] = yv[c];
-            orow[2] = sv[c];
-            orow[4] = (3.0 * dr - 2.0 * sv[c] - sh) * ir;
-            orow[6] = (sv[c] + sh - 2.0 * dr) * (ir * ir);
+            orow[ps] = sv[c];
+            orow[2 * ps] = (3.0 * dr - 2.0 * sv[c] - sh) * ir;
+            orow[3 * ps] = (sv[c] + sh - 2.0 * dr) * (ir * ir);
         }
         s_next = sn;
         yr1 = yv[C - 1];
@@ -513,6 +497,85 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
 #pragma unroll
     for (int c = 0; c < C; ++c)
         if (r0 - c >= 0) back(r0 - c, ga[c], yv[c]);
+}
+
+// Binary64 solve of the amplitude series handled by this workgroup, one lane
+// of wave 0 per real series.  LDS: h[K], inverse pivots invd[K], multipliers
+// wv[K] and bv[K] and 1 / h[K] of the shared grid (the sweeps multiply by
+// 1 / h_i instead of dividing: a division is a long dependent sequence on this
+// hardware, and the sweeps are latency bound).  Wave 0 forms the grid and one
+// of its lanes the factor while the other waves fetch knot values.
+// STAGED (K <= kFitStageKnots): those waves copy the workgroup's knot values,
+// [K][64] binary64, into LDS with many loads in flight, and the forward sweep
+// keeps its results in a second [K][64] LDS array, so neither sweep waits on
+// global memory.  Otherwise each lane streams its knot values from global
+// memory and the forward results go through the coefficient array.
+// Both sweeps work in batches of C rows: every operand of the batch is read
+// first, the serial chain (one fused multiply-add per row) runs in registers,
+// and the batch's results are stored after it.  STAGED, the back sweep finds
+// the slopes only and the whole workgroup then forms the coefficients, each
+// store of a wave covering 64 consecutive series.
+template <bool STAGED>
+__device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
+    const int K = jb.K, M = jb.M;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    double *hs = lds, *invd = lds + K, *wv = lds + 2 * K, *ih = lds + 3 * K, *bv = lds + 4 * K;
+    double *ys = lds + 5 * K;                        // STAGED: [K][64] knot values
+    double *gs = ys + (size_t)K * kFitSeriesPerBlock; // STAGED: [K][64] forward results
+    const int q0 = blk * kFitSeriesPerBlock;
+    const size_t ys_stride = 2 * (size_t)M;          // knot stride of amp
+    if (tid < kWave) {
+        for (int i = tid; i < K - 1; i += kWave) {
+            const double h = jb.t[i + 1] - jb.t[i];
+            hs[i] = h;
+            ih[i] = 1.0 / h;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (tid == 0) fit_factor_serial(hs, K, invd, wv);
+    } else if (STAGED) {
+        constexpr int B = 16;                        // loads in flight per lane
+        const int ns = min(kFitSeriesPerBlock, 2 * M - q0);
+        const int total = K * kFitSeriesPerBlock, nb = bs - kWave;
+        for (int x0 = tid - kWave; x0 < total; x0 += nb * B) {
+            double v[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                const int x = x0 + j * nb;
+                const int i = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
+                v[j] = (x < total && sj < ns) ? jb.amp[(size_t)i * ys_stride + q0 + sj] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                if (x0 + j * nb < total) ys[x0 + j * nb] = v[j];
+        }
+    }
+    __syncthreads();
+    fit_factor_finish(hs, K, invd, wv, bv);
+    __syncthreads();
+    const int q = q0 + tid;
+    // acoef is [K-1][4][2M]: coefficient p of series q on interval i at
+    // o[i * cs + p * ps], so the 64 lanes of a store write 512 contiguous bytes
+    const size_t ps = 2 * (size_t)M, cs = 4 * ps;
+    if (tid < kFitSeriesPerBlock && q < 2 * M)
+        fit_sweeps<STAGED>(jb, tid, q, K, M, hs, invd, wv, ih, bv, ys, gs);
+    if (!STAGED) return;
+    // STAGED: gs holds the slopes; every lane of the workgroup forms and
+    // stores coefficients, consecutive lanes writing consecutive series
+    __syncthreads();
+    const int ns = min(kFitSeriesPerBlock, 2 * M - q0);
+    for (int x = tid; x < (K - 1) * kFitSeriesPerBlock; x += bs) {
+        const int r = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
+        if (sj >= ns) continue;
+        const double y0 = ys[x], y1 = ys[x + kFitSeriesPerBlock];
+        const double s0 = gs[x], s1 = gs[x + kFitSeriesPerBlock];
+        const double ir = ih[r];
+        const double dr = (y1 - y0) * ir;
+        double *orow = jb.acoef + (size_t)r * cs + q0 + sj;
+        orow[0] = y0;
+        orow[ps] = s0;
+        orow[2 * ps] = (3.0 * dr - 2.0 * s0 - s1) * ir;
+        orow[3 * ps] = (s0 + s1 - 2.0 * dr) * (ir * ir);
+    }
 }
 
 // Workgroups 0 .. n_ph-1 fit the phases, the rest the amplitude series.
@@ -659,7 +722,18 @@ __device__ void fold_pair(const PrepJob &jb, int i, int term) {
             acc[2 * q + 1] += w.x * ai + w.y * ar;
         }
     };
-    const double *arow = jb.acoef + (size_t)i * jb.M * 8;
+    // acoef [K-1][4][2M]: coefficient p of mode k on interval i at
+    // arow[p * 2M + 2k + {0, 1}]
+    const size_t ps = 2 * (size_t)jb.M;
+    const double *arow = jb.acoef + (size_t)i * 4 * ps;
+    auto load8 = [&](int k, double *a) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const double2 v = *(const double2 *)(arow + p * ps + 2 * (size_t)k);
+            a[2 * p] = v.x;
+            a[2 * p + 1] = v.y;
+        }
+    };
     const int ea = jb.term_ptr[term], eb = jb.term_ptr[term + 1];
     int e = ea;
     // four contributors at a time: their weights, indices and coefficient rows
@@ -674,13 +748,15 @@ __device__ void fold_pair(const PrepJob &jb, int i, int term) {
             src[j] = jb.term_src[e + j];
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) av[j][c] = arow[(size_t)src[j].x * 8 + c];
+        for (int j = 0; j < 4; ++j) load8(src[j].x, av[j]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) add(w[j], src[j], av[j]);
     }
-    for (; e < eb; ++e) add(jb.ybuf[e], jb.term_src[e], arow + (size_t)jb.term_src[e].x * 8);
+    for (; e < eb; ++e) {
+        double a[8];
+        load8(jb.term_src[e].x, a);
+        add(jb.ybuf[e], jb.term_src[e], a);
+    }
     const double h = jb.t[i + 1] - jb.t[i];
     double f = jb.scale;
     // terms are stored in reverse order (position n_terms - 1 - term), so the
@@ -1481,7 +1557,17 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
     const int t0 = g0 < jb.n_segs ? jb.segs[g0].w : jb.n_terms;
     const int t1 = g1 < jb.n_segs ? jb.segs[g1].w : jb.n_terms;
     const double h = jb.t[iv + 1] - jb.t[iv];
-    const double *arow = jb.acoef + (size_t)iv * jb.M * 8;
+    // acoef [K-1][4][2M]: coefficient p of mode k at arow[p * 2M + 2k + {0, 1}]
+    const size_t ps = 2 * (size_t)jb.M;
+    const double *arow = jb.acoef + (size_t)iv * 4 * ps;
+    auto load8 = [&](int mode, double *a) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const double2 v = *(const double2 *)(arow + p * ps + 2 * (size_t)mode);
+            a[2 * p] = v.x;
+            a[2 * p + 1] = v.y;
+        }
+    };
     for (int tt = t0 + tid; tt < t1; tt += blockDim.x) {
         int g = g0;
         while (g + 1 < g1 && jb.segs[g + 1].w <= tt) ++g;
@@ -1504,23 +1590,25 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
                 acc[2 * q + 1] += w.x * ai + w.y * ar;
             }
         };
-        // four contributors at a time: indices, then their coefficient rows,
+        // three contributors at a time: indices, then their coefficient rows,
         // all loaded before any is added (in contributor order)
         const int ea = jb.term_ptr[tt], eb = jb.term_ptr[tt + 1];
         int e = ea;
-        for (; e + 4 <= eb; e += 4) {
-            int2 src[4];
-            double av[4][8];
+        for (; e + 3 <= eb; e += 3) {
+            int2 src[3];
+            double av[3][8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) src[j] = jb.term_src[e + j];
+            for (int j = 0; j < 3; ++j) src[j] = jb.term_src[e + j];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 3; ++j) load8(src[j].x, av[j]);
 #pragma unroll
-                for (int c = 0; c < 8; ++c) av[j][c] = arow[(size_t)src[j].x * 8 + c];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) add(src[j], av[j]);
+            for (int j = 0; j < 3; ++j) add(src[j], av[j]);
         }
-        for (; e < eb; ++e) add(jb.term_src[e], arow + (size_t)jb.term_src[e].x * 8);
+        for (; e < eb; ++e) {
+            double a[8];
+            load8(jb.term_src[e].x, a);
+            add(jb.term_src[e], a);
+        }
         double f = jb.scale, fi = jb.scale_im;
         double *dst = cf[k][n + kMfA - 1];
 #pragma unroll
@@ -1591,14 +1679,18 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
 }
 
 // 512 lanes: about one folded term per lane (the fold's dependent loads
-// dominate), two operand items per lane in the pack.
+// dominate), two operand items per lane in the pack; at most 128 registers,
+// so two workgroups fit a compute unit (the grid is slightly larger than the
+// number of compute units).
 constexpr int kFoldPackThreads = 512;
 
-__global__ __launch_bounds__(kFoldPackThreads) void fold_pack_kernel(PrepJob jb) {
+__global__ __launch_bounds__(kFoldPackThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void fold_pack_kernel(PrepJob jb) {
     fold_pack_body(jb, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kFoldPackThreads) void fold_pack_batch_kernel(const PrepJob *jobs) {
+__global__ __launch_bounds__(kFoldPackThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void fold_pack_batch_kernel(const PrepJob *jobs) {
     const PrepJob jb = jobs[blockIdx.y];
     fold_pack_body(jb, blockIdx.x);
 }
@@ -2162,6 +2254,27 @@ static void fit_lds_attributes() {
         hipFuncSetAttribute((const void *)fit_batch_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     });
+}
+
+// Amplitude coefficients in the documented export layout: dst [K-1][M][4][2]
+// from the internal [K-1][4][2M].
+__global__ __launch_bounds__(256) void acoef_export_kernel(const double *src, double *dst,
+                                                           long long K1, long long M) {
+    const long long n = K1 * M * 8;
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (long long)gridDim.x * blockDim.x) {
+        const long long c = x & 1, p = (x >> 1) & 3, k = (x >> 3) % M, i = (x >> 3) / M;
+        dst[x] = src[(i * 4 + p) * 2 * M + 2 * k + c];
+    }
+}
+
+hipError_t launch_acoef_export(const double *src, double *dst, int K, int M,
+                               hipStream_t stream) {
+    const long long n = (long long)(K - 1) * M * 8;
+    const int blocks = (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(acoef_export_kernel, dim3(blocks), dim3(256), 0, stream, src, dst,
+                       (long long)(K - 1), (long long)M);
+    return hipGetLastError();
 }
 
 hipError_t launch_fit(const FitJob &job, hipStream_t stream) {
