@@ -20,6 +20,12 @@ struct dd {
 // 2 pi as a double-double (hi = RN(2 pi), lo = RN(2 pi - hi)).
 #define FEW_TWO_PI_HI 6.283185307179586232e+00
 #define FEW_TWO_PI_LO 2.449293598294706414e-16
+// RN(1 / (2 pi)): the quotient that picks the multiple of 2 pi.  A product
+// instead of a division (a long dependent sequence on the GPU); the integer
+// it rounds to can differ from that of the exact quotient only when the
+// quotient is within a few ulps of a half-integer, and the remainder then
+// still lies within [-pi, pi] up to those ulps.
+#define FEW_INV_TWO_PI 1.591549430918953358e-01
 
 __host__ __device__ inline dd dd_make(double h, double l = 0.0) { return dd{h, l}; }
 
@@ -86,12 +92,12 @@ __host__ __device__ inline dd dd_div(dd a, dd b) {
 // k * 2pi_hi is formed exactly with TwoProd, so the result carries only the
 // rounding of the final dd additions.
 __host__ __device__ inline dd dd_reduce_2pi(dd a) {
-    double k = rint(a.hi / FEW_TWO_PI_HI);
+    double k = rint(a.hi * FEW_INV_TWO_PI);
     dd p = two_prod(k, FEW_TWO_PI_HI);
     dd r = dd_sub(a, p);
     r = dd_sub(r, dd_make(k * FEW_TWO_PI_LO, fma(k, FEW_TWO_PI_LO, -k * FEW_TWO_PI_LO)));
     // one more pass keeps the result in range when a.hi / 2pi rounded badly
-    double k2 = rint(r.hi / FEW_TWO_PI_HI);
+    double k2 = rint(r.hi * FEW_INV_TWO_PI);
     if (k2 != 0.0) {
         r = dd_sub(r, two_prod(k2, FEW_TWO_PI_HI));
         r = dd_sub(r, dd_make(k2 * FEW_TWO_PI_LO));
@@ -102,7 +108,7 @@ __host__ __device__ inline dd dd_reduce_2pi(dd a) {
 // binary64 reduction to [-pi, pi] (for quantities already accurate only to
 // binary64): a - k 2pi_hi by FMA, then - k 2pi_lo.
 __host__ __device__ inline double d_reduce_2pi(double a) {
-    double k = rint(a / FEW_TWO_PI_HI);
+    double k = rint(a * FEW_INV_TWO_PI);
     double r = fma(-k, FEW_TWO_PI_HI, a);
     return fma(-k, FEW_TWO_PI_LO, r);
 }

@@ -1518,7 +1518,8 @@ typedef float mf_float4 __attribute__((ext_vector_type(4)));
 // scaled by 2^-E, E the exponent of its largest |value| on the interval (so
 // scaled values stay below 1), and split into hi = fp16(v) and
 // lo = fp16(v - hi), both from binary64.  Table layout, per interval:
-// [p][mt][sign][t][hi, lo][lane 64][8 values], lane l's operand fragment of
+// [3 - p][mt][sign][t][hi, lo][lane 64][8 values] (p descending, the order of
+// the Horner recurrence that reads it), lane l's operand fragment of
 // v_mfma_f32_16x16x32_f16: matrix row l % 16 of the tile, columns
 // |n| = 16 t + 4 (l / 16) + i / 2 and c = i % 2 for value i (sign 0: n = |n|,
 // sign 1: n = -|n|, whose n = 0 column is zero).
@@ -1672,7 +1673,7 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
             }
         }
         const size_t at =
-            (((((size_t)p * kMfMT + mt) * 2 + sg) * kMfT + t) * 2) * 512 + (size_t)ln * 8;
+            (((((size_t)(3 - p) * kMfMT + mt) * 2 + sg) * kMfT + t) * 2) * 512 + (size_t)ln * 8;
         *(mf_half8 *)(dst + at) = hi;
         *(mf_half8 *)(dst + at + 512) = lo;
     }
@@ -1810,8 +1811,8 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
                 for (int nt = 0; nt < kMfNT; ++nt) acc[mt][nt] = acc[mt][nt] * uu[nt];
         }
         // operand fragments of power p, (mt, sign, t) in order, each read one
-        // fragment ahead of its products
-        const float4 *fp = lds + (size_t)p * kMfMT * 2 * kMfT * 2 * 64 + lane;
+        // fragment ahead of its products (constant offsets from fp)
+        const float4 *fp = lds + (size_t)(3 - p) * kMfMT * 2 * kMfT * 2 * 64 + lane;
         constexpr int NF = kMfMT * 2 * kMfT;
         float4 ch = fp[0], cl = fp[64];
 #pragma unroll
@@ -1844,9 +1845,22 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
         }
     }
     // Rows -> h.  Row r's harmonic is z_r = e^{-i m_r Phi_phi}.
-    // With consecutive m values (m_r = m_0 + r) it is z_0 E^r, E = e^{-i Phi_phi}:
-    // the sample's lane forms z_0 and E^2, E^4, E^6, E^8, and group g starts
-    // from z_0 E^{2g}.  Otherwise every row takes its own sincos.
+    // With consecutive m values (m_r = m_0 + r) every z_r is a power of
+    // E = e^{-i Phi_phi}: the sample's lane forms E^2, E^4, E^6, E^8 and
+    // z_0 = E^{m_0} (binary powering, E^{-1} = conj E), and group g starts
+    // from z_0 E^{2g}.  Each z_r then carries m_r times the phase error of E,
+    // at most max |m| of it.  Otherwise every row takes its own sincos.
+    // INNER: the data samples of this lane's columns, requested now so that
+    // their latency overlaps the row combination
+    float2 dv[kMfNT];
+    if constexpr (INNER) {
+#pragma unroll
+        for (int nt = 0; nt < kMfNT; ++nt) {
+            const long long jr = wbase + 16 * nt + col;
+            dv[nt] = (g == 0 && jr < e) ? ((const float2 *)jb.data)[jr] : make_float2(0.0f, 0.0f);
+        }
+    }
+    const int m0 = mm[0], am0 = m0 < 0 ? -m0 : m0;
     float z0r[OWN], z0i[OWN], e2r[OWN], e2i[OWN], e4r[OWN], e4i[OWN], e6r[OWN], e6i[OWN];
     float e8r[OWN], e8i[OWN];
 #pragma unroll
@@ -1854,11 +1868,30 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
         z0r[k] = z0i[k] = e2r[k] = e2i[k] = e4r[k] = e4i[k] = 0.0f;
         e6r[k] = e6i[k] = e8r[k] = e8i[k] = 0.0f;
         if (consec) {
-            unit_phasor<float>(d_reduce_2pi((double)mm[0] * pf[k]), &z0r[k], &z0i[k]);
             cmulf(er[k], ei[k], er[k], ei[k], &e2r[k], &e2i[k]);
             cmulf(e2r[k], e2i[k], e2r[k], e2i[k], &e4r[k], &e4i[k]);
             cmulf(e4r[k], e4i[k], e2r[k], e2i[k], &e6r[k], &e6i[k]);
             cmulf(e4r[k], e4i[k], e4r[k], e4i[k], &e8r[k], &e8i[k]);
+            // E^{|m_0|}; the bits of |m_0| are uniform across the workgroup
+            float zr = 1.0f, zi = 0.0f, br = e8r[k], bi = e8i[k];
+            auto take = [&](float pr, float pi) {
+                float nr, ni;
+                cmulf(zr, zi, pr, pi, &nr, &ni);
+                zr = nr;
+                zi = ni;
+            };
+            if (am0 & 1) take(er[k], ei[k]);
+            if (am0 & 2) take(e2r[k], e2i[k]);
+            if (am0 & 4) take(e4r[k], e4i[k]);
+            for (int bit = 8; bit <= am0; bit <<= 1) {
+                if (am0 & bit) take(br, bi);
+                float nr, ni;
+                cmulf(br, bi, br, bi, &nr, &ni);
+                br = nr;
+                bi = ni;
+            }
+            z0r[k] = zr;
+            z0i[k] = m0 < 0 ? -zi : zi;
         }
     }
     double dh = 0.0, hh = 0.0;
@@ -1924,8 +1957,7 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
         const long long jr = wbase + 16 * nt + col;
         if (g == 0 && jr < e) {
             if constexpr (INNER) {
-                const float *d = (const float *)jb.data + 2 * jr;
-                const double xr = hr, xi = hq, dr = d[0], di = d[1];
+                const double xr = hr, xi = hq, dr = dv[nt].x, di = dv[nt].y;
                 dh = dh + (dr * xr + di * xi);
                 hh = hh + (xr * xr + xi * xi);
             } else {
@@ -1939,12 +1971,13 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
 
 // Samples [lo, hi) of one job (matrix-core path), interval by interval; each
 // interval's operand table and row scales are staged in LDS first.  Every
-// lane of the workgroup runs the same loop (lo, hi uniform).
+// lane of the workgroup runs the same loop (lo, hi uniform).  INNER: each
+// lane's binary64 sums accumulate in its LDS slot iacc[threadIdx.x] (zeroed by
+// the caller), which keeps them out of the registers of the product loop.
 template <bool INNER>
-__device__ double2 mf_range(const SumJob &jb, long long lo, long long hi, float4 *lds,
-                            float *msc, int *mm) {
-    double2 acc = make_double2(0.0, 0.0);
-    if (lo >= hi) return acc;
+__device__ void mf_range(const SumJob &jb, long long lo, long long hi, float4 *lds,
+                         float *msc, int *mm, double2 *iacc) {
+    if (lo >= hi) return;
     __syncthreads();                                // rows of a previous job no longer read
     if ((int)threadIdx.x < kMfRows) {
         const int r = threadIdx.x;
@@ -1976,12 +2009,15 @@ __device__ double2 mf_range(const SumJob &jb, long long lo, long long hi, float4
         __syncthreads();
         for (long long base = lo; base < e; base += kMfRound) {
             const double2 v = mf_round<INNER>(jb, iv, base, e, lds, msc, mm, consec);
-            acc.x = acc.x + v.x;
-            acc.y = acc.y + v.y;
+            if constexpr (INNER) {
+                double2 a = iacc[threadIdx.x];
+                a.x = a.x + v.x;
+                a.y = a.y + v.y;
+                iacc[threadIdx.x] = a;
+            }
         }
         lo = e;
     }
-    return acc;
 }
 
 // Share r of G of [0, total): workgroup b runs on XCD b mod 8 and takes share
@@ -1998,12 +2034,14 @@ __global__ __launch_bounds__(64 * kMfWaves) void sum_mfma_kernel(SumJob jb) {
     extern __shared__ float4 mf_lds[];
     __shared__ float msc[kMfRows];
     __shared__ int mm[kMfRows];
+    __shared__ double2 iacc[INNER ? 64 * kMfWaves : 1];
+    if constexpr (INNER) iacc[threadIdx.x] = make_double2(0.0, 0.0);
     long long lo, hi;
     mf_share(jb.n, &lo, &hi);
-    double2 v = mf_range<INNER>(jb, lo, hi, mf_lds, msc, mm);
+    mf_range<INNER>(jb, lo, hi, mf_lds, msc, mm, iacc);
     if constexpr (INNER) {
         __shared__ double2 red[kMfWaves];
-        v = wave_sum(v);
+        double2 v = wave_sum(iacc[threadIdx.x]);
         if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -2036,7 +2074,7 @@ __global__ __launch_bounds__(64 * kMfWaves) void sum_mfma_batch_kernel(const Sum
         if (b0 >= hi) break;
         const SumJob jb = load_uniform(jobs + j);
         const long long a = max(lo, b0) - b0, e = min(hi, b0 + jb.n) - b0;
-        if (a < e) mf_range<false>(jb, a, e, mf_lds, msc, mm);
+        if (a < e) mf_range<false>(jb, a, e, mf_lds, msc, mm, nullptr);
     }
 }
 
