@@ -26,6 +26,8 @@ struct dd {
 // quotient is within a few ulps of a half-integer, and the remainder then
 // still lies within [-pi, pi] up to those ulps.
 #define FEW_INV_TWO_PI 1.591549430918953358e-01
+// RN(2 / pi), for the choice of the quadrant.
+#define FEW_TWO_OVER_PI 6.366197723675813431e-01
 
 __host__ __device__ inline dd dd_make(double h, double l = 0.0) { return dd{h, l}; }
 

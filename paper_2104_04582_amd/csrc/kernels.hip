@@ -842,6 +842,12 @@ __device__ __forceinline__ double phase_eval(const FEW_AS4 double *c, dd x) {
     return d_reduce_2pi(v);
 }
 
+// One phase at one sample, not reduced: the interval's binary64 cubic (the
+// leading parts of the double-double coefficients) at offset x.
+__device__ __forceinline__ double phase_raw(const FEW_AS4 double *c, double x) {
+    return fma(fma(fma(c[6], x, c[4]), x, c[2]), x, c[0]);
+}
+
 // e^{-i a} for a reduced phase a in [-pi, pi] (binary64): the binary32 path
 // rounds a to binary32 and takes the binary32 sincos (harmonics are binary32
 // there), the binary64 path the binary64 one.
@@ -1703,6 +1709,35 @@ __device__ __forceinline__ void cmulf(float ar, float ai, float br, float bi, fl
     *ci = __builtin_fmaf(ar, bi, ai * br);
 }
 
+// e^{-i v} in binary32 for a binary64 phase v (any size): v = q pi/2 + r, q the
+// nearest integer of v 2/pi and r = v - q pi/2 with pi/2 = 2pi_hi/4 + 2pi_lo/4
+// (both quarters exact), so |r| <= pi/4 up to rounding; sin r and cos r from
+// their Taylor series in binary32 (terms to r^9 and r^10: the first omitted
+// term is below 2e-9 for |r| <= pi/4), then the quadrant: e^{-iv} is
+// (cos r, -sin r) times (-i)^q.  No branch and no large-argument path.
+__device__ __forceinline__ void phasor_f32(double v, float *re, float *im) {
+    const double q = rint(v * FEW_TWO_OVER_PI);
+    const double rd = fma(-q, 0.25 * FEW_TWO_PI_LO, fma(-q, 0.25 * FEW_TWO_PI_HI, v));
+    const int qm = (int)fma(-4.0, floor(q * 0.25), q);      // q mod 4 in 0..3
+    const float r = (float)rd, r2 = r * r;
+    float ps = __builtin_fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    ps = __builtin_fmaf(ps, r2, 1.0f / 120.0f);
+    ps = __builtin_fmaf(ps, r2, -1.0f / 6.0f);
+    const float sn = __builtin_fmaf(r * r2, ps, r);
+    float pc = __builtin_fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    pc = __builtin_fmaf(pc, r2, -1.0f / 720.0f);
+    pc = __builtin_fmaf(pc, r2, 1.0f / 24.0f);
+    pc = __builtin_fmaf(pc, r2, -0.5f);
+    const float cs = __builtin_fmaf(pc, r2, 1.0f);
+    // cos v, sin v for q mod 4 = 0, 1, 2, 3: (c, s), (-s, c), (-c, -s), (s, -c)
+    const bool swap = qm & 1;
+    const float a = swap ? sn : cs, b = swap ? cs : sn;
+    const float cv = (qm == 1 || qm == 2) ? -a : a;
+    const float sv = (qm >= 2) ? -b : b;
+    *re = cv;
+    *im = -sv;
+}
+
 // fp16 hi/lo parts of a binary32 value: hi = fp16(a), lo = fp16(a - hi)
 // (the difference is exact in binary32), about 22 significant bits together.
 // `one` is 1.0 from the job descriptor: written as a * one - hi the
@@ -1748,11 +1783,11 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
         if (j >= e) j = e - 1;
         const double tj = dev_sample_time(jb.t_start, jb.dt, j);
         const dd x = two_sum(tj, -ti);
-        pf[k] = phase_eval<false>(pc, x);
-        pr[k] = phase_eval<false>(pc + 8, x);
+        pf[k] = phase_raw(pc, x.hi);
+        pr[k] = phase_raw(pc + 8, x.hi);
         u[k] = (float)(x.hi * inv_h);
-        unit_phasor<float>(pf[k], &er[k], &ei[k]);
-        unit_phasor<float>(pr[k], &fr[k], &fi[k]);
+        phasor_f32(pf[k], &er[k], &ei[k]);
+        phasor_f32(pr[k], &fr[k], &fi[k]);
         float f2r, f2i;
         cmulf(fr[k], fi[k], fr[k], fi[k], &f2r, &f2i);
         cmulf(f2r, f2i, f2r, f2i, &f4r[k], &f4i[k]);
@@ -1935,17 +1970,17 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
                 }
             }
         } else {
-            const double spf = __shfl(pf[k], src);
+            const double spf = d_reduce_2pi(__shfl(pf[k], src));
 #pragma unroll
             for (int mt = 0; mt < kMfMT; ++mt) {
                 const int r0 = 8 * mt + 2 * g;
                 const int m0 = mm[r0], m1 = mm[r0 + 1];
                 float zr, zi, yr, yi;
-                unit_phasor<float>(d_reduce_2pi((double)m0 * spf), &zr, &zi);
+                phasor_f32((double)m0 * spf, &zr, &zi);
                 if (m1 == m0 + 1)
                     cmulf(zr, zi, Er, Ei, &yr, &yi);
                 else
-                    unit_phasor<float>(d_reduce_2pi((double)m1 * spf), &yr, &yi);
+                    phasor_f32((double)m1 * spf, &yr, &yi);
                 add_rows(mt, zr, zi, yr, yi);
             }
         }
