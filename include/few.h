@@ -85,10 +85,14 @@ enum {
                                  delays the launch after it by several microseconds, so this
                                  keeps the other stages back to back while the dominant
                                  kernel is timed */
-    FEW_FLAG_VECTOR_ONLY = 4  /* FEW_MIXED: never use the matrix-core summation (fp16 hi/lo
+    FEW_FLAG_VECTOR_ONLY = 4, /* FEW_MIXED: never use the matrix-core summation (fp16 hi/lo
                                  operands on the MFMA units, fp32 accumulation); every sum
                                  runs on the vector units in binary32 with Kahan-compensated
                                  accumulation */
+    FEW_FLAG_SELECT_SORTED = 8 /* few_mode_select: sort every knot and sum sequentially; by
+                                 default a knot is decided from sums with a proven error
+                                 bound and sorted only when a comparison falls within it
+                                 (the result is the same either way) */
 };
 
 typedef struct few_plan_s *few_plan;
@@ -271,7 +275,11 @@ int32_t few_inner_product_noalloc(few_plan plan, few_spline spline, double theta
  *   eps    in [0, 1)
  *   keep   device [M] int32: 1 if the mode is kept at any knot (the union), else 0
  * Enqueued on the plan stream.  The result depends only on the inputs (no
- * order of floating-point reduction is left open).
+ * order of floating-point reduction is left open): every knot is decided
+ * either from sums whose error bound keeps each comparison on the same side
+ * as that of the sequential sums, or, when a comparison lies within the
+ * bound (or FEW_FLAG_SELECT_SORTED is set), from the sequential sums
+ * themselves.
  */
 int32_t few_mode_select(few_plan plan, int32_t K, int32_t M, const double *amp, double eps,
                         int32_t *keep);

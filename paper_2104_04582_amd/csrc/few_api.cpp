@@ -1166,7 +1166,8 @@ int32_t few_mode_select(few_plan p, int32_t K, int32_t M, const double *amp, dou
     if (!(eps >= 0.0 && eps < 1.0)) return fail(FEW_E_ARG, "eps must be in [0, 1)");
     std::lock_guard<std::mutex> g(p->sync_mu);
     HIP_TRY(hipSetDevice(p->device));
-    HIP_TRY(launch_select(amp, K, M, eps, keep, p->stream));
+    HIP_TRY(launch_select(amp, K, M, eps, (p->flags & FEW_FLAG_SELECT_SORTED) != 0, keep,
+                          p->stream));
     return FEW_OK;
 }
 

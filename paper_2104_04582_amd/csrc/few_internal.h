@@ -238,7 +238,7 @@ hipError_t launch_sum_mfma_inner(const SumJob &job, int n_wg, double two_dt, dou
                                  hipStream_t stream);
 hipError_t launch_sum_mfma_batch(const SumJob *jobs_dev, int n_jobs, long long total,
                                  int n_wg, hipStream_t stream);
-hipError_t launch_select(const double *amp, int K, int M, double eps, int *keep,
+hipError_t launch_select(const double *amp, int K, int M, double eps, bool sorted, int *keep,
                          hipStream_t stream);
 constexpr int kMaxSelectModes = 4096;   // LDS: (binary64 key + int index) per padded mode
 

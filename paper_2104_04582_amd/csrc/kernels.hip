@@ -2120,10 +2120,27 @@ __global__ __launch_bounds__(64 * kMfWaves) void sum_mfma_batch_kernel(const Sum
 // |A|^2 (ties by increasing index), sum the powers sequentially in that order,
 // and keep the shortest prefix that reaches (1 - eps) of the knot's total (at
 // least the top mode).  The selection is the union over knots.  One workgroup
-// of 1024 lanes per knot: bitonic sort of (power, index) held in registers;
-// one wave forms the binary64 partial sums in sorted order (values broadcast 64
-// at a time, so only the chain of adds is serial) and every threshold decision
-// is taken on exactly those sums.
+// of 1024 lanes per knot, in two stages.
+//
+// Bounded stage.  A mode j is kept iff S_j < (1 - eps) T, S_j the sequential
+// sum of the powers ranked before it and T the sequential total.  Any sum of
+// n non-negative binary64 values, in any order, is within (n - 1) u of the
+// exact sum times the exact sum (u = 2^-53), so sums formed in another order
+// (here: block reductions and LDS atomics) decide every comparison the same
+// way unless they lie within a margin, taken as 8 (M + 4) u T, of the
+// threshold.  The workgroup finds the last kept mode by a most-significant-
+// digit radix select on the power's bits (non-negative binary64 values order
+// as their bit patterns): per level, 8 bits below the candidates' common
+// prefix are bucketed with the bucket power sums, and the last bucket whose
+// preceding sum is below the threshold holds the last kept mode.  Each choice
+// is checked against the margin on both sides; equal powers are ranked by
+// index.
+//
+// Sorted stage, taken only when some comparison falls inside the margin (or
+// the total is 0 or not finite, or the plan asks for it): bitonic sort of
+// (power, index) held in registers; one lane forms the binary64 partial sums
+// in sorted order (values loaded 32 at a time, so only the chain of adds is
+// serial) and every threshold decision is taken on exactly those sums.
 // ===========================================================================
 __device__ __forceinline__ bool sel_before(double ka, int ia, double kb, int ib) {
     return ka > kb || (ka == kb && ia < ib);
@@ -2148,10 +2165,8 @@ __device__ __forceinline__ void sel_exchange(double &kv, int &iv, double kq, int
 // N = 1024 R positions (R = 1, 2 or 4); lane t holds positions t + 1024 r in
 // registers.  Partners closer than a wave are exchanged by shuffles, partners
 // 1024 or more apart are in the lane's own registers, the rest go through LDS.
-__global__ __launch_bounds__(kSelectThreads) void select_kernel(const double *amp, int M, int N,
-                                                                double one_minus_eps,
-                                                                int *keep) {
-    extern __shared__ double sel_lds[];
+__device__ void select_sorted(const double *amp, int M, int N, double one_minus_eps, int *keep,
+                              double *sel_lds) {
     double *key = sel_lds;
     int *idx = (int *)(sel_lds + N);
     __shared__ double total;
@@ -2275,6 +2290,210 @@ __global__ __launch_bounds__(kSelectThreads) void select_kernel(const double *am
     __syncthreads();
     const int cut = below > 0 ? below : 1;
     for (int j = tid; j < cut; j += kSelectThreads) keep[idx[j]] = 1;
+}
+
+// Bounded stage of one knot (see above).  Returns false, uniformly over the
+// workgroup and before writing anything, when the sorted stage must decide.
+// ties: LDS scratch for up to 4096 indices.
+__device__ bool select_bounded(const double *amp, int M, double one_minus_eps, int *keep,
+                               int *ties) {
+    constexpr int NW = kSelectThreads / kWave;
+    __shared__ double bsum[256];
+    __shared__ int bcnt[256];
+    __shared__ double wsum[NW];
+    __shared__ unsigned long long wand[NW], wor[NW];
+    __shared__ double s_total, s_above;
+    __shared__ unsigned long long s_pre, s_mask;
+    __shared__ int s_state, s_count, s_nties, s_bad;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const size_t k = blockIdx.x;
+    double pv[4];
+    unsigned long long kb[4];
+    bool ok[4];
+    double loc = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = tid + kSelectThreads * r;
+        ok[r] = p < M;
+        pv[r] = 0.0;
+        if (ok[r]) {
+            const double re = amp[(k * M + p) * 2], im = amp[(k * M + p) * 2 + 1];
+            pv[r] = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+        }
+        kb[r] = (unsigned long long)__double_as_longlong(pv[r]);
+        loc += pv[r];
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) loc += __shfl_xor(loc, off);
+    if (lane == 0) wsum[w] = loc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < NW; ++i) t += wsum[i];
+        s_total = t;
+        s_above = 0.0;
+        s_pre = 0ull;
+        s_mask = 0ull;
+        s_state = 0;
+        s_bad = 0;
+        s_nties = 0;
+    }
+    __syncthreads();
+    const double T = s_total;
+    if (!(T > 0.0) || !(T < INFINITY)) return false;
+    const double thr = __dmul_rn(one_minus_eps, T);
+    const double margin = 8.0 * (double)(M + 4) * 0x1p-53 * T;
+    // levels: the candidates are the modes whose masked bits equal s_pre
+    for (;;) {
+        const unsigned long long pre = s_pre, hm = s_mask;
+        unsigned long long a = ~0ull, o = 0ull;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (ok[r] && (kb[r] & hm) == pre) {
+                a &= kb[r];
+                o |= kb[r];
+            }
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            a &= (unsigned long long)__shfl_xor((long long)a, off);
+            o |= (unsigned long long)__shfl_xor((long long)o, off);
+        }
+        if (lane == 0) {
+            wand[w] = a;
+            wor[w] = o;
+        }
+        if (tid < 256) {
+            bsum[tid] = 0.0;
+            bcnt[tid] = 0;
+        }
+        __syncthreads();
+        a = ~0ull;
+        o = 0ull;
+        for (int i = 0; i < NW; ++i) {
+            a &= wand[i];
+            o |= wor[i];
+        }
+        const unsigned long long diff = a ^ o;
+        if (diff == 0ull) break;                    // the candidates share one power
+        const int hb = 63 - __clzll((long long)diff);
+        const int sh = hb >= 7 ? hb - 7 : 0;
+        const unsigned long long keepm = ~0ull << (hb + 1);   // bits common to all candidates
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (ok[r] && (kb[r] & hm) == pre) {
+                const int d = (int)((kb[r] >> sh) & 255ull);
+                atomicAdd(&bsum[d], pv[r]);
+                atomicAdd(&bcnt[d], 1);
+            }
+        __syncthreads();
+        if (w == 0) {
+            // rank order: e = 4 lane + i takes bucket 255 - e (larger powers first)
+            double sv[4];
+            int cv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                sv[i] = bsum[255 - (4 * lane + i)];
+                cv[i] = bcnt[255 - (4 * lane + i)];
+            }
+            double inc = ((sv[0] + sv[1]) + sv[2]) + sv[3];
+            for (int off = 1; off < kWave; off <<= 1) {
+                const double y = __shfl_up(inc, off);
+                if (lane >= off) inc += y;
+            }
+            double run = __shfl_up(inc, 1);
+            run = s_above + (lane == 0 ? 0.0 : run);
+            double C[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                C[i] = run;
+                run += sv[i];
+            }
+            int best = -1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (cv[i] > 0 && C[i] < thr) best = 4 * lane + i;
+            for (int off = kWave / 2; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off));
+            int nxt = 0x7fffffff;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (cv[i] > 0 && 4 * lane + i > best) nxt = min(nxt, 4 * lane + i);
+            for (int off = kWave / 2; off > 0; off >>= 1) nxt = min(nxt, __shfl_xor(nxt, off));
+            bool bad = best < 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = 4 * lane + i;
+                if (e == best && !(C[i] < thr - margin)) bad = true;
+                if (e == nxt && !(C[i] >= thr + margin)) bad = true;
+            }
+            bad = __any(bad);
+            if (bad) {
+                if (lane == 0) s_state = 2;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (4 * lane + i == best) {
+                        const unsigned long long d = (unsigned long long)(255 - best);
+                        s_pre = (a & keepm) | (d << sh);
+                        s_mask = sh > 0 ? (~0ull << sh) : ~0ull;
+                        s_above = C[i];
+                        s_count = cv[i];
+                        s_state = cv[i] == 1 ? 1 : (sh == 0 ? 3 : 0);
+                    }
+            }
+        }
+        __syncthreads();
+        if (s_state != 0) break;
+    }
+    const int state = s_state;
+    if (state == 2) return false;
+    const unsigned long long pre = s_pre, hm = s_mask;
+    if (state != 1) {
+        // the candidates have one power p: the one ranked q-th by index has q p
+        // before it within the candidates
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (ok[r] && (kb[r] & hm) == pre) ties[atomicAdd(&s_nties, 1)] = tid + kSelectThreads * r;
+        __syncthreads();
+        const int nt = s_nties;
+        const double above = s_above;
+        bool bad = false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (!(ok[r] && (kb[r] & hm) == pre)) continue;
+            const int me = tid + kSelectThreads * r;
+            int q = 0;
+            for (int i = 0; i < nt; ++i) q += ties[i] < me ? 1 : 0;
+            const double before = fma((double)q, pv[r], above);
+            if (!(before < thr - margin) && !(before >= thr + margin)) bad = true;
+            ok[r] = before < thr;                   // from here: kept among the candidates
+            kb[r] = pre;
+        }
+        if (bad) s_bad = 1;
+        __syncthreads();
+        if (s_bad) return false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = tid + kSelectThreads * r;
+            if (p >= M) continue;
+            const unsigned long long km =
+                (unsigned long long)__double_as_longlong(pv[r]) & hm;
+            const bool cand = km == pre;
+            if ((!cand && km > pre) || (cand && ok[r])) keep[p] = 1;
+        }
+        return true;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (ok[r] && (kb[r] & hm) >= pre) keep[tid + kSelectThreads * r] = 1;
+    return true;
+}
+
+// One workgroup per knot; `sorted` forces the sorted stage.
+__global__ __launch_bounds__(kSelectThreads) void select_kernel(const double *amp, int M, int N,
+                                                                double one_minus_eps,
+                                                                int sorted, int *keep) {
+    extern __shared__ double sel_lds[];
+    if (!sorted && select_bounded(amp, M, one_minus_eps, keep, (int *)sel_lds)) return;
+    __syncthreads();                                // the bounded stage's LDS reads are done
+    select_sorted(amp, M, N, one_minus_eps, keep, sel_lds);
 }
 
 __global__ void zero_u32_kernel(unsigned *p, int n) {
@@ -2618,7 +2837,7 @@ hipError_t launch_sum_batch(const SumJob *jobs_dev, int n_jobs, int total_slots,
     return hipGetLastError();
 }
 
-hipError_t launch_select(const double *amp, int K, int M, double eps, int *keep,
+hipError_t launch_select(const double *amp, int K, int M, double eps, bool sorted, int *keep,
                          hipStream_t stream) {
     int N = kSelectThreads;                 // 1024, 2048 or 4096 sort positions
     while (N < M) N <<= 1;
@@ -2628,7 +2847,7 @@ hipError_t launch_select(const double *amp, int K, int M, double eps, int *keep,
     if (e != hipSuccess) return e;
     const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)N;
     hipLaunchKernelGGL(select_kernel, dim3(K), dim3(kSelectThreads), lds, stream, amp, M, N,
-                       1.0 - eps, keep);
+                       1.0 - eps, sorted ? 1 : 0, keep);
     return hipGetLastError();
 }
 

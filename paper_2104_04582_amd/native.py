@@ -31,6 +31,7 @@ FEW_MIXED = 1
 FEW_FLAG_TIMING = 1
 FEW_FLAG_TIMING_SUM = 2
 FEW_FLAG_VECTOR_ONLY = 4
+FEW_FLAG_SELECT_SORTED = 8
 
 EXPORTED = [
     "few_plan_create", "few_plan_destroy", "few_spline_fit", "few_spline_free",
@@ -187,11 +188,13 @@ class Plan:
     timing: False, True (HIP events around every launch, FEW_FLAG_TIMING) or
     "sum" (around summation launches only, FEW_FLAG_TIMING_SUM).
     vector_only: mixed precision without the matrix-core summation
-    (FEW_FLAG_VECTOR_ONLY)."""
+    (FEW_FLAG_VECTOR_ONLY).
+    select_sorted: the mode selector sorts every knot (FEW_FLAG_SELECT_SORTED)."""
 
     def __init__(self, device: int = 0, precision: str = "fp64", stream: Optional[int] = None,
                  hbm_budget_bytes: int = 0, max_inflight: int = 0, timing=False,
-                 max_knots: int = 0, max_modes: int = 0, vector_only: bool = False):
+                 max_knots: int = 0, max_modes: int = 0, vector_only: bool = False,
+                 select_sorted: bool = False):
         import torch
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
@@ -206,7 +209,8 @@ class Plan:
                      hbm_budget_bytes=hbm_budget_bytes,
                      flags=(FEW_FLAG_TIMING_SUM if timing == "sum"
                             else FEW_FLAG_TIMING if timing else 0)
-                     | (FEW_FLAG_VECTOR_ONLY if vector_only else 0))
+                     | (FEW_FLAG_VECTOR_ONLY if vector_only else 0)
+                     | (FEW_FLAG_SELECT_SORTED if select_sorted else 0))
         h = ctypes.c_void_p()
         _check(load().few_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self.handle = h.value
