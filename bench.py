@@ -424,7 +424,7 @@ def cpu_small(threads: int):
 
 
 def served(native, precision: str, seconds: float, dev, budget: int,
-           check_oracle: bool = True):
+           check_oracle: bool = True, request_log=None):
     """Replay a Poisson trace (20 req/s, 10% full 4-yr requests) through
     few_submit/few_poll; latency = arrival -> completion seen by the host."""
     import torch
@@ -444,6 +444,8 @@ def served(native, precision: str, seconds: float, dev, budget: int,
     mode_samples = 0
     first_full = None   # (waveform, output) of the first full request served
     with native.Plan(0, precision, hbm_budget_bytes=budget, max_inflight=4) as plan:
+        if request_log:
+            plan.request_log(f"{request_log}.{precision}.jsonl")
         pending = {}
         t_start = time.perf_counter()
         nxt = 0
@@ -502,6 +504,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kerr", action="store_true", help="skip the generic-Kerr line")
     ap.add_argument("--batch", type=int, default=128, help="uneven instances in one launch")
+    ap.add_argument("--request-log", default=None, metavar="PREFIX",
+                    help="served replay: per-request JSON lines in PREFIX.<precision>.jsonl")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -601,7 +605,8 @@ def main() -> int:
     if args.serve_seconds > 0:
         for prec in ("mixed", "fp64"):
             log(f"[bench] served replay {prec}, {args.serve_seconds:.0f} s")
-            serve[prec] = served(native, prec, args.serve_seconds, dev, 8 << 30)
+            serve[prec] = served(native, prec, args.serve_seconds, dev, 8 << 30,
+                                 request_log=args.request_log)
             log(f"[bench] served {prec}: {json.dumps(serve[prec])}")
 
     cpu = None

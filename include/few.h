@@ -319,6 +319,18 @@ int32_t few_poll(few_plan plan, uint64_t ticket);
 /* Block until the ticket is no longer pending; returns what few_poll would. */
 int32_t few_wait(few_plan plan, uint64_t ticket);
 
+/*
+ * Request log of the server (few_submit): with a path, the scheduler appends
+ * one JSON line per request when it retires -- ticket, status, knots, modes,
+ * samples, path ("mfma", "vector" or "fp64"), batch number and size, and the
+ * times in microseconds since plan creation (host steady clock) at which it
+ * arrived (few_submit), was admitted into a batch and was seen complete
+ * (admit_us is -1 for a request that was never admitted).  The file is
+ * opened for appending and flushed after every retired batch; NULL closes
+ * it.  Returns FEW_E_ARG if the file cannot be opened.
+ */
+int32_t few_plan_log(few_plan plan, const char *path);
+
 /* Kernel times recorded so far (FEW_FLAG_TIMING), after synchronising the
  * plan stream; reset != 0 clears the counters. */
 int32_t few_plan_timing(few_plan plan, few_timing *out, int32_t reset);

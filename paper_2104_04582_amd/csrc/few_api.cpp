@@ -477,6 +477,10 @@ struct ServedReq {
     // work the caller enqueued there before few_submit (producing the inputs,
     // last using the output buffer) is complete before the request runs
     hipEvent_t ready = nullptr;
+    // request log: microseconds since plan creation (host steady clock)
+    double t_arrive = 0.0, t_admit = -1.0;
+    long long batch = -1;
+    int batch_size = 0;
 };
 
 struct Batch {
@@ -548,6 +552,10 @@ struct few_plan_s {
     std::mutex def_mu;                  // deferred and sync_events
     std::vector<Deferred> deferred;
     std::vector<hipEvent_t> sync_events;   // pool of timing-disabled events
+    // request log (few_plan_log), written under mu
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    FILE *log = nullptr;
+    long long n_batches = 0;
 };
 
 struct few_spline_s {
@@ -773,6 +781,40 @@ int32_t few_plan_create(const few_plan_desc *desc, few_plan *out) {
     }
 }
 
+namespace {
+double plan_us(few_plan p) {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - p->t0)
+        .count();
+}
+
+// One JSON line per retired served request (caller holds p->mu).
+void log_request(few_plan p, const ServedReq *r, double t_done) {
+    if (!p->log) return;
+    const char *path = !p->fp32 ? "fp64" : (r->h.mfma ? "mfma" : "vector");
+    std::fprintf(p->log,
+                 "{\"ticket\": %llu, \"status\": %d, \"knots\": %d, \"modes\": %d, "
+                 "\"samples\": %lld, \"path\": \"%s\", \"batch\": %lld, "
+                 "\"batch_size\": %d, \"arrive_us\": %.1f, \"admit_us\": %.1f, "
+                 "\"done_us\": %.1f}\n",
+                 (unsigned long long)r->ticket, r->status, r->h.K, r->h.M,
+                 (long long)r->r.n_samples, path, r->batch, r->batch_size, r->t_arrive,
+                 r->t_admit, t_done);
+}
+}  // namespace
+
+int32_t few_plan_log(few_plan p, const char *path) {
+    if (!p) return fail(FEW_E_STATE, "null plan");
+    std::lock_guard<std::mutex> g(p->mu);
+    if (p->log) {
+        std::fclose(p->log);
+        p->log = nullptr;
+    }
+    if (!path) return FEW_OK;
+    p->log = std::fopen(path, "a");
+    if (!p->log) return fail(FEW_E_ARG, "cannot open request log %s", path);
+    return FEW_OK;
+}
+
 int32_t few_plan_destroy(few_plan p) {
     if (!p) return fail(FEW_E_STATE, "null plan");
     try {
@@ -811,6 +853,7 @@ int32_t few_plan_destroy(few_plan p) {
         }
         p->pinned.clear();
         hipFree(p->arena_base);
+        if (p->log) std::fclose(p->log);
         delete p;
         return FEW_OK;
     } catch (...) {
@@ -1117,6 +1160,7 @@ int32_t few_submit(few_plan p, const few_request *req, uint64_t *ticket) {
             p->worker_started = true;
         }
         r->ticket = p->next_ticket++;
+        r->t_arrive = plan_us(p);
         p->tickets[r->ticket] = r;
         p->pending.push_back(r);
         *ticket = r->ticket;
@@ -1364,11 +1408,14 @@ void scheduler_main(few_plan p) {
                 continue;
             }
             int st = (q == hipSuccess) ? FEW_OK : FEW_E_HIP;
+            const double t_done = plan_us(p);
             for (ServedReq *r : b->reqs) {
                 r->status = st;
                 put_sync_event(p, r->ready);
                 r->ready = nullptr;
+                log_request(p, r, t_done);
             }
+            if (p->log) std::fflush(p->log);
             p->arena.release(b->arena_off);
             p->pinned.put(b->pinned);
             hipEventDestroy(b->done);
@@ -1415,6 +1462,8 @@ void scheduler_main(few_plan p) {
                     r->status = FEW_E_NOMEM;
                     put_sync_event(p, r->ready);
                     r->ready = nullptr;
+                    log_request(p, r, plan_us(p));
+                    if (p->log) std::fflush(p->log);
                     p->cv_done.notify_all();
                     continue;
                 }
@@ -1425,6 +1474,13 @@ void scheduler_main(few_plan p) {
                 b->slot = slot;
                 b->arena_off = off;
                 b->reqs = take;
+                const double t_admit = plan_us(p);
+                for (ServedReq *r : take) {
+                    r->t_admit = t_admit;
+                    r->batch = p->n_batches;
+                    r->batch_size = (int)take.size();
+                }
+                ++p->n_batches;
                 p->slot_busy[slot] = true;
                 g.unlock();
                 int rc = launch_batch(p, b, p->bstreams[slot], p->counters + 64 * slot);
@@ -1436,11 +1492,14 @@ void scheduler_main(few_plan p) {
                     } else {
                         hipStreamSynchronize(p->bstreams[slot]);
                     }
+                    const double t_done = plan_us(p);
                     for (ServedReq *r : b->reqs) {
                         r->status = rc;
                         put_sync_event(p, r->ready);
                         r->ready = nullptr;
+                        log_request(p, r, t_done);
                     }
+                    if (p->log) std::fflush(p->log);
                     p->arena.release(b->arena_off);
                     if (b->pinned) p->pinned.put(b->pinned);
                     p->slot_busy[slot] = false;

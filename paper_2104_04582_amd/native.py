@@ -14,7 +14,9 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfew.so")
+# FEW_LIBRARY selects another build of the same library (the host-sanitizer
+# build of build.py), never a different implementation.
+LIB_PATH = os.environ.get("FEW_LIBRARY") or os.path.join(HERE, "libfew.so")
 
 FEW_OK = 0
 FEW_PENDING = 1
@@ -36,7 +38,7 @@ FEW_FLAG_SELECT_SORTED = 8
 EXPORTED = [
     "few_plan_create", "few_plan_destroy", "few_spline_fit", "few_spline_free",
     "few_spline_coefs", "few_mode_sum", "few_mode_select", "few_batch", "few_submit",
-    "few_poll", "few_wait",
+    "few_poll", "few_wait", "few_plan_log",
     "few_plan_timing", "few_last_error", "few_host_terms", "few_host_interval_starts",
     "few_spline_fit_kerr", "few_host_terms_kerr", "few_inner_product", "few_mode_sum_ssb",
     "few_host_frame",
@@ -109,6 +111,7 @@ def load() -> ctypes.CDLL:
     lib.few_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
     lib.few_poll.argtypes = [vp, ctypes.c_uint64]
     lib.few_wait.argtypes = [vp, ctypes.c_uint64]
+    lib.few_plan_log.argtypes = [vp, ctypes.c_char_p]
     lib.few_plan_timing.argtypes = [vp, P(Timing), i32]
     lib.few_last_error.argtypes = []
     lib.few_last_error.restype = ctypes.c_char_p
@@ -354,6 +357,11 @@ class Plan:
         rc = load().few_wait(self.handle, ctypes.c_uint64(ticket))
         self._inflight.pop(ticket, None)
         _check(rc)
+
+    def request_log(self, path) -> None:
+        """few_plan_log: append one JSON line per retired served request to
+        `path` (None stops logging)."""
+        _check(load().few_plan_log(self.handle, None if path is None else os.fsencode(path)))
 
     def timing(self, reset: bool = False) -> dict:
         t = Timing()

@@ -113,16 +113,20 @@ def test_one_launch_batch_bitwise_equals_solo(env, prec):
 
 
 @pytest.mark.parametrize("prec", ["mixed"])
-def test_staggered_arrivals_same_as_alone(env, prec):
+def test_staggered_arrivals_same_as_alone(env, prec, tmp_path):
     """Requests submitted while earlier ones run are admitted into new
-    batches; every result equals its solo run."""
+    batches; every result equals its solo run.  The request log holds one
+    line per request with ordered arrival, admission and completion times."""
+    import json
     native, torch, dev = env
     ws = instances(8, max_samples=1_500_000)
     refs = [solo(native, torch, dev, w, prec) for w in ws]
     ins = [dev_inputs(torch, w, dev) for w in ws]
     outs = [torch.empty(w.n_samples, dtype=torch.complex64, device=dev) for w in ws]
     log(f"[serve] staggered {len(ws)}")
+    log_path = tmp_path / "requests.jsonl"
     with native.Plan(0, prec, max_inflight=3) as plan:
+        plan.request_log(str(log_path))
         tickets = []
         for i, w in enumerate(ws):
             tickets.append(submit(plan, w, ins[i], outs[i]))
@@ -137,6 +141,14 @@ def test_staggered_arrivals_same_as_alone(env, prec):
             time.sleep(0.0005)
     for i in range(len(ws)):
         assert np.array_equal(outs[i].cpu().numpy(), refs[i]), i
+    recs = {r["ticket"]: r for r in map(json.loads, log_path.read_text().splitlines())}
+    assert sorted(recs) == sorted(tickets)
+    for tk, w in zip(tickets, ws):
+        r = recs[tk]
+        assert r["status"] == 0 and r["samples"] == w.n_samples and r["modes"] == w.M
+        assert r["knots"] == w.K and r["batch"] >= 0 and r["batch_size"] >= 1
+        assert r["path"] in (("mfma", "vector") if prec == "mixed" else ("fp64",))
+        assert 0.0 <= r["arrive_us"] <= r["admit_us"] <= r["done_us"]
 
 
 def test_admission_under_small_budget(env):
