@@ -365,6 +365,7 @@ FitJob fit_job(const HostReq &r, ReqBase base, const double *pp, const double *p
     j.amp = amp;
     j.pcoef = at_dev<double>(r, base, r.L.off_pcoef);
     j.acoef = at_dev<double>(r, base, r.L.off_acoef);
+    j.acoef_pmajor = r.mfma ? 1 : 0;
     j.K = r.K;
     j.M = r.M;
     j.amp_blocks = (2 * r.M + kFitSeriesPerBlock - 1) / kFitSeriesPerBlock;
@@ -945,8 +946,13 @@ int32_t few_spline_coefs(few_spline s, int32_t which, void *dst) {
     HIP_TRY(hipSetDevice(p->device));
     char *base = p->arena.ptr(s->arena_off);
     if (which == 0) {
-        HIP_TRY(launch_acoef_export((const double *)(base + s->h.L.off_acoef), (double *)dst,
-                                    s->h.K, s->h.M, p->stream));
+        if (s->h.mfma)
+            HIP_TRY(launch_acoef_export((const double *)(base + s->h.L.off_acoef),
+                                        (double *)dst, s->h.K, s->h.M, p->stream));
+        else
+            HIP_TRY(hipMemcpyAsync(dst, base + s->h.L.off_acoef,
+                                   sizeof(double) * 8 * (size_t)(s->h.K - 1) * s->h.M,
+                                   hipMemcpyDeviceToDevice, p->stream));
     } else if (which == 1) {
         HIP_TRY(hipMemcpyAsync(dst, base + s->h.L.off_pcoef,
                                sizeof(double) * 8 * s->h.n_ph * (size_t)(s->h.K - 1),

@@ -124,7 +124,9 @@ struct FitJob {
     const double *phi_theta;  // [K] (generic Kerr) or null
     const double *amp;      // [K][M][2]
     double *pcoef;          // [K-1][n_ph][4][2] double-double phase cubics
-    double *acoef;          // [K-1][4][2M] amplitude cubics: coefficient p of series q = 2k + re/im
+    double *acoef;          // amplitude cubics: [K-1][M][4][2], or [K-1][4][2M] if pmajor
+    int acoef_pmajor;       // 1: coefficient p of series q = 2k + re/im at [i][p][q]
+                            // (matrix-core requests: read by fold_pack), 0: mode-major
     int K, M;
     int n_ph;               // phases: Phi_phi, Phi_r (, Phi_theta)
     int amp_blocks;         // blocks covering the 2M amplitude series (after n_ph phase blocks)

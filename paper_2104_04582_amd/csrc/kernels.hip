@@ -318,10 +318,13 @@ __device__ __forceinline__ void fit_sweeps(const FitJob &jb, int tid, int q, int
                                            const double *bv, const double *ys, double *gs) {
     constexpr int C = 16;
     const size_t ys_stride = 2 * (size_t)M;
-    const size_t ps = 2 * (size_t)M, cs = 4 * ps;
+    // coefficient p of series q on interval r at o[r * cs + p * ps]
+    // ([K-1][4][2M] or [K-1][M][4][2])
+    const bool pm = jb.acoef_pmajor != 0;
+    const size_t ps = pm ? 2 * (size_t)M : 2, cs = 8 * (size_t)M;
     const int k = q >> 1, comp = q & 1;
     const double *__restrict__ y = jb.amp + 2 * (size_t)k + comp;
-    double *__restrict__ o = jb.acoef + q;
+    double *__restrict__ o = jb.acoef + (pm ? (size_t)q : 8 * (size_t)k + comp);
     // knot value idx (clamped to the grid: in bounds, unused past it)
     auto ldy = [&](int idx) {
         const int i = min(max(idx, 0), K - 1);
@@ -514,7 +517,7 @@ __device__ __forceinline__ void fit_sweeps(const FitJob &jb, int tid, int q, int
 // first, the serial chain (one fused multiply-add per row) runs in registers,
 // and the batch's results are stored after it.  STAGED, the back sweep finds
 // the slopes only and the whole workgroup then forms the coefficients, each
-// store of a wave covering 64 consecutive series.
+// store of a wave covering 64 consecutive values of the coefficient array.
 template <bool STAGED>
 __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     const int K = jb.K, M = jb.M;
@@ -553,28 +556,57 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     fit_factor_finish(hs, K, invd, wv, bv);
     __syncthreads();
     const int q = q0 + tid;
-    // acoef is [K-1][4][2M]: coefficient p of series q on interval i at
-    // o[i * cs + p * ps], so the 64 lanes of a store write 512 contiguous bytes
-    const size_t ps = 2 * (size_t)M, cs = 4 * ps;
     if (tid < kFitSeriesPerBlock && q < 2 * M)
         fit_sweeps<STAGED>(jb, tid, q, K, M, hs, invd, wv, ih, bv, ys, gs);
     if (!STAGED) return;
-    // STAGED: gs holds the slopes; every lane of the workgroup forms and
-    // stores coefficients, consecutive lanes writing consecutive series
+    // STAGED: gs holds the slopes; every lane of the workgroup forms the four
+    // coefficients of one (interval, series) pair, consecutive lanes taking
+    // consecutive series (wave w takes interval r = 4 i + w).
     __syncthreads();
     const int ns = min(kFitSeriesPerBlock, 2 * M - q0);
-    for (int x = tid; x < (K - 1) * kFitSeriesPerBlock; x += bs) {
+    const int total = (K - 1) * kFitSeriesPerBlock;
+    if (jb.acoef_pmajor) {
+        // [K-1][4][2M]: each store of a wave writes 512 contiguous bytes
+        const size_t ps = 2 * (size_t)M, cs = 4 * ps;
+        for (int x = tid; x < total; x += bs) {
+            const int r = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
+            if (sj >= ns) continue;
+            const double y0 = ys[x], y1 = ys[x + kFitSeriesPerBlock];
+            const double s0 = gs[x], s1 = gs[x + kFitSeriesPerBlock];
+            const double ir = ih[r];
+            const double dr = (y1 - y0) * ir;
+            double *orow = jb.acoef + (size_t)r * cs + q0 + sj;
+            orow[0] = y0;
+            orow[ps] = s0;
+            orow[2 * ps] = (3.0 * dr - 2.0 * s0 - s1) * ir;
+            orow[3 * ps] = (s0 + s1 - 2.0 * dr) * (ir * ir);
+        }
+        return;
+    }
+    // [K-1][M][4][2]: the lanes write their coefficients into the wave's
+    // 2 KB LDS slot in that order and the wave stores the slot as the
+    // interval's contiguous run (two 1 KB stores).  LDS accesses of one wave
+    // complete in order, so the slot needs no barrier.
+    const int k0 = q0 >> 1, lane = tid & (kWave - 1);
+    double *wsc = gs + (size_t)K * kFitSeriesPerBlock + (tid / kWave) * (4 * kFitSeriesPerBlock);
+    for (int x = tid; x < total; x += bs) {
         const int r = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
-        if (sj >= ns) continue;
         const double y0 = ys[x], y1 = ys[x + kFitSeriesPerBlock];
         const double s0 = gs[x], s1 = gs[x + kFitSeriesPerBlock];
         const double ir = ih[r];
         const double dr = (y1 - y0) * ir;
-        double *orow = jb.acoef + (size_t)r * cs + q0 + sj;
-        orow[0] = y0;
-        orow[ps] = s0;
-        orow[2 * ps] = (3.0 * dr - 2.0 * s0 - s1) * ir;
-        orow[3 * ps] = (s0 + s1 - 2.0 * dr) * (ir * ir);
+        double *d = wsc + 8 * (sj >> 1) + (sj & 1);
+        d[0] = y0;
+        d[2] = s0;
+        d[4] = (3.0 * dr - 2.0 * s0 - s1) * ir;
+        d[6] = (s0 + s1 - 2.0 * dr) * (ir * ir);
+        __builtin_amdgcn_wave_barrier();
+        const double2 *rd = (const double2 *)wsc;
+        double2 *dst = (double2 *)(jb.acoef + ((size_t)r * M + k0) * 8);
+        const double2 v0 = rd[lane], v1 = rd[kWave + lane];
+        if (lane < 2 * ns) dst[lane] = v0;               // run of 4 ns doubles
+        if (kWave + lane < 2 * ns) dst[kWave + lane] = v1;
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -722,14 +754,13 @@ __device__ void fold_pair(const PrepJob &jb, int i, int term) {
             acc[2 * q + 1] += w.x * ai + w.y * ar;
         }
     };
-    // acoef [K-1][4][2M]: coefficient p of mode k on interval i at
-    // arow[p * 2M + 2k + {0, 1}]
-    const size_t ps = 2 * (size_t)jb.M;
-    const double *arow = jb.acoef + (size_t)i * 4 * ps;
+    // acoef [K-1][M][4][2] (vector-path requests): the 8 values of mode k on
+    // interval i are contiguous, one 64-byte segment per contributor
+    const double *arow = jb.acoef + (size_t)i * 8 * jb.M;
     auto load8 = [&](int k, double *a) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const double2 v = *(const double2 *)(arow + p * ps + 2 * (size_t)k);
+            const double2 v = *(const double2 *)(arow + 8 * (size_t)k + 2 * p);
             a[2 * p] = v.x;
             a[2 * p + 1] = v.y;
         }
@@ -1564,7 +1595,9 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
     const int t0 = g0 < jb.n_segs ? jb.segs[g0].w : jb.n_terms;
     const int t1 = g1 < jb.n_segs ? jb.segs[g1].w : jb.n_terms;
     const double h = jb.t[iv + 1] - jb.t[iv];
-    // acoef [K-1][4][2M]: coefficient p of mode k at arow[p * 2M + 2k + {0, 1}]
+    // acoef [K-1][4][2M] (matrix-core requests): coefficient p of mode k at
+    // arow[p * 2M + 2k + {0, 1}], so lanes taking consecutive modes read
+    // contiguous memory in each of the four planes
     const size_t ps = 2 * (size_t)jb.M;
     const double *arow = jb.acoef + (size_t)iv * 4 * ps;
     auto load8 = [&](int mode, double *a) {
@@ -2529,27 +2562,8 @@ hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t s
     return hipGetLastError();
 }
 
-static inline size_t fit_lds_bytes(int K) {
-    // phase workgroups: 9 arrays of K; amplitude workgroups: 5 arrays of K,
-    // plus (K <= kFitStageKnots) the staged knot values and forward results
-    size_t n = 9 * (size_t)K;
-    if (K <= kFitStageKnots) n = std::max(n, (5 + 2 * (size_t)kFitSeriesPerBlock) * K);
-    return sizeof(double) * n;
-}
-
-static void fit_lds_attributes() {
-    static std::once_flag once;
-    std::call_once(once, [] {
-        const int bytes = (int)fit_lds_bytes(kFitStageKnots);
-        hipFuncSetAttribute((const void *)fit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
-        hipFuncSetAttribute((const void *)fit_batch_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    });
-}
-
 // Amplitude coefficients in the documented export layout: dst [K-1][M][4][2]
-// from the internal [K-1][4][2M].
+// from the matrix-core requests' internal [K-1][4][2M].
 __global__ __launch_bounds__(256) void acoef_export_kernel(const double *src, double *dst,
                                                            long long K1, long long M) {
     const long long n = K1 * M * 8;
@@ -2567,6 +2581,26 @@ hipError_t launch_acoef_export(const double *src, double *dst, int K, int M,
     hipLaunchKernelGGL(acoef_export_kernel, dim3(blocks), dim3(256), 0, stream, src, dst,
                        (long long)(K - 1), (long long)M);
     return hipGetLastError();
+}
+
+static inline size_t fit_lds_bytes(int K) {
+    // phase workgroups: 9 arrays of K; amplitude workgroups: 5 arrays of K,
+    // plus (K <= kFitStageKnots) the staged knot values and forward results
+    size_t n = 9 * (size_t)K;
+    if (K <= kFitStageKnots)    // + one 2 KB coefficient slot per wave
+        n = std::max(n, (5 + 2 * (size_t)kFitSeriesPerBlock) * K + 4 * 4 * kFitSeriesPerBlock);
+    return sizeof(double) * n;
+}
+
+static void fit_lds_attributes() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const int bytes = (int)fit_lds_bytes(kFitStageKnots);
+        hipFuncSetAttribute((const void *)fit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+        hipFuncSetAttribute((const void *)fit_batch_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    });
 }
 
 hipError_t launch_fit(const FitJob &job, hipStream_t stream) {
