@@ -166,3 +166,35 @@ def test_mfma_inner_product_matches_its_waveform(env):
         f"hh err {abs(got[1] - ref_hh) / ref_hh:.2e}")
     assert abs(got[0] - ref_dh) <= 1e-12 * norm
     assert abs(got[1] - ref_hh) <= 1e-12 * ref_hh
+
+
+@pytest.mark.parametrize("K", [40, 150])
+def test_coefficient_layouts_export_the_same_values(env, K):
+    """Matrix-core requests keep their amplitude cubics interval-major
+    ([K-1][4][2M]), other requests mode-major ([K-1][M][4][2]); the fit
+    computes the same values either way, so few_spline_coefs returns the same
+    bits from a mixed plan (matrix-core layout, exported through the
+    transposing copy) and a vector-only plan, staged (K <= 128) or streamed
+    (K > 128).  The phase cubics are shared."""
+    native, torch, dev = env
+    w = full_modes_short(3, 2000, K=K)
+    assert takes_mfma_path(native, w.lmn)
+    pp, pr, amp = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                   for a in (w.phi_phi, w.phi_r, w.amp))
+    got = {}
+    for vec in (False, True):
+        with native.Plan(0, "mixed", vector_only=vec) as plan:
+            sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+            got[vec] = (sp.coefs(0).cpu().numpy(), sp.coefs(1).cpu().numpy())
+            torch.cuda.synchronize()
+    log(f"[mfma] layouts K={K} M={w.M}: {got[False][0].shape}")
+    assert got[False][0].shape == (K - 1, w.M, 4, 2)
+    np.testing.assert_array_equal(got[False][0], got[True][0])
+    np.testing.assert_array_equal(got[False][1], got[True][1])
+    ref = oracle.spline_coefs(w.t_knots, w.amp[:, :8].reshape(w.K, -1))   # 8 modes
+    ref = ref.reshape(w.K - 1, 8, 2, 4).transpose(0, 1, 3, 2)
+    h = np.diff(w.t_knots)
+    ya = np.abs(w.amp[:, :8]).max()
+    for p in range(4):
+        d = np.abs(got[False][0][:, :8, p, :] - ref[:, :, p, :]) * (h ** p)[:, None, None]
+        assert d.max() <= 1e-13 * ya, p
