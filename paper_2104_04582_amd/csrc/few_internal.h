@@ -89,10 +89,11 @@ inline int split_tile_samples() { return kWave * kSamplesPerLaneF32; }
 // fp32 accumulation; the sum over p is a Horner recurrence in u on the
 // accumulators.  Only the powers f^a, a = |n| >= 0, are formed: a column of
 // n < 0 multiplies conj(f^|n|), and the conjugation lives in the coefficient
-// matrix, so the columns of n and -n share one operand fragment.  Fixed
-// shape: kMfMT tiles of 16 matrix rows (8 signed m each), two signs x kMfT
-// steps of 32 columns (16 values of |n| each; |n| < 16 kMfT), kMfNT tiles of
-// 16 samples per wave, kMfWaves waves per workgroup.  A request takes this
+// matrix, so the terms n and -n meet the same operand fragment and their
+// coefficient rows are added into one (the product is linear in them).
+// Fixed shape: kMfMT tiles of 16 matrix rows (8 signed m each), kMfT steps of
+// 32 columns (16 values of |n| each; |n| < 16 kMfT), kMfNT tiles of 16
+// samples per wave, kMfWaves waves per workgroup.  A request takes this
 // path when its term layout fits the shape and is long enough to repay it.
 #ifndef FEW_MF_NT
 #define FEW_MF_NT 3
@@ -107,8 +108,8 @@ constexpr int kMfWaves = FEW_MF_WAVES;
 constexpr int kMfRows = 8 * kMfMT;          // signed m values per request
 constexpr int kMfA = 16 * kMfT;             // |n| < kMfA
 constexpr int kMfRound = kMfWaves * kMfNT * 16;   // samples per workgroup round
-// fp16 values of one interval: [p 4][mt][sign 2][t][hi, lo][lane 64][8]
-constexpr size_t kMfIntervalHalves = (size_t)4 * kMfMT * 2 * kMfT * 2 * 64 * 8;
+// fp16 values of one interval: [p 4][mt][t][hi, lo][lane 64][8]
+constexpr size_t kMfIntervalHalves = (size_t)4 * kMfMT * kMfT * 2 * 64 * 8;
 constexpr int kMfMinTerms = 480;            // below this the vector kernel is cheaper
 
 // ---------------------------------------------------------------------------

@@ -379,7 +379,7 @@ extern "C" void few_host_mfma_shape(int32_t *out8) {
     out8[1] = kMfNT;
     out8[2] = kMfMT;
     out8[3] = kMfT;
-    out8[4] = 4 * kMfMT * 2 * kMfT * 3;
+    out8[4] = 4 * kMfMT * kMfT * 3;
     out8[5] = kMfA;
     out8[6] = kMfRows;
     out8[7] = kMfMinTerms;

@@ -1547,19 +1547,20 @@ typedef float mf_float4 __attribute__((ext_vector_type(4)));
 // row and l.  The folded values stay in LDS.
 //
 // Pack.  Row r is the pair of matrix rows 2r (real part) and 2r + 1
-// (imaginary part).  For power p, column (n, c) multiplies Re w (c = 0) or
-// Im w (c = 1), w = f^|n|.  For n >= 0, C w is (Re C Re w - Im C Im w) +
-// i (Im C Re w + Re C Im w), so row 2r holds (Re C, -Im C) and row 2r + 1
-// holds (Im C, Re C); for n < 0, C conj(w) is (Re C Re w + Im C Im w) +
-// i (Im C Re w - Re C Im w): (Re C, Im C) and (Im C, -Re C).  Each row is
-// scaled by 2^-E, E the exponent of its largest |value| on the interval (so
-// scaled values stay below 1), and split into hi = fp16(v) and
-// lo = fp16(v - hi), both from binary64.  Table layout, per interval:
-// [3 - p][mt][sign][t][hi, lo][lane 64][8 values] (p descending, the order of
-// the Horner recurrence that reads it), lane l's operand fragment of
+// (imaginary part).  For power p, column (a, c) multiplies Re w (c = 0) or
+// Im w (c = 1), w = f^a, a = |n|.  The terms n = a and n = -a of the row
+// (coefficients P and Q) contribute P w + Q conj(w) =
+// ((Re P + Re Q) Re w + (Im Q - Im P) Im w) +
+// i ((Im P + Im Q) Re w + (Re P - Re Q) Im w),
+// so row 2r holds (Re P + Re Q, Im Q - Im P) and row 2r + 1 holds
+// (Im P + Im Q, Re P - Re Q) (Q = 0 for a = 0).  Each row is scaled by 2^-E,
+// E the exponent of its largest |coefficient| on the interval (so scaled
+// values stay below 2), and split into hi = fp16(v) and lo = fp16(v - hi),
+// both from binary64.  Table layout, per interval:
+// [3 - p][mt][t][hi, lo][lane 64][8 values] (p descending, the order of the
+// Horner recurrence that reads it), lane l's operand fragment of
 // v_mfma_f32_16x16x32_f16: matrix row l % 16 of the tile, columns
-// |n| = 16 t + 4 (l / 16) + i / 2 and c = i % 2 for value i (sign 0: n = |n|,
-// sign 1: n = -|n|, whose n = 0 column is zero).
+// a = 16 t + 4 (l / 16) + i / 2 and c = i % 2 for value i.
 __device__ void fold_pack_body(const PrepJob &jb, int b) {
     if (b == 0) {
         prep_intervals(jb);
@@ -1681,28 +1682,27 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
     }
     __syncthreads();
     _Float16 *dst = (_Float16 *)jb.mtab + (size_t)iv * kMfIntervalHalves;
-    for (int it = tid; it < 4 * 2 * kMfT * 64; it += blockDim.x) {
-        const int ln = it & 63, t = (it >> 6) % kMfT, sg = ((it >> 6) / kMfT) & 1;
-        const int p = (it >> 6) / (2 * kMfT);
+    for (int it = tid; it < 4 * kMfT * 64; it += blockDim.x) {
+        const int ln = it & 63, t = (it >> 6) % kMfT, p = (it >> 6) / kMfT;
         const int kk = (ln & 15) >> 1, comp = ln & 1, g = ln >> 4;
         const double sc = rsc[kk];
         mf_half8 hi, lo;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int a = 16 * t + 4 * g + j;
-            const int n = sg == 0 ? a : -a;
-            double cr = 0.0, ci = 0.0;
-            if (sg == 0 || a > 0) {
-                cr = cf[kk][n + kMfA - 1][2 * p];
-                ci = cf[kk][n + kMfA - 1][2 * p + 1];
+            const double pr = cf[kk][a + kMfA - 1][2 * p], pi = cf[kk][a + kMfA - 1][2 * p + 1];
+            double qr = 0.0, qi = 0.0;
+            if (a > 0) {
+                qr = cf[kk][-a + kMfA - 1][2 * p];
+                qi = cf[kk][-a + kMfA - 1][2 * p + 1];
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 double v;
-                if (sg == 0)
-                    v = c == 0 ? (comp == 0 ? cr : ci) : (comp == 0 ? -ci : cr);
+                if (comp == 0)
+                    v = c == 0 ? pr + qr : qi - pi;
                 else
-                    v = c == 0 ? (comp == 0 ? cr : ci) : (comp == 0 ? ci : -cr);
+                    v = c == 0 ? pi + qi : pr - qr;
                 v = v * sc;
                 // through binary32 (one instruction each way; the pair still
                 // carries about 22 bits: lo takes the exact binary64 residual)
@@ -1712,7 +1712,7 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
             }
         }
         const size_t at =
-            (((((size_t)(3 - p) * kMfMT + mt) * 2 + sg) * kMfT + t) * 2) * 512 + (size_t)ln * 8;
+            ((((size_t)(3 - p) * kMfMT + mt) * kMfT + t) * 2) * 512 + (size_t)ln * 8;
         *(mf_half8 *)(dst + at) = hi;
         *(mf_half8 *)(dst + at + 512) = lo;
     }
@@ -1878,14 +1878,14 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
 #pragma unroll
                 for (int nt = 0; nt < kMfNT; ++nt) acc[mt][nt] = acc[mt][nt] * uu[nt];
         }
-        // operand fragments of power p, (mt, sign, t) in order, each read one
+        // operand fragments of power p, (mt, t) in order, each read one
         // fragment ahead of its products (constant offsets from fp)
-        const float4 *fp = lds + (size_t)(3 - p) * kMfMT * 2 * kMfT * 2 * 64 + lane;
-        constexpr int NF = kMfMT * 2 * kMfT;
+        const float4 *fp = lds + (size_t)(3 - p) * kMfMT * kMfT * 2 * 64 + lane;
+        constexpr int NF = kMfMT * kMfT;
         float4 ch = fp[0], cl = fp[64];
 #pragma unroll
         for (int k = 0; k < NF; ++k) {
-            const int t = k % kMfT, mt = k / (2 * kMfT);
+            const int t = k % kMfT, mt = k / kMfT;
             float4 nh = ch, nl = cl;
             if (k + 1 < NF) {
                 nh = fp[((k + 1) * 2) * 64];

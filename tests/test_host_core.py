@@ -135,11 +135,11 @@ def test_request_bytes():
     a = native.host_request_bytes("fp64", 100, 3843, 1281)
     b = native.host_request_bytes("mixed", 100, 3843, 1281)
     # a binary32 request long enough for the matrix-core path holds the fp16
-    # operand table (99 intervals x 96 KiB) instead of a binary64 fold table
+    # operand table (99 intervals x 48 KiB) instead of a binary64 fold table
     # (99 x 1281 x 64 B)
-    assert b > a > 99 * 3843 * 64
+    assert a > b > 99 * 3843 * 64
     # (plus the per-interval row scales and row list, a few KiB)
-    assert abs((b - a) - (99 * 96 * 1024 - 99 * 1281 * 64)) <= 16384
+    assert abs((b - a) - (99 * 48 * 1024 - 99 * 1281 * 64)) <= 16384
     # shorter binary32 requests keep the binary32 fold table only
     c = native.host_request_bytes("fp64", 100, 300, 400)
     d = native.host_request_bytes("mixed", 100, 300, 400)
@@ -244,7 +244,9 @@ def test_mfma_path_and_shape():
     shape = native.host_mfma_shape()
     assert shape["max_rows"] == 24 and shape["abs_n_limit"] == 32
     assert shape["min_terms"] == 480
-    assert shape["mfma_per_tile"] == 4 * shape["row_tiles"] * 2 * shape["column_steps"] * 3
+    # per 16-sample tile and round: 4 powers x row tiles x column steps x
+    # 3 hi/lo products (the terms n and -n share one operand fragment)
+    assert shape["mfma_per_tile"] == 4 * shape["row_tiles"] * shape["column_steps"] * 3
     full = synth.mode_list(2, 10, 30)                 # 21 signed m, |n| <= 30, 1281 terms
     assert native.host_mfma_path(full)
     assert not native.host_mfma_path(synth.mode_list(2, 4, 5))        # 99 terms
