@@ -1784,20 +1784,32 @@ __device__ __forceinline__ void split1(float a, float one, _Float16 &hi, _Float1
 // Lane value of lane `src` (a row of 16 lanes broadcast to all four rows).
 __device__ __forceinline__ float lane_get(float v, int src) { return __shfl(v, src); }
 
+// Per-wave LDS area of the per-sample values of one round (SoA, SPW samples):
+// f, f^16, f^{4g} (g = 0..3), e^{-i Phi_phi}, its 8th power, the row
+// harmonic z_0 e^{-2ig Phi_phi} (g = 0..3), u, and the reduced Phi_phi.
+constexpr int kMfSPW = kMfNT * 16;                  // samples per wave and round
+struct MfSampleArea {
+    float2 f[kMfSPW], f16[kMfSPW], c[kMfSPW][4];
+    float2 e[kMfSPW], e8[kMfSPW], zg[kMfSPW][4];
+    float u[kMfSPW];
+    double pf[kMfSPW];
+};
+
 // One round of a workgroup: wave w takes the kMfNT * 16 samples
 // base + w kMfNT 16 + s, s = 16 nt + c (tiles nt of 16, valid below e).  The
 // lanes first form the per-sample values of sample s = lane + 64 k (phases,
-// harmonics and their powers); in tile nt the four lane groups g = l / 16 of
-// column c read them from the lane that formed them.  Group g holds the
-// operand columns |n| = 16 t + 4 g + j, j < 4, of step t: f^{16 t + 4 g} times
-// f^j (the same fragment serves n and -n).  The accumulators run a Horner
-// recurrence in u over p = 3 .. 0.  Returns this lane's binary64
-// inner-product sums (INNER) or stores h.
+// harmonics and their powers) into the wave's LDS area; in tile nt the four
+// lane groups g = l / 16 of column c read what they need of sample 16 nt + c
+// from there.  Group g holds the operand columns |n| = 16 t + 4 g + j, j < 4,
+// of step t: f^{16 t + 4 g} times f^j (the same fragment serves n and -n).
+// The accumulators run a Horner recurrence in u over p = 3 .. 0.  Returns this
+// lane's binary64 inner-product sums (INNER) or stores h.  The LDS accesses of
+// one wave complete in order, so its area needs no barrier.
 template <bool INNER>
 __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long base,
                                             long long e, const float4 *lds, const float *msc,
-                                            const int *mm, bool consec) {
-    constexpr int SPW = kMfNT * 16;                 // samples per wave
+                                            const int *mm, bool consec, MfSampleArea *sa) {
+    constexpr int SPW = kMfSPW;
     constexpr int OWN = (SPW + kWave - 1) / kWave;  // samples formed per lane
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int g = lane >> 4, col = lane & 15;
@@ -1806,42 +1818,87 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
     const double inv_h = 1.0 / (tk[iv + 1] - ti);
     const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 16;
     const long long wbase = base + (long long)w * SPW;
-    // this lane's samples
-    double pf[OWN], pr[OWN];
-    float u[OWN], er[OWN], ei[OWN], fr[OWN], fi[OWN], f4r[OWN], f4i[OWN], f8r[OWN], f8i[OWN];
-    float f12r[OWN], f12i[OWN], f16r[OWN], f16i[OWN];
+    const int m0 = mm[0], am0 = m0 < 0 ? -m0 : m0;
+    // this lane's samples -> the wave's area
 #pragma unroll
     for (int k = 0; k < OWN; ++k) {
-        long long j = wbase + lane + (long long)kWave * k;
+        const int sl = lane + kWave * k;
+        if (sl >= SPW) break;
+        long long j = wbase + sl;
         if (j >= e) j = e - 1;
         const double tj = dev_sample_time(jb.t_start, jb.dt, j);
         const dd x = two_sum(tj, -ti);
-        pf[k] = phase_raw(pc, x.hi);
-        pr[k] = phase_raw(pc + 8, x.hi);
-        u[k] = (float)(x.hi * inv_h);
-        phasor_f32(pf[k], &er[k], &ei[k]);
-        phasor_f32(pr[k], &fr[k], &fi[k]);
-        float f2r, f2i;
-        cmulf(fr[k], fi[k], fr[k], fi[k], &f2r, &f2i);
-        cmulf(f2r, f2i, f2r, f2i, &f4r[k], &f4i[k]);
-        cmulf(f4r[k], f4i[k], f4r[k], f4i[k], &f8r[k], &f8i[k]);
-        cmulf(f8r[k], f8i[k], f4r[k], f4i[k], &f12r[k], &f12i[k]);
-        cmulf(f8r[k], f8i[k], f8r[k], f8i[k], &f16r[k], &f16i[k]);
+        const double pf = phase_raw(pc, x.hi);
+        const double pr = phase_raw(pc + 8, x.hi);
+        float er, ei, fr, fi;
+        phasor_f32(pf, &er, &ei);
+        phasor_f32(pr, &fr, &fi);
+        float f2r, f2i, f4r, f4i, f8r, f8i, f12r, f12i, f16r, f16i;
+        cmulf(fr, fi, fr, fi, &f2r, &f2i);
+        cmulf(f2r, f2i, f2r, f2i, &f4r, &f4i);
+        cmulf(f4r, f4i, f4r, f4i, &f8r, &f8i);
+        cmulf(f8r, f8i, f4r, f4i, &f12r, &f12i);
+        cmulf(f8r, f8i, f8r, f8i, &f16r, &f16i);
+        sa->u[sl] = (float)(x.hi * inv_h);
+        sa->f[sl] = make_float2(fr, fi);
+        sa->f16[sl] = make_float2(f16r, f16i);
+        sa->c[sl][0] = make_float2(1.0f, 0.0f);
+        sa->c[sl][1] = make_float2(f4r, f4i);
+        sa->c[sl][2] = make_float2(f8r, f8i);
+        sa->c[sl][3] = make_float2(f12r, f12i);
+        sa->e[sl] = make_float2(er, ei);
+        if (consec) {
+            // Rows of consecutive m (m_r = m_0 + r): every z_r is a power of
+            // E = e^{-i Phi_phi}.  z_0 = E^{m_0} by binary powering (E^{-1} =
+            // conj E), so each z_r carries m_r times the phase error of E, at
+            // most max |m| of it.  Lane group g starts from z_0 E^{2g}.
+            float e2r, e2i, e4r, e4i, e6r, e6i, e8r, e8i;
+            cmulf(er, ei, er, ei, &e2r, &e2i);
+            cmulf(e2r, e2i, e2r, e2i, &e4r, &e4i);
+            cmulf(e4r, e4i, e2r, e2i, &e6r, &e6i);
+            cmulf(e4r, e4i, e4r, e4i, &e8r, &e8i);
+            float zr = 1.0f, zi = 0.0f, br = e8r, bi = e8i;
+            auto take = [&](float qr, float qi) {
+                float nr, ni;
+                cmulf(zr, zi, qr, qi, &nr, &ni);
+                zr = nr;
+                zi = ni;
+            };
+            if (am0 & 1) take(er, ei);
+            if (am0 & 2) take(e2r, e2i);
+            if (am0 & 4) take(e4r, e4i);
+            for (int bit = 8; bit <= am0; bit <<= 1) {
+                if (am0 & bit) take(br, bi);
+                float nr, ni;
+                cmulf(br, bi, br, bi, &nr, &ni);
+                br = nr;
+                bi = ni;
+            }
+            if (m0 < 0) zi = -zi;
+            sa->e8[sl] = make_float2(e8r, e8i);
+            sa->zg[sl][0] = make_float2(zr, zi);
+            float qr, qi;
+            cmulf(zr, zi, e2r, e2i, &qr, &qi);
+            sa->zg[sl][1] = make_float2(qr, qi);
+            cmulf(zr, zi, e4r, e4i, &qr, &qi);
+            sa->zg[sl][2] = make_float2(qr, qi);
+            cmulf(zr, zi, e6r, e6i, &qr, &qi);
+            sa->zg[sl][3] = make_float2(qr, qi);
+        } else {
+            sa->pf[sl] = d_reduce_2pi(pf);
+        }
     }
+    __builtin_amdgcn_wave_barrier();
     // operands: powers of f for every tile and step
     mf_half8 bh[kMfNT][kMfT], bl[kMfNT][kMfT];
     float uu[kMfNT];
 #pragma unroll
     for (int nt = 0; nt < kMfNT; ++nt) {
-        const int src = (16 * nt + col) % kWave, k = (16 * nt) / kWave;
-        uu[nt] = lane_get(u[k], src);
-        const float ar = lane_get(fr[k], src), ai = lane_get(fi[k], src);
-        const float b4r = lane_get(f4r[k], src), b4i = lane_get(f4i[k], src);
-        const float b8r = lane_get(f8r[k], src), b8i = lane_get(f8i[k], src);
-        const float b12r = lane_get(f12r[k], src), b12i = lane_get(f12i[k], src);
-        const float sr = lane_get(f16r[k], src), si = lane_get(f16i[k], src);
-        float cr = g == 0 ? 1.0f : g == 1 ? b4r : g == 2 ? b8r : b12r;
-        float ci = g == 0 ? 0.0f : g == 1 ? b4i : g == 2 ? b8i : b12i;
+        const int sl = 16 * nt + col;
+        uu[nt] = sa->u[sl];
+        const float2 fa = sa->f[sl], fs = sa->f16[sl], c0 = sa->c[sl][g];
+        const float ar = fa.x, ai = fa.y, sr = fs.x, si = fs.y;
+        float cr = c0.x, ci = c0.y;
 #pragma unroll
         for (int t = 0; t < kMfT; ++t) {
             float v[8];
@@ -1912,12 +1969,6 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
             cl = nl;
         }
     }
-    // Rows -> h.  Row r's harmonic is z_r = e^{-i m_r Phi_phi}.
-    // With consecutive m values (m_r = m_0 + r) every z_r is a power of
-    // E = e^{-i Phi_phi}: the sample's lane forms E^2, E^4, E^6, E^8 and
-    // z_0 = E^{m_0} (binary powering, E^{-1} = conj E), and group g starts
-    // from z_0 E^{2g}.  Each z_r then carries m_r times the phase error of E,
-    // at most max |m| of it.  Otherwise every row takes its own sincos.
     // INNER: the data samples of this lane's columns, requested now so that
     // their latency overlaps the row combination
     float2 dv[kMfNT];
@@ -1928,93 +1979,69 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
             dv[nt] = (g == 0 && jr < e) ? ((const float2 *)jb.data)[jr] : make_float2(0.0f, 0.0f);
         }
     }
-    const int m0 = mm[0], am0 = m0 < 0 ? -m0 : m0;
-    float z0r[OWN], z0i[OWN], e2r[OWN], e2i[OWN], e4r[OWN], e4i[OWN], e6r[OWN], e6i[OWN];
-    float e8r[OWN], e8i[OWN];
+    // Rows -> h.  The lane holds rows r = 8 mt + 2g (a0 + i b0) and r + 1
+    // (a1 + i b1) of tile mt, each to be scaled by 2^{E_r} and multiplied by
+    // its harmonic z_r = e^{-i m_r Phi_phi}.
+    float se[kMfMT], so[kMfMT];
+    int me[kMfMT], mo[kMfMT];
 #pragma unroll
-    for (int k = 0; k < OWN; ++k) {
-        z0r[k] = z0i[k] = e2r[k] = e2i[k] = e4r[k] = e4i[k] = 0.0f;
-        e6r[k] = e6i[k] = e8r[k] = e8i[k] = 0.0f;
-        if (consec) {
-            cmulf(er[k], ei[k], er[k], ei[k], &e2r[k], &e2i[k]);
-            cmulf(e2r[k], e2i[k], e2r[k], e2i[k], &e4r[k], &e4i[k]);
-            cmulf(e4r[k], e4i[k], e2r[k], e2i[k], &e6r[k], &e6i[k]);
-            cmulf(e4r[k], e4i[k], e4r[k], e4i[k], &e8r[k], &e8i[k]);
-            // E^{|m_0|}; the bits of |m_0| are uniform across the workgroup
-            float zr = 1.0f, zi = 0.0f, br = e8r[k], bi = e8i[k];
-            auto take = [&](float pr, float pi) {
-                float nr, ni;
-                cmulf(zr, zi, pr, pi, &nr, &ni);
-                zr = nr;
-                zi = ni;
-            };
-            if (am0 & 1) take(er[k], ei[k]);
-            if (am0 & 2) take(e2r[k], e2i[k]);
-            if (am0 & 4) take(e4r[k], e4i[k]);
-            for (int bit = 8; bit <= am0; bit <<= 1) {
-                if (am0 & bit) take(br, bi);
-                float nr, ni;
-                cmulf(br, bi, br, bi, &nr, &ni);
-                br = nr;
-                bi = ni;
-            }
-            z0r[k] = zr;
-            z0i[k] = m0 < 0 ? -zi : zi;
-        }
+    for (int mt = 0; mt < kMfMT; ++mt) {
+        const int r0 = 8 * mt + 2 * g;
+        se[mt] = msc[r0];
+        so[mt] = msc[r0 + 1];
+        me[mt] = mm[r0];
+        mo[mt] = mm[r0 + 1];
     }
     double dh = 0.0, hh = 0.0;
 #pragma unroll
     for (int nt = 0; nt < kMfNT; ++nt) {
-        const int src = (16 * nt + col) % kWave, k = (16 * nt) / kWave;
-        const float Er = lane_get(er[k], src), Ei = lane_get(ei[k], src);
-        float hr = 0.0f, hq = 0.0f;
-        // h += (z 2^E) (a + i b) for the lane's two rows of tile mt
-        auto add_rows = [&](int mt, float zr, float zi, float yr, float yi) {
-            const int r0 = 8 * mt + 2 * g;
-            const float s0 = msc[r0], s1 = msc[r0 + 1];
-            const float zsr = zr * s0, zsi = zi * s0, ysr = yr * s1, ysi = yi * s1;
-            const float a0 = acc[mt][nt][0], b0 = acc[mt][nt][1];
-            const float a1 = acc[mt][nt][2], b1 = acc[mt][nt][3];
-            hr = __builtin_fmaf(zsr, a0, __builtin_fmaf(-zsi, b0, hr));
-            hq = __builtin_fmaf(zsr, b0, __builtin_fmaf(zsi, a0, hq));
-            hr = __builtin_fmaf(ysr, a1, __builtin_fmaf(-ysi, b1, hr));
-            hq = __builtin_fmaf(ysr, b1, __builtin_fmaf(ysi, a1, hq));
-        };
+        const int sl = 16 * nt + col;
+        const float2 E = sa->e[sl];
+        float hr, hq;
         if (consec) {
-            const float q0r = lane_get(z0r[k], src), q0i = lane_get(z0i[k], src);
-            const float q2r = lane_get(e2r[k], src), q2i = lane_get(e2i[k], src);
-            const float q4r = lane_get(e4r[k], src), q4i = lane_get(e4i[k], src);
-            const float q6r = lane_get(e6r[k], src), q6i = lane_get(e6i[k], src);
-            const float q8r = lane_get(e8r[k], src), q8i = lane_get(e8i[k], src);
-            const float gr = g == 0 ? 1.0f : g == 1 ? q2r : g == 2 ? q4r : q6r;
-            const float gi = g == 0 ? 0.0f : g == 1 ? q2i : g == 2 ? q4i : q6i;
-            float zr, zi;
-            cmulf(q0r, q0i, gr, gi, &zr, &zi);          // z_{2g}
+            // z_r = z_0 E^{2g} E^{8 mt} (E for the odd row): Horner in E^8
+            // over the tiles of W_mt = s_e (a0 + i b0) + E s_o (a1 + i b1)
+            const float2 E8 = sa->e8[sl], Z = sa->zg[sl][g];
+            float qr = 0.0f, qi = 0.0f;
 #pragma unroll
-            for (int mt = 0; mt < kMfMT; ++mt) {
-                float yr, yi;
-                cmulf(zr, zi, Er, Ei, &yr, &yi);        // z_{8 mt + 2g + 1}
-                add_rows(mt, zr, zi, yr, yi);
-                if (mt + 1 < kMfMT) {
-                    float nr, ni;
-                    cmulf(zr, zi, q8r, q8i, &nr, &ni);  // z_{8 (mt + 1) + 2g}
-                    zr = nr;
-                    zi = ni;
+            for (int mt = kMfMT - 1; mt >= 0; --mt) {
+                const float a0 = acc[mt][nt][0] * se[mt], b0 = acc[mt][nt][1] * se[mt];
+                const float a1 = acc[mt][nt][2] * so[mt], b1 = acc[mt][nt][3] * so[mt];
+                const float wr = __builtin_fmaf(E.x, a1, __builtin_fmaf(-E.y, b1, a0));
+                const float wi = __builtin_fmaf(E.x, b1, __builtin_fmaf(E.y, a1, b0));
+                if (mt == kMfMT - 1) {
+                    qr = wr;
+                    qi = wi;
+                } else {
+                    const float nr = __builtin_fmaf(qr, E8.x, __builtin_fmaf(-qi, E8.y, wr));
+                    const float ni = __builtin_fmaf(qr, E8.y, __builtin_fmaf(qi, E8.x, wi));
+                    qr = nr;
+                    qi = ni;
                 }
             }
+            cmulf(qr, qi, Z.x, Z.y, &hr, &hq);
         } else {
-            const double spf = d_reduce_2pi(__shfl(pf[k], src));
+            // rows of arbitrary m: one phasor per row (the odd row from the
+            // even one when its m is the next integer)
+            const double spf = sa->pf[sl];
+            hr = 0.0f;
+            hq = 0.0f;
 #pragma unroll
             for (int mt = 0; mt < kMfMT; ++mt) {
-                const int r0 = 8 * mt + 2 * g;
-                const int m0 = mm[r0], m1 = mm[r0 + 1];
                 float zr, zi, yr, yi;
-                phasor_f32((double)m0 * spf, &zr, &zi);
-                if (m1 == m0 + 1)
-                    cmulf(zr, zi, Er, Ei, &yr, &yi);
+                phasor_f32((double)me[mt] * spf, &zr, &zi);
+                if (mo[mt] == me[mt] + 1)
+                    cmulf(zr, zi, E.x, E.y, &yr, &yi);
                 else
-                    phasor_f32((double)m1 * spf, &yr, &yi);
-                add_rows(mt, zr, zi, yr, yi);
+                    phasor_f32((double)mo[mt] * spf, &yr, &yi);
+                const float zsr = zr * se[mt], zsi = zi * se[mt];
+                const float ysr = yr * so[mt], ysi = yi * so[mt];
+                const float a0 = acc[mt][nt][0], b0 = acc[mt][nt][1];
+                const float a1 = acc[mt][nt][2], b1 = acc[mt][nt][3];
+                hr = __builtin_fmaf(zsr, a0, __builtin_fmaf(-zsi, b0, hr));
+                hq = __builtin_fmaf(zsr, b0, __builtin_fmaf(zsi, a0, hq));
+                hr = __builtin_fmaf(ysr, a1, __builtin_fmaf(-ysi, b1, hr));
+                hq = __builtin_fmaf(ysr, b1, __builtin_fmaf(ysi, a1, hq));
             }
         }
         // the four lane groups hold the other rows of the same sample
@@ -2034,6 +2061,8 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
             }
         }
     }
+    // the area is rewritten by the next round only after these reads
+    __builtin_amdgcn_wave_barrier();
     return make_double2(dh, hh);
 }
 
@@ -2046,6 +2075,9 @@ template <bool INNER>
 __device__ void mf_range(const SumJob &jb, long long lo, long long hi, float4 *lds,
                          float *msc, int *mm, double2 *iacc) {
     if (lo >= hi) return;
+    // the waves' sample areas follow the operand table in LDS
+    MfSampleArea *sa = (MfSampleArea *)((char *)lds + kMfIntervalHalves * sizeof(_Float16)) +
+                       threadIdx.x / kWave;
     __syncthreads();                                // rows of a previous job no longer read
     if ((int)threadIdx.x < kMfRows) {
         const int r = threadIdx.x;
@@ -2076,7 +2108,7 @@ __device__ void mf_range(const SumJob &jb, long long lo, long long hi, float4 *l
             msc[threadIdx.x] = jb.mscale[(size_t)iv * kMfRows + threadIdx.x];
         __syncthreads();
         for (long long base = lo; base < e; base += kMfRound) {
-            const double2 v = mf_round<INNER>(jb, iv, base, e, lds, msc, mm, consec);
+            const double2 v = mf_round<INNER>(jb, iv, base, e, lds, msc, mm, consec, sa);
             if constexpr (INNER) {
                 double2 a = iacc[threadIdx.x];
                 a.x = a.x + v.x;
@@ -2794,7 +2826,9 @@ hipError_t launch_fold_pack_batch(const PrepJob *jobs_dev, int n_jobs, int max_K
     return hipGetLastError();
 }
 
-static constexpr size_t mf_lds_bytes() { return kMfIntervalHalves * sizeof(_Float16); }
+static constexpr size_t mf_lds_bytes() {
+    return kMfIntervalHalves * sizeof(_Float16) + kMfWaves * sizeof(MfSampleArea);
+}
 
 // One workgroup per compute unit (the operand table takes most of the LDS).
 int mfma_workgroups() {
