@@ -459,7 +459,6 @@ SumJob sum_job(const HostReq &r, ReqBase base, double t_start, double dt, int64_
     j.n_mrows = r.terms.n_mrows;
     j.n_min = r.terms.n_min;
     j.sample_base = 0;
-    j.unit = 1.0f;
     return j;
 }
 

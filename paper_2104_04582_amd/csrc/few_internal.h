@@ -192,7 +192,6 @@ struct SumJob {
     const int2 *mrows;      // [n_mrows + 1]
     int n_mrows, n_min;
     long long sample_base;  // first sample of this job in a batched launch's range
-    float unit;             // 1.0 (an operand the compiler cannot fold away)
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.

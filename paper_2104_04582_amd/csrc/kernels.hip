@@ -1771,14 +1771,24 @@ __device__ __forceinline__ void phasor_f32(double v, float *re, float *im) {
     *im = -sv;
 }
 
-// fp16 hi/lo parts of a binary32 value: hi = fp16(a), lo = fp16(a - hi)
-// (the difference is exact in binary32), about 22 significant bits together.
-// `one` is 1.0 from the job descriptor: written as a * one - hi the
-// difference maps onto one mixed-precision multiply-add reading hi as fp16.
-__device__ __forceinline__ void split1(float a, float one, _Float16 &hi, _Float16 &lo) {
-    const _Float16 h = (_Float16)a;
-    hi = h;
-    lo = (_Float16)__builtin_fmaf(a, one, -(float)h);
+// fp16 hi/lo parts of binary32 values, hi = fp16(a), lo = fp16(a - hi) (the
+// difference is exact in binary32): about 22 significant bits together.
+// Here for a pair, packed as two fp16 values per 32-bit word: both hi
+// parts by one packed conversion (round to nearest even), each lo part by one
+// mixed-precision multiply-add a * 1 - hi that reads hi as fp16 and writes its
+// fp16 result into one half of the lo word (written out because the compiler
+// otherwise forms each lo in binary32 and packs the pair again).
+typedef _Float16 mf_half2 __attribute__((ext_vector_type(2)));
+typedef float mf_f2 __attribute__((ext_vector_type(2)));
+typedef unsigned mf_u4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void split_pair(float a0, float a1, unsigned &hi, unsigned &lo) {
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector((mf_f2){a0, a1}, mf_half2));
+    unsigned l;
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(l) : "v"(a0), "v"(hi));
+    asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "+v"(l)
+        : "v"(a1), "v"(hi));
+    lo = l;
 }
 
 // Lane value of lane `src` (a row of 16 lanes broadcast to all four rows).
@@ -1889,8 +1899,8 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
         }
     }
     __builtin_amdgcn_wave_barrier();
-    // operands: powers of f for every tile and step
-    mf_half8 bh[kMfNT][kMfT], bl[kMfNT][kMfT];
+    // operands: powers of f for every tile and step (fp16 pairs per word)
+    mf_u4 bh[kMfNT][kMfT], bl[kMfNT][kMfT];
     float uu[kMfNT];
 #pragma unroll
     for (int nt = 0; nt < kMfNT; ++nt) {
@@ -1908,9 +1918,9 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
             cmulf(v[2], v[3], ar, ai, &v[4], &v[5]);
             cmulf(v[4], v[5], ar, ai, &v[6], &v[7]);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                _Float16 h, l;
-                split1(v[i], jb.unit, h, l);
+            for (int i = 0; i < 4; ++i) {
+                unsigned h, l;
+                split_pair(v[2 * i], v[2 * i + 1], h, l);
                 bh[nt][t][i] = h;
                 bl[nt][t][i] = l;
             }
@@ -1954,16 +1964,16 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
             const mf_half8 al = __builtin_bit_cast(mf_half8, cl);
 #pragma unroll
             for (int nt = 0; nt < kMfNT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[nt][t],
-                                                                     acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                    al, __builtin_bit_cast(mf_half8, bh[nt][t]), acc[mt][nt], 0, 0, 0);
 #pragma unroll
             for (int nt = 0; nt < kMfNT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[nt][t],
-                                                                     acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                    ah, __builtin_bit_cast(mf_half8, bl[nt][t]), acc[mt][nt], 0, 0, 0);
 #pragma unroll
             for (int nt = 0; nt < kMfNT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[nt][t],
-                                                                     acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                    ah, __builtin_bit_cast(mf_half8, bh[nt][t]), acc[mt][nt], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
             ch = nh;
             cl = nl;
