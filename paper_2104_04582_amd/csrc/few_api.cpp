@@ -607,8 +607,10 @@ hipError_t pinned_upload(void *dst, void *host, size_t bytes, hipStream_t s) {
     return launch_upload(src, dst, bytes, s);
 }
 
-// Copy n bytes from host to device on the plan stream through a pinned slot.
-int sync_upload(few_plan p, const HostReq &r, char *dst) {
+// Pack a request's host tables into the next pinned slot (waiting, if need
+// be, until the launch that last read that slot has completed); *slot is the
+// slot's index and *dev its device address.
+int stage_slot(few_plan p, const HostReq &r, int *slot, void **dev) {
     int s = p->stage_next;
     p->stage_next ^= 1;
     if (p->stage_pending[s]) {
@@ -623,11 +625,18 @@ int sync_upload(few_plan p, const HostReq &r, char *dst) {
         p->stage_size[s] = sz;
     }
     stage_upload(r, (char *)p->stage[s]);
-    HIP_TRY(pinned_upload(dst, p->stage[s], r.upload_bytes, p->stream));
-    HIP_TRY(hipEventRecord(p->stage_ev[s], p->stream));
-    p->stage_pending[s] = true;
+    HIP_TRY(hipHostGetDevicePointer(dev, p->stage[s], 0));
+    *slot = s;
     return FEW_OK;
 }
+
+// The slot may be rewritten once the work enqueued so far has read it.
+int release_slot(few_plan p, int slot) {
+    HIP_TRY(hipEventRecord(p->stage_ev[slot], p->stream));
+    p->stage_pending[slot] = true;
+    return FEW_OK;
+}
+
 
 void scheduler_main(few_plan p);
 int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter);
@@ -893,10 +902,20 @@ int spline_fit_impl(few_plan p, int32_t K, const double *t_knots, const double *
         }
         s->plan = p;
         char *base = p->arena.ptr(s->arena_off);
-        rc = sync_upload(p, s->h, base);
+        // the fit launch carries the upload: no separate copy launch
+        int slot = 0;
+        void *staged = nullptr;
+        rc = stage_slot(p, s->h, &slot, &staged);
         if (!rc) {
             FitJob job = fit_job(s->h, one_block(s->h, base), phi_phi, phi_r, amp, phi_theta);
-            rc = timed_launch(p, ST_FIT, p->stream, [&] { return launch_fit(job, p->stream); });
+            job.t = (const double *)((const char *)staged + s->h.L.off_t);
+            job.up_src = (const uint4 *)staged;
+            job.up_dst = (uint4 *)base;
+            job.up_bytes = (long long)s->h.upload_bytes;
+            rc = timed_launch(p, ST_FIT, p->stream,
+                              [&] { return launch_fit(job, s->h.t.data(), p->stream); });
+            const int rr = release_slot(p, slot);
+            if (!rc) rc = rr;
         }
         if (rc) {
             defer_release(p, s->arena_off, nullptr, p->stream);
@@ -1327,7 +1346,7 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
                                                 tile, q.short_tile);
         if (slots * tl.parts > 0x7fffffffLL) return fail(FEW_E_ARG, "too many samples");
         HIP_TRY(pinned_upload(dev, host, upload_end, s));
-        HIP_TRY(launch_fit(f, s));
+        HIP_TRY(launch_fit(f, r->h.t.data(), s));
         if (r->h.mfma) {
             HIP_TRY(launch_fold_pack(q, s));
             HIP_TRY(launch_sum_mfma(u, p->mf_wg, s));

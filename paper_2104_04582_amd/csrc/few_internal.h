@@ -131,9 +131,22 @@ struct FitJob {
     int K, M;
     int n_ph;               // phases: Phi_phi, Phi_r (, Phi_theta)
     int amp_blocks;         // blocks covering the 2M amplitude series (after n_ph phase blocks)
+    // Upload carried by this launch (single-request fits): up_bytes bytes
+    // from the pinned, host-coherent staging slot up_src to the request's
+    // arena block up_dst, copied by the amplitude workgroups' waves that do
+    // not sweep; t then points at the knots in the staging slot.  0: none.
+    const uint4 *up_src;
+    uint4 *up_dst;
+    long long up_bytes;
 };
 
 constexpr int kMaxPhases = 3;
+
+// Knot times of a single-request fit of at most kFitStageKnots knots, passed
+// by value as a launch argument.
+struct FitKnots {
+    double t[kFitStageKnots];
+};
 
 // Fold + interval bookkeeping for one request.
 struct PrepJob {
@@ -202,7 +215,9 @@ hipError_t launch_upload(const void *src, void *dst, size_t bytes, hipStream_t s
 // acoef [K-1][4][2M] -> dst [K-1][M][4][2] (the few_spline_coefs layout)
 hipError_t launch_acoef_export(const double *src, double *dst, int K, int M,
                                hipStream_t stream);
-hipError_t launch_fit(const FitJob &job, hipStream_t stream);
+// t_host: the K knot times in host memory (copied into the launch's arguments
+// when K <= kFitStageKnots).
+hipError_t launch_fit(const FitJob &job, const double *t_host, hipStream_t stream);
 hipError_t launch_fit_batch(const FitJob *jobs_dev, int n_jobs, int max_blocks, int max_K,
                             hipStream_t stream);
 hipError_t launch_prepare(const PrepJob &job, bool fp32, hipStream_t stream);

@@ -31,6 +31,7 @@
 #include "swsh.h"
 
 #include <climits>
+#include <cstring>
 #include <mutex>
 
 namespace few {
@@ -166,9 +167,8 @@ __device__ __forceinline__ void fit_factor_finish(const double *h, int K, double
 // coefficient p on interval i; p = 0 holds y_i reduced mod 2 pi.
 // LDS (binary64 arrays of length K): h hi/lo, delta hi/lo, w, inverse pivot,
 // first solution s0, right-hand side / residual / correction.
-__device__ void fit_phase_dd(const FitJob &jb, int ph, double *lds) {
+__device__ void fit_phase_dd(const FitJob &jb, const double *t, int ph, double *lds) {
     const double *y = ph == 0 ? jb.phi_phi : (ph == 1 ? jb.phi_r : jb.phi_theta);
-    const double *t = jb.t;
     const int K = jb.K;
     const int tid = threadIdx.x, bs = blockDim.x;
     double *Hh = lds, *Hl = lds + K, *Dh = lds + 2 * K, *Dl = lds + 3 * K;
@@ -502,6 +502,20 @@ __device__ __forceinline__ void fit_sweeps(const FitJob &jb, int tid, int q, int
         if (r0 - c >= 0) back(r0 - c, ga[c], yv[c]);
 }
 
+// The upload carried by a single-request fit launch: amplitude workgroup blk
+// copies its share of the 16-byte words (the tail word may run into the
+// block's alignment padding; the staging slot is at least 1 MiB), on the
+// lanes of waves 1-3, which do not take part in the sweeps.
+__device__ __forceinline__ void fit_copy_upload(const FitJob &jb, int blk) {
+    if (jb.up_bytes <= 0) return;
+    const long long words = (jb.up_bytes + 15) / 16;
+    const long long per = (words + jb.amp_blocks - 1) / jb.amp_blocks;
+    const long long w0 = (long long)blk * per, w1 = min(words, w0 + per);
+    const int lanes = (int)blockDim.x - kWave;
+    for (long long x = w0 + ((int)threadIdx.x - kWave); x < w1; x += lanes)
+        jb.up_dst[x] = jb.up_src[x];
+}
+
 // Binary64 solve of the amplitude series handled by this workgroup, one lane
 // of wave 0 per real series.  LDS: h[K], inverse pivots invd[K], multipliers
 // wv[K] and bv[K] and 1 / h[K] of the shared grid (the sweeps multiply by
@@ -519,7 +533,7 @@ __device__ __forceinline__ void fit_sweeps(const FitJob &jb, int tid, int q, int
 // the slopes only and the whole workgroup then forms the coefficients, each
 // store of a wave covering 64 consecutive values of the coefficient array.
 template <bool STAGED>
-__device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
+__device__ void fit_amplitudes(const FitJob &jb, const double *t, int blk, double *lds) {
     const int K = jb.K, M = jb.M;
     const int tid = threadIdx.x, bs = blockDim.x;
     double *hs = lds, *invd = lds + K, *wv = lds + 2 * K, *ih = lds + 3 * K, *bv = lds + 4 * K;
@@ -529,7 +543,7 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     const size_t ys_stride = 2 * (size_t)M;          // knot stride of amp
     if (tid < kWave) {
         for (int i = tid; i < K - 1; i += kWave) {
-            const double h = jb.t[i + 1] - jb.t[i];
+            const double h = t[i + 1] - t[i];
             hs[i] = h;
             ih[i] = 1.0 / h;
         }
@@ -558,6 +572,7 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     const int q = q0 + tid;
     if (tid < kFitSeriesPerBlock && q < 2 * M)
         fit_sweeps<STAGED>(jb, tid, q, K, M, hs, invd, wv, ih, bv, ys, gs);
+    if (tid >= kWave) fit_copy_upload(jb, blk);
     if (!STAGED) return;
     // STAGED: gs holds the slopes; every lane of the workgroup forms the four
     // coefficients of one (interval, series) pair, consecutive lanes taking
@@ -610,28 +625,32 @@ __device__ void fit_amplitudes(const FitJob &jb, int blk, double *lds) {
     }
 }
 
-// Workgroups 0 .. n_ph-1 fit the phases, the rest the amplitude series.
-__device__ __forceinline__ void fit_body(const FitJob &jb, double *lds) {
+// Workgroups 0 .. n_ph-1 fit the phases, the rest the amplitude series; t:
+// the knot times.
+__device__ __forceinline__ void fit_body(const FitJob &jb, const double *t, double *lds) {
     if ((int)blockIdx.x < jb.n_ph) {
-        fit_phase_dd(jb, blockIdx.x, lds);
+        fit_phase_dd(jb, t, blockIdx.x, lds);
         return;
     }
     if ((int)blockIdx.x - jb.n_ph >= jb.amp_blocks) return;
     if (jb.K <= kFitStageKnots)
-        fit_amplitudes<true>(jb, blockIdx.x - jb.n_ph, lds);
+        fit_amplitudes<true>(jb, t, blockIdx.x - jb.n_ph, lds);
     else
-        fit_amplitudes<false>(jb, blockIdx.x - jb.n_ph, lds);
+        fit_amplitudes<false>(jb, t, blockIdx.x - jb.n_ph, lds);
 }
 
-__global__ __launch_bounds__(256) void fit_kernel(FitJob jb) {
+// Single-request fit.  Grids of at most kFitStageKnots knots also arrive in
+// the launch's arguments (kt), so no workgroup waits on the host-memory
+// staging slot for them.
+__global__ __launch_bounds__(256) void fit_kernel(FitJob jb, FitKnots kt) {
     extern __shared__ double lds_fit[];
-    fit_body(jb, lds_fit);
+    fit_body(jb, jb.K <= kFitStageKnots ? kt.t : jb.t, lds_fit);
 }
 
 __global__ __launch_bounds__(256) void fit_batch_kernel(const FitJob *jobs) {
     extern __shared__ double lds_fit[];
     const FitJob jb = jobs[blockIdx.y];
-    fit_body(jb, lds_fit);
+    fit_body(jb, jb.t, lds_fit);
 }
 
 // ===========================================================================
@@ -2645,10 +2664,12 @@ static void fit_lds_attributes() {
     });
 }
 
-hipError_t launch_fit(const FitJob &job, hipStream_t stream) {
+hipError_t launch_fit(const FitJob &job, const double *t_host, hipStream_t stream) {
     fit_lds_attributes();
     dim3 grid(job.n_ph + job.amp_blocks);
-    hipLaunchKernelGGL(fit_kernel, grid, dim3(256), fit_lds_bytes(job.K), stream, job);
+    FitKnots kt;
+    if (job.K <= kFitStageKnots) std::memcpy(kt.t, t_host, sizeof(double) * job.K);
+    hipLaunchKernelGGL(fit_kernel, grid, dim3(256), fit_lds_bytes(job.K), stream, job, kt);
     return hipGetLastError();
 }
 
