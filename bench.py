@@ -275,7 +275,7 @@ def host_threads() -> int:
 
 
 CSRC = os.path.join(ROOT, "paper_2104_04582_amd", "csrc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sum_kernel_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sum_mfma_kernel_traffic.txt")
 
 
 def sources_digest() -> str:
