@@ -3,18 +3,28 @@
 // Schwarzschild sum of Eq. (10) with the mirror modes of Eq. (9), and the
 // generic-Kerr sum of Sec. VII (a third phase).
 //
-//  upload_kernel   copies a request's host tables (knots, term layout) from
-//                  pinned host memory, ordered on the compute queue.
+//  upload_kernel   copies a batch's host tables (knots, term layouts, job
+//                  descriptors) from pinned host memory, ordered on the
+//                  compute queue (a single-request fit carries its own copy).
 //  fit_kernel      not-a-knot cubic splines of every series on the shared knot
 //                  grid.  Amplitude series: binary64, one lane per real series,
 //                  the grid's tridiagonal factor computed once per workgroup
 //                  in LDS.  Phase series: double-double (one refinement step).
-//  prepare_kernel  per-request constants: first sample of every knot interval
-//                  and the tile prefixes; -2Y_lm and the fold of the l-sum
-//                  into one complex cubic per signed (m, [k,] n) term.
-//  sum_wg_kernel   binary32: one workgroup of 4 waves = one tile of
-//                  consecutive samples inside one knot interval; the term
-//                  coefficients are staged in LDS and broadcast to VGPR
+//  fold_pack_kernel  matrix-core requests: interval starts; per interval and
+//                  row tile, -2Y_lm, the fold of the l-sum, the row scales and
+//                  the fp16 hi/lo operand table.
+//  prepare_kernel  vector-path requests: interval starts and tile prefixes;
+//                  -2Y_lm and the fold of the l-sum into one complex cubic per
+//                  signed (m, [k,] n) term.
+//  sum_mfma_kernel binary32 result on the matrix cores: per interval the
+//                  product of the coefficient matrix (signed m rows) with the
+//                  harmonics f^|n| of the samples, v_mfma_f32_16x16x32_f16 on
+//                  fp16 hi/lo parts with fp32 accumulation, a Horner
+//                  recurrence in u on the accumulators, rows combined with
+//                  e^{-i m Phi_phi}.
+//  sum_wg_kernel   binary32 on the vector units: one workgroup of 4 waves = one
+//                  tile of consecutive samples inside one knot interval; the
+//                  term coefficients are staged in LDS and broadcast to VGPR
 //                  operands.  Per sample: phases in binary64 reduced mod 2 pi,
 //                  one sincos each; then for every segment of terms a Horner
 //                  recurrence in e^{-i Phi_r} over n, seeded by
@@ -24,8 +34,9 @@
 //                  term-split tiles (the four waves take one group each).
 //  sum_kernel      binary64: one wave = one tile; phases in double-double;
 //                  coefficients read by scalar loads into SGPR operands.
-//  select_kernel   the mode selector of Sec. III D (per-knot sort and
-//                  cumulative power threshold).
+//  select_kernel   the mode selector of Sec. III D: per knot a radix select
+//                  with error-bounded sums, the sorted sequential sums when a
+//                  comparison falls inside the bound.
 #include "dd.h"
 #include "few_internal.h"
 #include "swsh.h"
@@ -1810,8 +1821,6 @@ __device__ __forceinline__ void split_pair(float a0, float a1, unsigned &hi, uns
     lo = l;
 }
 
-// Lane value of lane `src` (a row of 16 lanes broadcast to all four rows).
-__device__ __forceinline__ float lane_get(float v, int src) { return __shfl(v, src); }
 
 // Per-wave LDS area of the per-sample values of one round (SoA, SPW samples):
 // f, f^16, f^{4g} (g = 0..3), e^{-i Phi_phi}, its 8th power, the row
