@@ -75,21 +75,22 @@ def path_flops(native, lmn, n: int, precision: str) -> float:
 
 def mfma_instructions(native, w, n_wg: int) -> int:
     """MFMA instructions of one matrix-core launch of request w: every
-    workgroup takes an equal contiguous share of the samples and runs whole
-    rounds (waves x tiles x 16 samples) inside each knot interval."""
+    workgroup takes an equal contiguous share of the samples and runs rounds
+    (waves x tiles x 16 samples) inside each knot interval; in the last round
+    of an interval only the waves with samples run."""
     sh = native.host_mfma_shape()
-    per_round = sh["waves"] * sh["tiles_per_wave"] * 16
+    per_wave = sh["tiles_per_wave"] * 16
     starts = [int(x) for x in native.host_interval_starts(w.t_knots, w.t_start, w.dt,
                                                           w.n_samples)]
     n = w.n_samples
-    rounds = 0
+    wave_rounds = 0
     for r in range(n_wg):
         lo, hi = n * r // n_wg, n * (r + 1) // n_wg
         for i in range(len(starts) - 1):
             a, e = max(lo, starts[i]), min(hi, starts[i + 1])
             if e > a:
-                rounds += (e - a + per_round - 1) // per_round
-    return rounds * sh["waves"] * sh["tiles_per_wave"] * sh["mfma_per_tile"]
+                wave_rounds += (e - a + per_wave - 1) // per_wave
+    return wave_rounds * sh["tiles_per_wave"] * sh["mfma_per_tile"]
 
 
 def time_path(native, plan, w, dev, steps: int, warmup: int, settle_s: float = 0.0):

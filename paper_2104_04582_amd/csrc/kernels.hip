@@ -2145,7 +2145,11 @@ __device__ void mf_range(const SumJob &jb, long long lo, long long hi, float4 *l
         if ((int)threadIdx.x < kMfRows)
             msc[threadIdx.x] = jb.mscale[(size_t)iv * kMfRows + threadIdx.x];
         __syncthreads();
+        // a wave whose samples of a round all lie past the interval's end (the
+        // last round of an interval) skips that round
+        const long long wfirst = (long long)(threadIdx.x / kWave) * kMfSPW;
         for (long long base = lo; base < e; base += kMfRound) {
+            if (base + wfirst >= e) continue;           // uniform per wave
             const double2 v = mf_round<INNER>(jb, iv, base, e, lds, msc, mm, consec, sa);
             if constexpr (INNER) {
                 double2 a = iacc[threadIdx.x];
