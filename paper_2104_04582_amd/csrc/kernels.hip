@@ -44,6 +44,7 @@
 #include <climits>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 namespace few {
 
@@ -1772,16 +1773,20 @@ __device__ __forceinline__ void cmulf(float ar, float ai, float br, float bi, fl
     *ci = __builtin_fmaf(ar, bi, ai * br);
 }
 
-// e^{-i v} in binary32 for a binary64 phase v (any size): v = q pi/2 + r, q the
-// nearest integer of v 2/pi and r = v - q pi/2 with pi/2 = 2pi_hi/4 + 2pi_lo/4
-// (both quarters exact), so |r| <= pi/4 up to rounding; sin r and cos r from
-// their Taylor series in binary32 (terms to r^9 and r^10: the first omitted
-// term is below 2e-9 for |r| <= pi/4), then the quadrant: e^{-iv} is
-// (cos r, -sin r) times (-i)^q.  No branch and no large-argument path.
+// e^{-i v} in binary32 for a binary64 phase v, |v| < 2^50: v = q pi/2 + r, q
+// the nearest integer of v 2/pi and r = v - q pi/2 with pi/2 = 2pi_hi/4 +
+// 2pi_lo/4 (both quarters exact), so |r| <= pi/4 up to rounding; sin r and
+// cos r from their Taylor series in binary32 (terms to r^9 and r^10: the first
+// omitted term is below 2e-9 for |r| <= pi/4), then the quadrant: e^{-iv} is
+// (cos r, -sin r) times (-i)^q.  q comes from adding 1.5 2^52 to v 2/pi in
+// one rounding (the sum's unit in the last place is 1, so its low mantissa
+// bits hold q, and q mod 4 is its two lowest).  No branch.
 __device__ __forceinline__ void phasor_f32(double v, float *re, float *im) {
-    const double q = rint(v * FEW_TWO_OVER_PI);
+    constexpr double kRound = 6755399441055744.0;           // 1.5 * 2^52
+    const double qs = fma(v, FEW_TWO_OVER_PI, kRound);
+    const double q = qs - kRound;
     const double rd = fma(-q, 0.25 * FEW_TWO_PI_LO, fma(-q, 0.25 * FEW_TWO_PI_HI, v));
-    const int qm = (int)fma(-4.0, floor(q * 0.25), q);      // q mod 4 in 0..3
+    const int qm = (int)(__builtin_bit_cast(unsigned long long, qs) & 3);   // q mod 4
     const float r = (float)rd, r2 = r * r;
     float ps = __builtin_fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
     ps = __builtin_fmaf(ps, r2, 1.0f / 120.0f);
@@ -1822,6 +1827,11 @@ __device__ __forceinline__ void split_pair(float a0, float a1, unsigned &hi, uns
 }
 
 
+// The value v of the lane whose byte address (4 x lane index) is addr.
+__device__ __forceinline__ float lane_xchg(int addr, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+
 // Per-wave LDS area of the per-sample values of one round (SoA, SPW samples):
 // f, f^16, f^{4g} (g = 0..3), e^{-i Phi_phi}, its 8th power, the row
 // harmonic z_0 e^{-2ig Phi_phi} (g = 0..3), u, and the reduced Phi_phi.
@@ -1844,16 +1854,14 @@ struct MfSampleArea {
 // lane's binary64 inner-product sums (INNER) or stores h.  The LDS accesses of
 // one wave complete in order, so its area needs no barrier.
 template <bool INNER>
-__device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long base,
-                                            long long e, const float4 *lds, const float *msc,
-                                            const int *mm, bool consec, MfSampleArea *sa) {
+__device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, double ti, double inv_h,
+                                            long long base, long long e, const float4 *lds,
+                                            const float *msc, const int *mm, bool consec,
+                                            MfSampleArea *sa) {
     constexpr int SPW = kMfSPW;
     constexpr int OWN = (SPW + kWave - 1) / kWave;  // samples formed per lane
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int g = lane >> 4, col = lane & 15;
-    const FEW_AS4 double *tk = cptr(jb.t);
-    const double ti = tk[iv];
-    const double inv_h = 1.0 / (tk[iv + 1] - ti);
     const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 16;
     const long long wbase = base + (long long)w * SPW;
     const int m0 = mm[0], am0 = m0 < 0 ? -m0 : m0;
@@ -1961,20 +1969,12 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
         }
     }
     mf_float4 acc[kMfMT][kMfNT];
-#pragma unroll
-    for (int mt = 0; mt < kMfMT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < kMfNT; ++nt) acc[mt][nt] = mf_float4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
-    for (int p = 3; p >= 0; --p) {
-        if (p < 3) {
-#pragma unroll
-            for (int mt = 0; mt < kMfMT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < kMfNT; ++nt) acc[mt][nt] = acc[mt][nt] * uu[nt];
-        }
-        // operand fragments of power p, (mt, t) in order, each read one
-        // fragment ahead of its products (constant offsets from fp)
+    // the products of power p, (mt, t) in order, each fragment read one
+    // fragment ahead of its products (constant offsets from fp).  FIRST: the
+    // first power, whose first product of each (mt, t = 0) starts from zero
+    // (no accumulator to clear).
+    auto power = [&](int p, auto first) {
+        constexpr bool FIRST = decltype(first)::value;
         const float4 *fp = lds + (size_t)(3 - p) * kMfMT * kMfT * 2 * 64 + lane;
         constexpr int NF = kMfMT * kMfT;
         float4 ch = fp[0], cl = fp[64];
@@ -1993,7 +1993,8 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
 #pragma unroll
             for (int nt = 0; nt < kMfNT; ++nt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                    al, __builtin_bit_cast(mf_half8, bh[nt][t]), acc[mt][nt], 0, 0, 0);
+                    al, __builtin_bit_cast(mf_half8, bh[nt][t]),
+                    (FIRST && t == 0) ? mf_float4{0.0f, 0.0f, 0.0f, 0.0f} : acc[mt][nt], 0, 0, 0);
 #pragma unroll
             for (int nt = 0; nt < kMfNT; ++nt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
@@ -2006,6 +2007,18 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
             ch = nh;
             cl = nl;
         }
+    };
+    power(3, std::true_type{});
+#pragma unroll 1
+    for (int p = 2; p >= 0; --p) {
+        // Horner step: every accumulator element of column nt times u
+#pragma unroll
+        for (int mt = 0; mt < kMfMT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < kMfNT; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[mt][nt][i] = acc[mt][nt][i] * uu[nt];
+        power(p, std::false_type{});
     }
     // INNER: the data samples of this lane's columns, requested now so that
     // their latency overlaps the row combination
@@ -2031,6 +2044,8 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
         mo[mt] = mm[r0 + 1];
     }
     double dh = 0.0, hh = 0.0;
+    // byte addresses of lanes l ^ 16 and l ^ 32 for ds_bpermute
+    const int bp16 = (lane ^ 16) << 2, bp32 = (lane ^ 32) << 2;
 #pragma unroll
     for (int nt = 0; nt < kMfNT; ++nt) {
         const int sl = 16 * nt + col;
@@ -2083,10 +2098,10 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, long long 
             }
         }
         // the four lane groups hold the other rows of the same sample
-        hr = hr + __shfl_xor(hr, 16);
-        hq = hq + __shfl_xor(hq, 16);
-        hr = hr + __shfl_xor(hr, 32);
-        hq = hq + __shfl_xor(hq, 32);
+        hr = hr + lane_xchg(bp16, hr);
+        hq = hq + lane_xchg(bp16, hq);
+        hr = hr + lane_xchg(bp32, hr);
+        hq = hq + lane_xchg(bp32, hq);
         const long long jr = wbase + 16 * nt + col;
         if (g == 0 && jr < e) {
             if constexpr (INNER) {
@@ -2148,9 +2163,11 @@ __device__ void mf_range(const SumJob &jb, long long lo, long long hi, float4 *l
         // a wave whose samples of a round all lie past the interval's end (the
         // last round of an interval) skips that round
         const long long wfirst = (long long)(threadIdx.x / kWave) * kMfSPW;
+        const double ti = jb.t[iv], inv_h = 1.0 / (jb.t[iv + 1] - ti);
         for (long long base = lo; base < e; base += kMfRound) {
             if (base + wfirst >= e) continue;           // uniform per wave
-            const double2 v = mf_round<INNER>(jb, iv, base, e, lds, msc, mm, consec, sa);
+            const double2 v =
+                mf_round<INNER>(jb, iv, ti, inv_h, base, e, lds, msc, mm, consec, sa);
             if constexpr (INNER) {
                 double2 a = iacc[threadIdx.x];
                 a.x = a.x + v.x;
