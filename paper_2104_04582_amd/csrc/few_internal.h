@@ -20,12 +20,12 @@ constexpr int kMaxGap = 4;            // zero terms filled inside one segment
 #ifndef FEW_CHUNK_TERMS
 #define FEW_CHUNK_TERMS 1024
 #endif
-// Amplitude series per fit workgroup: one wave of the four does the sweeps,
-// so the series (and their scattered coefficient stores) spread over four
-// times as many compute units as with one series per lane of every wave.
+// Amplitude series per fit workgroup (lane = series; the four waves take a
+// quarter of the rows each, or wave 0 all of them on larger grids).
 constexpr int kFitSeriesPerBlock = 64;
-// Grids of at most this many knots stage each workgroup's knot values and
-// forward-sweep results in LDS (2 x 64 x K binary64, 128 KiB at the limit).
+// Grids of at most this many knots keep each lane's knot values in registers
+// (a quarter of the rows per wave) and factor the grid with one wave's scan;
+// larger grids stream knot values with one lane per series.
 constexpr int kFitStageKnots = 128;
 constexpr int kChunkTerms = FEW_CHUNK_TERMS;   // terms staged in LDS at once (binary32: 32 B each)
 

@@ -8,8 +8,10 @@
 //                  compute queue (a single-request fit carries its own copy).
 //  fit_kernel      not-a-knot cubic splines of every series on the shared knot
 //                  grid.  Amplitude series: binary64, one lane per real series,
-//                  the grid's tridiagonal factor computed once per workgroup
-//                  in LDS.  Phase series: double-double (one refinement step).
+//                  rows split over the workgroup's four waves and joined by
+//                  the multipliers' products; the grid's tridiagonal factor by
+//                  one wave's scan.  Phase series: double-double (one
+//                  refinement step, scan solves).
 //  fold_pack_kernel  matrix-core requests: interval starts; per interval and
 //                  row tile, -2Y_lm, the fold of the l-sum, the row scales and
 //                  the fp16 hi/lo operand table.
@@ -170,6 +172,132 @@ __device__ __forceinline__ void fit_factor_finish(const double *h, int K, double
     }
 }
 
+// LDS writes of one wave made visible to its other lanes (the wave's LDS
+// accesses complete in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Row r of the slope system: sub-diagonal b, diagonal a, super-diagonal c
+// (the table above).
+__device__ __forceinline__ void slope_row(const double *h, int K, int r, double *b, double *a,
+                                          double *c) {
+    if (r == 0) {
+        *b = 0.0;
+        *a = h[1];
+        *c = h[0] + h[1];
+    } else if (r < K - 1) {
+        *b = h[r];
+        *a = 2.0 * (h[r - 1] + h[r]);
+        *c = h[r - 1];
+    } else {
+        *b = h[K - 2] + h[K - 3];
+        *a = h[K - 3];
+        *c = 0.0;
+    }
+}
+
+// The same factor (invd, wv, bv as fit_factor_finish leaves them) on one wave
+// for K <= kFitStageKnots.  With every continuant divided by the diagonals,
+// qt_r = q_r / (a_0 ... a_r), the recurrence becomes
+//   qt_r = qt_{r-1} - g_r qt_{r-2},  g_r = b_r c_{r-1} / (a_r a_{r-1}),
+// qt_{-1} = qt_0 = 1, and den_r = a_r qt_r / qt_{r-1}.  For this system
+// 0 <= g_r <= 1/4 on interior rows and g_r = 1/2 on rows 1 and K - 1, so
+// qt_r / qt_{r-1} lies in [1/2, 1] on rows 1 .. K - 2 (by induction) and in
+// (0, 1) on row K - 1: the qt stay positive and above 2^-K times the last
+// ratio, with no rescaling.  In matrix form (qt_r, qt_{r-1}) =
+// T_r (qt_{r-1}, qt_{r-2}), T_r = [[1, -g_r], [1, 0]]; lane l takes rows
+// 2l + 1 and 2l + 2, and the lanes' products are composed by a log-step scan
+// (later rows on the left).
+__device__ void fit_factor_wave(const double *h, int K, double *invd, double *wv, double *bv) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r0 = 2 * lane + 1, r1 = r0 + 1;
+    double bb0 = 0.0, aa0 = 1.0, cc0 = 0.0, bb1 = 0.0, aa1 = 1.0, cc1 = 0.0;
+    double g0 = 0.0, g1 = 0.0;
+    if (r0 < K) {
+        double bp, ap, cp;
+        slope_row(h, K, r0 - 1, &bp, &ap, &cp);
+        slope_row(h, K, r0, &bb0, &aa0, &cc0);
+        g0 = bb0 * cp / (aa0 * ap);
+    }
+    if (r1 < K) {
+        slope_row(h, K, r1, &bb1, &aa1, &cc1);
+        g1 = bb1 * cc0 / (aa1 * aa0);
+    }
+    // this lane's product T_{r1} T_{r0} (identity rows past the end)
+    double m00, m01, m10, m11;
+    if (r1 < K) {
+        m00 = 1.0 - g1; m01 = -g0; m10 = 1.0; m11 = -g0;
+    } else if (r0 < K) {
+        m00 = 1.0; m01 = -g0; m10 = 1.0; m11 = 0.0;
+    } else {
+        m00 = 1.0; m01 = 0.0; m10 = 0.0; m11 = 1.0;
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const double o00 = __shfl_up(m00, d), o01 = __shfl_up(m01, d);
+        const double o10 = __shfl_up(m10, d), o11 = __shfl_up(m11, d);
+        if (lane >= d) {
+            const double n00 = fma(m00, o00, m01 * o10), n01 = fma(m00, o01, m01 * o11);
+            const double n10 = fma(m10, o00, m11 * o10), n11 = fma(m10, o01, m11 * o11);
+            m00 = n00; m01 = n01; m10 = n10; m11 = n11;
+        }
+    }
+    // (qt_{r0-1}, qt_{r0-2}) = (rows before this lane's) applied to (1, 1)
+    double p00 = __shfl_up(m00, 1), p01 = __shfl_up(m01, 1);
+    double p10 = __shfl_up(m10, 1), p11 = __shfl_up(m11, 1);
+    if (lane == 0) { p00 = 1.0; p01 = 0.0; p10 = 0.0; p11 = 1.0; }
+    const double qa = p00 + p01, qb = p10 + p11;    // qt_{r0-1}, qt_{r0-2}
+    if (r0 < K) {
+        const double q0 = fma(-g0, qb, qa);           // qt_{r0}
+        const double id0 = qa / (aa0 * q0);
+        invd[r0] = id0;
+        wv[r0] = cc0 * id0;
+        bv[r0] = bb0 * id0;
+        if (r1 < K) {
+            const double q1 = fma(-g1, qa, q0);
+            const double id1 = q0 / (aa1 * q1);
+            invd[r1] = id1;
+            wv[r1] = cc1 * id1;
+            bv[r1] = bb1 * id1;
+        }
+    }
+    if (lane == 0) {                                 // row 0: den_0 = a_0
+        const double id = 1.0 / h[1];
+        invd[0] = id;
+        wv[0] = (h[0] + h[1]) * id;
+        bv[0] = 0.0;
+    }
+}
+
+// y_r = a(r) + m(r) y_{r-1} for r < n <= 2 kWave, y_{-1} = 0, on one wave:
+// lane l takes rows 2l and 2l + 1, and the lanes' affine maps y -> A + M y are
+// composed by a log-step scan (later rows on the left).  Returns this lane's
+// two values (y_{2l}, y_{2l+1}); rows past n are identities.
+template <typename FA, typename FM>
+__device__ __forceinline__ double2 wave_affine(int n, FA a, FM m) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r0 = 2 * lane, r1 = r0 + 1;
+    double a0 = 0.0, m0 = 1.0, a1 = 0.0, m1 = 1.0;
+    if (r0 < n) { a0 = a(r0); m0 = m(r0); }
+    if (r1 < n) { a1 = a(r1); m1 = m(r1); }
+    double A = fma(m1, a0, a1), M = m1 * m0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const double Ao = __shfl_up(A, d), Mo = __shfl_up(M, d);
+        if (lane >= d) {
+            A = fma(M, Ao, A);
+            M = M * Mo;
+        }
+    }
+    double yin = __shfl_up(A, 1);
+    if (lane == 0) yin = 0.0;
+    const double y0 = fma(m0, yin, a0);
+    return make_double2(y0, fma(m1, y0, a1));
+}
+
 // Phase series ph (workgroup ph), to double-double accuracy by one step of
 // iterative refinement: solve the slope system in binary64 (Thomas), form
 // the residual with the exact double-double matrix and right-hand side, solve
@@ -218,11 +346,27 @@ __device__ void fit_phase_dd(const FitJob &jb, const double *t, int ph, double *
                              dd_mul(dd_mul(dd_add(dd_mul_d(sum, 2.0), hb), ha), D(K - 2))),
                       sum);
     };
-    // binary64 Thomas sweep with the factor in invd / wv / bv (of the rounded
+    // binary64 Thomas sweeps with the factor in invd / wv / bv (of the rounded
     // matrix; the refinement step uses the exact rows): x <- A^-1 x in place.
-    // The recurrence is carried in registers: the LDS operands of C rows are
+    // K <= kFitStageKnots: wave 0 takes each sweep as one affine scan
+    // (wave_affine; the back sweep in reversed row order).  Otherwise one lane
+    // carries the recurrence in registers: the LDS operands of C rows are
     // loaded together, the rows eliminated (one fused multiply-add each on
     // the serial chain), and the C results stored after the batch.
+    const bool wave_solve = K <= kFitStageKnots;
+    auto solve_wave = [&](double *x) {
+        const int r0 = 2 * tid, r1 = r0 + 1;
+        const double2 g = wave_affine(
+            K, [&](int r) { return x[r] * invd[r]; }, [&](int r) { return -bv[r]; });
+        if (r0 < K) x[r0] = g.x;
+        if (r1 < K) x[r1] = g.y;
+        lds_wave_sync();
+        const double2 v = wave_affine(
+            K, [&](int r) { return x[K - 1 - r]; }, [&](int r) { return -wv[K - 1 - r]; });
+        lds_wave_sync();
+        if (r0 < K) x[K - 1 - r0] = v.x;
+        if (r1 < K) x[K - 1 - r1] = v.y;
+    };
     auto solve = [&](double *x) {
         constexpr int C = 16;
         double g = x[0] * invd[0];
@@ -280,15 +424,23 @@ __device__ void fit_phase_dd(const FitJob &jb, const double *t, int ph, double *
         Dh[i] = d.hi; Dl[i] = d.lo;
     }
     __syncthreads();
-    // binary64 factor of the rounded matrix (one lane of wave 0) while the
-    // other waves form the right-hand side, then the first solve
-    if (tid == 0) fit_factor_serial(Hh, K, invd, wv);
+    // binary64 factor of the rounded matrix (wave 0, or one lane of it) while
+    // the other waves form the right-hand side, then the first solve
+    if (wave_solve) {
+        if (tid < kWave) fit_factor_wave(Hh, K, invd, wv, bv);
+    } else if (tid == 0) {
+        fit_factor_serial(Hh, K, invd, wv);
+    }
     if (tid >= kWave)
         for (int r = tid - kWave; r < K; r += bs - kWave) s0[r] = rhs(r).hi;
     __syncthreads();
-    fit_factor_finish(Hh, K, invd, wv, bv);
-    __syncthreads();
-    if (tid == 0) solve(s0);
+    if (!wave_solve) {
+        fit_factor_finish(Hh, K, invd, wv, bv);
+        __syncthreads();
+    }
+    if (wave_solve ? tid < kWave : tid == 0) {
+        if (wave_solve) solve_wave(s0); else solve(s0);
+    }
     __syncthreads();
     // residual of the exact (double-double) system at s0
     for (int r = tid; r < K; r += bs) {
@@ -300,7 +452,9 @@ __device__ void fit_phase_dd(const FitJob &jb, const double *t, int ph, double *
         rr[r] = dd_sub(rhs(r), ax).hi;
     }
     __syncthreads();
-    if (tid == 0) solve(rr);
+    if (wave_solve ? tid < kWave : tid == 0) {
+        if (wave_solve) solve_wave(rr); else solve(rr);
+    }
     __syncthreads();
     double *pc = jb.pcoef;
     for (int r = tid; r < K - 1; r += bs) {
@@ -317,17 +471,14 @@ __device__ void fit_phase_dd(const FitJob &jb, const double *t, int ph, double *
     }
 }
 
-// The two sweeps of one real amplitude series q (lane tid of wave 0).
-// STAGED: knot values from ys, forward results kept in gs and replaced by the
-// slopes in the back sweep (the workgroup forms the coefficients afterwards).
-// Otherwise knot values come from global memory, the forward results go
-// through the coefficient array, and each row's coefficients are stored as
-// its slope is found.
-template <bool STAGED>
+// The two sweeps of one real amplitude series q (lane tid of wave 0) for
+// grids of more than kFitStageKnots knots: knot values stream from global
+// memory, the forward results go through the coefficient array, and each
+// row's coefficients are stored as its slope is found.
 __device__ __forceinline__ void fit_sweeps(const FitJob &jb, int tid, int q, int K, int M,
                                            const double *hs, const double *invd,
                                            const double *wv, const double *ih,
-                                           const double *bv, const double *ys, double *gs) {
+                                           const double *bv) {
     constexpr int C = 16;
     const size_t ys_stride = 2 * (size_t)M;
     // coefficient p of series q on interval r at o[r * cs + p * ps]
@@ -340,18 +491,10 @@ __device__ __forceinline__ void fit_sweeps(const FitJob &jb, int tid, int q, int
     // knot value idx (clamped to the grid: in bounds, unused past it)
     auto ldy = [&](int idx) {
         const int i = min(max(idx, 0), K - 1);
-        return STAGED ? ys[i * kFitSeriesPerBlock + tid] : y[(size_t)i * ys_stride];
+        return y[(size_t)i * ys_stride];
     };
-    auto stg = [&](int r, double gv) {
-        if (STAGED)
-            gs[r * kFitSeriesPerBlock + tid] = gv;
-        else
-            o[(size_t)r * cs + ps] = gv;
-    };
-    auto ldg = [&](int r) {
-        const int i = max(r, 0);
-        return STAGED ? gs[i * kFitSeriesPerBlock + tid] : o[(size_t)i * cs + ps];
-    };
+    auto stg = [&](int r, double gv) { o[(size_t)r * cs + ps] = gv; };
+    auto ldg = [&](int r) { return o[(size_t)max(r, 0) * cs + ps]; };
 
     // Forward elimination.  Knot idx gives delta_{idx-1}; rows 0 and 1 close
     // at knot 2, row idx - 1 at every later knot, row K - 1 after the last.
@@ -422,32 +565,6 @@ __device__ __forceinline__ void fit_sweeps(const FitJob &jb, int tid, int q, int
         const double ha = hs[K - 3], hb = hs[K - 2];
         const double rhs = (hb * hb * dm1 + (2.0 * (ha + hb) + hb) * ha * d0) / (ha + hb);
         g = fma(-bv[K - 1], g, rhs * invd[K - 1]);
-    }
-    if (STAGED) {
-        // back substitution: slopes only, s_r = g_r - wv_r s_{r+1}, into gs
-        double sn = g;
-        gs[(K - 1) * kFitSeriesPerBlock + tid] = sn;
-        int r0 = K - 2;
-        for (; r0 - C + 1 >= 0; r0 -= C) {
-            double gv[C], wr[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                gv[c] = gs[(r0 - c) * kFitSeriesPerBlock + tid];
-                wr[c] = wv[r0 - c];
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                sn = fma(-wr[c], sn, gv[c]);
-                gv[c] = sn;
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) gs[(r0 - c) * kFitSeriesPerBlock + tid] = gv[c];
-        }
-        for (; r0 >= 0; --r0) {
-            sn = fma(-wv[r0], sn, gs[r0 * kFitSeriesPerBlock + tid]);
-            gs[r0 * kFitSeriesPerBlock + tid] = sn;
-        }
-        return;
     }
     // Back substitution and coefficients, interval K-2 down to 0, in batches
     // of C rows r0, r0 - 1, ...: operands first (the batch's forward results
@@ -528,31 +645,20 @@ __device__ __forceinline__ void fit_copy_upload(const FitJob &jb, int blk) {
         jb.up_dst[x] = jb.up_src[x];
 }
 
-// Binary64 solve of the amplitude series handled by this workgroup, one lane
-// of wave 0 per real series.  LDS: h[K], inverse pivots invd[K], multipliers
-// wv[K] and bv[K] and 1 / h[K] of the shared grid (the sweeps multiply by
-// 1 / h_i instead of dividing: a division is a long dependent sequence on this
-// hardware, and the sweeps are latency bound).  Wave 0 forms the grid and one
-// of its lanes the factor while the other waves fetch knot values.
-// STAGED (K <= kFitStageKnots): those waves copy the workgroup's knot values,
-// [K][64] binary64, into LDS with many loads in flight, and the forward sweep
-// keeps its results in a second [K][64] LDS array, so neither sweep waits on
-// global memory.  Otherwise each lane streams its knot values from global
-// memory and the forward results go through the coefficient array.
-// Both sweeps work in batches of C rows: every operand of the batch is read
-// first, the serial chain (one fused multiply-add per row) runs in registers,
-// and the batch's results are stored after it.  STAGED, the back sweep finds
-// the slopes only and the whole workgroup then forms the coefficients, each
-// store of a wave covering 64 consecutive values of the coefficient array.
-template <bool STAGED>
-__device__ void fit_amplitudes(const FitJob &jb, const double *t, int blk, double *lds) {
+// Binary64 solve of the amplitude series handled by this workgroup for grids
+// of more than kFitStageKnots knots, one lane of wave 0 per real series.  LDS:
+// h[K], inverse pivots invd[K], multipliers wv[K] and bv[K] and 1 / h[K] of
+// the shared grid (the sweeps multiply by 1 / h_i instead of dividing: a
+// division is a long dependent sequence on this hardware, and the sweeps are
+// latency bound).  Wave 0 forms the grid and one of its lanes the factor;
+// each lane streams its knot values from global memory, both sweeps working in
+// batches of C rows (operands first, the serial chain in registers, the
+// results stored after it).
+__device__ void fit_amplitudes_stream(const FitJob &jb, const double *t, int blk, double *lds) {
     const int K = jb.K, M = jb.M;
-    const int tid = threadIdx.x, bs = blockDim.x;
+    const int tid = threadIdx.x;
     double *hs = lds, *invd = lds + K, *wv = lds + 2 * K, *ih = lds + 3 * K, *bv = lds + 4 * K;
-    double *ys = lds + 5 * K;                        // STAGED: [K][64] knot values
-    double *gs = ys + (size_t)K * kFitSeriesPerBlock; // STAGED: [K][64] forward results
     const int q0 = blk * kFitSeriesPerBlock;
-    const size_t ys_stride = 2 * (size_t)M;          // knot stride of amp
     if (tid < kWave) {
         for (int i = tid; i < K - 1; i += kWave) {
             const double h = t[i + 1] - t[i];
@@ -561,79 +667,215 @@ __device__ void fit_amplitudes(const FitJob &jb, const double *t, int blk, doubl
         }
         __builtin_amdgcn_wave_barrier();
         if (tid == 0) fit_factor_serial(hs, K, invd, wv);
-    } else if (STAGED) {
-        constexpr int B = 16;                        // loads in flight per lane
-        const int ns = min(kFitSeriesPerBlock, 2 * M - q0);
-        const int total = K * kFitSeriesPerBlock, nb = bs - kWave;
-        for (int x0 = tid - kWave; x0 < total; x0 += nb * B) {
-            double v[B];
-#pragma unroll
-            for (int j = 0; j < B; ++j) {
-                const int x = x0 + j * nb;
-                const int i = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
-                v[j] = (x < total && sj < ns) ? jb.amp[(size_t)i * ys_stride + q0 + sj] : 0.0;
-            }
-#pragma unroll
-            for (int j = 0; j < B; ++j)
-                if (x0 + j * nb < total) ys[x0 + j * nb] = v[j];
-        }
     }
     __syncthreads();
     fit_factor_finish(hs, K, invd, wv, bv);
     __syncthreads();
     const int q = q0 + tid;
-    if (tid < kFitSeriesPerBlock && q < 2 * M)
-        fit_sweeps<STAGED>(jb, tid, q, K, M, hs, invd, wv, ih, bv, ys, gs);
+    if (tid < kFitSeriesPerBlock && q < 2 * M) fit_sweeps(jb, tid, q, K, M, hs, invd, wv, ih, bv);
     if (tid >= kWave) fit_copy_upload(jb, blk);
-    if (!STAGED) return;
-    // STAGED: gs holds the slopes; every lane of the workgroup forms the four
-    // coefficients of one (interval, series) pair, consecutive lanes taking
-    // consecutive series (wave w takes interval r = 4 i + w).
-    __syncthreads();
-    const int ns = min(kFitSeriesPerBlock, 2 * M - q0);
-    const int total = (K - 1) * kFitSeriesPerBlock;
-    if (jb.acoef_pmajor) {
-        // [K-1][4][2M]: each store of a wave writes 512 contiguous bytes
-        const size_t ps = 2 * (size_t)M, cs = 4 * ps;
-        for (int x = tid; x < total; x += bs) {
-            const int r = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
-            if (sj >= ns) continue;
-            const double y0 = ys[x], y1 = ys[x + kFitSeriesPerBlock];
-            const double s0 = gs[x], s1 = gs[x + kFitSeriesPerBlock];
-            const double ir = ih[r];
-            const double dr = (y1 - y0) * ir;
-            double *orow = jb.acoef + (size_t)r * cs + q0 + sj;
-            orow[0] = y0;
-            orow[ps] = s0;
-            orow[2 * ps] = (3.0 * dr - 2.0 * s0 - s1) * ir;
-            orow[3 * ps] = (s0 + s1 - 2.0 * dr) * (ir * ir);
-        }
-        return;
+}
+
+// Row l of a wave-uniform value held by lane l (both halves by readlane).
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Binary64 solve of the amplitude series of workgroup blk (64 real series,
+// lane = series) for K <= kFitStageKnots.  The rows are split over the four
+// waves: wave w takes rows [R_w, R_{w+1}) and keeps its lanes' knot values
+// y_{R_w - 1} .. y_{R_{w+1}} and its forward results and slopes in
+// registers; row-wise constants are formed lane-parallel (lane c for row
+// R_w + c) and broadcast with readlane.  Wave 0 forms the factor
+// (fit_factor_wave) while every wave's knot values are in flight.  Row r's
+// forward input rhs_r invd_r is
+//   al_r (y_{a+1} - y_a) + be_r (y_{a+2} - y_{a+1}),  a = clamp(r - 1, 0, K - 3)
+// (its two divided differences).  Each wave runs its rows from a zero start
+// and the chunks are joined afterwards, since a first-order recurrence at row
+// r is its zero-start value plus the product of the multipliers since the
+// chunk start times the value entering the chunk:
+//   forward g_r = rhs_r invd_r - bv_r g_{r-1}:  g_r = gl_r + F_r G,
+//           F_r = prod_{j = R_w .. r} (-bv_j), G = g_{R_w - 1};
+//   back    s_r = g_r - wv_r s_{r+1}:          s_r = sl_r + B_r S,
+//           B_r = prod_{j = r .. R_{w+1} - 1} (-wv_j), S = s_{R_{w+1}}.
+// The values entering the chunks follow from the chunk ends (exchanged in
+// LDS) in at most three steps.  Each wave then writes the coefficients of its
+// intervals.
+__device__ void fit_amplitudes_staged(const FitJob &jb, const double *t, int blk, double *lds) {
+    constexpr int NW = 4;                            // waves (launched with 256 lanes)
+    constexpr int LC = (kFitStageKnots + NW - 1) / NW;   // most rows of a chunk
+    const int K = jb.K, M = jb.M;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    double *hs = lds, *invd = lds + K, *wv = lds + 2 * K, *bv = lds + 3 * K;
+    double *cf = lds + 4 * K;                        // [NW][64] forward values at chunk ends
+    double *cb = cf + NW * kWave;                    // [NW][64] back values at chunk starts
+    double *fe = cb + NW * kWave;                    // [NW] F at chunk ends
+    double *bs0 = fe + NW;                           // [NW] B at chunk starts
+    const int q = blk * kFitSeriesPerBlock + lane;
+    const bool live = q < 2 * M;
+    const int L = (K + NW - 1) / NW;
+    const int r_lo = min(K, w * L), n = min(K, r_lo + L) - r_lo;
+    // the workgroup's share of the upload: each lane's first word requested
+    // now (host memory is far) and stored at the end
+    long long up_x = -1, up_end = 0;
+    uint4 up_w = make_uint4(0u, 0u, 0u, 0u);
+    if (jb.up_bytes > 0) {
+        const long long words = (jb.up_bytes + 15) / 16;
+        const long long per = (words + jb.amp_blocks - 1) / jb.amp_blocks;
+        up_end = min(words, (long long)blk * per + per);
+        up_x = (long long)blk * per + tid;
+        if (up_x < up_end) up_w = jb.up_src[up_x];
     }
-    // [K-1][M][4][2]: the lanes write their coefficients into the wave's
-    // 2 KB LDS slot in that order and the wave stores the slot as the
-    // interval's contiguous run (two 1 KB stores).  LDS accesses of one wave
-    // complete in order, so the slot needs no barrier.
-    const int k0 = q0 >> 1, lane = tid & (kWave - 1);
-    double *wsc = gs + (size_t)K * kFitSeriesPerBlock + (tid / kWave) * (4 * kFitSeriesPerBlock);
-    for (int x = tid; x < total; x += bs) {
-        const int r = x / kFitSeriesPerBlock, sj = x % kFitSeriesPerBlock;
-        const double y0 = ys[x], y1 = ys[x + kFitSeriesPerBlock];
-        const double s0 = gs[x], s1 = gs[x + kFitSeriesPerBlock];
-        const double ir = ih[r];
-        const double dr = (y1 - y0) * ir;
-        double *d = wsc + 8 * (sj >> 1) + (sj & 1);
-        d[0] = y0;
-        d[2] = s0;
-        d[4] = (3.0 * dr - 2.0 * s0 - s1) * ir;
-        d[6] = (s0 + s1 - 2.0 * dr) * (ir * ir);
-        __builtin_amdgcn_wave_barrier();
-        const double2 *rd = (const double2 *)wsc;
-        double2 *dst = (double2 *)(jb.acoef + ((size_t)r * M + k0) * 8);
-        const double2 v0 = rd[lane], v1 = rd[kWave + lane];
-        if (lane < 2 * ns) dst[lane] = v0;               // run of 4 ns doubles
-        if (kWave + lane < 2 * ns) dst[kWave + lane] = v1;
-        __builtin_amdgcn_wave_barrier();
+    // knot values y_{r_lo - 2 + j} (clamped to the grid), all in flight
+    double yv[LC + 4];
+    {
+        const double *y = jb.amp + q;
+        const size_t stride = 2 * (size_t)M;
+#pragma unroll
+        for (int j = 0; j < LC + 4; ++j) {
+            const int i = min(max(r_lo - 2 + j, 0), K - 1);
+            yv[j] = live ? y[(size_t)i * stride] : 0.0;
+        }
+    }
+    if (w == 0) {
+        for (int i = lane; i < K - 1; i += kWave) hs[i] = t[i + 1] - t[i];
+        lds_wave_sync();
+        fit_factor_wave(hs, K, invd, wv, bv);
+    }
+    __syncthreads();
+    // row-wise constants of row r_lo + c in lane c
+    double c_al = 0.0, c_be = 0.0, c_bv = 0.0, c_wv = 0.0, c_ih = 0.0;
+    if (lane < n) {
+        const int r = r_lo + lane;
+        double P, Q;
+        int a;
+        if (r == 0) {
+            const double h0 = hs[0], h1 = hs[1];
+            P = (h0 + 2.0 * (h0 + h1)) * h1 / (h0 + h1);
+            Q = h0 * h0 / (h0 + h1);
+            a = 0;
+        } else if (r < K - 1) {
+            P = 3.0 * hs[r];
+            Q = 3.0 * hs[r - 1];
+            a = r - 1;
+        } else {
+            const double ha = hs[K - 3], hb = hs[K - 2];
+            P = hb * hb / (ha + hb);
+            Q = (2.0 * (ha + hb) + hb) * ha / (ha + hb);
+            a = K - 3;
+        }
+        const double id = invd[r];
+        c_al = id * P / hs[a];
+        c_be = id * Q / hs[a + 1];
+        c_bv = bv[r];
+        c_wv = wv[r];
+        c_ih = r < K - 1 ? 1.0 / hs[r] : 0.0;
+    }
+    // chunk products: F in lane c over rows r_lo .. r_lo + c, B over
+    // r_lo + c .. r_lo + n - 1 (log-step scans; identities past the chunk)
+    double c_F = lane < n ? -c_bv : 1.0, c_B = lane < n ? -c_wv : 1.0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const double fo = __shfl_up(c_F, d), bo = __shfl_down(c_B, d);
+        if (lane >= d) c_F *= fo;
+        if (lane + d < kWave) c_B *= bo;
+    }
+    // forward chain of the chunk from a zero start
+    double gv[LC];
+    double g = 0.0;
+#pragma unroll
+    for (int c = 0; c < LC; ++c) {
+        if (c < n) {
+            const int r = r_lo + c;
+            // y_a, y_{a+1}, y_{a+2}: yv[c+1 ..] on interior rows (a = r - 1),
+            // one further on row 0 (a = 0) and one back on row K - 1 (a = K - 3)
+            const int sh = r == 0 ? 1 : (r == K - 1 ? -1 : 0);
+            const double y0 = sh > 0 ? yv[c + 2] : (sh < 0 ? yv[c] : yv[c + 1]);
+            const double y1 = sh > 0 ? yv[c + 3] : (sh < 0 ? yv[c + 1] : yv[c + 2]);
+            const double y2 = sh > 0 ? yv[c + 4] : (sh < 0 ? yv[c + 2] : yv[c + 3]);
+            const double v = fma(lane_value(c_al, c), y1 - y0, lane_value(c_be, c) * (y2 - y1));
+            g = fma(-lane_value(c_bv, c), g, v);
+            gv[c] = g;
+        }
+    }
+    cf[w * kWave + lane] = g;
+    if (lane == max(n, 1) - 1) fe[w] = n > 0 ? c_F : 1.0;
+    __syncthreads();
+    {
+        // forward value entering the chunk, then the back chain of the chunk
+        // on the joined forward values
+        double G = 0.0;
+        for (int cc = 0; cc < w; ++cc) G = fma(fe[cc], G, cf[cc * kWave + lane]);
+        double sl = 0.0;
+#pragma unroll
+        for (int c = LC - 1; c >= 0; --c) {
+            if (c < n) {
+                const double gj = fma(lane_value(c_F, c), G, gv[c]);
+                sl = fma(-lane_value(c_wv, c), sl, gj);
+                gv[c] = sl;
+            }
+        }
+        cb[w * kWave + lane] = sl;
+        if (lane == 0) bs0[w] = n > 0 ? c_B : 1.0;
+    }
+    __syncthreads();
+    // slope entering the chunk from above, s_{r_lo + n}
+    double Sx = 0.0;
+    for (int cc = NW - 1; cc > w; --cc) Sx = fma(bs0[cc], Sx, cb[cc * kWave + lane]);
+#pragma unroll
+    for (int c = 0; c < LC; ++c)
+        if (c < n) gv[c] = fma(lane_value(c_B, c), Sx, gv[c]);
+    // coefficients of the chunk's intervals r = r_lo + c <= K - 2: stored
+    // directly in the [K-1][4][2M] layout (each store 512 contiguous bytes);
+    // in the [K-1][M][4][2] layout through the wave's 2 KB LDS slot, so that
+    // the wave stores each interval's run of 32 modes as two 1 KB pieces
+    const bool pm = jb.acoef_pmajor != 0;
+    const int k0 = blk * (kFitSeriesPerBlock / 2);
+    const int ns = min(kFitSeriesPerBlock, 2 * M - blk * kFitSeriesPerBlock);
+    double *slot = bs0 + NW + (size_t)w * 4 * kWave;
+#pragma unroll
+    for (int c = 0; c < LC; ++c) {
+        const int r = r_lo + c;
+        if (c < n && r <= K - 2) {
+            const double y0 = yv[c + 2], y1 = yv[c + 3];
+            // s_{r+1}: past the chunk's last row, the next chunk's first
+            const double s1 = (c + 1 < LC && c + 1 < n) ? gv[c + 1 < LC ? c + 1 : c] : Sx;
+            const double s0 = gv[c];
+            const double ir = lane_value(c_ih, c);
+            const double dr = (y1 - y0) * ir;
+            const double c2 = (3.0 * dr - 2.0 * s0 - s1) * ir, c3 = (s0 + s1 - 2.0 * dr) * (ir * ir);
+            if (pm) {
+                if (live) {
+                    double *orow = jb.acoef + (size_t)r * 8 * M + q;
+                    const size_t ps = 2 * (size_t)M;
+                    orow[0] = y0;
+                    orow[ps] = s0;
+                    orow[2 * ps] = c2;
+                    orow[3 * ps] = c3;
+                }
+            } else {
+                double *d = slot + 8 * (lane >> 1) + (lane & 1);
+                d[0] = y0;
+                d[2] = s0;
+                d[4] = c2;
+                d[6] = c3;
+                lds_wave_sync();
+                const double2 *rd = (const double2 *)slot;
+                double2 *dst = (double2 *)(jb.acoef + ((size_t)r * M + k0) * 8);
+                const double2 v0 = rd[lane], v1 = rd[kWave + lane];
+                if (lane < 2 * ns) dst[lane] = v0;               // run of 4 ns doubles
+                if (kWave + lane < 2 * ns) dst[kWave + lane] = v1;
+                lds_wave_sync();
+            }
+        }
+    }
+    if (up_x >= 0) {
+        if (up_x < up_end) jb.up_dst[up_x] = up_w;
+        for (long long x = up_x + (long long)blockDim.x; x < up_end; x += blockDim.x)
+            jb.up_dst[x] = jb.up_src[x];
     }
 }
 
@@ -646,9 +888,9 @@ __device__ __forceinline__ void fit_body(const FitJob &jb, const double *t, doub
     }
     if ((int)blockIdx.x - jb.n_ph >= jb.amp_blocks) return;
     if (jb.K <= kFitStageKnots)
-        fit_amplitudes<true>(jb, t, blockIdx.x - jb.n_ph, lds);
+        fit_amplitudes_staged(jb, t, blockIdx.x - jb.n_ph, lds);
     else
-        fit_amplitudes<false>(jb, t, blockIdx.x - jb.n_ph, lds);
+        fit_amplitudes_stream(jb, t, blockIdx.x - jb.n_ph, lds);
 }
 
 // Single-request fit.  Grids of at most kFitStageKnots knots also arrive in
@@ -2675,11 +2917,10 @@ hipError_t launch_acoef_export(const double *src, double *dst, int K, int M,
 }
 
 static inline size_t fit_lds_bytes(int K) {
-    // phase workgroups: 9 arrays of K; amplitude workgroups: 5 arrays of K,
-    // plus (K <= kFitStageKnots) the staged knot values and forward results
+    // phase workgroups: 9 arrays of K; amplitude workgroups: 5 arrays of K
     size_t n = 9 * (size_t)K;
-    if (K <= kFitStageKnots)    // + one 2 KB coefficient slot per wave
-        n = std::max(n, (5 + 2 * (size_t)kFitSeriesPerBlock) * K + 4 * 4 * kFitSeriesPerBlock);
+    if (K <= kFitStageKnots)    // 4 arrays of K, the chunk values, a 2 KB slot per wave
+        n = std::max(n, 4 * (size_t)K + 2 * 4 * kWave + 8 + 4 * 4 * kWave);
     return sizeof(double) * n;
 }
 
