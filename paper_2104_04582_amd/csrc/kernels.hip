@@ -1834,6 +1834,8 @@ typedef float mf_float4 __attribute__((ext_vector_type(4)));
 // Horner recurrence that reads it), lane l's operand fragment of
 // v_mfma_f32_16x16x32_f16: matrix row l % 16 of the tile, columns
 // a = 16 t + 4 (l / 16) + i / 2 and c = i % 2 for value i.
+constexpr int kFoldSegs = 64;                       // segments of a row tile kept in LDS
+
 __device__ void fold_pack_body(const PrepJob &jb, int b) {
     if (b == 0) {
         prep_intervals(jb);
@@ -1846,28 +1848,51 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
     __shared__ double cf[8][NN][8];
     __shared__ double rsc[8];
     __shared__ int rowm[9];
+    __shared__ double2 trig[9];                     // (cos, sin) of theta / 2 and of m_r phi
+    __shared__ int2 segv[kFoldSegs];
     const int tid = threadIdx.x;
     const int r0 = 8 * mt;
+    {
+        const int sg0 = jb.mrows[min(r0, jb.n_mrows)].y, sg1 = jb.mrows[min(r0 + 8, jb.n_mrows)].y;
+        if (tid < sg1 - sg0 && tid < kFoldSegs) {
+            const int4 S = jb.segs[sg0 + tid];
+            segv[tid] = make_int2(S.w, S.y);
+        }
+    }
     if (tid < 9) {
         const int r = r0 + tid;
         rowm[tid] = r <= jb.n_mrows ? jb.mrows[r].y : jb.mrows[jb.n_mrows].y;   // first segment
+        double sv, cv;
+        if (tid == 8)
+            sincos(0.5 * jb.theta, &sv, &cv);
+        else
+            sincos((double)(r < jb.n_mrows ? jb.mrows[r].x : 0) * jb.phi, &sv, &cv);
+        trig[tid] = make_double2(cv, sv);
     }
+    for (int x = tid; x < 8 * NN * 8; x += blockDim.x) (&cf[0][0][0])[x] = 0.0;
+    __syncthreads();
     for (int x = tid; x < 8 * NL; x += blockDim.x) {
         const int k = x / NL, l = x % NL, r = r0 + k;
         double yr = 0.0, yi = 0.0;
         if (r < jb.n_mrows) {
             const int m = jb.mrows[r].x;
             if (l >= 2 && l >= abs(m) && l <= jb.l_max)
-                few_swsh_m2(l, m, jb.theta, jb.phi, &yr, &yi);
+                few_swsh_m2_cs(l, m, trig[8].x, trig[8].y, trig[k].x, trig[k].y, &yr, &yi);
         }
         yw[k][l] = make_double2(yr, yi);
     }
-    for (int x = tid; x < 8 * NN * 8; x += blockDim.x) (&cf[0][0][0])[x] = 0.0;
     __syncthreads();
     // terms of rows r0 .. r0 + 7 are one contiguous run [t0, t1)
     const int g0 = rowm[0], g1 = rowm[8];
     const int t0 = g0 < jb.n_segs ? jb.segs[g0].w : jb.n_terms;
     const int t1 = g1 < jb.n_segs ? jb.segs[g1].w : jb.n_terms;
+    // the tile's segments (first term, n of the first term) in LDS when few
+    const bool seg_lds = g1 - g0 <= kFoldSegs;
+    auto seg_of = [&](int g) {
+        if (seg_lds) return make_int2(segv[g - g0].x, segv[g - g0].y);
+        const int4 S = jb.segs[g];
+        return make_int2(S.w, S.y);
+    };
     const double h = jb.t[iv + 1] - jb.t[iv];
     // acoef [K-1][4][2M] (matrix-core requests): coefficient p of mode k at
     // arow[p * 2M + 2k + {0, 1}], so lanes taking consecutive modes read
@@ -1884,11 +1909,11 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
     };
     for (int tt = t0 + tid; tt < t1; tt += blockDim.x) {
         int g = g0;
-        while (g + 1 < g1 && jb.segs[g + 1].w <= tt) ++g;
-        const int4 S = jb.segs[g];
+        while (g + 1 < g1 && seg_of(g + 1).x <= tt) ++g;
+        const int2 S = seg_of(g);
         int k = 0;
         while (k + 1 < 8 && rowm[k + 1] <= g) ++k;
-        const int n = S.y + (tt - S.w);
+        const int n = S.y + (tt - S.x);
         double acc[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc[c] = 0.0;
@@ -1904,24 +1929,27 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
                 acc[2 * q + 1] += w.x * ai + w.y * ar;
             }
         };
-        // three contributors at a time: indices, then their coefficient rows,
-        // all loaded before any is added (in contributor order)
+        // three contributors at a time, added in contributor order: their
+        // coefficient rows are requested, then the next three indices (so
+        // that those arrive while these rows do), then the rows are added
         const int ea = jb.term_ptr[tt], eb = jb.term_ptr[tt + 1];
-        int e = ea;
-        for (; e + 3 <= eb; e += 3) {
-            int2 src[3];
+        int2 src[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) src[j] = ea + j < eb ? jb.term_src[ea + j] : make_int2(0, 0);
+        for (int e = ea; e < eb; e += 3) {
             double av[3][8];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) src[j] = jb.term_src[e + j];
+            for (int j = 0; j < 3; ++j)
+                if (e + j < eb) load8(src[j].x, av[j]);
+            int2 nsrc[3];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) load8(src[j].x, av[j]);
+            for (int j = 0; j < 3; ++j)
+                nsrc[j] = e + 3 + j < eb ? jb.term_src[e + 3 + j] : make_int2(0, 0);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) add(src[j], av[j]);
-        }
-        for (; e < eb; ++e) {
-            double a[8];
-            load8(jb.term_src[e].x, a);
-            add(jb.term_src[e], a);
+            for (int j = 0; j < 3; ++j)
+                if (e + j < eb) add(src[j], av[j]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) src[j] = nsrc[j];
         }
         double f = jb.scale, fi = jb.scale_im;
         double *dst = cf[k][n + kMfA - 1];

@@ -18,19 +18,17 @@
 
 #include <hip/hip_runtime.h>
 
-__host__ __device__ inline double few_fact(int n) {
-    double f = 1.0;
-    for (int k = 2; k <= n; ++k) f *= (double)k;
-    return f;
-}
-
 __host__ __device__ inline double few_ipow(double x, int k) {
     double r = 1.0;
     for (int i = 0; i < k; ++i) r *= x;
     return r;
 }
 
-// Wigner small-d d^l_{mp,m}(b) from its half-angle cosine c and sine s.
+// Wigner small-d d^l_{mp,m}(b) from its half-angle cosine c and sine s.  The
+// factorial ratio n! (n+mu+nu)! / ((n+mu)! (n+nu)!) is taken as
+// prod_{k=1..mu} (n+nu+k) / (n+k), and each step of the degree recurrence
+// multiplies by the reciprocal of its leading factor (formed off the
+// recurrence's dependent chain).
 __host__ __device__ inline double few_wigner_d(int l, int mp, int m, double c, double s) {
     const int mu = m > mp ? m - mp : mp - m;
     const int nu = m + mp > 0 ? m + mp : -(m + mp);
@@ -45,16 +43,37 @@ __host__ __device__ inline double few_wigner_d(int l, int mp, int m, double c, d
             const double c1 = 2.0 * k * (k + a + b) * (t - 2.0);
             const double c2 = (t - 1.0) * (t * (t - 2.0) * x + a * a - b * b);
             const double c3 = 2.0 * (k + a - 1.0) * (k + b - 1.0) * t;
-            const double pk = (c2 * p1 - c3 * p0) / c1;
+            const double ic1 = 1.0 / c1;
+            const double pk = (c2 * p1 - c3 * p0) * ic1;
             p0 = p1;
             p1 = pk;
         }
         p = p1;
     }
     const double xi = (m >= mp || ((m - mp) & 1) == 0) ? 1.0 : -1.0;
-    const double norm = sqrt(few_fact(n) * few_fact(n + mu + nu) /
-                             (few_fact(n + mu) * few_fact(n + nu)));
+    double num = 1.0, den = 1.0;
+    for (int k = 1; k <= mu; ++k) {
+        num *= (double)(n + nu + k);
+        den *= (double)(n + k);
+    }
+    const double norm = sqrt(num / den);
     return xi * norm * few_ipow(s, mu) * few_ipow(c, nu) * p;
+}
+
+// -2Y_lm(theta, phi) from c = cos(theta/2), s = sin(theta/2) and
+// (cos m phi, sin m phi); zero when |m| > l or l < 2.
+__host__ __device__ inline void few_swsh_m2_cs(int l, int m, double c, double s, double cmp,
+                                               double smp, double *re, double *im) {
+    if (m > l || -m > l || l < 2) {
+        *re = 0.0;
+        *im = 0.0;
+        return;
+    }
+    const double inv_4pi = 0.07957747154594767;   // 1 / (4 pi)
+    const double d = few_wigner_d(l, m, 2, c, s);
+    const double a = sqrt((2 * l + 1) * inv_4pi) * d;
+    *re = a * cmp;
+    *im = a * smp;
 }
 
 // -2Y_lm(theta, phi); zero when |m| > l.
@@ -65,12 +84,7 @@ __host__ __device__ inline void few_swsh_m2(int l, int m, double theta, double p
         *im = 0.0;
         return;
     }
-    const double inv_4pi = 0.07957747154594767;   // 1 / (4 pi)
-    double c = cos(0.5 * theta), s = sin(0.5 * theta);
-    double d = few_wigner_d(l, m, 2, c, s);
-    double a = sqrt((2 * l + 1) * inv_4pi) * d;
     double sp, cp;
     sincos((double)m * phi, &sp, &cp);
-    *re = a * cp;
-    *im = a * sp;
+    few_swsh_m2_cs(l, m, cos(0.5 * theta), sin(0.5 * theta), cp, sp, re, im);
 }
