@@ -69,12 +69,13 @@ def check(got, ref, prec):
 
 def test_spline_coefficients_match_oracle(native_mod, torch_dev):
     import torch
-    # knot counts around the 16-row batches of the sweeps: tail only (4, 5,
-    # 18), one full batch and no tail (19), full batches and a tail (20, 23,
-    # 35, 40), many batches (1024)
+    # knot counts: one row per wave's chunk (4), an empty last chunk (5, 9),
+    # chunks of ragged length (18, 19, 20, 23, 35, 40, 127), the largest grid
+    # kept in registers (128), the first and a large one that stream with
+    # one lane per series (129, 1024)
     cases = [("config0", synth.config0()),
              ("tiny K=4", synth.tiny_waveform(11, K=4, M=3))]
-    for i, K in enumerate((5, 18, 19, 20, 23, 35, 1024)):
+    for i, K in enumerate((5, 9, 18, 19, 20, 23, 35, 127, 128, 129, 1024)):
         cases.append((f"tiny K={K}", synth.tiny_waveform(12 + i, K=K, M=9, l_max=5, n_max=4)))
     for name, w in cases:
         log(f"[spline] {name} K={w.K} M={w.M}")
