@@ -499,7 +499,7 @@ def served(native, precision: str, seconds: float, dev, budget: int,
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--no-cpu", action="store_true")

@@ -55,6 +55,68 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 // ---------------------------------------------------------------------------
+// XCD split of the matrix-core summation (one per stream the plan launches
+// on).  The workgroups of each store launch report their times, tagged with
+// the launch's number, in the pinned array rep; before a launch, the latest
+// complete report (every workgroup with one tag, and the weights that launch
+// used still in the history) moves each weight half way towards equal XCD
+// finishing times, w_x (1 + (T / T_x - 1) / 2) with T_x the longest time of
+// XCD x and T their mean, renormalised to mean 1 within [1/2, 2].  Reports
+// are read while later launches may overwrite them: a mixed set is skipped.
+// ---------------------------------------------------------------------------
+struct XcdSplit {
+    unsigned long long *rep = nullptr;  // [kMfBalanceWG], pinned host memory
+    double w[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    unsigned tag = 0;                   // tag of the next launch
+    unsigned applied = ~0u;             // last report folded in
+    struct Used {
+        unsigned tag = ~0u;
+        double w[8];
+    } hist[8];                          // weights of the last launches, by tag mod 8
+    std::mutex mu;
+
+    void apply(SumJob *j, int G) {
+        std::lock_guard<std::mutex> g(mu);
+        constexpr unsigned kTagMask = (1u << (64 - kMfTagShift)) - 1;
+        if (G % 8 == 0 && G <= kMfBalanceWG) {
+            const volatile unsigned long long *r = rep;
+            const unsigned t = (unsigned)(r[0] >> kMfTagShift);
+            bool ok = t != applied;
+            double T[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int i = 0; i < G && ok; ++i) {
+                const unsigned long long v = r[i];
+                ok = (unsigned)(v >> kMfTagShift) == t;
+                T[i & 7] = std::max(T[i & 7], (double)(v & ((1ull << kMfTagShift) - 1)));
+            }
+            const Used &u = hist[t % 8];
+            ok = ok && u.tag == t;
+            double mean = 0.0;
+            for (int x = 0; x < 8; ++x) {
+                ok = ok && T[x] > 0.0;
+                mean += 0.125 * T[x];
+            }
+            if (ok) {
+                double s = 0.0;
+                for (int x = 0; x < 8; ++x) {
+                    w[x] = u.w[x] * (1.0 + 0.5 * (mean / T[x] - 1.0));
+                    s += 0.125 * w[x];
+                }
+                for (int x = 0; x < 8; ++x) w[x] = std::min(2.0, std::max(0.5, w[x] / s));
+                applied = t;
+            }
+        }
+        const unsigned tg = tag & kTagMask;
+        j->btime = rep;
+        j->btag = tg;
+        for (int x = 0; x < 8; ++x) j->bw[x] = (float)w[x];
+        Used &h = hist[tg % 8];
+        h.tag = tg;
+        for (int x = 0; x < 8; ++x) h.w[x] = (double)j->bw[x];
+        ++tag;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Device arena: one hipMalloc per plan, first-fit sub-allocation on the host.
 // ---------------------------------------------------------------------------
 class Arena {
@@ -539,6 +601,9 @@ struct few_plan_s {
     unsigned *counters = nullptr;   // one persistent-kernel counter per stream slot
     // few_batch on the plan stream: its own counter
     unsigned *sync_counter = nullptr;
+    // XCD split of the matrix-core summation: one per served stream slot,
+    // then the plan stream's
+    std::unique_ptr<XcdSplit[]> xsplit;
     // Arena blocks (and pinned buffers) released once the event recorded after
     // the last work that uses them has completed: few_spline_free, few_batch
     // blocks and grown inner-product buffers.  The served scheduler carves the
@@ -776,6 +841,21 @@ int32_t few_plan_create(const few_plan_desc *desc, few_plan *out) {
             p->counters = (unsigned *)p->arena.ptr(off);
             p->sync_counter = p->counters + 64 * p->max_inflight;
         }
+        {
+            const size_t nb = (size_t)p->max_inflight + 1;
+            p->xsplit.reset(new XcdSplit[nb]);
+            for (size_t i = 0; i < nb; ++i) {
+                void *h = nullptr;
+                if (hipHostMalloc(&h, sizeof(unsigned long long) * kMfBalanceWG) != hipSuccess) {
+                    for (size_t k = 0; k < i; ++k) hipHostFree(p->xsplit[k].rep);
+                    hipFree(base);
+                    delete p;
+                    return fail(FEW_E_NOMEM, "pinned report array allocation failed");
+                }
+                std::memset(h, 0, sizeof(unsigned long long) * kMfBalanceWG);
+                p->xsplit[i].rep = (unsigned long long *)h;
+            }
+        }
         for (int s = 0; s < 2; ++s) {
             if (hipEventCreateWithFlags(&p->stage_ev[s], hipEventDisableTiming) != hipSuccess) {
                 hipFree(base);
@@ -862,6 +942,8 @@ int32_t few_plan_destroy(few_plan p) {
         }
         p->pinned.clear();
         hipFree(p->arena_base);
+        if (p->xsplit)
+            for (int i = 0; i <= p->max_inflight; ++i) hipHostFree(p->xsplit[i].rep);
         if (p->log) std::fclose(p->log);
         delete p;
         return FEW_OK;
@@ -1017,9 +1099,12 @@ int sum_impl(few_plan p, few_spline s, double theta, double phi, double scale, d
             return mf ? launch_fold_pack(pj, p->stream) : launch_prepare(pj, p->fp32, p->stream);
         };
         auto sum = [&]() -> hipError_t {
-            if (mf)
-                return inner ? launch_sum_mfma_inner(sj, p->mf_wg, 2.0 * dt, out2, p->stream)
-                             : launch_sum_mfma(sj, p->mf_wg, p->stream);
+            if (mf) {
+                if (inner) return launch_sum_mfma_inner(sj, p->mf_wg, 2.0 * dt, out2, p->stream);
+                SumJob sb = sj;
+                p->xsplit[p->max_inflight].apply(&sb, p->mf_wg);
+                return launch_sum_mfma(sb, p->mf_wg, p->stream);
+            }
             return inner ? launch_sum_inner(sj, (int)slots, p->fp32, 2.0 * dt, out2, p->stream)
                          : launch_sum(sj, (int)slots, p->fp32, p->stream);
         };
@@ -1348,8 +1433,10 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         HIP_TRY(pinned_upload(dev, host, upload_end, s));
         HIP_TRY(launch_fit(f, r->h.t.data(), s));
         if (r->h.mfma) {
+            SumJob ub = u;
+            p->xsplit[(counter - p->counters) / 64].apply(&ub, p->mf_wg);   // this stream's
             HIP_TRY(launch_fold_pack(q, s));
-            HIP_TRY(launch_sum_mfma(u, p->mf_wg, s));
+            HIP_TRY(launch_sum_mfma(ub, p->mf_wg, s));
         } else {
             HIP_TRY(launch_prepare(q, fp32, s));
             HIP_TRY(launch_sum(u, (int)slots, fp32, s));

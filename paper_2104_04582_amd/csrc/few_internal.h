@@ -178,6 +178,16 @@ struct PrepJob {
     int l_max;              // largest listed l
 };
 
+// Split of the matrix-core summation between the eight XCDs: the XCDs of
+// one device run at different clocks under load, so a store launch may give
+// XCD x a share of the samples proportional to a weight w[x], and each of its
+// workgroups then reports its time (with the launch's tag) in pinned host
+// memory, from which the host forms the weights of later launches.  Only
+// performance depends on it: any weights give a split that covers every
+// sample once.
+constexpr int kMfBalanceWG = 256;       // workgroups a report array holds
+constexpr int kMfTagShift = 40;         // report word: tag << 40 | s_memrealtime ticks
+
 // Summation stage for one request.
 struct SumJob {
     const double *t;
@@ -205,6 +215,11 @@ struct SumJob {
     const int2 *mrows;      // [n_mrows + 1]
     int n_mrows, n_min;
     long long sample_base;  // first sample of this job in a batched launch's range
+    // matrix-core store launches: XCD split weights (all 0: equal split), and
+    // where each workgroup reports (tag << kMfTagShift | its time), or nullptr
+    float bw[8];
+    unsigned long long *btime;
+    unsigned btag;
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.

@@ -2458,6 +2458,36 @@ __device__ __forceinline__ void mf_share(long long total, long long *lo, long lo
     *hi = total * (r + 1) / G;
 }
 
+// Launches whose XCD split follows the weights: a multiple of 8 workgroups
+// (XCD b mod 8 takes workgroup b), at most kMfBalanceWG, and weights within
+// [1/4, 4].
+__device__ __forceinline__ bool mf_balanced(const SumJob &jb) {
+    if (jb.btime == nullptr || gridDim.x % 8 != 0 || gridDim.x > kMfBalanceWG) return false;
+    for (int x = 0; x < 8; ++x)
+        if (!(jb.bw[x] >= 0.25f && jb.bw[x] <= 4.0f)) return false;
+    return true;
+}
+
+// Share of workgroup b with the weights wl: XCD x takes the samples
+// [X_x, X_{x+1}), X_x = floor(total W_x / W_8) with W the running sum of the
+// weights (X_0 = 0, X_8 = total), in equal contiguous slots of its G/8
+// workgroups.
+__device__ __forceinline__ void mf_share_w(const float *wl, long long total, long long *lo,
+                                           long long *hi) {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, j = b >> 3, S = G >> 3;
+    double cw = 0.0, all = 0.0;
+    for (int i = 0; i < 8; ++i) {
+        const double w = wl[i];
+        if (i < x) cw += w;
+        all += w;
+    }
+    const long long a = x == 0 ? 0 : (long long)((double)total * (cw / all));
+    const long long e = x == 7 ? total : (long long)((double)total * ((cw + (double)wl[x]) / all));
+    *lo = a + (e - a) * j / S;
+    *hi = a + (e - a) * (j + 1) / S;
+}
+
 template <bool INNER>
 __global__ __launch_bounds__(64 * kMfWaves) void sum_mfma_kernel(SumJob jb) {
     extern __shared__ float4 mf_lds[];
@@ -2466,8 +2496,21 @@ __global__ __launch_bounds__(64 * kMfWaves) void sum_mfma_kernel(SumJob jb) {
     __shared__ double2 iacc[INNER ? 64 * kMfWaves : 1];
     if constexpr (INNER) iacc[threadIdx.x] = make_double2(0.0, 0.0);
     long long lo, hi;
-    mf_share(jb.n, &lo, &hi);
+    // the inner-product launch keeps the equal split (its binary64 sums
+    // then do not depend on the weights)
+    const unsigned long long t0 = wall_clock64();
+    if (!INNER && mf_balanced(jb))
+        mf_share_w(jb.bw, jb.n, &lo, &hi);
+    else
+        mf_share(jb.n, &lo, &hi);
     mf_range<INNER>(jb, lo, hi, mf_lds, msc, mm, iacc);
+    if (!INNER && jb.btime != nullptr && (int)blockIdx.x < kMfBalanceWG) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long dt = min(wall_clock64() - t0, (1ull << kMfTagShift) - 1);
+            jb.btime[blockIdx.x] = ((unsigned long long)jb.btag << kMfTagShift) | dt;
+        }
+    }
     if constexpr (INNER) {
         __shared__ double2 red[kMfWaves];
         double2 v = wave_sum(iacc[threadIdx.x]);

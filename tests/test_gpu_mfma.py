@@ -140,6 +140,25 @@ def test_mfma_repeat_is_bitwise_deterministic(env):
     assert np.array_equal(a, b)
 
 
+def test_mfma_split_between_xcds_does_not_change_the_waveform(env):
+    """Repeated sums on one plan: each launch moves the split of the samples
+    between the XCDs after the measured times, and every output stays
+    bitwise equal to the first (equal split) one."""
+    native, torch, dev = env
+    w = synth.config1()
+    pp, pr, amp = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                   for a in (w.phi_phi, w.phi_r, w.amp))
+    with native.Plan(0, "mixed") as plan:
+        sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+        outs = []
+        for _ in range(6):
+            o = plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples)
+            torch.cuda.synchronize()
+            outs.append(o.cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_mfma_inner_product_matches_its_waveform(env):
     """few_inner_product on a matrix-core request forms the same h as
     few_mode_sum (binary64 reductions of the stored waveform agree to 1e-12)."""
