@@ -38,7 +38,12 @@
  *    until the plan's stream passes the enqueued work; for few_submit, until
  *    few_poll returns something other than FEW_PENDING.
  *  - The library owns plan scratch, few_spline objects and request state,
- *    all carved from one device arena of hbm_budget_bytes per plan.
+ *    all carved from one device arena of hbm_budget_bytes per plan, and a
+ *    little pinned host memory per plan: the upload staging buffers and, per
+ *    stream the plan launches on, a 2 KiB array in which the matrix-core
+ *    summation's workgroups report their times (the plan splits later
+ *    launches' samples between the GPU's XCDs by them; results do not depend
+ *    on the split).
  *
  * Errors
  *  - Every function returns a few_status.  Argument, knot and mode errors are
