@@ -2106,6 +2106,7 @@ __device__ __forceinline__ float lane_xchg(int addr, float v) {
 // f, f^16, f^{4g} (g = 0..3), e^{-i Phi_phi}, its 8th power, the row
 // harmonic z_0 e^{-2ig Phi_phi} (g = 0..3), u, and the reduced Phi_phi.
 constexpr int kMfSPW = kMfNT * 16;                  // samples per wave and round
+static_assert(kMfNT <= 4, "one sample tile per lane group in the epilogue");
 struct MfSampleArea {
     float2 f[kMfSPW], f16[kMfSPW], c[kMfSPW][4];
     float2 e[kMfSPW], e8[kMfSPW], zg[kMfSPW][4];
@@ -2135,6 +2136,17 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, double ti,
     const FEW_AS4 double *pc = cptr(jb.pcoef) + (size_t)iv * 16;
     const long long wbase = base + (long long)w * SPW;
     const int m0 = mm[0], am0 = m0 < 0 ? -m0 : m0;
+    // After the row combination every lane holds h of its column's sample in
+    // each tile; lane group g < kMfNT then stores (or takes into the inner
+    // products) the sample of tile g, so a wave issues one store per round.
+    const long long jo = wbase + 16 * g + col;
+    const bool own = g < kMfNT && jo < e;
+    // INNER: that sample's data, requested first so that its latency passes
+    // under the round's products
+    // (every lane loads, at a clamped index, so that the load is not under a
+    // branch, which would make the compiler wait for it at the join)
+    float2 dv = make_float2(0.0f, 0.0f);
+    if constexpr (INNER) dv = ((const float2 *)jb.data)[min(jo, e - 1)];
     // this lane's samples -> the wave's area
 #pragma unroll
     for (int k = 0; k < OWN; ++k) {
@@ -2290,16 +2302,6 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, double ti,
                 for (int i = 0; i < 4; ++i) acc[mt][nt][i] = acc[mt][nt][i] * uu[nt];
         power(p, std::false_type{});
     }
-    // INNER: the data samples of this lane's columns, requested now so that
-    // their latency overlaps the row combination
-    float2 dv[kMfNT];
-    if constexpr (INNER) {
-#pragma unroll
-        for (int nt = 0; nt < kMfNT; ++nt) {
-            const long long jr = wbase + 16 * nt + col;
-            dv[nt] = (g == 0 && jr < e) ? ((const float2 *)jb.data)[jr] : make_float2(0.0f, 0.0f);
-        }
-    }
     // Rows -> h.  The lane holds rows r = 8 mt + 2g (a0 + i b0) and r + 1
     // (a1 + i b1) of tile mt, each to be scaled by 2^{E_r} and multiplied by
     // its harmonic z_r = e^{-i m_r Phi_phi}.
@@ -2314,6 +2316,7 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, double ti,
         mo[mt] = mm[r0 + 1];
     }
     double dh = 0.0, hh = 0.0;
+    float hro = 0.0f, hqo = 0.0f;                   // h of this lane group's sample
     // byte addresses of lanes l ^ 16 and l ^ 32 for ds_bpermute
     const int bp16 = (lane ^ 16) << 2, bp32 = (lane ^ 32) << 2;
 #pragma unroll
@@ -2372,16 +2375,19 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, double ti,
         hq = hq + lane_xchg(bp16, hq);
         hr = hr + lane_xchg(bp32, hr);
         hq = hq + lane_xchg(bp32, hq);
-        const long long jr = wbase + 16 * nt + col;
-        if (g == 0 && jr < e) {
-            if constexpr (INNER) {
-                const double xr = hr, xi = hq, dr = dv[nt].x, di = dv[nt].y;
-                dh = dh + (dr * xr + di * xi);
-                hh = hh + (xr * xr + xi * xi);
-            } else {
-                float2 *o = (float2 *)jb.out + jr;
-                *o = make_float2(hr, hq);
-            }
+        if (g == nt) {
+            hro = hr;
+            hqo = hq;
+        }
+    }
+    if (own) {
+        if constexpr (INNER) {
+            const double xr = hro, xi = hqo, dr = dv.x, di = dv.y;
+            dh = dr * xr + di * xi;
+            hh = xr * xr + xi * xi;
+        } else {
+            float2 *o = (float2 *)jb.out + jo;
+            *o = make_float2(hro, hqo);
         }
     }
     // the area is rewritten by the next round only after these reads
