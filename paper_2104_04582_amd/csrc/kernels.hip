@@ -1808,9 +1808,9 @@ typedef _Float16 mf_half8 __attribute__((ext_vector_type(8)));
 typedef float mf_float4 __attribute__((ext_vector_type(4)));
 
 // Fold and pack for the matrix-core path: workgroup 0 computes the interval
-// starts and tile prefixes; workgroup 1 + iv kMfMT + mt folds interval iv of
-// row tile mt (rows 8 mt .. 8 mt + 7, the signed m values m_r) and writes its
-// fp16 operand table.
+// starts and tile prefixes; each other workgroup folds one interval iv for
+// one row tile mt (rows 8 mt .. 8 mt + 7, the signed m values m_r; numbering
+// below) and writes its part of the fp16 operand table.
 //
 // Fold (Eqs. (9)-(10) for fixed viewing angles, Sec. IV): every term (m_r, n)
 // is C = scale sum_contributors w A, with w = -2Y_{l, m_r} for a listed mode
@@ -1841,8 +1841,13 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
         prep_intervals(jb);
         return;
     }
-    const int iv = (b - 1) / kMfMT, mt = (b - 1) % kMfMT;
-    if (iv >= jb.K - 1) return;                     // uniform per workgroup (batched grid)
+    // workgroup 1 + 8 (kMfMT (iv / 8) + mt) + iv % 8 folds row tile mt of
+    // interval iv: the tiles of one interval are 8 workgroups apart and so run
+    // on one XCD (workgroup b runs on XCD b mod 8), whose L2 then serves the
+    // coefficient rows that several tiles read (a mode's own and mirror terms)
+    const int c = b - 1, q = c >> 3;
+    const int mt = q % kMfMT, iv = 8 * (q / kMfMT) + (c & 7);
+    if (iv >= jb.K - 1) return;                     // uniform per workgroup
     constexpr int NL = kMaxL + 1, NN = 2 * kMfA;    // l = 0..30; n + kMfA - 1 in [0, NN - 1)
     __shared__ double2 yw[8][NL];
     __shared__ double cf[8][NN][8];
@@ -3192,15 +3197,19 @@ hipError_t launch_sum_inner(const SumJob &job, int slots, bool fp32, double two_
     return hipGetLastError();
 }
 
+// Workgroup 0 and the (interval, row tile) workgroups of a K-knot request,
+// the intervals in groups of 8 (fold_pack_body).
+static int fold_pack_blocks(int K) { return 1 + 8 * kMfMT * ((K - 1 + 7) / 8); }
+
 hipError_t launch_fold_pack(const PrepJob &job, hipStream_t stream) {
-    hipLaunchKernelGGL(fold_pack_kernel, dim3(1 + (job.K - 1) * kMfMT), dim3(kFoldPackThreads), 0,
+    hipLaunchKernelGGL(fold_pack_kernel, dim3(fold_pack_blocks(job.K)), dim3(kFoldPackThreads), 0,
                        stream, job);
     return hipGetLastError();
 }
 
 hipError_t launch_fold_pack_batch(const PrepJob *jobs_dev, int n_jobs, int max_K,
                                   hipStream_t stream) {
-    hipLaunchKernelGGL(fold_pack_batch_kernel, dim3(1 + (max_K - 1) * kMfMT, n_jobs),
+    hipLaunchKernelGGL(fold_pack_batch_kernel, dim3(fold_pack_blocks(max_K), n_jobs),
                        dim3(kFoldPackThreads), 0, stream, jobs_dev);
     return hipGetLastError();
 }
