@@ -548,9 +548,10 @@ def main() -> int:
         pp = "mixed" if prec == "mixed_vector" else prec
         vec = prec == "mixed_vector"
         log(f"[bench] {prec}: warmup {args.warmup} (and >= 0.2 s), steps {args.steps}")
-        # Timed region: HIP events around the summation launches only (an event
-        # pair delays the launch after it; the other stages stay back to back).
-        with native.Plan(0, pp, timing="sum", vector_only=vec) as plan:
+        # Timed region: HIP events around every 8th summation launch only (an
+        # event pair delays the launch after it; the other stages and the
+        # other steps stay back to back).
+        with native.Plan(0, pp, timing="sum_sparse", vector_only=vec) as plan:
             sec, tm, out, step = time_path(native, plan, w, dev, args.steps, args.warmup, 0.2)
             spread = step_spread(step, args.steps)
             if not vec:

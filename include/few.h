@@ -94,6 +94,9 @@ enum {
                                  operands on the MFMA units, fp32 accumulation); every sum
                                  runs on the vector units in binary32 with Kahan-compensated
                                  accumulation */
+    FEW_FLAG_TIMING_SPARSE = 16, /* with FEW_FLAG_TIMING_SUM: events around every 8th
+                                   summation launch only (the first, the ninth, ...), so the
+                                   instrumentation delays one step in eight */
     FEW_FLAG_SELECT_SORTED = 8 /* few_mode_select: sort every knot and sum sequentially; by
                                  default a knot is decided from sums with a proven error
                                  bound and sorted only when a comparison falls within it

@@ -604,6 +604,7 @@ struct few_plan_s {
     // XCD split of the matrix-core summation: one per served stream slot,
     // then the plan stream's
     std::unique_ptr<XcdSplit[]> xsplit;
+    std::atomic<unsigned long long> sum_launches{0};    // FEW_FLAG_TIMING_SPARSE
     // Arena blocks (and pinned buffers) released once the event recorded after
     // the last work that uses them has completed: few_spline_free, few_batch
     // blocks and grown inner-product buffers.  The served scheduler carves the
@@ -647,7 +648,10 @@ hipEvent_t pool_event(few_plan p) {
 template <typename F>
 int timed_launch(few_plan p, int stage, hipStream_t s, F launch) {
     hipEvent_t a = nullptr, b = nullptr;
-    if ((p->flags & FEW_FLAG_TIMING) || ((p->flags & FEW_FLAG_TIMING_SUM) && stage == ST_SUM)) {
+    bool timed = (p->flags & FEW_FLAG_TIMING) || ((p->flags & FEW_FLAG_TIMING_SUM) && stage == ST_SUM);
+    if (timed && stage == ST_SUM && (p->flags & FEW_FLAG_TIMING_SPARSE))
+        timed = p->sum_launches++ % 8 == 0;
+    if (timed) {
         a = pool_event(p);
         b = pool_event(p);
         if (a && b) hipEventRecord(a, s);

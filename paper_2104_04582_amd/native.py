@@ -34,6 +34,7 @@ FEW_FLAG_TIMING = 1
 FEW_FLAG_TIMING_SUM = 2
 FEW_FLAG_VECTOR_ONLY = 4
 FEW_FLAG_SELECT_SORTED = 8
+FEW_FLAG_TIMING_SPARSE = 16
 
 EXPORTED = [
     "few_plan_create", "few_plan_destroy", "few_spline_fit", "few_spline_free",
@@ -188,8 +189,9 @@ class Spline:
 class Plan:
     """few_plan: device arena, precision, stream and the request server.
 
-    timing: False, True (HIP events around every launch, FEW_FLAG_TIMING) or
-    "sum" (around summation launches only, FEW_FLAG_TIMING_SUM).
+    timing: False, True (HIP events around every launch, FEW_FLAG_TIMING),
+    "sum" (around summation launches only, FEW_FLAG_TIMING_SUM) or "sum_sparse"
+    (around every 8th summation launch, FEW_FLAG_TIMING_SUM | _SPARSE).
     vector_only: mixed precision without the matrix-core summation
     (FEW_FLAG_VECTOR_ONLY).
     select_sorted: the mode selector sorts every knot (FEW_FLAG_SELECT_SORTED)."""
@@ -211,6 +213,8 @@ class Plan:
                      max_knots=max_knots, max_modes=max_modes, max_inflight=max_inflight,
                      hbm_budget_bytes=hbm_budget_bytes,
                      flags=(FEW_FLAG_TIMING_SUM if timing == "sum"
+                            else FEW_FLAG_TIMING_SUM | FEW_FLAG_TIMING_SPARSE
+                            if timing == "sum_sparse"
                             else FEW_FLAG_TIMING if timing else 0)
                      | (FEW_FLAG_VECTOR_ONLY if vector_only else 0)
                      | (FEW_FLAG_SELECT_SORTED if select_sorted else 0))

@@ -217,3 +217,21 @@ def test_coefficient_layouts_export_the_same_values(env, K):
     for p in range(4):
         d = np.abs(got[False][0][:, :8, p, :] - ref[:, :, p, :]) * (h ** p)[:, None, None]
         assert d.max() <= 1e-13 * ya, p
+
+
+def test_sparse_timing_times_every_eighth_summation(env):
+    """FEW_FLAG_TIMING_SUM | FEW_FLAG_TIMING_SPARSE: events around the first,
+    ninth, ... summation launches only."""
+    native, torch, dev = env
+    w = full_modes_short(48, 8640)
+    pp, pr, amp = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                   for a in (w.phi_phi, w.phi_r, w.amp))
+    with native.Plan(0, "mixed", timing="sum_sparse") as plan:
+        sp = plan.spline_fit(w.t_knots, pp, pr, w.lmn, amp)
+        for _ in range(17):
+            plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples)
+        torch.cuda.synchronize()
+        t = plan.timing(reset=True)
+    assert t["sum_launches"] == 3
+    assert t["spline_launches"] == 0 and t["prepare_launches"] == 0
+    assert t["sum_ms"] > 0.0
