@@ -1826,10 +1826,11 @@ typedef float mf_float4 __attribute__((ext_vector_type(4)));
 // ((Re P + Re Q) Re w + (Im Q - Im P) Im w) +
 // i ((Im P + Im Q) Re w + (Re P - Re Q) Im w),
 // so row 2r holds (Re P + Re Q, Im Q - Im P) and row 2r + 1 holds
-// (Im P + Im Q, Re P - Re Q) (Q = 0 for a = 0).  Each row is scaled by 2^-E,
-// E the exponent of its largest |coefficient| on the interval (so scaled
-// values stay below 2), and split into hi = fp16(v) and lo = fp16(v - hi),
-// both from binary64.  Table layout, per interval:
+// (Im P + Im Q, Re P - Re Q) (Q = 0 for a = 0).  Each pair of rows (signed m
+// rows 2j and 2j + 1, which one lane of the product holds) is scaled by
+// 2^-E, E the exponent of the pair's largest |coefficient| on the interval
+// (so scaled values stay below 2), and split into hi = fp16(v) and
+// lo = fp16(v - hi), both from binary64.  Table layout, per interval:
 // [3 - p][mt][t][hi, lo][lane 64][8 values] (p descending, the order of the
 // Horner recurrence that reads it), lane l's operand fragment of
 // v_mfma_f32_16x16x32_f16: matrix row l % 16 of the tile, columns
@@ -1973,6 +1974,9 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
         if (k < 8)
             for (int x = sub; x < NN * 8; x += 32) mx = fmax(mx, fabs((&cf[k][0][0])[x]));
         for (int off = 16; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 32));
+        // one scale for the row pair 2j, 2j + 1 (rows k and k ^ 1, the two
+        // rows one lane of the product holds): the epilogue applies it once
+        mx = fmax(mx, __shfl_xor(mx, 32));
         if (k < 8 && sub == 0) {
             int e = 0;
             double sc = 0.0;
@@ -2331,15 +2335,17 @@ __device__ __forceinline__ double2 mf_round(const SumJob &jb, int iv, double ti,
         float hr, hq;
         if (consec) {
             // z_r = z_0 E^{2g} E^{8 mt} (E for the odd row): Horner in E^8
-            // over the tiles of W_mt = s_e (a0 + i b0) + E s_o (a1 + i b1)
+            // over the tiles of W_mt = s (a0 + i b0 + E (a1 + i b1)), s the
+            // scale the two rows share
             const float2 E8 = sa->e8[sl], Z = sa->zg[sl][g];
             float qr = 0.0f, qi = 0.0f;
 #pragma unroll
             for (int mt = kMfMT - 1; mt >= 0; --mt) {
-                const float a0 = acc[mt][nt][0] * se[mt], b0 = acc[mt][nt][1] * se[mt];
-                const float a1 = acc[mt][nt][2] * so[mt], b1 = acc[mt][nt][3] * so[mt];
-                const float wr = __builtin_fmaf(E.x, a1, __builtin_fmaf(-E.y, b1, a0));
-                const float wi = __builtin_fmaf(E.x, b1, __builtin_fmaf(E.y, a1, b0));
+                // the two rows share their scale (fold_pack_body)
+                const float a0 = acc[mt][nt][0], b0 = acc[mt][nt][1];
+                const float a1 = acc[mt][nt][2], b1 = acc[mt][nt][3];
+                const float wr = se[mt] * __builtin_fmaf(E.x, a1, __builtin_fmaf(-E.y, b1, a0));
+                const float wi = se[mt] * __builtin_fmaf(E.x, b1, __builtin_fmaf(E.y, a1, b0));
                 if (mt == kMfMT - 1) {
                     qr = wr;
                     qi = wi;
