@@ -1854,44 +1854,54 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
     __shared__ double cf[8][NN][8];
     __shared__ double rsc[8];
     __shared__ int rowm[9];
+    __shared__ int rowmv[8];                        // m_r of the tile's rows
     __shared__ double2 trig[9];                     // (cos, sin) of theta / 2 and of m_r phi
     __shared__ int2 segv[kFoldSegs];
     const int tid = threadIdx.x;
     const int r0 = 8 * mt;
-    {
-        const int sg0 = jb.mrows[min(r0, jb.n_mrows)].y, sg1 = jb.mrows[min(r0 + 8, jb.n_mrows)].y;
-        if (tid < sg1 - sg0 && tid < kFoldSegs) {
-            const int4 S = jb.segs[sg0 + tid];
-            segv[tid] = make_int2(S.w, S.y);
-        }
+    // the tile's segments [g0, g1); its terms are one contiguous run [t0, t1)
+    // (uniform values: scalar loads)
+    const int g0 = jb.mrows[min(r0, jb.n_mrows)].y, g1 = jb.mrows[min(r0 + 8, jb.n_mrows)].y;
+    const int t0 = g0 < jb.n_segs ? jb.segs[g0].w : jb.n_terms;
+    const int t1 = g1 < jb.n_segs ? jb.segs[g1].w : jb.n_terms;
+    if (tid < g1 - g0 && tid < kFoldSegs) {
+        const int4 S = jb.segs[g0 + tid];
+        segv[tid] = make_int2(S.w, S.y);
     }
     if (tid < 9) {
         const int r = r0 + tid;
-        rowm[tid] = r <= jb.n_mrows ? jb.mrows[r].y : jb.mrows[jb.n_mrows].y;   // first segment
+        const int2 R = jb.mrows[min(r, jb.n_mrows)];
+        rowm[tid] = R.y;                            // first segment
+        const int m = r < jb.n_mrows ? R.x : 0;
+        if (tid < 8) rowmv[tid] = m;
         double sv, cv;
         if (tid == 8)
             sincos(0.5 * jb.theta, &sv, &cv);
         else
-            sincos((double)(r < jb.n_mrows ? jb.mrows[r].x : 0) * jb.phi, &sv, &cv);
+            sincos((double)m * jb.phi, &sv, &cv);
         trig[tid] = make_double2(cv, sv);
     }
     for (int x = tid; x < 8 * NN * 8; x += blockDim.x) (&cf[0][0][0])[x] = 0.0;
     __syncthreads();
+    // this lane's first term's contributor range, requested before the weights
+    // are formed (from LDS only), so that it arrives meanwhile
+    int tt = t0 + tid;
+    int ea = 0, eb = 0;
+    if (tt < t1) {
+        ea = jb.term_ptr[tt];
+        eb = jb.term_ptr[tt + 1];
+    }
     for (int x = tid; x < 8 * NL; x += blockDim.x) {
         const int k = x / NL, l = x % NL, r = r0 + k;
         double yr = 0.0, yi = 0.0;
         if (r < jb.n_mrows) {
-            const int m = jb.mrows[r].x;
+            const int m = rowmv[k];
             if (l >= 2 && l >= abs(m) && l <= jb.l_max)
                 few_swsh_m2_cs(l, m, trig[8].x, trig[8].y, trig[k].x, trig[k].y, &yr, &yi);
         }
         yw[k][l] = make_double2(yr, yi);
     }
     __syncthreads();
-    // terms of rows r0 .. r0 + 7 are one contiguous run [t0, t1)
-    const int g0 = rowm[0], g1 = rowm[8];
-    const int t0 = g0 < jb.n_segs ? jb.segs[g0].w : jb.n_terms;
-    const int t1 = g1 < jb.n_segs ? jb.segs[g1].w : jb.n_terms;
     // the tile's segments (first term, n of the first term) in LDS when few
     const bool seg_lds = g1 - g0 <= kFoldSegs;
     auto seg_of = [&](int g) {
@@ -1913,7 +1923,11 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
             a[2 * p + 1] = v.y;
         }
     };
-    for (int tt = t0 + tid; tt < t1; tt += blockDim.x) {
+    for (; tt < t1; tt += blockDim.x) {
+        if (tt != t0 + tid) {
+            ea = jb.term_ptr[tt];
+            eb = jb.term_ptr[tt + 1];
+        }
         int g = g0;
         while (g + 1 < g1 && seg_of(g + 1).x <= tt) ++g;
         const int2 S = seg_of(g);
@@ -1938,7 +1952,6 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
         // three contributors at a time, added in contributor order: their
         // coefficient rows are requested, then the next three indices (so
         // that those arrive while these rows do), then the rows are added
-        const int ea = jb.term_ptr[tt], eb = jb.term_ptr[tt + 1];
         int2 src[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) src[j] = ea + j < eb ? jb.term_src[ea + j] : make_int2(0, 0);
