@@ -560,7 +560,9 @@ def main() -> int:
         # Stage breakdown: the same steps with events around every launch.
         with native.Plan(0, pp, timing=True, vector_only=vec) as plan:
             _, tms, _, _ = time_path(native, plan, w, dev, 5, 2)
-        sum_ms = tm["sum_ms"] / max(tm["sum_launches"], 1)
+        if tm["sum_launches"] < 1:
+            raise RuntimeError("no summation launch of the timed pass was timed")
+        sum_ms = tm["sum_ms"] / tm["sum_launches"]
         flops = flops_mf if (prec == "mixed" and mfma) else flops_vec
         res[prec] = {
             "ms_per_step": sec * 1e3,

@@ -95,8 +95,9 @@ enum {
                                  runs on the vector units in binary32 with Kahan-compensated
                                  accumulation */
     FEW_FLAG_TIMING_SPARSE = 16, /* with FEW_FLAG_TIMING_SUM: events around every 8th
-                                   summation launch only (the first, the ninth, ...), so the
-                                   instrumentation delays one step in eight */
+                                   summation launch only (the first, the ninth, ... counted
+                                   from plan creation or the last few_plan_timing reset), so
+                                   the instrumentation delays one step in eight */
     FEW_FLAG_SELECT_SORTED = 8 /* few_mode_select: sort every knot and sum sequentially; by
                                  default a knot is decided from sums with a proven error
                                  bound and sorted only when a comparison falls within it
@@ -340,7 +341,8 @@ int32_t few_wait(few_plan plan, uint64_t ticket);
 int32_t few_plan_log(few_plan plan, const char *path);
 
 /* Kernel times recorded so far (FEW_FLAG_TIMING), after synchronising the
- * plan stream; reset != 0 clears the counters. */
+ * plan stream; reset != 0 clears the counters (and restarts the count of
+ * FEW_FLAG_TIMING_SPARSE, so the next summation launch is timed). */
 int32_t few_plan_timing(few_plan plan, few_timing *out, int32_t reset);
 
 /* The calling thread's last error message ("" if none). */

@@ -1203,6 +1203,7 @@ int32_t few_plan_timing(few_plan p, few_timing *out, int32_t reset) {
             p->acc_ms[i] = 0;
             p->acc_n[i] = 0;
         }
+        p->sum_launches = 0;        // FEW_FLAG_TIMING_SPARSE: the next launch is timed
     }
     return FEW_OK;
 }

@@ -221,7 +221,7 @@ def test_coefficient_layouts_export_the_same_values(env, K):
 
 def test_sparse_timing_times_every_eighth_summation(env):
     """FEW_FLAG_TIMING_SUM | FEW_FLAG_TIMING_SPARSE: events around the first,
-    ninth, ... summation launches only."""
+    ninth, ... summation launches only, counted from the last timing reset."""
     native, torch, dev = env
     w = full_modes_short(48, 8640)
     pp, pr, amp = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -232,6 +232,12 @@ def test_sparse_timing_times_every_eighth_summation(env):
             plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples)
         torch.cuda.synchronize()
         t = plan.timing(reset=True)
+        # the reset restarts the count: the first of three more launches is timed
+        for _ in range(3):
+            plan.mode_sum(sp, w.theta, w.phi, w.dt, w.n_samples)
+        torch.cuda.synchronize()
+        t2 = plan.timing(reset=True)
     assert t["sum_launches"] == 3
     assert t["spline_launches"] == 0 and t["prepare_launches"] == 0
     assert t["sum_ms"] > 0.0
+    assert t2["sum_launches"] == 1 and t2["sum_ms"] > 0.0
