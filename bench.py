@@ -427,7 +427,10 @@ def cpu_small(threads: int):
 def served(native, precision: str, seconds: float, dev, budget: int,
            check_oracle: bool = True, request_log=None):
     """Replay a Poisson trace (20 req/s, 10% full 4-yr requests) through
-    few_submit/few_poll; latency = arrival -> completion seen by the host."""
+    few_submit/few_poll; latency = arrival -> completion seen by the host.
+    The client submits at the arrival time (it sleeps until shortly before an
+    arrival, then spins) and, while requests are pending, polls them back to
+    back, so that its own sleeps add no latency."""
     import torch
     from paper_2104_04582_amd import synth
     trace = synth.served_trace(rate=20.0, duration=seconds, p_full=0.1, seed=4)
@@ -469,7 +472,12 @@ def served(native, precision: str, seconds: float, dev, budget: int,
                 if a.kind == "full" and first_full is None:
                     first_full = (w, out)
             if not done:
-                time.sleep(0.0002)
+                if pending:
+                    time.sleep(0)
+                elif nxt < len(reqs):
+                    wait = reqs[nxt][0].t_arrival - (time.perf_counter() - t_start)
+                    if wait > 2e-3:
+                        time.sleep(wait - 1e-3)
         wall = time.perf_counter() - t_start
     lat = np.array(lat) * 1e3
     kinds = np.array(kinds)

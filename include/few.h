@@ -309,7 +309,9 @@ int32_t few_batch(few_plan plan, int32_t n, const few_request *reqs);
  * while their arena footprint fits the plan budget, packs the admitted ones
  * into one batched launch on one of max_inflight library-owned streams, and
  * retires them when that launch completes.  Each result is bitwise identical
- * to the same request run alone.
+ * to the same request run alone.  While launches are in flight the scheduler
+ * polls their completion back to back, so it keeps one host core busy; it
+ * sleeps when nothing is queued or running.
  * Ordering: few_submit records an event on the plan stream and the request's
  * launch waits for it, so work the caller enqueued on the plan stream before
  * the call (writing phi_phi, phi_r, amp; last reads of out) completes first.

@@ -1446,7 +1446,8 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
             HIP_TRY(launch_prepare(q, fp32, s));
             HIP_TRY(launch_sum(u, (int)slots, fp32, s));
         }
-        HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+        b->done = sync_event(p);
+        if (!b->done) return fail(FEW_E_HIP, "event creation failed");
         HIP_TRY(hipEventRecord(b->done, s));
         return FEW_OK;
     }
@@ -1492,7 +1493,8 @@ int launch_batch(few_plan p, Batch *b, hipStream_t s, unsigned *counter) {
         HIP_TRY(launch_fold_pack_batch(pd + nv, n - nv, max_K_mf, s));
         HIP_TRY(launch_sum_mfma_batch(sd + nv, n - nv, mf_total, p->mf_wg, s));
     }
-    HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    b->done = sync_event(p);
+    if (!b->done) return fail(FEW_E_HIP, "event creation failed");
     HIP_TRY(hipEventRecord(b->done, s));
     return FEW_OK;
 }
@@ -1534,7 +1536,7 @@ void scheduler_main(few_plan p) {
             if (p->log) std::fflush(p->log);
             p->arena.release(b->arena_off);
             p->pinned.put(b->pinned);
-            hipEventDestroy(b->done);
+            put_sync_event(p, b->done);
             p->slot_busy[b->slot] = false;
             delete b;
             p->inflight.erase(p->inflight.begin() + i);
@@ -1604,7 +1606,7 @@ void scheduler_main(few_plan p) {
                 if (rc != FEW_OK) {
                     if (b->done) {
                         hipEventSynchronize(b->done);
-                        hipEventDestroy(b->done);
+                        put_sync_event(p, b->done);
                     } else {
                         hipStreamSynchronize(p->bstreams[slot]);
                     }
@@ -1628,10 +1630,17 @@ void scheduler_main(few_plan p) {
             }
         }
         if (p->stop && p->pending.empty() && p->inflight.empty()) break;
-        if (p->inflight.empty() && p->pending.empty())
+        if (p->inflight.empty() && p->pending.empty()) {
             p->cv_work.wait(g, [&] { return p->stop || !p->pending.empty(); });
-        else
+        } else if (!p->inflight.empty()) {
+            // batches in flight: their completion is polled back to back (a
+            // timed wait sleeps ~60 us, which a request's latency would carry)
+            g.unlock();
+            std::this_thread::yield();
+            g.lock();
+        } else {
             p->cv_work.wait_for(g, std::chrono::microseconds(50));
+        }
     }
 }
 
