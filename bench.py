@@ -528,7 +528,7 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes": x.numel(), "copies": 5}), flush=True)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
 
