@@ -718,6 +718,13 @@ __device__ void fit_amplitudes_staged(const FitJob &jb, const double *t, int blk
     const bool live = q < 2 * M;
     const int L = (K + NW - 1) / NW;
     const int r_lo = min(K, w * L), n = min(K, r_lo + L) - r_lo;
+    // The knot times of the spacings h_i = t_{i+1} - t_i that wave 0 forms for
+    // the factor (i = lane and lane + 64, clamped), requested first: a wave's
+    // loads complete in order, so the factor waits only for these and starts
+    // while the knot values and the upload requested below are in flight.
+    static_assert(kFitStageKnots <= 2 * kWave + 1, "two spacings per lane");
+    double ta0 = t[min(lane, K - 2)], tb0 = t[min(lane, K - 2) + 1];
+    double ta1 = t[min(lane + kWave, K - 2)], tb1 = t[min(lane + kWave, K - 2) + 1];
     // the workgroup's share of the upload: each lane's first word requested
     // now (host memory is far) and stored at the end
     long long up_x = -1, up_end = 0;
@@ -740,8 +747,12 @@ __device__ void fit_amplitudes_staged(const FitJob &jb, const double *t, int blk
             yv[j] = live ? y[(size_t)i * stride] : 0.0;
         }
     }
+    // the knot times are taken here, after the loads above were issued (this
+    // keeps the compiler from moving their loads into the branch below)
+    asm volatile("" : "+v"(ta0), "+v"(tb0), "+v"(ta1), "+v"(tb1));
     if (w == 0) {
-        for (int i = lane; i < K - 1; i += kWave) hs[i] = t[i + 1] - t[i];
+        if (lane < K - 1) hs[lane] = tb0 - ta0;
+        if (lane + kWave < K - 1) hs[lane + kWave] = tb1 - ta1;
         lds_wave_sync();
         fit_factor_wave(hs, K, invd, wv, bv);
     }
