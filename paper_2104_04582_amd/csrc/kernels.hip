@@ -1875,13 +1875,24 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
     const int g0 = jb.mrows[min(r0, jb.n_mrows)].y, g1 = jb.mrows[min(r0 + 8, jb.n_mrows)].y;
     const int t0 = g0 < jb.n_segs ? jb.segs[g0].w : jb.n_terms;
     const int t1 = g1 < jb.n_segs ? jb.segs[g1].w : jb.n_terms;
-    if (tid < g1 - g0 && tid < kFoldSegs) {
-        const int4 S = jb.segs[g0 + tid];
-        segv[tid] = make_int2(S.w, S.y);
+    // This lane's first term: its contributor range is requested first, its
+    // first three contributor indices once that has arrived (after the first
+    // barrier) and before the weights are formed (from LDS only), so that the
+    // rows can be requested as soon as the weights are in place.
+    int tt = t0 + tid;
+    int ea = 0, eb = 0;
+    if (tt < t1) {
+        ea = jb.term_ptr[tt];
+        eb = jb.term_ptr[tt + 1];
     }
+    // the tile's segments and its rows' (m, first segment), both requested
+    // before either is used (every lane loads, at clamped indices, so that
+    // no load sits under a branch)
+    const int4 S = jb.segs[min(g0 + tid, max(g1 - 1, 0))];
+    const int2 R = jb.mrows[min(r0 + min(tid, 8), jb.n_mrows)];
+    if (tid < g1 - g0 && tid < kFoldSegs) segv[tid] = make_int2(S.w, S.y);
     if (tid < 9) {
         const int r = r0 + tid;
-        const int2 R = jb.mrows[min(r, jb.n_mrows)];
         rowm[tid] = R.y;                            // first segment
         const int m = r < jb.n_mrows ? R.x : 0;
         if (tid < 8) rowmv[tid] = m;
@@ -1894,14 +1905,10 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
     }
     for (int x = tid; x < 8 * NN * 8; x += blockDim.x) (&cf[0][0][0])[x] = 0.0;
     __syncthreads();
-    // this lane's first term's contributor range, requested before the weights
-    // are formed (from LDS only), so that it arrives meanwhile
-    int tt = t0 + tid;
-    int ea = 0, eb = 0;
-    if (tt < t1) {
-        ea = jb.term_ptr[tt];
-        eb = jb.term_ptr[tt + 1];
-    }
+    // (clamped, unconditional loads; indices past eb are never used)
+    int2 src[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) src[j] = jb.term_src[min(ea + j, max(eb - 1, 0))];
     for (int x = tid; x < 8 * NL; x += blockDim.x) {
         const int k = x / NL, l = x % NL, r = r0 + k;
         double yr = 0.0, yi = 0.0;
@@ -1938,6 +1945,9 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
         if (tt != t0 + tid) {
             ea = jb.term_ptr[tt];
             eb = jb.term_ptr[tt + 1];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                src[j] = ea + j < eb ? jb.term_src[ea + j] : make_int2(0, 0);
         }
         int g = g0;
         while (g + 1 < g1 && seg_of(g + 1).x <= tt) ++g;
@@ -1948,8 +1958,8 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
         double acc[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-        auto add = [&](int2 src, const double *a) {
-            const int l = src.y & 255, mir = (src.y >> 16) & 1;
+        auto add = [&](int2 cs, const double *a) {
+            const int l = cs.y & 255, mir = (cs.y >> 16) & 1;
             double2 w = yw[k][l];
             if (mir && (l & 1)) w = make_double2(-w.x, -w.y);
             const double sgn = mir ? -1.0 : 1.0;
@@ -1963,9 +1973,6 @@ __device__ void fold_pack_body(const PrepJob &jb, int b) {
         // three contributors at a time, added in contributor order: their
         // coefficient rows are requested, then the next three indices (so
         // that those arrive while these rows do), then the rows are added
-        int2 src[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) src[j] = ea + j < eb ? jb.term_src[ea + j] : make_int2(0, 0);
         for (int e = ea; e < eb; e += 3) {
             double av[3][8];
 #pragma unroll
