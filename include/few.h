@@ -412,11 +412,24 @@ uint64_t few_host_request_bytes(int32_t precision, int32_t K, int32_t M,
  * writes the launch shape: out8 = (waves per workgroup, 16-sample tiles per
  * wave, 16-row tiles, 32-column steps per sign of n, MFMA instructions per
  * tile and round, largest |n| + 1, largest number of signed m values,
- * smallest number of folded terms).  Each workgroup takes an equal contiguous
- * share of the samples, one per compute unit.
+ * smallest number of folded terms).  Each workgroup (one per compute unit)
+ * takes a contiguous share of the samples; the shares of the GPU's eight XCDs
+ * are weighted by the rule of few_host_xcd_split_step.
  */
 int32_t few_host_mfma_path(int32_t M, const int32_t *lmn);
 void few_host_mfma_shape(int32_t *out8);
+
+/*
+ * The XCD split of the matrix-core summation (a performance rule; results do
+ * not depend on it): from the weights w_prev[8] a launch gave the samples of
+ * XCD x (workgroup b runs on XCD b mod 8; the weights have mean 1) and the
+ * time its slowest workgroup on each XCD took, times[8], the plan's next
+ * launch uses w_next[x] = w_prev[x] (1 + (T / times[x] - 1) / 2), T the mean
+ * of the times, renormalised to mean 1 and clamped to [1/2, 2]: half a step
+ * towards equal finishing times.  FEW_E_ARG for a null pointer or a time or
+ * weight that is not finite and > 0.
+ */
+int32_t few_host_xcd_split_step(const double *w_prev, const double *times, double *w_next);
 
 #ifdef __cplusplus
 }

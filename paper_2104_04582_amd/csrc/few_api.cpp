@@ -64,6 +64,19 @@ int fail(int code, const char *fmt, ...) {
 // XCD x and T their mean, renormalised to mean 1 within [1/2, 2].  Reports
 // are read while later launches may overwrite them: a mixed set is skipped.
 // ---------------------------------------------------------------------------
+// One step of that rule: the weights wp[8] a launch used and its XCDs'
+// finishing times T[8] > 0 give the next weights w[8].
+void xcd_split_step(const double *wp, const double *T, double *w) {
+    double mean = 0.0;
+    for (int x = 0; x < 8; ++x) mean += 0.125 * T[x];
+    double s = 0.0;
+    for (int x = 0; x < 8; ++x) {
+        w[x] = wp[x] * (1.0 + 0.5 * (mean / T[x] - 1.0));
+        s += 0.125 * w[x];
+    }
+    for (int x = 0; x < 8; ++x) w[x] = std::min(2.0, std::max(0.5, w[x] / s));
+}
+
 struct XcdSplit {
     unsigned long long *rep = nullptr;  // [kMfBalanceWG], pinned host memory
     double w[8] = {1, 1, 1, 1, 1, 1, 1, 1};
@@ -90,18 +103,9 @@ struct XcdSplit {
             }
             const Used &u = hist[t % 8];
             ok = ok && u.tag == t;
-            double mean = 0.0;
-            for (int x = 0; x < 8; ++x) {
-                ok = ok && T[x] > 0.0;
-                mean += 0.125 * T[x];
-            }
+            for (int x = 0; x < 8; ++x) ok = ok && T[x] > 0.0;
             if (ok) {
-                double s = 0.0;
-                for (int x = 0; x < 8; ++x) {
-                    w[x] = u.w[x] * (1.0 + 0.5 * (mean / T[x] - 1.0));
-                    s += 0.125 * w[x];
-                }
-                for (int x = 0; x < 8; ++x) w[x] = std::min(2.0, std::max(0.5, w[x] / s));
+                xcd_split_step(u.w, T, w);
                 applied = t;
             }
         }
@@ -1176,6 +1180,16 @@ int32_t few_inner_product_noalloc(few_plan p, few_spline s, double theta, double
                                   const void *data, double *out2) {
     if (!data) return fail(FEW_E_ARG, "null data pointer");
     return sum_impl(p, s, theta, phi, scale, t_start, dt, n, nullptr, data, out2, 0.0, true);
+}
+
+int32_t few_host_xcd_split_step(const double *w_prev, const double *times, double *w_next) {
+    if (!w_prev || !times || !w_next) return fail(FEW_E_ARG, "null argument");
+    for (int x = 0; x < 8; ++x)
+        if (!(times[x] > 0.0) || !std::isfinite(times[x]) || !(w_prev[x] > 0.0) ||
+            !std::isfinite(w_prev[x]))
+            return fail(FEW_E_ARG, "times and weights must be finite and > 0");
+    xcd_split_step(w_prev, times, w_next);
+    return FEW_OK;
 }
 
 int32_t few_plan_timing(few_plan p, few_timing *out, int32_t reset) {

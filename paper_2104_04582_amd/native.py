@@ -44,7 +44,7 @@ EXPORTED = [
     "few_spline_fit_kerr", "few_host_terms_kerr", "few_inner_product", "few_mode_sum_ssb",
     "few_host_frame",
     "few_host_request_bytes", "few_inner_product_noalloc", "few_host_mfma_path",
-    "few_host_mfma_shape",
+    "few_host_mfma_shape", "few_host_xcd_split_step",
 ]
 
 
@@ -124,6 +124,7 @@ def load() -> ctypes.CDLL:
     lib.few_host_request_bytes.argtypes = [i32, i32, i32, i32]
     lib.few_host_mfma_path.argtypes = [i32, vp]
     lib.few_host_mfma_shape.argtypes = [vp]
+    lib.few_host_xcd_split_step.argtypes = [vp, vp, vp]
     lib.few_host_request_bytes.restype = ctypes.c_uint64
     for name in EXPORTED:
         f = getattr(lib, name)
@@ -420,6 +421,16 @@ def host_mfma_path(lmn) -> bool:
     is summed on the matrix cores."""
     lm = _host_i32(lmn).reshape(-1, 3)
     return bool(_check(load().few_host_mfma_path(lm.shape[0], lm.ctypes.data)))
+
+
+def host_xcd_split_step(w_prev, times) -> np.ndarray:
+    """few_host_xcd_split_step: the next XCD weights of the matrix-core
+    summation from the weights and per-XCD finishing times of a launch."""
+    wp = np.ascontiguousarray(w_prev, dtype=np.float64).reshape(8)
+    tm = np.ascontiguousarray(times, dtype=np.float64).reshape(8)
+    out = np.zeros(8, dtype=np.float64)
+    _check(load().few_host_xcd_split_step(wp.ctypes.data, tm.ctypes.data, out.ctypes.data))
+    return out
 
 
 def host_mfma_shape() -> dict:

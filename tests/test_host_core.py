@@ -255,3 +255,55 @@ def test_mfma_path_and_shape():
     assert not native.host_mfma_path(synth.mode_list(2, 12, 20))      # 25 signed m
     with pytest.raises(native.FewError):
         native.host_mfma_path(np.array([[1, 0, 0]], dtype=np.int32))
+
+
+def test_xcd_split_step_keeps_balanced_weights():
+    """Equal finishing times leave weights of mean 1 unchanged."""
+    w = np.array([1.2, 0.8, 1.0, 1.1, 0.9, 1.0, 1.05, 0.95])
+    assert abs(w.mean() - 1.0) < 1e-15
+    nxt = native.host_xcd_split_step(w, np.full(8, 3.0e4))
+    np.testing.assert_allclose(nxt, w, rtol=0, atol=1e-15)
+
+
+def test_xcd_split_step_moves_half_way_and_keeps_mean_one():
+    """A slow XCD loses share, the others gain, by half a step of the
+    proportional correction; the result has mean 1 when nothing is clamped."""
+    t = np.full(8, 1.0)
+    t[3] = 1.25
+    nxt = native.host_xcd_split_step(np.ones(8), t)
+    mean_t = t.mean()
+    raw = 1.0 + 0.5 * (mean_t / t - 1.0)
+    np.testing.assert_allclose(nxt, raw / raw.mean(), rtol=1e-14)
+    assert nxt[3] < 1.0 and np.all(np.delete(nxt, 3) > 1.0)
+    assert abs(nxt.mean() - 1.0) < 1e-14
+
+
+def test_xcd_split_step_converges_to_equal_finishing_times():
+    """With XCD x taking c_x per unit of work (time = weight x c_x), repeated
+    steps reach the split w_x proportional to 1 / c_x, where every XCD
+    finishes together."""
+    c = np.array([1.00, 1.04, 0.97, 1.10, 1.00, 0.93, 1.02, 1.06])
+    w = np.ones(8)
+    for _ in range(60):
+        w = native.host_xcd_split_step(w, w * c)
+    target = (1.0 / c) / np.mean(1.0 / c)
+    np.testing.assert_allclose(w, target, rtol=1e-9)
+    t = w * c
+    assert t.max() / t.min() - 1.0 < 1e-9
+
+
+def test_xcd_split_step_clamps_and_rejects_bad_input():
+    """Weights stay within [1/2, 2]; non-positive or non-finite times are an
+    argument error."""
+    t = np.ones(8)
+    t[0] = 1e6                                   # one XCD far slower
+    w = np.ones(8)
+    for _ in range(20):
+        w = native.host_xcd_split_step(w, t)
+        assert np.all(w >= 0.5) and np.all(w <= 2.0)
+    assert w[0] == 0.5
+    for bad in (0.0, -1.0, np.inf, np.nan):
+        t = np.ones(8)
+        t[5] = bad
+        with pytest.raises(native.FewError):
+            native.host_xcd_split_step(np.ones(8), t)
